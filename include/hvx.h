@@ -1,0 +1,271 @@
+/*
+ * hvx: OpenVX-style image graphs executed as fused HIP kernels on gfx950.
+ *
+ * The calls follow the graph formulation of OpenVX as the paper uses it
+ * (Section 3.1 and its edge-detection listing): create a context and a graph,
+ * create images (some of them virtual), add function nodes, verify the graph,
+ * then process it, possibly many times with new frames.  Verification is
+ * where the graph is checked and optimised (Section 5.2): parameter checks,
+ * cycle and bipartiteness checks, lowering of each node to point and local
+ * operators (Section 4, Table 2), elimination of dead computations
+ * (Section 5.2.2, Algorithm 1), fusion of producer/consumer operators so that
+ * intermediates stay on chip (Section 6.3), and the launch plan.
+ *
+ * Conventions (apply to every call):
+ *  - Every call returns an hvx_status; no C++ exception crosses this
+ *    boundary.  Handles are checked against a registry: a released or
+ *    foreign handle gives HVX_ERROR_INVALID_REFERENCE, never a crash.
+ *  - hvx_last_error(ctx) returns a message for the context's last failure.
+ *  - Device pointers passed in (hvx_image_from_ptr, hvx_image_swap_ptr) are
+ *    BORROWED: the library never frees them, and the caller keeps them alive
+ *    until the work that uses them has completed (hvx_graph_wait, or a
+ *    synchronisation of the stream given to hvx_graph_schedule).
+ *  - Images made by hvx_image_create and virtual images are owned by the
+ *    library and freed when released, or when their context is released.
+ *  - Pixel layout: row-major, row y starts at byte y * pitch.  The pitch of
+ *    every device image must be a multiple of 64 bytes and at least
+ *    width * bytes-per-pixel.  Bytes between the end of a row and the next
+ *    pitch boundary are padding: the library may read them, and kernels may
+ *    overwrite the padding of OUTPUT images; pixel data is never touched
+ *    outside the images a node writes.
+ *  - Not thread-safe per graph: calls on one graph must not overlap.
+ *    Distinct graphs and servers may be used from distinct threads.
+ */
+#ifndef HVX_H
+#define HVX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hvx_context_s* hvx_context;
+typedef struct hvx_graph_s* hvx_graph;
+typedef struct hvx_image_s* hvx_image;
+typedef struct hvx_node_s* hvx_node;
+typedef struct hvx_conv_s* hvx_convolution;
+typedef struct hvx_batch_s* hvx_batch;
+typedef struct hvx_server_s* hvx_server;
+
+typedef int32_t hvx_status;
+#define HVX_SUCCESS 0
+#define HVX_ERROR_INVALID_REFERENCE (-1)  /* null, released or wrong-type handle */
+#define HVX_ERROR_INVALID_PARAMETERS (-2) /* bad value of a scalar argument */
+#define HVX_ERROR_INVALID_FORMAT (-3)     /* image format not accepted by the node */
+#define HVX_ERROR_INVALID_DIMENSION (-4)  /* image sizes do not match */
+#define HVX_ERROR_INVALID_GRAPH (-5)      /* cycle, not bipartite, two writers, foreign image */
+#define HVX_ERROR_NOT_VERIFIED (-6)       /* graph changed or never verified */
+#define HVX_ERROR_NO_MEMORY (-7)          /* host/device allocation or HBM budget */
+#define HVX_ERROR_NOT_SUPPORTED (-8)
+#define HVX_ERROR_DEVICE (-9)             /* a HIP call failed or no device is present */
+
+/* Image formats.  Bytes per pixel: U8 1, S16 2, S32 4, F32 4, UYVY 2. */
+#define HVX_DF_VIRT 0 /* only for virtual images: resolved at verification */
+#define HVX_DF_U8 1
+#define HVX_DF_S16 2
+#define HVX_DF_S32 3
+#define HVX_DF_F32 4
+#define HVX_DF_UYVY 5 /* 4:2:2, bytes U Y0 V Y1 per pixel pair; width must be even */
+
+/* Border modes of a local operator's input (applied per node). */
+#define HVX_BORDER_UNDEFINED 0 /* output pixels whose window leaves the image are unspecified */
+#define HVX_BORDER_CONSTANT 1  /* pixels outside the image read as the constant */
+#define HVX_BORDER_REPLICATE 2 /* pixels outside the image read as the nearest edge pixel */
+
+#define HVX_POLICY_SATURATE 0
+#define HVX_POLICY_WRAP 1
+
+#define HVX_CHANNEL_Y 0
+
+/* Graph options (hvx_graph_set_option).  Changing one un-verifies the graph. */
+#define HVX_OPT_FUSION 1     /* 1 (default): fuse producer/consumer operators; 0: one kernel per operator */
+#define HVX_OPT_DCE 2        /* 1 (default): remove operators whose results reach no non-virtual image */
+#define HVX_OPT_TILE 3       /* 0 (default): tuned/default tiles; else rows per work item (fast kernels) */
+#define HVX_OPT_SPECIALIZE 4 /* 1 (default): use hand-fused kernels for recognised subgraphs; 0: generic */
+#define HVX_OPT_XCD_REMAP 5  /* 1 (default): map work items to XCDs in contiguous chunks */
+
+/* Graph queries (hvx_graph_query); valid after verification. */
+#define HVX_QUERY_NUM_NODES 1      /* function nodes added */
+#define HVX_QUERY_NUM_OPS 2        /* point/local operators after lowering */
+#define HVX_QUERY_NUM_LIVE_OPS 3   /* operators left after dead-computation elimination */
+#define HVX_QUERY_NUM_KERNELS 4    /* kernel launches per process call */
+#define HVX_QUERY_ALG_BYTES 5      /* bytes a process call must move: inputs read once, outputs written once */
+#define HVX_QUERY_HBM_BYTES 6      /* bytes the plan moves, materialised intermediates included (no halos) */
+#define HVX_QUERY_KERNEL_KIND 7    /* kind of the first kernel: 0 generic, 1 edge, 2 corner, 3 gauss5 */
+#define HVX_QUERY_SCRATCH_BYTES 8  /* device bytes of materialised intermediates */
+#define HVX_QUERY_OP_LIVE_MASK 9   /* bit i set: lowered operator i is live (first 63 operators) */
+#define HVX_QUERY_ROWS_PER_ITEM 10 /* rows per work item of the first kernel */
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context bound to HIP device `hip_device`.  No device work happens
+ * until something needs the device, so graphs can be built and verified on a
+ * machine without a GPU.  Context (Section 3.1). */
+hvx_status hvx_context_create(int hip_device, hvx_context* out);
+/* Release a context and every object created in it (images, graphs, nodes,
+ * convolutions, batches, servers); waits for their device work first.
+ * *ctx is set to NULL.  Implicit freeing at context release (Section 3.1). */
+hvx_status hvx_context_release(hvx_context* ctx);
+/* Message for the last failed call made with this context (never NULL). */
+const char* hvx_last_error(hvx_context ctx);
+/* Name of a status code (never NULL). */
+const char* hvx_status_name(hvx_status s);
+
+/* ---- images ------------------------------------------------------------- */
+
+/* Wrap caller-owned device memory (w x h pixels of format df, row pitch in
+ * bytes).  Non-virtual images are the data a program can read and write
+ * (Section 5.2.1). */
+hvx_status hvx_image_from_ptr(hvx_context ctx, uint32_t w, uint32_t h, int df, void* dev_ptr, size_t pitch_bytes,
+                              hvx_image* out);
+/* Allocate a device image owned by the library (pitch rounded up to 64). */
+hvx_status hvx_image_create(hvx_context ctx, uint32_t w, uint32_t h, int df, hvx_image* out);
+/* Point a non-virtual image at a new frame of the same size and format; a
+ * verified graph stays verified (a verified graph runs repeatedly on new
+ * frames, Section 3.1). */
+hvx_status hvx_image_swap_ptr(hvx_image img, void* dev_ptr, size_t pitch_bytes);
+/* Describe an image: any output pointer may be NULL. */
+hvx_status hvx_image_query(hvx_image img, uint32_t* w, uint32_t* h, int* df, void** dev_ptr, size_t* pitch_bytes);
+/* Copy between host memory (row pitch host_pitch bytes) and a non-virtual
+ * image; synchronous.  to_device = 1 writes the image, 0 reads it. */
+hvx_status hvx_image_copy(hvx_image img, void* host, size_t host_pitch, int to_device);
+/* An intermediate image of one graph: not host-accessible; w, h = 0 and
+ * df = HVX_DF_VIRT mean "inferred at verification" (Section 3.1). */
+hvx_status hvx_image_create_virtual(hvx_graph graph, uint32_t w, uint32_t h, int df, hvx_image* out);
+
+/* Integer convolution mask: cols x rows coefficients (odd sizes 1..5),
+ * row-major, centre at (cols/2, rows/2); scale must be a power of two
+ * (1..2^15).  Copied. */
+hvx_status hvx_convolution_create(hvx_context ctx, uint32_t cols, uint32_t rows, const int16_t* coeffs,
+                                  uint32_t scale, hvx_convolution* out);
+
+/* ---- graph and nodes ---------------------------------------------------- */
+
+hvx_status hvx_graph_create(hvx_context ctx, hvx_graph* out);
+
+/* Node constructors.  Each adds one OpenVX function node to the graph and
+ * un-verifies it; `node_out` may be NULL.  Inputs precede outputs.  Formats
+ * are checked at verification.  The arithmetic of each node:
+ *  channel_extract  UYVY -> U8: the luma byte of each pixel.
+ *  gaussian3x3      U8 -> U8: sum of (1 2 1)x(1 2 1)-weighted window, >> 4.
+ *  gaussian5x5      U8 -> U8: sum of (1 4 6 4 1)^2-weighted window, >> 8.
+ *  box3x3           U8 -> U8: window sum / 9, floor.
+ *  box5x5_f32       F32 -> F32: unnormalised 5x5 window sum.
+ *  sobel3x3         U8 -> S16 gx (right minus left), S16 gy (bottom minus top),
+ *                   (1 2 1) smoothing across; either output may be NULL.
+ *  magnitude        S16,S16 -> S16: sqrt(gx^2+gy^2) rounded to nearest, saturated.
+ *  phase            S16,S16 -> U8: atan2(gy,gx) in [0,2pi) scaled to 256 levels,
+ *                   rounded, modulo 256 (within 1 level of the exact value).
+ *  add              U8/S16 -> U8/S16 with HVX_POLICY_SATURATE or _WRAP.
+ *  multiply_f32     S16,S16 -> F32: exact product (custom point node).
+ *  harris_response  F32 x3 (Sxx, Syy, Sxy) -> F32: Sxx*Syy - Sxy^2 - k (Sxx+Syy)^2
+ *                   (custom point node).
+ *  threshold        U8/S16/F32 -> U8: true_v where in > value, else false_v.
+ *  convolve         U8 -> U8/S16: true convolution with the mask, / scale
+ *                   truncated toward zero, saturated.
+ * Point and local operators as in Section 4 and Table 2; Sobel is lowered to
+ * two local operators (Section 5.2.2). */
+hvx_status hvx_channel_extract_node(hvx_graph g, hvx_image uyvy, int channel, hvx_image out, hvx_node* node_out);
+hvx_status hvx_gaussian3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
+hvx_status hvx_gaussian5x5_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
+hvx_status hvx_box3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
+hvx_status hvx_box5x5_f32_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
+hvx_status hvx_sobel3x3_node(hvx_graph g, hvx_image in, hvx_image gx, hvx_image gy, hvx_node* node_out);
+hvx_status hvx_magnitude_node(hvx_graph g, hvx_image gx, hvx_image gy, hvx_image out, hvx_node* node_out);
+hvx_status hvx_phase_node(hvx_graph g, hvx_image gx, hvx_image gy, hvx_image out, hvx_node* node_out);
+hvx_status hvx_add_node(hvx_graph g, hvx_image a, hvx_image b, int policy, hvx_image out, hvx_node* node_out);
+hvx_status hvx_multiply_f32_node(hvx_graph g, hvx_image a, hvx_image b, hvx_image out, hvx_node* node_out);
+hvx_status hvx_harris_response_node(hvx_graph g, hvx_image sxx, hvx_image syy, hvx_image sxy, float k,
+                                    hvx_image out, hvx_node* node_out);
+hvx_status hvx_threshold_node(hvx_graph g, hvx_image in, double value, uint8_t true_v, uint8_t false_v,
+                              hvx_image out, hvx_node* node_out);
+hvx_status hvx_convolve_node(hvx_graph g, hvx_image in, hvx_convolution conv, hvx_image out, hvx_node* node_out);
+
+/* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the
+ * value is read as the input's element type (0..255 for U8). */
+hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value);
+
+hvx_status hvx_graph_set_option(hvx_graph g, int option, int64_t value);
+
+/* Verify and plan: checks (parameters, formats, sizes, single writer per
+ * image, no cycles, bipartite node/data structure; Sections 3.1 and 5.2),
+ * virtual image inference, lowering, dead-computation elimination, fusion
+ * grouping and the launch plan.  No device work. */
+hvx_status hvx_graph_verify(hvx_graph g);
+/* Verify if needed, run on the device, and wait for completion. */
+hvx_status hvx_graph_process(hvx_graph g);
+/* Verify if needed and enqueue on `hip_stream` (a hipStream_t; NULL = the
+ * null stream) without waiting. */
+hvx_status hvx_graph_schedule(hvx_graph g, void* hip_stream);
+/* Wait for the work last scheduled for this graph. */
+hvx_status hvx_graph_wait(hvx_graph g);
+hvx_status hvx_graph_query(hvx_graph g, int attr, int64_t* out);
+
+/* Time candidate launch configurations of the verified graph on the device
+ * (`iters` timed runs each, outputs checked equal across candidates), keep the
+ * fastest in the context's tune cache and re-plan with it. */
+hvx_status hvx_graph_autotune(hvx_graph g, void* hip_stream, int iters);
+/* Tune cache as JSON text keyed by device, graph signature and size. */
+hvx_status hvx_context_save_tune_cache(hvx_context ctx, const char* path);
+hvx_status hvx_context_load_tune_cache(hvx_context ctx, const char* path);
+
+/* ---- batches: many verified graphs in one persistent launch ------------- */
+
+/* Build a batch over n verified graphs (any mix of kinds and sizes).  Work
+ * items of all graphs go into one work list consumed by one persistent
+ * kernel through an atomic counter; the launch is captured once into a HIP
+ * graph and replayed.  Graphs keep their image pointers as of this call or
+ * of the last hvx_batch_refresh. */
+hvx_status hvx_batch_create(hvx_context ctx, const hvx_graph* graphs, uint32_t n, hvx_batch* out);
+/* Re-read the graphs' image pointers (after hvx_image_swap_ptr). */
+hvx_status hvx_batch_refresh(hvx_batch b);
+/* Enqueue one execution of every graph in the batch on `hip_stream`. */
+hvx_status hvx_batch_schedule(hvx_batch b, void* hip_stream);
+/* One-shot form: create, schedule, and release once the stream is done. */
+hvx_status hvx_process_batch(hvx_context ctx, const hvx_graph* graphs, uint32_t n, void* hip_stream);
+hvx_status hvx_batch_query(hvx_batch b, int attr, int64_t* out); /* HVX_QUERY_ALG_BYTES, _NUM_KERNELS */
+
+/* ---- serving ------------------------------------------------------------ */
+
+#define HVX_SERVER_CONTINUOUS 0 /* admit by budget, batch admitted requests into overlapping steps */
+#define HVX_SERVER_PLAIN 1      /* one request at a time: copy in, process, copy out, wait */
+
+/* A request loop over device memory of at most hbm_budget_bytes, holding at
+ * most max_slots requests on the device, using n_streams streams (>= 1). */
+hvx_status hvx_server_create(hvx_context ctx, int mode, size_t hbm_budget_bytes, uint32_t max_slots,
+                             uint32_t n_streams, hvx_server* out);
+/* Queue a request: run verified `templ` (one non-virtual input, one
+ * non-virtual output, both U8 or UYVY) on host frame `in` (row pitch
+ * in_pitch) and write its output to host memory `out` (row pitch
+ * out_pitch).  Host buffers must stay valid until the request is reported
+ * done.  `tag` is returned by hvx_server_poll. */
+hvx_status hvx_server_submit(hvx_server s, hvx_graph templ, const void* in, size_t in_pitch, void* out,
+                             size_t out_pitch, uint64_t tag);
+/* Collect up to `max` finished requests: tags, statuses, latencies (s, from
+ * submit to completion).  Non-blocking; *n = number returned. */
+hvx_status hvx_server_poll(hvx_server s, uint64_t* tags, int32_t* statuses, double* latency_s, uint32_t max,
+                           uint32_t* n);
+/* Block until every submitted request has finished. */
+hvx_status hvx_server_drain(hvx_server s);
+/* Counters: 0 submitted, 1 completed, 2 peak device bytes, 3 peak requests
+ * in flight, 4 device steps launched, 5 current device bytes in use. */
+hvx_status hvx_server_stats(hvx_server s, int what, int64_t* out);
+/* Test hook: make the request with this tag fail (HVX_ERROR_DEVICE) without
+ * running it; other requests are unaffected. */
+hvx_status hvx_server_inject_failure(hvx_server s, uint64_t tag);
+
+/* ---- release ------------------------------------------------------------ */
+
+hvx_status hvx_release_graph(hvx_graph* g);
+hvx_status hvx_release_image(hvx_image* img);
+hvx_status hvx_release_node(hvx_node* node);
+hvx_status hvx_release_convolution(hvx_convolution* conv);
+hvx_status hvx_release_batch(hvx_batch* b);
+hvx_status hvx_release_server(hvx_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HVX_H */

@@ -1,0 +1,155 @@
+// Plain descriptors passed from the host runtime to the kernels by value.
+// Shared by host C++ and device code; no HIP types, no pointers to host data.
+#pragma once
+#include <stdint.h>
+
+namespace hvx {
+
+// Point and local operators after lowering (Section 4, Table 2).  Sobel3x3
+// lowers to the two local operators SOBEL_X and SOBEL_Y (Section 5.2.2).
+enum OpKind : int32_t {
+  OP_CHANNEL_Y = 1,
+  OP_GAUSS3,
+  OP_GAUSS5,
+  OP_BOX3,
+  OP_BOX5F,
+  OP_SOBEL_X,
+  OP_SOBEL_Y,
+  OP_MAGNITUDE,
+  OP_PHASE,
+  OP_ADD,
+  OP_MULF,
+  OP_HARRIS,
+  OP_THRESHOLD,
+  OP_CONVOLVE,
+};
+
+// Element formats (same numbering as the public HVX_DF_* constants).
+enum Df : int32_t { DF_VIRT = 0, DF_U8 = 1, DF_S16 = 2, DF_S32 = 3, DF_F32 = 4, DF_UYVY = 5 };
+enum Border : int32_t { B_UNDEFINED = 0, B_CONSTANT = 1, B_REPLICATE = 2 };
+
+inline int df_bytes(int df) {
+  switch (df) {
+    case DF_U8: return 1;
+    case DF_S16: return 2;
+    case DF_UYVY: return 2;
+    case DF_S32: return 4;
+    case DF_F32: return 4;
+    default: return 0;
+  }
+}
+
+// ---- generic fused-group program (LDS tile interpreter) -------------------
+constexpr int kMaxGVals = 16;
+constexpr int kMaxGOps = 12;
+constexpr int kMaxIO = 8;
+constexpr int kMaxMask = 25;
+
+struct GVal {
+  int32_t df;     // element format
+  int32_t ext;    // halo (pixels) around the tile over which the value is needed
+  int32_t lds;    // offset in 32-bit LDS words of the value's tile, -1 if not kept on chip
+  int32_t io;     // index into the I/O table, -1 if the value never touches global memory
+  int32_t input;  // 1: read from global memory (a group input)
+  int32_t store;  // 1: written to global memory (a group output)
+};
+
+struct GOp {
+  int32_t kind;
+  int32_t out;
+  int32_t in[3];
+  int32_t border;
+  int32_t cint;  // border constant for integer inputs
+  float cf;      // border constant for F32 inputs
+  int32_t rx, ry;
+  int32_t p0, p1, p2, p3;  // threshold: true, false, integer bound; add: policy; convolve: cols, rows, shift
+  float pf;                // corner response k; threshold bound for F32 input
+  int16_t mask[kMaxMask];
+};
+
+struct GProg {
+  int32_t nvals, nops;
+  int32_t tw, th;     // output tile of one work-group
+  int32_t lds_words;  // LDS words used by one tile
+  int32_t w, h;
+  int32_t tiles_x, tiles_y;
+  GVal vals[kMaxGVals];
+  GOp ops[kMaxGOps];
+};
+
+struct IOTable {
+  void* ptr[kMaxIO];
+  int64_t pitch[kMaxIO];
+};
+
+// ---- fast fused kernels -------------------------------------------------------
+// Work decomposition shared by the register-streaming kernels: a wave owns a
+// vertical strip of 62 * 16 output columns (plus one halo lane on each side)
+// and a band of `rows` output rows, streamed top to bottom.
+constexpr int kLanePx = 16;
+constexpr int kStripPx = 62 * kLanePx;
+
+struct StripGrid {
+  int32_t w, h;
+  int32_t rows;     // output rows per work item
+  int32_t nstrips;  // ceil(w / kStripPx)
+  int32_t nbands;   // ceil(h / rows)
+};
+
+// Gaussian3x3 -> Sobel3x3 -> Magnitude -> Threshold (and optionally Phase).
+struct EdgeDesc {
+  StripGrid g;
+  const uint8_t* in;
+  int64_t in_pitch;
+  uint8_t* out;  // threshold output
+  int64_t out_pitch;
+  uint8_t* phase;  // phase output or null
+  int64_t phase_pitch;
+  int32_t b0, c0;   // border of the Gaussian's input
+  int32_t b1, c1;   // border of the Sobel's input
+  int32_t thr_not;  // edge iff gx^2 + gy^2 + thr_not >= 0 (thr_not = ~T, T = u(u-1))
+  uint32_t tv4, fv4;
+};
+
+// Sobel3x3 -> products -> Box5x5 (x3) -> corner response -> Threshold.
+struct CornerDesc {
+  StripGrid g;
+  const uint8_t* in;
+  int64_t in_pitch;
+  uint8_t* out;
+  int64_t out_pitch;
+  int32_t b0, c0;  // border of the Sobel's input
+  int32_t b1;      // border of the box filters' inputs
+  float c1;        // their constant
+  float k;
+  float thr;  // response threshold (strict >), as the largest float not above the value
+  uint32_t tv4, fv4;
+};
+
+// Gaussian5x5, optionally fed by the luma of a UYVY frame.
+struct Gauss5Desc {
+  StripGrid g;
+  const uint8_t* in;
+  int64_t in_pitch;
+  int32_t uyvy;  // 1: input is UYVY, take its luma
+  uint8_t* out;
+  int64_t out_pitch;
+  int32_t b0, c0;
+};
+
+enum FastKind : int32_t { FK_GENERIC = 0, FK_EDGE = 1, FK_CORNER = 2, FK_GAUSS5 = 3 };
+
+// One image of a batch: the kind selects which fused body processes its items.
+struct BatchImage {
+  int32_t kind;
+  int32_t first_item;  // index of its first work item in the flat work list
+  int32_t nitems;
+  int32_t pad;
+  union {
+    EdgeDesc e;
+    CornerDesc c;
+    Gauss5Desc g5;
+  } d;
+};
+
+}  // namespace hvx

@@ -1,0 +1,176 @@
+// Host-side objects, graph IR and launch plan of the hvx library.
+#pragma once
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hvx.h"
+#include "hvx_desc.h"
+
+namespace hvx {
+
+enum ObjType : uint32_t { T_CONTEXT = 0x5a01, T_GRAPH, T_IMAGE, T_NODE, T_CONV, T_BATCH, T_SERVER };
+
+struct Context;
+struct Graph;
+
+struct Object {
+  uint32_t type;
+  Context* ctx;
+  virtual ~Object() {}
+};
+
+struct Image : Object {
+  uint32_t w = 0, h = 0;
+  int df = DF_VIRT;
+  bool is_virtual = false;
+  Graph* vgraph = nullptr;  // owning graph of a virtual image
+  void* ptr = nullptr;
+  size_t pitch = 0;
+  bool owned = false;  // device memory allocated by the library
+};
+
+struct Conv : Object {
+  uint32_t cols = 0, rows = 0, scale = 1;
+  std::vector<int16_t> coeffs;
+};
+
+// OpenVX function nodes as the user adds them.
+enum NodeKind : int32_t {
+  NK_CHANNEL_EXTRACT = 1,
+  NK_GAUSS3,
+  NK_GAUSS5,
+  NK_BOX3,
+  NK_BOX5F,
+  NK_SOBEL3,
+  NK_MAGNITUDE,
+  NK_PHASE,
+  NK_ADD,
+  NK_MULF,
+  NK_HARRIS,
+  NK_THRESHOLD,
+  NK_CONVOLVE,
+};
+
+struct Node : Object {
+  Graph* g = nullptr;
+  int kind = 0;
+  std::vector<Image*> in;   // inputs in API order
+  std::vector<Image*> out;  // outputs in API order (may hold nulls: Sobel)
+  int border = B_REPLICATE;
+  uint32_t bconst = 0;
+  double dval = 0;  // threshold value
+  int tv = 255, fv = 0;
+  int policy = 0;
+  float k = 0.04f;
+  Conv* conv = nullptr;
+  int channel = 0;
+};
+
+// ---- lowered graph and plan -------------------------------------------------
+
+struct Value {
+  Image* img = nullptr;
+  int df = DF_VIRT;
+  uint32_t w = 0, h = 0;
+  bool is_virtual = false;
+  int producer = -1;           // lowered op writing it, -1 for graph inputs
+  std::vector<int> consumers;  // lowered ops reading it (live ones after DCE)
+  bool live = false;
+  // materialised device copy (virtual values crossing kernel boundaries)
+  bool materialize = false;
+};
+
+struct LOp {
+  int kind = 0;
+  int node = -1;  // index of the function node it came from
+  int in[3] = {-1, -1, -1};
+  int nin = 0;
+  int out = -1;
+  int border = B_REPLICATE;
+  uint32_t bconst = 0;
+  double dval = 0;
+  int tv = 255, fv = 0, policy = 0;
+  float k = 0.04f;
+  const Conv* conv = nullptr;
+  int rx = 0, ry = 0;
+  bool live = true;
+};
+
+struct Group {
+  std::vector<int> ops;      // lowered ops, topological order
+  std::vector<int> inputs;   // values read from global memory
+  std::vector<int> outputs;  // values written to global memory
+  std::vector<int> gvals;    // generic program value index -> plan value id
+  int kind = FK_GENERIC;
+  int footprint = 0;  // max total stencil radius along any path
+  GProg prog{};       // generic program (kind == FK_GENERIC)
+  int rows = 0;       // rows per work item (fast kinds); 0 = tuned or default
+  int xcd = 1;        // XCD-contiguous work mapping
+  uint32_t w = 0, h = 0;
+  // indices (into Plan::vals) bound to the fast descriptors' pointers
+  int v_in = -1, v_out = -1, v_aux = -1;
+};
+
+struct Plan {
+  std::vector<Value> vals;
+  std::vector<LOp> ops;
+  std::vector<Group> groups;
+  int num_nodes = 0, num_ops = 0, num_live = 0;
+  int64_t alg_bytes = 0, hbm_bytes = 0, scratch_bytes = 0;
+  std::vector<int> topo;  // live op order
+};
+
+struct Graph : Object {
+  std::vector<Node*> nodes;
+  std::vector<Image*> virt;
+  bool verified = false;
+  int opt_fusion = 1, opt_dce = 1, opt_tile = 0, opt_specialize = 1, opt_xcd = 1;
+  std::unique_ptr<Plan> plan;
+  // device state
+  std::vector<void*> scratch;  // one buffer per materialised value (index = value id), or null
+  std::vector<size_t> scratch_pitch;
+  void* last_stream = nullptr;
+  bool scheduled = false;
+};
+
+struct TuneEntry {
+  int rows = 0;
+  int xcd = 1;
+  double us = 0;
+};
+
+struct Context : Object {
+  int device = 0;
+  std::recursive_mutex mu;
+  std::string last_error;
+  std::vector<Object*> children;  // every object created in this context
+  bool dev_ready = false;
+  int num_cus = 256;
+  std::string dev_name;
+  std::map<std::string, TuneEntry> tune;  // key: device|signature|size
+};
+
+// ---- registry and errors ----------------------------------------------------
+bool registry_check(const void* h, uint32_t type);
+void registry_add(Object* o);
+void registry_remove(Object* o);
+hvx_status set_error(Context* ctx, hvx_status s, const char* fmt, ...);
+
+// ---- planner (verify.cpp) ---------------------------------------------------
+hvx_status verify_graph(Graph* g);
+std::string graph_signature(const Graph* g);
+
+// ---- runtime (runtime.cpp) --------------------------------------------------
+hvx_status ensure_device(Context* ctx);
+hvx_status schedule_graph(Graph* g, void* stream);
+void free_graph_device(Graph* g);
+int default_rows(const Group& gr, int num_cus);
+void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi);
+int64_t fast_items(const Group& gr);
+
+}  // namespace hvx

@@ -1,0 +1,596 @@
+// Device runtime: launching verified graphs, batches, autotuning, tune cache.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <fstream>
+#include <sstream>
+
+#include "hvx_internal.h"
+#include "kernels.h"
+
+namespace hvx {
+
+int32_t edge_threshold_not(double t);  // verify.cpp
+
+hvx_status ensure_device(Context* ctx) {
+  std::lock_guard<std::recursive_mutex> l(ctx->mu);
+  if (ctx->dev_ready) {
+    (void)hipSetDevice(ctx->device);
+    return HVX_SUCCESS;
+  }
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) return set_error(ctx, HVX_ERROR_DEVICE, "no HIP device available");
+  if (ctx->device >= n) return set_error(ctx, HVX_ERROR_DEVICE, "device %d out of range (%d devices)", ctx->device, n);
+  e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return set_error(ctx, HVX_ERROR_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+    ctx->num_cus = prop.multiProcessorCount;
+    ctx->dev_name = prop.gcnArchName;
+  }
+  ctx->dev_ready = true;
+  return HVX_SUCCESS;
+}
+
+void free_graph_device(Graph* g) {
+  if (g->scheduled && g->last_stream != (void*)-1) (void)hipStreamSynchronize((hipStream_t)g->last_stream);
+  for (void* p : g->scratch)
+    if (p) (void)hipFree(p);
+  g->scratch.clear();
+  g->scratch_pitch.clear();
+  g->scheduled = false;
+}
+
+static hvx_status ensure_scratch(Graph* g) {
+  Plan& p = *g->plan;
+  if (g->scratch.size() == p.vals.size()) return HVX_SUCCESS;
+  g->scratch.assign(p.vals.size(), nullptr);
+  g->scratch_pitch.assign(p.vals.size(), 0);
+  for (size_t v = 0; v < p.vals.size(); ++v) {
+    if (!p.vals[v].materialize) continue;
+    size_t pitch = ((size_t)p.vals[v].w * df_bytes(p.vals[v].df) + 63) / 64 * 64;
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, pitch * p.vals[v].h) != hipSuccess) {
+      free_graph_device(g);
+      return set_error(g->ctx, HVX_ERROR_NO_MEMORY, "cannot allocate %zu bytes for an intermediate image",
+                       pitch * p.vals[v].h);
+    }
+    g->scratch[v] = ptr;
+    g->scratch_pitch[v] = pitch;
+  }
+  return HVX_SUCCESS;
+}
+
+static void value_ptr(const Graph* g, int v, void** ptr, int64_t* pitch) {
+  const Value& val = g->plan->vals[v];
+  if (!val.is_virtual) {
+    *ptr = val.img->ptr;
+    *pitch = (int64_t)val.img->pitch;
+  } else {
+    *ptr = v < (int)g->scratch.size() ? g->scratch[v] : nullptr;
+    *pitch = v < (int)g->scratch_pitch.size() ? (int64_t)g->scratch_pitch[v] : 0;
+  }
+}
+
+static const LOp* find_op(const Plan& p, const Group& gr, int kind) {
+  for (int o : gr.ops)
+    if (p.ops[o].kind == kind) return &p.ops[o];
+  return nullptr;
+}
+
+static std::string tune_key(const Graph* g) { return g->ctx->dev_name + "|" + graph_signature(g); }
+
+int default_rows(const Group& gr, int num_cus) {
+  // enough work items to give every CU several waves, without letting the
+  // halo rows (footprint on each side) dominate a work item
+  const int nstrips = ((int)gr.w + kStripPx - 1) / kStripPx;
+  int64_t target = 4LL * num_cus;
+  int64_t rows = ((int64_t)gr.h * nstrips) / std::max<int64_t>(1, target);
+  int r = 4;
+  while (r * 2 <= rows && r < 64) r *= 2;
+  return r;
+}
+
+static int rows_for(const Graph* g, const Group& gr) {
+  if (gr.rows > 0) return gr.rows;
+  auto it = g->ctx->tune.find(tune_key(g));
+  if (it != g->ctx->tune.end() && it->second.rows > 0) return it->second.rows;
+  return default_rows(gr, g->ctx->num_cus);
+}
+
+static int xcd_for(const Graph* g, const Group& gr) {
+  if (gr.rows > 0) return gr.xcd;
+  auto it = g->ctx->tune.find(tune_key(g));
+  if (it != g->ctx->tune.end() && it->second.rows > 0) return it->second.xcd;
+  return gr.xcd;
+}
+
+static StripGrid strip_grid(const Group& gr, int rows) {
+  StripGrid s;
+  s.w = (int)gr.w;
+  s.h = (int)gr.h;
+  s.rows = std::max(1, rows);
+  s.nstrips = (s.w + kStripPx - 1) / kStripPx;
+  s.nbands = (s.h + s.rows - 1) / s.rows;
+  return s;
+}
+
+int64_t fast_items(const Group& gr) { return (int64_t)gr.prog.tiles_x; }
+
+void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi) {
+  const Plan& p = *g->plan;
+  memset(bi, 0, sizeof *bi);
+  bi->kind = gr.kind;
+  const int rows = rows_for(g, gr);
+  void* ptr;
+  int64_t pitch;
+  if (gr.kind == FK_EDGE) {
+    EdgeDesc& d = bi->d.e;
+    d.g = strip_grid(gr, rows);
+    value_ptr(g, gr.v_in, &ptr, &pitch);
+    d.in = (const uint8_t*)ptr;
+    d.in_pitch = pitch;
+    value_ptr(g, gr.v_out, &ptr, &pitch);
+    d.out = (uint8_t*)ptr;
+    d.out_pitch = pitch;
+    if (gr.v_aux >= 0) {
+      value_ptr(g, gr.v_aux, &ptr, &pitch);
+      d.phase = (uint8_t*)ptr;
+      d.phase_pitch = pitch;
+    }
+    const LOp* ga = find_op(p, gr, OP_GAUSS3);
+    const LOp* sx = find_op(p, gr, OP_SOBEL_X);
+    const LOp* th = find_op(p, gr, OP_THRESHOLD);
+    d.b0 = ga->border;
+    d.c0 = (int)std::min<uint32_t>(ga->bconst, 255);
+    d.b1 = sx->border;
+    d.c1 = (int)std::min<uint32_t>(sx->bconst, 255);
+    d.thr_not = edge_threshold_not(th->dval);
+    d.tv4 = 0x01010101u * (uint32_t)(th->tv & 0xFF);
+    d.fv4 = 0x01010101u * (uint32_t)(th->fv & 0xFF);
+    bi->nitems = d.g.nstrips * d.g.nbands;
+  } else if (gr.kind == FK_GAUSS5) {
+    Gauss5Desc& d = bi->d.g5;
+    d.g = strip_grid(gr, rows);
+    value_ptr(g, gr.v_in, &ptr, &pitch);
+    d.in = (const uint8_t*)ptr;
+    d.in_pitch = pitch;
+    d.uyvy = p.vals[gr.v_in].df == DF_UYVY;
+    value_ptr(g, gr.v_out, &ptr, &pitch);
+    d.out = (uint8_t*)ptr;
+    d.out_pitch = pitch;
+    const LOp* g5 = find_op(p, gr, OP_GAUSS5);
+    d.b0 = g5->border;
+    d.c0 = (int)std::min<uint32_t>(g5->bconst, 255);
+    bi->nitems = d.g.nstrips * d.g.nbands;
+  }
+}
+
+static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (gr.kind == FK_GENERIC) {
+    IOTable io;
+    memset(&io, 0, sizeof io);
+    for (int i = 0; i < gr.prog.nvals; ++i) {
+      const GVal& v = gr.prog.vals[i];
+      if (v.io < 0) continue;
+      value_ptr(g, gr.gvals[i], &io.ptr[v.io], &io.pitch[v.io]);
+      if (!io.ptr[v.io]) return set_error(g->ctx, HVX_ERROR_DEVICE, "unbound image in plan");
+    }
+    e = launch_generic(gr.prog, io, s);
+  } else {
+    BatchImage bi;
+    fill_fast_desc(g, gr, &bi);
+    const bool xcd = xcd_for(g, gr) != 0;
+    if (gr.kind == FK_EDGE) e = launch_edge(bi.d.e, xcd, s);
+    else if (gr.kind == FK_GAUSS5) e = launch_gauss5(bi.d.g5, xcd, s);
+    else return set_error(g->ctx, HVX_ERROR_NOT_SUPPORTED, "no kernel for group kind %d", gr.kind);
+  }
+  if (e != hipSuccess) return set_error(g->ctx, HVX_ERROR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+  return HVX_SUCCESS;
+}
+
+hvx_status prepare_graph(Graph* g) {
+  hvx_status s = ensure_device(g->ctx);
+  if (s) return s;
+  return ensure_scratch(g);
+}
+
+hvx_status schedule_graph(Graph* g, void* stream) {
+  hvx_status s = prepare_graph(g);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  for (const Group& gr : g->plan->groups) {
+    s = launch_group(g, gr, st);
+    if (s) return s;
+  }
+  g->last_stream = stream;
+  g->scheduled = true;
+  return HVX_SUCCESS;
+}
+
+// ---- batches --------------------------------------------------------------------
+
+struct Batch : Object {
+  std::vector<Graph*> graphs;
+  std::vector<Graph*> separate;  // graphs not expressible as batch work items
+  std::vector<BatchImage> imgs;
+  std::vector<uint16_t> item_img;
+  BatchImage* d_imgs = nullptr;
+  uint16_t* d_item_img = nullptr;
+  unsigned* d_counter = nullptr;
+  int total = 0, grid = 0;
+  bool persistent = true, use_graph = true;
+  hipGraph_t hg = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t alg_bytes = 0;
+  void* last_stream = nullptr;
+  bool scheduled = false;
+};
+
+static void batch_free_device(Batch* b) {
+  if (b->scheduled) (void)hipStreamSynchronize((hipStream_t)b->last_stream);
+  b->scheduled = false;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->hg) (void)hipGraphDestroy(b->hg);
+  b->exec = nullptr;
+  b->hg = nullptr;
+  if (b->d_imgs) (void)hipFree(b->d_imgs);
+  if (b->d_item_img) (void)hipFree(b->d_item_img);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  b->d_imgs = nullptr;
+  b->d_item_img = nullptr;
+  b->d_counter = nullptr;
+}
+
+void destroy_batch_object(Object* o) {
+  Batch* b = (Batch*)o;
+  batch_free_device(b);
+  registry_remove(b);
+  delete b;
+}
+
+static double kind_cost(const BatchImage& bi) {
+  switch (bi.kind) {
+    case FK_EDGE: return bi.d.e.phase ? 3.0 * bi.d.e.g.rows : 2.0 * bi.d.e.g.rows;
+    case FK_CORNER: return 4.0 * bi.d.c.g.rows;
+    case FK_GAUSS5: return 1.0 * bi.d.g5.g.rows;
+  }
+  return 1.0;
+}
+
+static hvx_status batch_build(Batch* b) {
+  Context* c = b->ctx;
+  batch_free_device(b);
+  b->imgs.clear();
+  b->separate.clear();
+  b->alg_bytes = 0;
+  for (Graph* g : b->graphs) {
+    if (!g->verified) {
+      hvx_status s = verify_graph(g);
+      if (s) return s;
+    }
+    hvx_status s = prepare_graph(g);
+    if (s) return s;
+    b->alg_bytes += g->plan->alg_bytes;
+    const auto& gs = g->plan->groups;
+    if (gs.size() == 1 && (gs[0].kind == FK_EDGE || gs[0].kind == FK_GAUSS5)) {
+      BatchImage bi;
+      fill_fast_desc(g, gs[0], &bi);
+      b->imgs.push_back(bi);
+    } else {
+      b->separate.push_back(g);
+    }
+  }
+  // heaviest items first, so the last items handed out are the cheapest
+  std::stable_sort(b->imgs.begin(), b->imgs.end(),
+                   [](const BatchImage& x, const BatchImage& y) { return kind_cost(x) > kind_cost(y); });
+  if (b->imgs.size() > 65535) return set_error(c, HVX_ERROR_NOT_SUPPORTED, "at most 65535 images per batch");
+  b->item_img.clear();
+  int first = 0;
+  for (size_t i = 0; i < b->imgs.size(); ++i) {
+    b->imgs[i].first_item = first;
+    for (int k = 0; k < b->imgs[i].nitems; ++k) b->item_img.push_back((uint16_t)i);
+    first += b->imgs[i].nitems;
+  }
+  b->total = first;
+  b->grid = std::max(1, std::min(b->total, c->num_cus * batch_waves_per_cu()));
+  if (!b->imgs.empty()) {
+    if (hipMalloc((void**)&b->d_imgs, b->imgs.size() * sizeof(BatchImage)) != hipSuccess ||
+        hipMalloc((void**)&b->d_item_img, b->item_img.size() * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void**)&b->d_counter, 2 * sizeof(unsigned)) != hipSuccess) {
+      batch_free_device(b);
+      return set_error(c, HVX_ERROR_NO_MEMORY, "batch descriptors");
+    }
+    hipError_t e = hipMemcpy(b->d_imgs, b->imgs.data(), b->imgs.size() * sizeof(BatchImage), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_item_img, b->item_img.data(), b->item_img.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_counter, 0, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      batch_free_device(b);
+      return set_error(c, HVX_ERROR_DEVICE, "batch upload: %s", hipGetErrorString(e));
+    }
+  }
+  return HVX_SUCCESS;
+}
+
+static hvx_status batch_enqueue(Batch* b, hipStream_t s) {
+  if (b->total > 0) {
+    hipError_t e = launch_batch(b->d_imgs, b->d_item_img, b->total, b->d_counter, b->grid, b->persistent, s);
+    if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "batch launch: %s", hipGetErrorString(e));
+  }
+  for (Graph* g : b->separate) {
+    hvx_status st = HVX_SUCCESS;
+    for (const Group& gr : g->plan->groups) {
+      st = launch_group(g, gr, s);
+      if (st) return st;
+    }
+  }
+  return HVX_SUCCESS;
+}
+
+}  // namespace hvx
+
+using namespace hvx;
+
+extern "C" {
+
+hvx_status hvx_batch_create(hvx_context ctx, const hvx_graph* graphs, uint32_t n, hvx_batch* out) {
+  if (!registry_check(ctx, T_CONTEXT)) return HVX_ERROR_INVALID_REFERENCE;
+  Context* c = (Context*)ctx;
+  if (!out || (!graphs && n)) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "null argument");
+  *out = nullptr;
+  for (uint32_t i = 0; i < n; ++i)
+    if (!registry_check(graphs[i], T_GRAPH) || ((Graph*)graphs[i])->ctx != c)
+      return set_error(c, HVX_ERROR_INVALID_REFERENCE, "batch graph %u is invalid", i);
+  hvx_status s = ensure_device(c);
+  if (s) return s;
+  Batch* b = new Batch();
+  b->type = T_BATCH;
+  b->ctx = c;
+  for (uint32_t i = 0; i < n; ++i) b->graphs.push_back((Graph*)graphs[i]);
+  s = batch_build(b);
+  if (s) {
+    batch_free_device(b);
+    delete b;
+    return s;
+  }
+  registry_add(b);
+  {
+    std::lock_guard<std::recursive_mutex> l(c->mu);
+    c->children.push_back(b);
+  }
+  *out = (hvx_batch)b;
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_batch_refresh(hvx_batch hb) {
+  if (!registry_check(hb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
+  return batch_build((Batch*)hb);
+}
+
+hvx_status hvx_batch_schedule(hvx_batch hb, void* stream) {
+  if (!registry_check(hb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
+  Batch* b = (Batch*)hb;
+  hipStream_t s = (hipStream_t)stream;
+  hvx_status st = ensure_device(b->ctx);
+  if (st) return st;
+  if (b->use_graph && s != nullptr) {
+    if (!b->exec) {
+      // capture once: the persistent launch plus the launches of any graph
+      // that is not expressible as batch work items
+      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "begin capture: %s", hipGetErrorString(e));
+      st = batch_enqueue(b, s);
+      hipGraph_t hg = nullptr;
+      e = hipStreamEndCapture(s, &hg);
+      if (st) {
+        if (hg) (void)hipGraphDestroy(hg);
+        return st;
+      }
+      if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "end capture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&b->exec, hg, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(hg);
+        b->exec = nullptr;
+        return set_error(b->ctx, HVX_ERROR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+      }
+      b->hg = hg;
+    }
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "graph launch: %s", hipGetErrorString(e));
+  } else {
+    st = batch_enqueue(b, s);
+    if (st) return st;
+  }
+  b->last_stream = stream;
+  b->scheduled = true;
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_batch_query(hvx_batch hb, int attr, int64_t* out) {
+  if (!registry_check(hb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
+  Batch* b = (Batch*)hb;
+  if (!out) return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "null output");
+  switch (attr) {
+    case HVX_QUERY_ALG_BYTES: *out = b->alg_bytes; break;
+    case HVX_QUERY_NUM_KERNELS: {
+      int64_t k = b->total > 0 ? 1 : 0;
+      for (Graph* g : b->separate) k += (int64_t)g->plan->groups.size();
+      *out = k;
+      break;
+    }
+    case HVX_QUERY_NUM_OPS: *out = b->total; break;  // work items of the persistent launch
+    default: return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown batch query %d", attr);
+  }
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_release_batch(hvx_batch* pb) {
+  if (!pb || !registry_check(*pb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
+  Batch* b = (Batch*)*pb;
+  Context* c = b->ctx;
+  {
+    std::lock_guard<std::recursive_mutex> l(c->mu);
+    auto& v = c->children;
+    v.erase(std::remove(v.begin(), v.end(), (Object*)b), v.end());
+  }
+  destroy_batch_object(b);
+  *pb = nullptr;
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_process_batch(hvx_context ctx, const hvx_graph* graphs, uint32_t n, void* stream) {
+  hvx_batch b = nullptr;
+  hvx_status s = hvx_batch_create(ctx, graphs, n, &b);
+  if (s) return s;
+  ((Batch*)b)->use_graph = false;
+  s = hvx_batch_schedule(b, stream);
+  if (!s && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    s = set_error((Context*)ctx, HVX_ERROR_DEVICE, "stream synchronize failed");
+  hvx_release_batch(&b);
+  return s;
+}
+
+// ---- autotuning -----------------------------------------------------------------
+
+static hvx_status read_outputs(Graph* g, std::vector<std::vector<uint8_t>>* out) {
+  out->clear();
+  const Plan& p = *g->plan;
+  for (size_t v = 0; v < p.vals.size(); ++v) {
+    const Value& val = p.vals[v];
+    if (val.is_virtual || val.producer < 0 || !p.ops[val.producer].live) continue;
+    size_t row = (size_t)val.w * df_bytes(val.df);
+    std::vector<uint8_t> buf(row * val.h);
+    if (hipMemcpy2D(buf.data(), row, val.img->ptr, val.img->pitch, row, val.h, hipMemcpyDeviceToHost) != hipSuccess)
+      return set_error(g->ctx, HVX_ERROR_DEVICE, "autotune readback failed");
+    out->push_back(std::move(buf));
+  }
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_graph_autotune(hvx_graph hg, void* stream, int iters) {
+  if (!registry_check(hg, T_GRAPH)) return HVX_ERROR_INVALID_REFERENCE;
+  Graph* g = (Graph*)hg;
+  if (iters < 1) iters = 1;
+  if (!g->verified) {
+    hvx_status s = verify_graph(g);
+    if (s) return s;
+  }
+  hvx_status s = prepare_graph(g);
+  if (s) return s;
+  Plan& p = *g->plan;
+  if (p.groups.size() != 1 || p.groups[0].kind == FK_GENERIC) return HVX_SUCCESS;  // nothing to tune
+  Group& gr = p.groups[0];
+  const int saved_rows = gr.rows, saved_xcd = gr.xcd;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  std::vector<std::vector<uint8_t>> ref, cur;
+  double best_us = 1e30;
+  int best_rows = 0, best_xcd = 1;
+  static const int cand_rows[] = {4, 8, 16, 32, 64, 128};
+  for (int rows : cand_rows) {
+    if (rows > (int)gr.h * 2 && rows != 4) continue;
+    for (int xcd = 0; xcd <= 1; ++xcd) {
+      gr.rows = rows;
+      gr.xcd = xcd;
+      s = schedule_graph(g, st);  // warm-up, also the output check
+      if (!s && hipStreamSynchronize(st) != hipSuccess) s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune sync failed");
+      if (!s) s = read_outputs(g, ref.empty() ? &ref : &cur);
+      if (!s && !cur.empty() && cur != ref)
+        s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune candidate rows=%d xcd=%d changed the output", rows, xcd);
+      cur.clear();
+      if (s) break;
+      (void)hipEventRecord(e0, st);
+      for (int i = 0; i < iters && !s; ++i) s = schedule_graph(g, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      double us = 1000.0 * ms / iters;
+      if (us < best_us) {
+        best_us = us;
+        best_rows = rows;
+        best_xcd = xcd;
+      }
+    }
+    if (s) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  gr.rows = saved_rows;
+  gr.xcd = saved_xcd;
+  if (s) return s;
+  TuneEntry t;
+  t.rows = best_rows;
+  t.xcd = best_xcd;
+  t.us = best_us;
+  g->ctx->tune[tune_key(g)] = t;
+  return HVX_SUCCESS;
+}
+
+// Tune cache file: one JSON object, {"key": [rows, xcd, microseconds], ...}.
+hvx_status hvx_context_save_tune_cache(hvx_context ctx, const char* path) {
+  if (!registry_check(ctx, T_CONTEXT)) return HVX_ERROR_INVALID_REFERENCE;
+  Context* c = (Context*)ctx;
+  if (!path) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "null path");
+  std::ofstream f(path);
+  if (!f) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "cannot write %s", path);
+  f << "{";
+  bool first = true;
+  for (auto& kv : c->tune) {
+    std::string k;
+    for (char ch : kv.first) {
+      if (ch == '"' || ch == '\\') k += '\\';
+      k += ch;
+    }
+    f << (first ? "" : ",") << "\n  \"" << k << "\": [" << kv.second.rows << ", " << kv.second.xcd << ", "
+      << kv.second.us << "]";
+    first = false;
+  }
+  f << "\n}\n";
+  return f.good() ? HVX_SUCCESS : set_error(c, HVX_ERROR_INVALID_PARAMETERS, "write failed");
+}
+
+hvx_status hvx_context_load_tune_cache(hvx_context ctx, const char* path) {
+  if (!registry_check(ctx, T_CONTEXT)) return HVX_ERROR_INVALID_REFERENCE;
+  Context* c = (Context*)ctx;
+  if (!path) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "null path");
+  std::ifstream f(path);
+  if (!f) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "cannot read %s", path);
+  std::stringstream ss;
+  ss << f.rdbuf();
+  std::string t = ss.str();
+  size_t i = 0;
+  int n = 0;
+  while (true) {
+    size_t q = t.find('"', i);
+    if (q == std::string::npos) break;
+    std::string key;
+    size_t j = q + 1;
+    for (; j < t.size() && t[j] != '"'; ++j) {
+      if (t[j] == '\\' && j + 1 < t.size()) ++j;
+      key += t[j];
+    }
+    size_t lb = t.find('[', j), rb = t.find(']', j);
+    if (lb == std::string::npos || rb == std::string::npos || rb < lb)
+      return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "malformed tune cache %s", path);
+    TuneEntry e;
+    if (sscanf(t.c_str() + lb + 1, "%d , %d , %lf", &e.rows, &e.xcd, &e.us) != 3)
+      return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "malformed tune entry for %s", key.c_str());
+    c->tune[key] = e;
+    ++n;
+    i = rb + 1;
+  }
+  return HVX_SUCCESS;
+}
+
+}  // extern "C"
