@@ -226,6 +226,17 @@ hvx_status hvx_batch_schedule(hvx_batch b, void* hip_stream);
 /* One-shot form: create, schedule, and release once the stream is done. */
 hvx_status hvx_process_batch(hvx_context ctx, const hvx_graph* graphs, uint32_t n, void* hip_stream);
 hvx_status hvx_batch_query(hvx_batch b, int attr, int64_t* out); /* HVX_QUERY_ALG_BYTES, _NUM_KERNELS */
+/* Batch options.  HVX_BATCH_PERSISTENT (default 1): a grid sized to the
+ * machine pulls chunks of work items from per-XCD atomic counters; 0: one
+ * wave per work item.  HVX_BATCH_USE_GRAPH (default 1): capture the launches
+ * once into a HIP graph and replay it.  Changing an option drops the capture. */
+#define HVX_BATCH_PERSISTENT 1
+#define HVX_BATCH_USE_GRAPH 2
+hvx_status hvx_batch_set_option(hvx_batch b, int option, int64_t value);
+/* Time candidate rows-per-work-item settings (shared by all images) and both
+ * launch modes on the device (`iters` timed runs each; outputs of the first
+ * and last graph checked equal across candidates); keep the fastest. */
+hvx_status hvx_batch_autotune(hvx_batch b, void* hip_stream, int iters);
 
 /* ---- serving ------------------------------------------------------------ */
 

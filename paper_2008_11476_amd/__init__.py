@@ -36,6 +36,7 @@ HVX_OPT_FUSION, HVX_OPT_DCE, HVX_OPT_TILE, HVX_OPT_SPECIALIZE, HVX_OPT_XCD_REMAP
  HVX_QUERY_HBM_BYTES, HVX_QUERY_KERNEL_KIND, HVX_QUERY_SCRATCH_BYTES, HVX_QUERY_OP_LIVE_MASK,
  HVX_QUERY_ROWS_PER_ITEM) = range(1, 11)
 HVX_SERVER_CONTINUOUS, HVX_SERVER_PLAIN = 0, 1
+HVX_BATCH_PERSISTENT, HVX_BATCH_USE_GRAPH = 1, 2
 
 BYTES_PER_PIXEL = {HVX_DF_U8: 1, HVX_DF_S16: 2, HVX_DF_S32: 4, HVX_DF_F32: 4, HVX_DF_UYVY: 2}
 
@@ -99,6 +100,8 @@ def _load():
         "hvx_batch_schedule": [_vp, _vp],
         "hvx_process_batch": [_vp, _P(_vp), ctypes.c_uint32, _vp],
         "hvx_batch_query": [_vp, ctypes.c_int, _P(ctypes.c_int64)],
+        "hvx_batch_set_option": [_vp, ctypes.c_int, ctypes.c_int64],
+        "hvx_batch_autotune": [_vp, _vp, ctypes.c_int],
         "hvx_server_create": [_vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, _P(_vp)],
         "hvx_server_submit": [_vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, ctypes.c_uint64],
         "hvx_server_poll": [_vp, _P(ctypes.c_uint64), _P(ctypes.c_int32), _P(ctypes.c_double), ctypes.c_uint32,
@@ -326,6 +329,14 @@ def hvx_batch_query(b, attr, ctx=None) -> int:
     v = ctypes.c_int64()
     _check(_load().hvx_batch_query(b, attr, ctypes.byref(v)), ctx)
     return v.value
+
+
+def hvx_batch_set_option(b, option, value, ctx=None):
+    _check(_load().hvx_batch_set_option(b, option, value), ctx)
+
+
+def hvx_batch_autotune(b, stream=None, iters=3, ctx=None):
+    _check(_load().hvx_batch_autotune(b, stream, iters), ctx)
 
 
 def hvx_server_create(ctx, mode, budget_bytes, max_slots, n_streams):

@@ -543,7 +543,9 @@ hvx_status hvx_graph_query(hvx_graph graph, int attr, int64_t* out) {
       *out = m;
       break;
     }
-    case HVX_QUERY_ROWS_PER_ITEM: *out = p.groups.empty() ? 0 : p.groups[0].rows; break;
+    case HVX_QUERY_ROWS_PER_ITEM:
+      *out = (p.groups.empty() || p.groups[0].kind == FK_GENERIC) ? 0 : rows_for(g, p.groups[0]);
+      break;
     default: return set_error(g->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown query %d", attr);
   }
   return HVX_SUCCESS;

@@ -34,9 +34,10 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32 perm(u32 hi, u32 lo, u32 sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
 __device__ __forceinline__ u32 alignbit16(u32 hi, u32 lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }
-// lane i receives lane i-1's value / lane i+1's value (whole-wave shifts)
-__device__ __forceinline__ u32 from_left(u32 v) { return __builtin_amdgcn_update_dpp(0u, v, 0x138, 0xF, 0xF, false); }
-__device__ __forceinline__ u32 from_right(u32 v) { return __builtin_amdgcn_update_dpp(0u, v, 0x130, 0xF, 0xF, false); }
+// lane i receives lane i-1's value / lane i+1's value (whole-wave shifts; the lane
+// without a source reads 0, which only halo lanes ever see)
+__device__ __forceinline__ u32 from_left(u32 v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ u32 from_right(u32 v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
 __device__ __forceinline__ u32 bfi(u32 mask, u32 a, u32 b) { return (mask & a) | (~mask & b); }
 
 __device__ __forceinline__ u32 add2(u32 a, u32 b) {
@@ -102,7 +103,8 @@ __device__ __forceinline__ Lanes make_lanes(const StripGrid& g, int strip) {
   L.mR = (L.m == 0 && L.xs + 16 == g.w) ? 0xFFFF0000u : 0u;
   L.mRag = (L.m != 0 && L.xs == g.w - L.m) ? 0xFFFFFFFFu : 0u;
   L.edgeL = strip == 0;
-  L.edgeR = strip >= g.nstrips - 2;
+  // some lane of the strip (halo lanes included) holds W-1 or W
+  L.edgeR = g.w <= (strip + 1) * kStripPx + kLanePx;
   return L;
 }
 
@@ -112,38 +114,53 @@ struct Ext {
 };
 
 // Value of pixel m-1 (the last in-image pixel of the lane holding W-1 when
-// W % 16 = m != 0) in both halves.  m is wave-uniform.
+// W % 16 = m != 0) in both halves; m is wave-uniform.
 __device__ __forceinline__ u32 last_pixel_pair(const u32 p[8], int m) {
-  const int pos = m - 1;  // 0..14
-  const int k = pos & 7;
-  u32 r = p[0];
-#pragma unroll
-  for (int kk = 1; kk < 8; ++kk)
-    if (kk == k) r = p[kk];
-  u32 v = pos >= 8 ? (r >> 16) : (r & 0xFFFFu);
+  // an explicit switch: a select chain over p[] would be turned into a
+  // dynamically indexed (scratch) access
+  u32 v;
+  switch (m - 1) {
+    case 0: v = p[0] & 0xFFFFu; break;
+    case 1: v = p[1] & 0xFFFFu; break;
+    case 2: v = p[2] & 0xFFFFu; break;
+    case 3: v = p[3] & 0xFFFFu; break;
+    case 4: v = p[4] & 0xFFFFu; break;
+    case 5: v = p[5] & 0xFFFFu; break;
+    case 6: v = p[6] & 0xFFFFu; break;
+    case 7: v = p[7] & 0xFFFFu; break;
+    case 8: v = p[0] >> 16; break;
+    case 9: v = p[1] >> 16; break;
+    case 10: v = p[2] >> 16; break;
+    case 11: v = p[3] >> 16; break;
+    case 12: v = p[4] >> 16; break;
+    case 13: v = p[5] >> 16; break;
+    default: v = p[6] >> 16; break;
+  }
   return v | (v << 16);
 }
 
 // Build the extended row of a value array before a stencil of radius R (1 or
-// 2) reads it.  `repl` selects REPLICATE (else CONSTANT with `cpair` = the
+// 2) reads it.  HEDGE: the strip touches the left or right image border, so
+// the pixels just outside the image are replaced by the border value
+// (`repl`: the nearest in-image value of the same array, else `cpair`, the
 // constant in both halves).  In the lane holding W-1 with W % 16 = m != 0,
-// pixels m .. m+R-1 of p are overwritten with the border value.
-template <int R>
+// pixels m .. m+R-1 of p are overwritten in place.
+template <int R, bool HEDGE>
 __device__ __forceinline__ void extend(u32 p[8], Ext& e, const Lanes& L, bool repl, u32 cpair) {
-  const bool rag = L.edgeR && L.m != 0;
   u32 fill_rag = cpair;
-  if (rag) {
+  if (HEDGE && L.m != 0) {
     if (repl) fill_rag = last_pixel_pair(p, L.m);
+    // per register k: halves at positions m .. m+R-1 of the ragged lane
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const int pos = L.m + t;  // 1..16; 16 is handled on the extended row
-      if (pos < 16) {
-        const u32 hm = pos >= 8 ? 0xFFFF0000u : 0x0000FFFFu;
-        const int k = pos & 7;
+    for (int k = 0; k < 8; ++k) {
+      u32 hm = 0;
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk)
-          if (kk == k) p[kk] = bfi(L.mRag & hm, fill_rag, p[kk]);
+      for (int t = 0; t < R; ++t) {
+        const int pos = L.m + t;
+        hm |= (pos == k) ? 0x0000FFFFu : 0u;
+        hm |= (pos == k + 8) ? 0xFFFF0000u : 0u;
       }
+      p[k] = bfi(L.mRag & hm, fill_rag, p[k]);
     }
   }
   e.v[1] = alignbit16(p[7], from_left(p[7]));
@@ -154,17 +171,16 @@ __device__ __forceinline__ void extend(u32 p[8], Ext& e, const Lanes& L, bool re
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) e.v[k + 2] = p[k];
-  if (L.edgeL) {
-    const u32 f = repl ? p[0] : cpair;  // low half: pixel 0 or the constant
-    e.v[1] = bfi(L.mL, f, e.v[1]);
-    if (R >= 2) e.v[0] = bfi(L.mL, f, e.v[0]);
-  }
-  if (L.edgeR) {
-    const u32 f = repl ? p[7] : cpair;  // high half: pixel 15 or the constant
-    e.v[10] = bfi(L.mR, f, e.v[10]);
-    if (R >= 2) e.v[11] = bfi(L.mR, f, e.v[11]);
-    // pixel 16 of the ragged lane is read only when m + R - 1 >= 16
-    if (rag && L.m + R - 1 >= 16) e.v[10] = bfi(L.mRag & 0xFFFF0000u, fill_rag, e.v[10]);
+  if (HEDGE) {
+    const u32 fl = repl ? p[0] : cpair;  // low half: pixel 0 or the constant
+    e.v[1] = bfi(L.mL, fl, e.v[1]);
+    if (R >= 2) e.v[0] = bfi(L.mL, fl, e.v[0]);
+    const u32 fr = repl ? p[7] : cpair;  // high half: pixel 15 or the constant
+    // pixel 16 (and 17) beyond a lane ending at W, or of the ragged lane when m + R - 1 >= 16
+    const u32 m16 = L.mR | ((L.m + R - 1 >= 16) ? (L.mRag & 0xFFFF0000u) : 0u);
+    const u32 f16 = L.mR ? fr : fill_rag;
+    e.v[10] = bfi(m16, f16, e.v[10]);
+    if (R >= 2) e.v[11] = bfi(L.mR, fr, e.v[11]);
   }
 }
 
@@ -188,157 +204,248 @@ __device__ __forceinline__ int phase_level(int gx, int gy) {
   return ((int)(t + 0.5f)) & 255;
 }
 
-template <bool PHASE>
-__device__ void edge_item(const EdgeDesc& d, int strip, int band) {
-  const StripGrid& g = d.g;
-  const Lanes L = make_lanes(g, strip);
-  const int W = g.w, H = g.h;
-  (void)W;
-  const int y0 = band * g.rows;
-  const int y1 = min(y0 + g.rows, H);
-  const bool repl0 = d.b0 != B_CONSTANT, repl1 = d.b1 != B_CONSTANT;
-  const u32 c0 = (u32)d.c0 & 0xFF, c1 = (u32)d.c1 & 0xFFFF;
-  const u32 cin = c0 | (c0 << 16);        // input constant
-  const u32 cv0 = (4 * c0) | ((4 * c0) << 16);  // vertical (1 2 1) sum of the constant
-  const u32 cg = c1 | (c1 << 16);         // Gaussian-output constant
-  const u32 cs1 = (4 * c1) | ((4 * c1) << 16);
-  const uint8_t* inb = d.in + L.xl;
+// One wave streams its band: at output row y it finishes Gaussian row y+1 and
+// Sobel/magnitude/threshold row y.  All (1 2 1) sums are formed from pairwise
+// sums shared between neighbouring rows or pixels (a + 2b + c = (a+b) + (b+c)).
+// The loop is unrolled by six so that every rotating row buffer (periods two
+// and three) is renamed statically, and input rows are loaded two rows ahead.
+template <bool PHASE, bool HEDGE>
+struct EdgeStream {
+  const EdgeDesc& d;
+  Lanes L;
+  int H, y1;
+  bool repl0, repl1;
+  u32 cin, cv0, cg, cs1;
+  const uint8_t* inb;
+  uint8_t* outb;
+  uint8_t* phb;
+  // rotating state
+  u32 inr[2][8];  // input row y+1 (role alternates)
+  u32 tr[2][8];   // in(y) + in(y+1)
+  u32 gr[3][8];   // Gaussian rows y-1, y, y+1
+  u32 sr[2][8];   // G(y-1) + G(y)
+  u32x4 raw[3];   // prefetched input rows
 
-  auto fetch = [&](int y, u32 p[8]) {
+  __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip) : d(d_) {
+    L = make_lanes(d.g, strip);
+    H = d.g.h;
+    repl0 = d.b0 != B_CONSTANT;
+    repl1 = d.b1 != B_CONSTANT;
+    const u32 c0 = (u32)d.c0 & 0xFF, c1 = (u32)d.c1 & 0xFF;
+    cin = c0 | (c0 << 16);
+    cv0 = (4 * c0) | ((4 * c0) << 16);
+    cg = c1 | (c1 << 16);
+    cs1 = (4 * c1) | ((4 * c1) << 16);
+    inb = d.in + L.xl;
+    outb = d.out + L.xs;
+    phb = PHASE ? d.phase + L.xs : nullptr;
+  }
+  __device__ __forceinline__ u32x4 load(int y) const {
     const int yc = min(max(y, 0), H - 1);
-    u32x4 r = __builtin_nontemporal_load((const u32x4*)(inb + (size_t)yc * d.in_pitch));
+    return __builtin_nontemporal_load((const u32x4*)(inb + (size_t)yc * d.in_pitch));
+  }
+  __device__ __forceinline__ void unpk(u32x4 r, int y, u32 p[8]) const {
     unpack16(r, p);
     if (!repl0 && (y < 0 || y >= H)) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) p[k] = cin;
     }
-  };
-  // G row from input rows a (y-1), b (y), c (y+1)
-  auto gauss = [&](const u32 a[8], const u32 b[8], const u32 c[8], u32 out[8]) {
-    u32 v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = add2(add2(a[k], c[k]), shl2(b[k], 1));
+  }
+  // Gaussian row from the vertical (1 2 1) sums v of its three input rows
+  __device__ __forceinline__ void gauss_h(u32 v[8], u32 g[8]) const {
     Ext e;
-    extend<1>(v, e, L, repl0, cv0);
+    extend<1, HEDGE>(v, e, L, repl0, cv0);
+    u32 u[9];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) out[k] = shr2(add2(add2(e.v[k + 1], e.v[k + 3]), shl2(e.v[k + 2], 1)), 4);
-  };
-
-  u32 ia[8], ib[8], ic[8], g0[8], g1[8], g2[8];
-  // G(y0 - 1)
-  fetch(y0 - 2, ia);
-  fetch(y0 - 1, ib);
-  fetch(y0, ic);
-  if (y0 >= 1) gauss(ia, ib, ic, g0);
-  // G(y0)
+    for (int i = 0; i < 9; ++i) u[i] = add2(e.v[i + 1], e.v[i + 2]);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    ia[k] = ib[k];
-    ib[k] = ic[k];
+    for (int k = 0; k < 8; ++k) g[k] = shr2(add2(u[k], u[k + 1]), 4);
   }
-  fetch(y0 + 1, ic);
-  gauss(ia, ib, ic, g1);
-  if (y0 == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) g0[k] = repl1 ? g1[k] : cg;
-  }
-  const int64_t op = d.out_pitch;
-  uint8_t* outb = d.out + L.xs;
-  for (int y = y0; y < y1; ++y) {
-    // G(y + 1)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      ia[k] = ib[k];
-      ib[k] = ic[k];
-    }
-    if (y + 1 < H) {
-      fetch(y + 2, ic);
-      gauss(ia, ib, ic, g2);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) g2[k] = repl1 ? g1[k] : cg;
-    }
-    // Sobel on G rows (y-1, y, y+1): vertical (1 2 1) sum and difference first
-    u32 sv[8], dv[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      sv[k] = add2(add2(g0[k], g2[k]), shl2(g1[k], 1));
-      dv[k] = sub2(g2[k], g0[k]);
-    }
+  __device__ __forceinline__ void emit(int y, u32 sv[8], u32 dv[8]) {
     Ext es, ed;
-    extend<1>(sv, es, L, repl1, cs1);
-    extend<1>(dv, ed, L, repl1, 0u);
-    u32 gx[8], gy[8];
+    extend<1, HEDGE>(sv, es, L, repl1, cs1);
+    extend<1, HEDGE>(dv, ed, L, repl1, 0u);
+    u32 gx[8], gy[8], eu[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) eu[i] = add2(ed.v[i + 1], ed.v[i + 2]);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       gx[k] = sub2(es.v[k + 3], es.v[k + 1]);
-      gy[k] = add2(add2(ed.v[k + 1], ed.v[k + 3]), shl2(ed.v[k + 2], 1));
+      gy[k] = add2(eu[k], eu[k + 1]);
+    }
+    if (PHASE) {
+      // four output bytes at a time (pixels 4j..4j+3), with scheduling
+      // barriers so that only one group's temporaries are live at once
+      u32x4 po;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        u32 word = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = (j & 1) * 4 + i;  // register
+          const bool hi = j >= 2;         // half
+          const int a = hi ? ((int)gx[k]) >> 16 : (int)(short)(gx[k] & 0xFFFF);
+          const int b = hi ? ((int)gy[k]) >> 16 : (int)(short)(gy[k] & 0xFFFF);
+          word |= (u32)phase_level(a, b) << (8 * i);
+        }
+        po[j] = word;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (L.store) __builtin_nontemporal_store(po, (u32x4*)(phb + (size_t)y * d.phase_pitch));
     }
     // magnitude + threshold as one integer test: gx^2 + gy^2 > T
-    int r[16];
+    u32 r[16];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      u32 lo = perm(gy[k], gx[k], 0x05040100u);  // (gx_k, gy_k)
-      u32 hi = perm(gy[k], gx[k], 0x07060302u);  // (gx_k+8, gy_k+8)
-      r[k] = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, lo), __builtin_bit_cast(s16x2, lo), d.thr_not, false);
-      r[k + 8] = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, hi), __builtin_bit_cast(s16x2, hi), d.thr_not, false);
+      const u32 lo = perm(gy[k], gx[k], 0x05040100u);  // (gx_k, gy_k)
+      const u32 hi = perm(gy[k], gx[k], 0x07060302u);  // (gx_k+8, gy_k+8)
+      r[k] = (u32)__builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, lo), __builtin_bit_cast(s16x2, lo), d.thr_not,
+                                         false);
+      r[k + 8] = (u32)__builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, hi), __builtin_bit_cast(s16x2, hi),
+                                             d.thr_not, false);
     }
-    // sign bytes: 0xFF where r < 0 (no edge)
     u32x4 o;
-    u32 q[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      u32 lo2 = perm((u32)r[4 * j + 1], (u32)r[4 * j + 0], 0x0c0c0b09u);
-      u32 hi2 = perm((u32)r[4 * j + 3], (u32)r[4 * j + 2], 0x0b090c0cu);
-      q[j] = bfi(lo2 | hi2, d.fv4, d.tv4);
-    }
-    o.x = q[0];
-    o.y = q[1];
-    o.z = q[2];
-    o.w = q[3];
-    if (L.store) __builtin_nontemporal_store(o, (u32x4*)(outb + (size_t)y * op));
-    if (PHASE) {
-      u32 ph[8];
+    // mask bytes are 0xFF where the sum is below the bound (no edge);
+    // out = tv ^ (mask & (tv ^ fv)) picks fv there and tv elsewhere
+    const u32 x4 = d.tv4 ^ d.fv4;
+    o.x = d.tv4 ^ ((perm(r[1], r[0], 0x0c0c0b09u) | perm(r[3], r[2], 0x0b090c0cu)) & x4);
+    o.y = d.tv4 ^ ((perm(r[5], r[4], 0x0c0c0b09u) | perm(r[7], r[6], 0x0b090c0cu)) & x4);
+    o.z = d.tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
+    o.w = d.tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
+    if (L.store) __builtin_nontemporal_store(o, (u32x4*)(outb + (size_t)y * d.out_pitch));
+  }
+  // Output row y; J is the phase of y in the six-row unrolled sequence.
+  template <int J>
+  __device__ __forceinline__ void step(int y) {
+    u32(&in1)[8] = inr[J % 2];
+    u32(&in2)[8] = inr[(J + 1) % 2];
+    u32(&t0)[8] = tr[J % 2];
+    u32(&t1)[8] = tr[(J + 1) % 2];
+    u32(&gm1)[8] = gr[J % 3];
+    u32(&g0)[8] = gr[(J + 1) % 3];
+    u32(&g1)[8] = gr[(J + 2) % 3];
+    u32(&s0)[8] = sr[J % 2];
+    u32(&s1)[8] = sr[(J + 1) % 2];
+    const u32x4 cur = raw[J % 3];
+    raw[(J + 2) % 3] = load(y + 4);  // two rows ahead
+    if (y + 1 < H) {
+      unpk(cur, y + 2, in2);
+      u32 v[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        int lo = phase_level((int)(short)(gx[k] & 0xFFFF), (int)(short)(gy[k] & 0xFFFF));
-        int hi = phase_level(((int)gx[k]) >> 16, ((int)gy[k]) >> 16);
-        ph[k] = (u32)lo | ((u32)hi << 16);
+        t1[k] = add2(in1[k], in2[k]);
+        v[k] = add2(t0[k], t1[k]);
       }
-      u32x4 po = pack16(ph);
-      if (L.store) __builtin_nontemporal_store(po, (u32x4*)(d.phase + L.xs + (size_t)y * d.phase_pitch));
+      gauss_h(v, g1);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) g1[k] = repl1 ? g0[k] : cg;
+    }
+    u32 sv[8], dv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      s1[k] = add2(g0[k], g1[k]);
+      sv[k] = add2(s0[k], s1[k]);
+      dv[k] = sub2(g1[k], gm1[k]);
+    }
+    emit(y, sv, dv);
+  }
+  __device__ __forceinline__ void run(int y0, int y1_) {
+    y1 = y1_;
+    // prologue: G(y0-1), G(y0) and the pairwise state for row y0
+    u32 a[8], b[8], c[8], e[8];
+    unpk(load(y0 - 2), y0 - 2, a);
+    unpk(load(y0 - 1), y0 - 1, b);
+    unpk(load(y0), y0, c);
+    unpk(load(y0 + 1), y0 + 1, e);
+    raw[0] = load(y0 + 2);
+    raw[1] = load(y0 + 3);
+    u32 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = add2(add2(b[k], c[k]), add2(c[k], e[k]));
+    gauss_h(v, gr[1]);  // G(y0)
+    if (y0 >= 1) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = add2(add2(a[k], b[k]), add2(b[k], c[k]));
+      gauss_h(v, gr[0]);  // G(y0-1)
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) gr[0][k] = repl1 ? gr[1][k] : cg;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      g0[k] = g1[k];
-      g1[k] = g2[k];
+      inr[0][k] = e[k];
+      tr[0][k] = add2(c[k], e[k]);
+      sr[0][k] = add2(gr[0][k], gr[1][k]);
     }
+    for (int y = y0; y < y1; y += 6) {
+      step<0>(y);
+      if (y + 1 >= y1) break;
+      step<1>(y + 1);
+      if (y + 2 >= y1) break;
+      step<2>(y + 2);
+      if (y + 3 >= y1) break;
+      step<3>(y + 3);
+      if (y + 4 >= y1) break;
+      step<4>(y + 4);
+      if (y + 5 >= y1) break;
+      step<5>(y + 5);
+    }
+  }
+};
+
+template <bool PHASE>
+__device__ __forceinline__ void edge_item(const EdgeDesc& d, int strip, int band) {
+  const int y0 = band * d.g.rows;
+  const int y1 = min(y0 + d.g.rows, d.g.h);
+  if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
+    EdgeStream<PHASE, true> s(d, strip);
+    s.run(y0, y1);
+  } else {
+    EdgeStream<PHASE, false> s(d, strip);
+    s.run(y0, y1);
   }
 }
 
 // ---- Gaussian 5x5 (optionally of the luma of a UYVY frame) -----------------
+// (1 4 6 4 1) = (1 1) applied four times: vertically each level keeps one
+// pairwise sum per row (four packed adds per pixel pair per row);
+// horizontally the four levels run over the extended row.
+template <bool UYVY, bool HEDGE>
+struct G5Stream {
+  const Gauss5Desc& d;
+  Lanes L;
+  int H;
+  bool repl;
+  u32 cin, cv;
+  const uint8_t* inb;
+  uint8_t* outb;
+  u32 rr[2][8];  // last input row
+  u32 p1[2][8];  // level-1 vertical sums (rows y, y+1) ...
+  u32 p2[2][8];
+  u32 p3[2][8];
+  u32x4 raw[3][2];
 
-template <bool UYVY>
-__device__ void gauss5_item(const Gauss5Desc& d, int strip, int band) {
-  const StripGrid& g = d.g;
-  const Lanes L = make_lanes(g, strip);
-  const int H = g.h;
-  const int y0 = band * g.rows;
-  const int y1 = min(y0 + g.rows, H);
-  const bool repl = d.b0 != B_CONSTANT;
-  const u32 c = (u32)d.c0 & 0xFF;
-  const u32 cin = c | (c << 16);
-  const u32 cv = (16 * c) | ((16 * c) << 16);
-  const uint8_t* inb = d.in + (UYVY ? 2 * L.xl : L.xl);
-
-  auto fetch = [&](int y, u32 p[8]) {
+  __device__ __forceinline__ G5Stream(const Gauss5Desc& d_, int strip) : d(d_) {
+    L = make_lanes(d.g, strip);
+    H = d.g.h;
+    repl = d.b0 != B_CONSTANT;
+    const u32 c = (u32)d.c0 & 0xFF;
+    cin = c | (c << 16);
+    cv = (16 * c) | ((16 * c) << 16);
+    inb = d.in + (UYVY ? 2 * L.xl : L.xl);
+    outb = d.out + L.xs;
+  }
+  __device__ __forceinline__ void load(int y, u32x4 r[2]) const {
     const int yc = min(max(y, 0), H - 1);
     const uint8_t* row = inb + (size_t)yc * d.in_pitch;
+    r[0] = __builtin_nontemporal_load((const u32x4*)row);
+    if (UYVY) r[1] = __builtin_nontemporal_load((const u32x4*)(row + 16));
+  }
+  __device__ __forceinline__ void unpk(const u32x4 r[2], int y, u32 p[8]) const {
     if (UYVY) {
-      // 32 bytes U Y V Y ...: luma bytes are the odd ones
-      u32x4 a = __builtin_nontemporal_load((const u32x4*)row);
-      u32x4 b = __builtin_nontemporal_load((const u32x4*)(row + 16));
-      // pixel k (k < 8) lives in a, pixel k+8 in b; luma of pixel k is byte 2k+1
+      // pixel k (k < 8) is in the first 16 bytes, pixel k+8 in the next; luma is byte 2k+1
+      const u32x4 a = r[0], b = r[1];
       p[0] = perm(b.x, a.x, 0x0c050c01u);
       p[1] = perm(b.x, a.x, 0x0c070c03u);
       p[2] = perm(b.y, a.y, 0x0c050c01u);
@@ -348,48 +455,338 @@ __device__ void gauss5_item(const Gauss5Desc& d, int strip, int band) {
       p[6] = perm(b.w, a.w, 0x0c050c01u);
       p[7] = perm(b.w, a.w, 0x0c070c03u);
     } else {
-      unpack16(__builtin_nontemporal_load((const u32x4*)row), p);
+      unpack16(r[0], p);
     }
     if (!repl && (y < 0 || y >= H)) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) p[k] = cin;
     }
-  };
-
-  u32 r0[8], r1[8], r2[8], r3[8], r4[8];
-  fetch(y0 - 2, r0);
-  fetch(y0 - 1, r1);
-  fetch(y0, r2);
-  fetch(y0 + 1, r3);
-  uint8_t* outb = d.out + L.xs;
-  for (int y = y0; y < y1; ++y) {
-    fetch(y + 2, r4);
-    // vertical (1 4 6 4 1): max 16*255 = 4080 per column
+  }
+  __device__ __forceinline__ void horiz_store(int y, u32 v[8]) {
+    Ext e;
+    extend<2, HEDGE>(v, e, L, repl, cv);
+    u32 a[11], b[10], c[9];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) a[i] = add2(e.v[i], e.v[i + 1]);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) b[i] = add2(a[i], a[i + 1]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c[i] = add2(b[i], b[i + 1]);
+    u32 o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = shr2(add2(c[k], c[k + 1]), 8);
+    if (L.store) __builtin_nontemporal_store(pack16(o), (u32x4*)(outb + (size_t)y * d.out_pitch));
+  }
+  // output row y: the new input row is y+2
+  template <int J>
+  __device__ __forceinline__ void step(int y) {
+    u32(&r0)[8] = rr[J % 2];
+    u32(&r1)[8] = rr[(J + 1) % 2];
+    u32(&a0)[8] = p1[J % 2];
+    u32(&a1)[8] = p1[(J + 1) % 2];
+    u32(&b0)[8] = p2[J % 2];
+    u32(&b1)[8] = p2[(J + 1) % 2];
+    u32(&c0)[8] = p3[J % 2];
+    u32(&c1)[8] = p3[(J + 1) % 2];
+    u32x4 cur[2] = {raw[J % 3][0], raw[J % 3][1]};
+    load(y + 4, raw[(J + 2) % 3]);
+    unpk(cur, y + 2, r1);
     u32 v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      u32 a = add2(r0[k], r4[k]);
-      u32 b = add2(r1[k], r3[k]);
-      v[k] = add2(add2(a, shl2(b, 2)), add2(shl2(r2[k], 2), shl2(r2[k], 1)));
+      a1[k] = add2(r0[k], r1[k]);  // rows y+1, y+2
+      b1[k] = add2(a0[k], a1[k]);  // rows y .. y+2
+      c1[k] = add2(b0[k], b1[k]);  // rows y-1 .. y+2
+      v[k] = add2(c0[k], c1[k]);   // rows y-2 .. y+2
     }
-    Ext e;
-    extend<2>(v, e, L, repl, cv);
-    u32 o[8];
+    horiz_store(y, v);
+  }
+  __device__ __forceinline__ void run(int y0, int y1) {
+    u32 q[4][8];
+    u32x4 t[2];
+    for (int j = 0; j < 4; ++j) {
+      load(y0 - 2 + j, t);
+      unpk(t, y0 - 2 + j, q[j]);
+    }
+    load(y0 + 2, raw[0]);
+    load(y0 + 3, raw[1]);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      // horizontal (1 4 6 4 1): max 65280, fits 16 bits
-      u32 a = add2(e.v[k], e.v[k + 4]);
-      u32 b = add2(e.v[k + 1], e.v[k + 3]);
-      u32 s = add2(add2(a, shl2(b, 2)), add2(shl2(e.v[k + 2], 2), shl2(e.v[k + 2], 1)));
-      o[k] = shr2(s, 8);
+      const u32 s01 = add2(q[0][k], q[1][k]), s12 = add2(q[1][k], q[2][k]), s23 = add2(q[2][k], q[3][k]);
+      rr[0][k] = q[3][k];
+      p1[0][k] = s23;                        // rows y0, y0+1
+      p2[0][k] = add2(s12, s23);             // rows y0-1 .. y0+1
+      p3[0][k] = add2(add2(s01, s12), p2[0][k]);  // rows y0-2 .. y0+1
     }
-    if (L.store) __builtin_nontemporal_store(pack16(o), (u32x4*)(outb + (size_t)y * d.out_pitch));
+    for (int y = y0; y < y1; y += 6) {
+      step<0>(y);
+      if (y + 1 >= y1) break;
+      step<1>(y + 1);
+      if (y + 2 >= y1) break;
+      step<2>(y + 2);
+      if (y + 3 >= y1) break;
+      step<3>(y + 3);
+      if (y + 4 >= y1) break;
+      step<4>(y + 4);
+      if (y + 5 >= y1) break;
+      step<5>(y + 5);
+    }
+  }
+};
+
+template <bool UYVY>
+__device__ __forceinline__ void gauss5_item(const Gauss5Desc& d, int strip, int band) {
+  const int y0 = band * d.g.rows;
+  const int y1 = min(y0 + d.g.rows, d.g.h);
+  if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
+    G5Stream<UYVY, true> s(d, strip);
+    s.run(y0, y1);
+  } else {
+    G5Stream<UYVY, false> s(d, strip);
+    s.run(y0, y1);
+  }
+}
+
+// ---- Sobel 3x3 -> products -> Box5x5 (x3) -> corner response -> Threshold ----
+//
+// Four pixels per lane in 32-bit registers (the products need 21 bits, the
+// window sums 25).  Strip: lanes 1..62 produce 4 output pixels each.  The
+// structure-tensor sums are exact integers: each row's 5-pixel horizontal
+// sums go into a ring of the last five rows and a running vertical sum is
+// updated by adding the entering row and subtracting the leaving one.  The
+// response is then evaluated in F32 from the exact sums.
+namespace corner {
+
+constexpr int LPX = 4;
+constexpr int STRIP = 62 * LPX;
+
+struct Lanes4 {
+  int lane, xs, xl;
+  bool store;
+  bool mL;        // lane holding x = 0
+  bool mR;        // lane whose last pixel is W-1 (W % 4 == 0)
+  bool mRag;      // lane holding W-1 when W % 4 != 0
+  int m;          // W % 4
+  bool edgeL, edgeR;
+};
+
+__device__ __forceinline__ Lanes4 make_lanes(const StripGrid& g, int strip) {
+  Lanes4 L;
+  L.lane = threadIdx.x & 63;
+  L.xs = strip * STRIP + (L.lane - 1) * LPX;
+  const int wr = (g.w + 3) & ~3;
+  L.xl = min(max(L.xs, 0), wr - 4);
+  L.store = L.lane >= 1 && L.lane <= 62 && L.xs >= 0 && L.xs < g.w;
+  L.m = g.w & 3;
+  L.mL = L.xs == 0;
+  L.mR = L.m == 0 && L.xs + 4 == g.w;
+  L.mRag = L.m != 0 && L.xs == g.w - L.m;
+  L.edgeL = strip == 0;
+  L.edgeR = g.w <= (strip + 1) * STRIP + LPX;
+  return L;
+}
+
+__device__ __forceinline__ int ileft(int v) { return (int)from_left((u32)v); }
+__device__ __forceinline__ int iright(int v) { return (int)from_right((u32)v); }
+
+// e[0..7] = values at x-2, x-1, x..x+3, x+4, x+5 after the border rule.
+template <int R>
+__device__ __forceinline__ void extend4(int p[4], int e[8], const Lanes4& L, bool repl, int c) {
+  if (L.edgeR && L.m != 0) {
+    const int last = L.m == 1 ? p[0] : (L.m == 2 ? p[1] : p[2]);
+    const int f = repl ? last : c;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      r0[k] = r1[k];
-      r1[k] = r2[k];
-      r2[k] = r3[k];
-      r3[k] = r4[k];
+    for (int t = 0; t < R; ++t) {
+      const int pos = L.m + t;  // 1..4
+#pragma unroll
+      for (int k = 1; k < 4; ++k)
+        if (k == pos) p[k] = L.mRag ? f : p[k];
+    }
+  }
+  e[1] = ileft(p[3]);
+  e[6] = iright(p[0]);
+  if (R >= 2) {
+    e[0] = ileft(p[2]);
+    e[7] = iright(p[1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) e[k + 2] = p[k];
+  if (L.edgeL && L.mL) {
+    const int f = repl ? p[0] : c;
+    e[1] = f;
+    if (R >= 2) e[0] = f;
+  }
+  if (L.edgeR) {
+    if (L.mR) {
+      const int f = repl ? p[3] : c;
+      e[6] = f;
+      if (R >= 2) e[7] = f;
+    }
+    if (L.m != 0 && L.mRag && L.m + R - 1 >= 4) {  // pixel 4 of the ragged lane (m = 3, R = 2)
+      e[6] = repl ? p[2] : c;
+    }
+  }
+}
+
+struct St {
+  const CornerDesc* d;
+  Lanes4 L;
+  const uint8_t* inb;
+  bool repl0, repl1;
+  int c0, c1;
+};
+
+__device__ __forceinline__ void load_row(const St& s, int y, int a[4]) {
+  const int H = s.d->g.h;
+  const int yc = min(max(y, 0), H - 1);
+  u32 r = __builtin_nontemporal_load((const u32*)(s.inb + (size_t)yc * s.d->in_pitch));
+  if (!s.repl0 && (y < 0 || y >= H)) r = 0x01010101u * (u32)s.c0;
+  a[0] = r & 0xFF;
+  a[1] = (r >> 8) & 0xFF;
+  a[2] = (r >> 16) & 0xFF;
+  a[3] = r >> 24;
+}
+
+// Horizontal 5-sums of the three products at in-image row r (rows r-1, r, r+1 given).
+__device__ __forceinline__ void hsums(const St& s, const int a[4], const int b[4], const int c[4], int h[3][4]) {
+  int sv[4], dv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    sv[k] = a[k] + 2 * b[k] + c[k];
+    dv[k] = c[k] - a[k];
+  }
+  int es[8], ed[8];
+  extend4<1>(sv, es, s.L, s.repl0, 4 * s.c0);
+  extend4<1>(dv, ed, s.L, s.repl0, 0);
+  int p[3][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int gx = es[k + 3] - es[k + 1];
+    const int gy = ed[k + 1] + 2 * ed[k + 2] + ed[k + 3];
+    p[0][k] = __mul24(gx, gx);
+    p[1][k] = __mul24(gy, gy);
+    p[2][k] = __mul24(gx, gy);
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    int e[8];
+    extend4<2>(p[q], e, s.L, s.repl1, s.c1);
+    const int t01 = e[0] + e[1], t23 = e[2] + e[3], t45 = e[4] + e[5], t67 = e[6] + e[7];
+    h[q][0] = t01 + t23 + e[4];
+    h[q][1] = e[1] + t23 + t45;
+    h[q][2] = t23 + t45 + e[6];
+    h[q][3] = e[3] + t45 + t67;
+  }
+}
+
+}  // namespace corner
+
+__device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int band) {
+  using namespace corner;
+  St s;
+  s.d = &d;
+  s.L = corner::make_lanes(d.g, strip);
+  s.inb = d.in + s.L.xl;
+  s.repl0 = d.b0 != B_CONSTANT;
+  s.repl1 = d.b1 != B_CONSTANT;
+  s.c0 = d.c0 & 0xFF;
+  s.c1 = (int)d.c1;
+  const int H = d.g.h;
+  const int y0 = band * d.g.rows;
+  const int y1 = min(y0 + d.g.rows, H);
+
+  // input rows r-1, r, r+1 for the next gradient row r = nr
+  int ia[4], ib[4], ic[4];
+  int nr = max(y0 - 2, 0);
+  load_row(s, nr - 1, ia);
+  load_row(s, nr, ib);
+  load_row(s, nr + 1, ic);
+  // H rows of the product planes; row y of the box needs rows y-2..y+2
+  int ring[5][3][4];
+  int last[3][4];  // most recent in-image H row (for REPLICATE below the image)
+  auto next_h = [&](int r, int out[3][4]) {
+    if (r < 0 || r >= H) {
+      // rows outside the image: border of the box filters' input
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[q][k] = s.repl1 ? last[q][k] : 5 * s.c1;
+      return;
+    }
+    hsums(s, ia, ib, ic, out);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) last[q][k] = out[q][k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ia[k] = ib[k];
+      ib[k] = ic[k];
+    }
+    load_row(s, r + 2, ic);
+  };
+  // prologue: rows y0-2 .. y0+2; above the image REPLICATE needs row 0 first
+  if (y0 - 2 < 0) {
+    int h0[3][4];
+    next_h(0, h0);  // computes row 0 and sets `last`
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int r = y0 - 2 + j;
+      if (r < 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ring[j][q][k] = s.repl1 ? h0[q][k] : 5 * s.c1;
+      } else if (r == 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ring[j][q][k] = h0[q][k];
+      } else {
+        next_h(r, ring[j]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) next_h(y0 - 2 + j, ring[j]);
+  }
+  int v[3][4];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      v[q][k] = ring[0][q][k] + ring[1][q][k] + ring[2][q][k] + ring[3][q][k] + ring[4][q][k];
+
+  uint8_t* outb = d.out + s.L.xs;
+  auto emit = [&](int y) {
+    u32 o = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float sxx = (float)v[0][k], syy = (float)v[1][k], sxy = (float)v[2][k];
+      const float det = fmaf(sxx, syy, -sxy * sxy);
+      const float tr = sxx + syy;
+      const float r = fmaf(-d.k * tr, tr, det);
+      o |= (r > d.thr ? (d.tv4 & 0xFFu) : (d.fv4 & 0xFFu)) << (8 * k);
+    }
+    if (s.L.store) __builtin_nontemporal_store(o, (u32*)(outb + (size_t)y * d.out_pitch));
+  };
+  // unrolled by the ring length so that every ring slot index is a
+  // compile-time constant; each step is guarded by a uniform branch
+  for (int y = y0; y < y1; y += 5) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      if (y + j < y1) {
+        emit(y + j);
+        int hn[3][4];
+        next_h(y + j + 3, hn);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            v[q][k] += hn[q][k] - ring[j][q][k];
+            ring[j][q][k] = hn[q][k];
+          }
+      }
     }
   }
 }

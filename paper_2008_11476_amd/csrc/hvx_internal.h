@@ -134,6 +134,7 @@ struct Graph : Object {
   // device state
   std::vector<void*> scratch;  // one buffer per materialised value (index = value id), or null
   std::vector<size_t> scratch_pitch;
+  GProg* dev_progs = nullptr;  // device copies of the groups' generic programs (index = group)
   void* last_stream = nullptr;
   bool scheduled = false;
 };
@@ -170,7 +171,8 @@ hvx_status ensure_device(Context* ctx);
 hvx_status schedule_graph(Graph* g, void* stream);
 void free_graph_device(Graph* g);
 int default_rows(const Group& gr, int num_cus);
-void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi);
+int rows_for(const Graph* g, const Group& gr);  // rows per work item in effect (option, tuned, default)
+void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_override = 0);
 int64_t fast_items(const Group& gr);
 
 }  // namespace hvx

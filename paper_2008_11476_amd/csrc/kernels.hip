@@ -16,9 +16,12 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
   return x * q + min(x, r) + i;
 }
 
-__global__ __launch_bounds__(256) void k_generic(const GProg P, const IOTable io) {
+// The program lives in device memory: the interpreter indexes its value and
+// operator tables with wave-uniform indices (scalar loads), which a by-value
+// kernel argument would turn into a private (scratch) copy.
+__global__ __launch_bounds__(256) void k_generic(const GProg* __restrict__ P, const IOTable io) {
   extern __shared__ int32_t lds[];
-  generic_tile<256>(P, io, blockIdx.x, lds);
+  generic_tile<256>(*P, io, blockIdx.x, lds);
 }
 
 template <bool PHASE>
@@ -27,75 +30,99 @@ __global__ __launch_bounds__(64) void k_edge(const EdgeDesc d, int xcd) {
   edge_item<PHASE>(d, item % d.g.nstrips, item / d.g.nstrips);
 }
 
+__global__ __launch_bounds__(64) void k_corner(const CornerDesc d, int xcd) {
+  const int item = xcd ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x;
+  corner_item(d, item % d.g.nstrips, item / d.g.nstrips);
+}
+
 template <bool UYVY>
 __global__ __launch_bounds__(64) void k_gauss5(const Gauss5Desc d, int xcd) {
   const int item = xcd ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x;
   gauss5_item<UYVY>(d, item % d.g.nstrips, item / d.g.nstrips);
 }
 
-// Persistent batch kernel: every wave takes work items from one atomic
-// counter until the flat list is exhausted (each wave's last fetch is the one
-// that fails, so every wave reaches the exit).  The next fetch is issued
-// before the current item is processed to hide the atomic's latency.  The
-// wave that finishes last resets both counters, so the next launch on the
-// stream (or the next replay of a captured graph) starts from zero.
+// Persistent batch kernel.  The flat work list is cut into 8 contiguous
+// ranges, one per XCD group of waves (block b belongs to group b % 8, the
+// XCD the hardware dispatches it to), so that the atomics of different
+// groups hit different counters and neighbouring items share an L2.  Within
+// a group, waves take `chunk` consecutive items per atomic fetch until the
+// range is exhausted; the next fetch is issued before the current chunk is
+// processed.  Every wave's last fetch is the one past the end of its range,
+// so every wave exits.  The last wave of a group to finish resets that
+// group's counters, so the next launch (or graph replay) starts from zero.
+constexpr int kCtrStride = 32;  // counters 128 bytes apart
+
+// KS: the set of kinds a batch holds (bit 1 edge, 2 corner, 4 Gaussian5x5);
+// only those bodies are compiled into the batch kernel, so a batch of one
+// kind keeps that kind's register budget and occupancy.
+template <int KS>
 __device__ __forceinline__ void run_item(const BatchImage& bi, int local) {
-  switch (bi.kind) {
-    case FK_EDGE: {
-      const EdgeDesc& d = bi.d.e;
-      if (d.phase) edge_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
-      else edge_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
-      break;
-    }
-    case FK_GAUSS5: {
-      const Gauss5Desc& d = bi.d.g5;
-      if (d.uyvy) gauss5_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
-      else gauss5_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
-      break;
-    }
-    default: break;
+  if ((KS & 1) && bi.kind == FK_EDGE) {
+    const EdgeDesc& d = bi.d.e;
+    if (d.phase) edge_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
+    else edge_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
+  } else if ((KS & 2) && bi.kind == FK_CORNER) {
+    const CornerDesc& d = bi.d.c;
+    corner_item(d, local % d.g.nstrips, local / d.g.nstrips);
+  } else if ((KS & 4) && bi.kind == FK_GAUSS5) {
+    const Gauss5Desc& d = bi.d.g5;
+    if (d.uyvy) gauss5_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
+    else gauss5_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
   }
 }
 
+template <int KS>
+__device__ __forceinline__ void run_flat(const BatchImage* __restrict__ imgs, const uint16_t* __restrict__ item_img,
+                                         int item) {
+  const int im = item_img[item];
+  const BatchImage& bi = imgs[im];
+  run_item<KS>(bi, item - bi.first_item);
+}
+
+template <int KS>
 __global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ imgs,
-                                              const uint16_t* __restrict__ item_img, int total,
+                                              const uint16_t* __restrict__ item_img, int total, int chunk,
                                               unsigned* __restrict__ counter) {
   const int lane = threadIdx.x & 63;
+  const int grp = blockIdx.x & 7;
+  const int begin = (int)((long long)total * grp / 8), end = (int)((long long)total * (grp + 1) / 8);
+  unsigned* next = counter + grp * kCtrStride;
+  unsigned* done = counter + (8 + grp) * kCtrStride;
   unsigned got = 0;
-  if (lane == 0) got = atomicAdd(&counter[0], 1u);
-  int item = __builtin_amdgcn_readfirstlane((int)got);
-  while (item < total) {
+  if (lane == 0) got = atomicAdd(next, (unsigned)chunk);
+  int base = begin + __builtin_amdgcn_readfirstlane((int)got);
+  while (base < end) {
     unsigned nxt = 0;
-    if (lane == 0) nxt = atomicAdd(&counter[0], 1u);
-    const int im = item_img[item];
-    const BatchImage& bi = imgs[im];
-    run_item(bi, item - bi.first_item);
-    item = __builtin_amdgcn_readfirstlane((int)nxt);
+    if (lane == 0) nxt = atomicAdd(next, (unsigned)chunk);
+    const int stop = min(base + chunk, end);
+    for (int item = base; item < stop; ++item) run_flat<KS>(imgs, item_img, item);
+    base = begin + __builtin_amdgcn_readfirstlane((int)nxt);
   }
   if (lane == 0) {
-    unsigned done = atomicAdd(&counter[1], 1u);
-    if (done == gridDim.x - 1) {
-      atomicExch(&counter[0], 0u);
-      atomicExch(&counter[1], 0u);
+    const unsigned waves = (gridDim.x - grp + 7) / 8;  // blocks of this group
+    const unsigned d = atomicAdd(done, 1u);
+    if (d == waves - 1) {
+      atomicExch(next, 0u);
+      atomicExch(done, 0u);
     }
   }
 }
 
-// One work item per wave, no counter (used when the tuner finds it faster).
+// One wave per work item, no counter; items mapped XCD-contiguously.
+template <int KS>
 __global__ __launch_bounds__(64) void k_batch_direct(const BatchImage* __restrict__ imgs,
                                                      const uint16_t* __restrict__ item_img, int total) {
-  const int item = blockIdx.x;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= total) return;
-  const BatchImage& bi = imgs[item_img[item]];
-  run_item(bi, item - bi.first_item);
+  run_flat<KS>(imgs, item_img, item);
 }
 
 // ---- host launchers ---------------------------------------------------------
 
-hipError_t launch_generic(const GProg& P, const IOTable& io, hipStream_t s) {
+hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& io, hipStream_t s) {
   const int tiles = P.tiles_x * P.tiles_y;
   if (tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_generic, dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, P, io);
+  hipLaunchKernelGGL(k_generic, dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
   return hipGetLastError();
 }
 
@@ -115,17 +142,52 @@ hipError_t launch_gauss5(const Gauss5Desc& d, bool xcd, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchImage* imgs, const uint16_t* item_img, int total, unsigned* counter, int grid,
-                        bool persistent, hipStream_t s) {
-  if (total <= 0) return hipSuccess;
-  if (persistent) hipLaunchKernelGGL(k_batch, dim3(grid), dim3(64), 0, s, imgs, item_img, total, counter);
-  else hipLaunchKernelGGL(k_batch_direct, dim3(total), dim3(64), 0, s, imgs, item_img, total);
+hipError_t launch_corner(const CornerDesc& d, bool xcd, hipStream_t s) {
+  const int n = d.g.nstrips * d.g.nbands;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_corner, dim3(n), dim3(64), 0, s, d, xcd ? 1 : 0);
   return hipGetLastError();
 }
 
-int batch_waves_per_cu() {
+template <int KS>
+static void launch_batch_ks(const BatchImage* imgs, const uint16_t* item_img, int total, unsigned* counter, int grid,
+                            bool persistent, hipStream_t s) {
+  if (persistent) {
+    grid = max(grid, 8);  // every group of the 8 ranges needs at least one wave
+    const int per_group_waves = max(1, grid / 8);
+    const int chunk = max(1, (total / 8) / (per_group_waves * 4));
+    hipLaunchKernelGGL(k_batch<KS>, dim3(grid), dim3(64), 0, s, imgs, item_img, total, chunk, counter);
+  } else {
+    hipLaunchKernelGGL(k_batch_direct<KS>, dim3(total), dim3(64), 0, s, imgs, item_img, total);
+  }
+}
+
+hipError_t launch_batch(const BatchImage* imgs, const uint16_t* item_img, int total, unsigned* counter, int grid,
+                        bool persistent, int kinds, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  switch (kinds) {
+    case 1: launch_batch_ks<1>(imgs, item_img, total, counter, grid, persistent, s); break;
+    case 2: launch_batch_ks<2>(imgs, item_img, total, counter, grid, persistent, s); break;
+    case 4: launch_batch_ks<4>(imgs, item_img, total, counter, grid, persistent, s); break;
+    default: launch_batch_ks<7>(imgs, item_img, total, counter, grid, persistent, s); break;
+  }
+  return hipGetLastError();
+}
+
+int kind_bit(int kind) { return kind == FK_EDGE ? 1 : kind == FK_CORNER ? 2 : kind == FK_GAUSS5 ? 4 : 0; }
+
+size_t batch_counter_bytes() { return 16 * kCtrStride * sizeof(unsigned); }
+
+int batch_waves_per_cu(int kinds) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch, 64, 0) != hipSuccess || blocks <= 0) blocks = 8;
+  hipError_t e;
+  switch (kinds) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<1>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<2>, 64, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<4>, 64, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<7>, 64, 0); break;
+  }
+  if (e != hipSuccess || blocks <= 0) blocks = 8;
   return blocks;
 }
 

@@ -41,6 +41,8 @@ void free_graph_device(Graph* g) {
   if (g->scheduled && g->last_stream != (void*)-1) (void)hipStreamSynchronize((hipStream_t)g->last_stream);
   for (void* p : g->scratch)
     if (p) (void)hipFree(p);
+  if (g->dev_progs) (void)hipFree(g->dev_progs);
+  g->dev_progs = nullptr;
   g->scratch.clear();
   g->scratch_pitch.clear();
   g->scheduled = false;
@@ -49,6 +51,15 @@ void free_graph_device(Graph* g) {
 static hvx_status ensure_scratch(Graph* g) {
   Plan& p = *g->plan;
   if (g->scratch.size() == p.vals.size()) return HVX_SUCCESS;
+  // generic programs, one device copy per group
+  std::vector<GProg> progs(p.groups.size());
+  for (size_t i = 0; i < p.groups.size(); ++i) progs[i] = p.groups[i].prog;
+  if (hipMalloc((void**)&g->dev_progs, progs.size() * sizeof(GProg)) != hipSuccess ||
+      hipMemcpy(g->dev_progs, progs.data(), progs.size() * sizeof(GProg), hipMemcpyHostToDevice) != hipSuccess) {
+    if (g->dev_progs) (void)hipFree(g->dev_progs);
+    g->dev_progs = nullptr;
+    return set_error(g->ctx, HVX_ERROR_NO_MEMORY, "cannot upload kernel programs");
+  }
   g->scratch.assign(p.vals.size(), nullptr);
   g->scratch_pitch.assign(p.vals.size(), 0);
   for (size_t v = 0; v < p.vals.size(); ++v) {
@@ -88,7 +99,8 @@ static std::string tune_key(const Graph* g) { return g->ctx->dev_name + "|" + gr
 int default_rows(const Group& gr, int num_cus) {
   // enough work items to give every CU several waves, without letting the
   // halo rows (footprint on each side) dominate a work item
-  const int nstrips = ((int)gr.w + kStripPx - 1) / kStripPx;
+  const int sp = gr.kind == FK_CORNER ? 62 * 4 : kStripPx;
+  const int nstrips = ((int)gr.w + sp - 1) / sp;
   int64_t target = 4LL * num_cus;
   int64_t rows = ((int64_t)gr.h * nstrips) / std::max<int64_t>(1, target);
   int r = 4;
@@ -96,7 +108,7 @@ int default_rows(const Group& gr, int num_cus) {
   return r;
 }
 
-static int rows_for(const Graph* g, const Group& gr) {
+int rows_for(const Graph* g, const Group& gr) {
   if (gr.rows > 0) return gr.rows;
   auto it = g->ctx->tune.find(tune_key(g));
   if (it != g->ctx->tune.end() && it->second.rows > 0) return it->second.rows;
@@ -110,23 +122,25 @@ static int xcd_for(const Graph* g, const Group& gr) {
   return gr.xcd;
 }
 
+static int strip_px(int kind) { return kind == FK_CORNER ? 62 * 4 : kStripPx; }
+
 static StripGrid strip_grid(const Group& gr, int rows) {
   StripGrid s;
   s.w = (int)gr.w;
   s.h = (int)gr.h;
   s.rows = std::max(1, rows);
-  s.nstrips = (s.w + kStripPx - 1) / kStripPx;
+  s.nstrips = (s.w + strip_px(gr.kind) - 1) / strip_px(gr.kind);
   s.nbands = (s.h + s.rows - 1) / s.rows;
   return s;
 }
 
 int64_t fast_items(const Group& gr) { return (int64_t)gr.prog.tiles_x; }
 
-void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi) {
+void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_override) {
   const Plan& p = *g->plan;
   memset(bi, 0, sizeof *bi);
   bi->kind = gr.kind;
-  const int rows = rows_for(g, gr);
+  const int rows = rows_override > 0 ? rows_override : rows_for(g, gr);
   void* ptr;
   int64_t pitch;
   if (gr.kind == FK_EDGE) {
@@ -154,6 +168,30 @@ void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi) {
     d.tv4 = 0x01010101u * (uint32_t)(th->tv & 0xFF);
     d.fv4 = 0x01010101u * (uint32_t)(th->fv & 0xFF);
     bi->nitems = d.g.nstrips * d.g.nbands;
+  } else if (gr.kind == FK_CORNER) {
+    CornerDesc& d = bi->d.c;
+    d.g = strip_grid(gr, rows);
+    value_ptr(g, gr.v_in, &ptr, &pitch);
+    d.in = (const uint8_t*)ptr;
+    d.in_pitch = pitch;
+    value_ptr(g, gr.v_out, &ptr, &pitch);
+    d.out = (uint8_t*)ptr;
+    d.out_pitch = pitch;
+    const LOp* sx = find_op(p, gr, OP_SOBEL_X);
+    const LOp* bx = find_op(p, gr, OP_BOX5F);
+    const LOp* hr = find_op(p, gr, OP_HARRIS);
+    const LOp* th = find_op(p, gr, OP_THRESHOLD);
+    d.b0 = sx->border;
+    d.c0 = (int)std::min<uint32_t>(sx->bconst, 255);
+    d.b1 = bx->border;
+    d.c1 = (float)bx->bconst;
+    d.k = hr->k;
+    float f = (float)th->dval;
+    if ((double)f > th->dval) f = nextafterf(f, -INFINITY);
+    d.thr = f;
+    d.tv4 = 0x01010101u * (uint32_t)(th->tv & 0xFF);
+    d.fv4 = 0x01010101u * (uint32_t)(th->fv & 0xFF);
+    bi->nitems = d.g.nstrips * d.g.nbands;
   } else if (gr.kind == FK_GAUSS5) {
     Gauss5Desc& d = bi->d.g5;
     d.g = strip_grid(gr, rows);
@@ -173,6 +211,7 @@ void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi) {
 
 static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
   hipError_t e = hipSuccess;
+  const int gi = (int)(&gr - g->plan->groups.data());
   if (gr.kind == FK_GENERIC) {
     IOTable io;
     memset(&io, 0, sizeof io);
@@ -182,12 +221,13 @@ static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
       value_ptr(g, gr.gvals[i], &io.ptr[v.io], &io.pitch[v.io]);
       if (!io.ptr[v.io]) return set_error(g->ctx, HVX_ERROR_DEVICE, "unbound image in plan");
     }
-    e = launch_generic(gr.prog, io, s);
+    e = launch_generic(gr.prog, g->dev_progs + gi, io, s);
   } else {
     BatchImage bi;
     fill_fast_desc(g, gr, &bi);
     const bool xcd = xcd_for(g, gr) != 0;
     if (gr.kind == FK_EDGE) e = launch_edge(bi.d.e, xcd, s);
+    else if (gr.kind == FK_CORNER) e = launch_corner(bi.d.c, xcd, s);
     else if (gr.kind == FK_GAUSS5) e = launch_gauss5(bi.d.g5, xcd, s);
     else return set_error(g->ctx, HVX_ERROR_NOT_SUPPORTED, "no kernel for group kind %d", gr.kind);
   }
@@ -229,6 +269,8 @@ struct Batch : Object {
   hipGraph_t hg = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t alg_bytes = 0;
+  int rows_override = 0;  // rows per work item for every image (0: each graph's own)
+  int kinds = 0;          // bit set of the kinds in the persistent launch
   void* last_stream = nullptr;
   bool scheduled = false;
 };
@@ -279,9 +321,9 @@ static hvx_status batch_build(Batch* b) {
     if (s) return s;
     b->alg_bytes += g->plan->alg_bytes;
     const auto& gs = g->plan->groups;
-    if (gs.size() == 1 && (gs[0].kind == FK_EDGE || gs[0].kind == FK_GAUSS5)) {
+    if (gs.size() == 1 && gs[0].kind != FK_GENERIC) {
       BatchImage bi;
-      fill_fast_desc(g, gs[0], &bi);
+      fill_fast_desc(g, gs[0], &bi, b->rows_override);
       b->imgs.push_back(bi);
     } else {
       b->separate.push_back(g);
@@ -299,18 +341,20 @@ static hvx_status batch_build(Batch* b) {
     first += b->imgs[i].nitems;
   }
   b->total = first;
-  b->grid = std::max(1, std::min(b->total, c->num_cus * batch_waves_per_cu()));
+  b->kinds = 0;
+  for (const BatchImage& bi : b->imgs) b->kinds |= kind_bit(bi.kind);
+  b->grid = std::max(1, std::min(b->total, c->num_cus * batch_waves_per_cu(b->kinds)));
   if (!b->imgs.empty()) {
     if (hipMalloc((void**)&b->d_imgs, b->imgs.size() * sizeof(BatchImage)) != hipSuccess ||
         hipMalloc((void**)&b->d_item_img, b->item_img.size() * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc((void**)&b->d_counter, 2 * sizeof(unsigned)) != hipSuccess) {
+        hipMalloc((void**)&b->d_counter, batch_counter_bytes()) != hipSuccess) {
       batch_free_device(b);
       return set_error(c, HVX_ERROR_NO_MEMORY, "batch descriptors");
     }
     hipError_t e = hipMemcpy(b->d_imgs, b->imgs.data(), b->imgs.size() * sizeof(BatchImage), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(b->d_item_img, b->item_img.data(), b->item_img.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(b->d_counter, 0, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(b->d_counter, 0, batch_counter_bytes());
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       batch_free_device(b);
@@ -322,7 +366,7 @@ static hvx_status batch_build(Batch* b) {
 
 static hvx_status batch_enqueue(Batch* b, hipStream_t s) {
   if (b->total > 0) {
-    hipError_t e = launch_batch(b->d_imgs, b->d_item_img, b->total, b->d_counter, b->grid, b->persistent, s);
+    hipError_t e = launch_batch(b->d_imgs, b->d_item_img, b->total, b->d_counter, b->grid, b->persistent, b->kinds, s);
     if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "batch launch: %s", hipGetErrorString(e));
   }
   for (Graph* g : b->separate) {
@@ -427,7 +471,87 @@ hvx_status hvx_batch_query(hvx_batch hb, int attr, int64_t* out) {
       break;
     }
     case HVX_QUERY_NUM_OPS: *out = b->total; break;  // work items of the persistent launch
+    case HVX_QUERY_ROWS_PER_ITEM: *out = b->rows_override; break;  // 0: each graph's own
     default: return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown batch query %d", attr);
+  }
+  return HVX_SUCCESS;
+}
+
+// Outputs of the first and last graph of a batch (the tuner's equality check).
+static hvx_status read_outputs(Graph* g, std::vector<std::vector<uint8_t>>* out);
+
+hvx_status hvx_batch_autotune(hvx_batch hb, void* stream, int iters) {
+  if (!registry_check(hb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
+  Batch* b = (Batch*)hb;
+  if (iters < 1) iters = 1;
+  hipStream_t st = (hipStream_t)stream;
+  const bool saved_graph = b->use_graph;
+  b->use_graph = false;  // time plain launches while candidates change
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  std::vector<std::vector<uint8_t>> ref, cur;
+  double best = 1e30;
+  int best_rows = b->rows_override;
+  bool best_persistent = b->persistent;
+  hvx_status s = HVX_SUCCESS;
+  static const int cand_rows[] = {0, 8, 16, 32, 64, 128};
+  for (int rows : cand_rows) {
+    b->rows_override = rows;
+    s = batch_build(b);
+    if (s) break;
+    for (int pers = 0; pers <= 1 && !s; ++pers) {
+      b->persistent = pers != 0;
+      s = batch_enqueue(b, st);
+      if (!s && hipStreamSynchronize(st) != hipSuccess) s = set_error(b->ctx, HVX_ERROR_DEVICE, "tune sync failed");
+      if (s) break;
+      for (Graph* g : {b->graphs.front(), b->graphs.back()}) {
+        std::vector<std::vector<uint8_t>> o;
+        s = read_outputs(g, &o);
+        if (s) break;
+        for (auto& x : o) cur.push_back(std::move(x));
+      }
+      if (s) break;
+      if (ref.empty()) ref.swap(cur);
+      else if (cur != ref) s = set_error(b->ctx, HVX_ERROR_DEVICE, "batch candidate rows=%d changed the output", rows);
+      cur.clear();
+      if (s) break;
+      (void)hipEventRecord(e0, st);
+      for (int i = 0; i < iters && !s; ++i) s = batch_enqueue(b, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms / iters < best) {
+        best = ms / iters;
+        best_rows = rows;
+        best_persistent = b->persistent;
+      }
+    }
+    if (s) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->rows_override = best_rows;
+  b->persistent = best_persistent;
+  b->use_graph = saved_graph;
+  hvx_status s2 = batch_build(b);
+  return s ? s : s2;
+}
+
+hvx_status hvx_batch_set_option(hvx_batch hb, int option, int64_t value) {
+  if (!registry_check(hb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
+  Batch* b = (Batch*)hb;
+  if (b->scheduled) (void)hipStreamSynchronize((hipStream_t)b->last_stream);
+  b->scheduled = false;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->hg) (void)hipGraphDestroy(b->hg);
+  b->exec = nullptr;
+  b->hg = nullptr;
+  switch (option) {
+    case HVX_BATCH_PERSISTENT: b->persistent = value != 0; break;
+    case HVX_BATCH_USE_GRAPH: b->use_graph = value != 0; break;
+    default: return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown batch option %d", option);
   }
   return HVX_SUCCESS;
 }

@@ -137,8 +137,7 @@ struct Server : Object {
 };
 
 static bool batchable(const Graph* g) {
-  return g->plan && g->plan->groups.size() == 1 &&
-         (g->plan->groups[0].kind == FK_EDGE || g->plan->groups[0].kind == FK_GAUSS5);
+  return g->plan && g->plan->groups.size() == 1 && g->plan->groups[0].kind != FK_GENERIC;
 }
 
 static void finish(Server* sv, Request* r, int32_t status, double t) {
@@ -161,6 +160,11 @@ static void request_desc(Request* r, BatchImage* bi) {
     bi->d.e.out = (uint8_t*)r->d_out;
     bi->d.e.out_pitch = (int64_t)r->d_out_pitch;
     bi->d.e.phase = nullptr;
+  } else if (bi->kind == FK_CORNER) {
+    bi->d.c.in = (const uint8_t*)r->d_in;
+    bi->d.c.in_pitch = (int64_t)r->d_in_pitch;
+    bi->d.c.out = (uint8_t*)r->d_out;
+    bi->d.c.out_pitch = (int64_t)r->d_out_pitch;
   } else if (bi->kind == FK_GAUSS5) {
     bi->d.g5.in = (const uint8_t*)r->d_in;
     bi->d.g5.in_pitch = (int64_t)r->d_in_pitch;
@@ -204,7 +208,9 @@ static bool launch_step(Server* sv, StreamSlot& sl, std::vector<Request*>& reqs)
         BatchImage bi;
         request_desc(r, &bi);
         const bool xcd = r->templ->plan->groups[0].xcd != 0;
-        hipError_t e = bi.kind == FK_EDGE ? launch_edge(bi.d.e, xcd, s) : launch_gauss5(bi.d.g5, xcd, s);
+        hipError_t e = bi.kind == FK_EDGE     ? launch_edge(bi.d.e, xcd, s)
+                       : bi.kind == FK_CORNER ? launch_corner(bi.d.c, xcd, s)
+                                              : launch_gauss5(bi.d.g5, xcd, s);
         if (e != hipSuccess) return false;
       }
     }
@@ -227,8 +233,11 @@ static bool launch_step(Server* sv, StreamSlot& sl, std::vector<Request*>& reqs)
       return false;
     if (hipMemcpyAsync(sl.d_items, sl.h_items, nitems * sizeof(uint16_t), hipMemcpyHostToDevice, s) != hipSuccess)
       return false;
-    const int grid = std::max(1, std::min((int)nitems, sv->grid));
-    if (launch_batch(sl.d_imgs, sl.d_items, (int)nitems, sl.d_counter, grid, true, s) != hipSuccess) return false;
+    int kinds = 0;
+    for (const BatchImage& bi : imgs) kinds |= kind_bit(bi.kind);
+    const int grid = std::max(1, std::min((int)nitems, sv->ctx->num_cus * batch_waves_per_cu(kinds)));
+    if (launch_batch(sl.d_imgs, sl.d_items, (int)nitems, sl.d_counter, grid, true, kinds, s) != hipSuccess)
+      return false;
   }
   for (Request* r : live) {
     if (hipMemcpy2DAsync(r->out, r->out_pitch, r->d_out, r->d_out_pitch, r->out_row, r->vout->h,
@@ -370,15 +379,15 @@ hvx_status hvx_server_create(hvx_context ctx, int mode, size_t budget, uint32_t 
     // default priority streams only
     if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc((void**)&sl.d_counter, 2 * sizeof(unsigned)) != hipSuccess ||
-        hipMemset(sl.d_counter, 0, 2 * sizeof(unsigned)) != hipSuccess) {
+        hipMalloc((void**)&sl.d_counter, batch_counter_bytes()) != hipSuccess ||
+        hipMemset(sl.d_counter, 0, batch_counter_bytes()) != hipSuccess) {
       registry_add(sv);
       destroy_server_object(sv);
       return set_error(c, HVX_ERROR_DEVICE, "server stream setup failed");
     }
   }
   (void)hipDeviceSynchronize();
-  sv->grid = c->num_cus * batch_waves_per_cu();
+  sv->grid = c->num_cus * batch_waves_per_cu(7);
   registry_add(sv);
   {
     std::lock_guard<std::recursive_mutex> l(c->mu);

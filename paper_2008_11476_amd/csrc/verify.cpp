@@ -178,6 +178,8 @@ static bool match_corner(const Plan& p, const Group& gr, int* in_v, int* out_v) 
   }
   for (int i = 1; i < 3; ++i)
     if (p.ops[box[i]].border != p.ops[box[0]].border || p.ops[box[i]].bconst != p.ops[box[0]].bconst) return false;
+  // the fast kernel sums exactly in int32: 25 * constant must stay in range
+  if (p.ops[box[0]].border == B_CONSTANT && p.ops[box[0]].bconst > 1040400u) return false;
   // identify gradients
   for (int o : gr.ops) {
     if (p.ops[o].kind == OP_SOBEL_X) sx = o;

@@ -1,0 +1,228 @@
+"""GPU tests of batched execution (one persistent launch over many graphs,
+replayed from a captured HIP graph) and of the serving loop: every result
+must equal the same graph run alone, and the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2008_11476_amd as hvx
+import synth
+from tests import graphspec as gs
+from tests.gpu_util import compare, device_image, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = hvx.hvx_context_create(0)
+    yield c
+    hvx.hvx_context_release(c)
+
+
+def _mixed_specs():
+    rng = np.random.default_rng(7)
+    specs = []
+    kinds = ["edge", "edge_phase", "corner", "gauss5", "uyvy", "generic", "unfused_edge"]
+    for i in range(21):
+        kind = kinds[i % len(kinds)]
+        w = int(rng.integers(1, 2100)) if kind != "uyvy" else 2 * int(rng.integers(1, 1000))
+        h = int(rng.integers(1, 300))
+        if kind == "edge":
+            specs.append((kind, gs.edge_spec(synth.edge_image(w, h, seed=i))))
+        elif kind == "edge_phase":
+            specs.append((kind, gs.edge_spec(synth.edge_image(w, h, seed=i), phase=True,
+                                             b1=("constant", 9))))
+        elif kind == "corner":
+            specs.append((kind, gs.corner_spec(synth.corner_image(w, h, seed=i))))
+        elif kind == "gauss5":
+            specs.append((kind, gs.gauss5_spec(synth.edge_image(w, h, seed=i), ("constant", 3))))
+        elif kind == "uyvy":
+            specs.append((kind, gs.uyvy_gauss5_spec(synth.uyvy_image(w, h, seed=i))))
+        elif kind == "generic":
+            img = synth.edge_image(w, h, seed=i)
+            specs.append((kind, gs.Spec([gs.N("box3x3", ["in"], ["b"]),
+                                         gs.N("add", ["in", "b"], ["out"], params={"policy": "wrap"})],
+                                        {"in": img}, {"out": np.uint8})))
+        else:
+            specs.append((kind, gs.edge_spec(synth.edge_image(w, h, seed=i))))
+    return specs
+
+
+def _build(ctx, spec, fusion=True):
+    """Device images (random padding) + a verified graph; returns graph and
+    {output name: (tensor, width)}."""
+    imgs, keep, outs = {}, [], {}
+    for name, arr in spec.inputs.items():
+        df = hvx.HVX_DF_UYVY if name in spec.uyvy else gs.DF_OF_DTYPE[arr.dtype]
+        im, t = device_image(ctx, arr, df, seed=3)
+        imgs[name] = im
+        keep.append(t)
+        h = arr.shape[0]
+        w = arr.shape[1] // 2 if df == hvx.HVX_DF_UYVY else arr.shape[1]
+    for name, dt in spec.outputs.items():
+        im, t = device_image(ctx, np.zeros((h, w), np.dtype(dt)), gs.DF_OF_DTYPE[np.dtype(dt)], seed=4)
+        imgs[name] = im
+        outs[name] = (t, w)
+    g, _, _ = gs.build_hvx(spec, ctx, imgs)
+    hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, int(fusion))
+    hvx.hvx_graph_verify(g, ctx=ctx)
+    return g, outs, keep, imgs
+
+
+def _read(outs):
+    return {k: t.cpu().numpy()[:, :w] for k, (t, w) in outs.items()}
+
+
+def test_batch_equals_alone_and_oracle(ctx):
+    import torch
+    specs = _mixed_specs()
+    built = []
+    for kind, spec in specs:
+        g, outs, keep, imgs = _build(ctx, spec, fusion=(kind != "unfused_edge"))
+        built.append((kind, spec, g, outs, keep))
+    # alone
+    alone = []
+    for kind, spec, g, outs, keep in built:
+        log("alone %s" % kind)
+        hvx.hvx_graph_process(g, ctx=ctx)
+        alone.append(_read(outs))
+        for t, _ in outs.values():
+            t.fill_(0x5A)
+    torch.cuda.synchronize()
+    b = hvx.hvx_batch_create(ctx, [x[2] for x in built])
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) >= 2  # persistent launch + separate graphs
+    stream = torch.cuda.current_stream().cuda_stream
+    for rep in range(3):  # capture, then replays with eager work in between
+        log("batch replay %d" % rep)
+        hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+        torch.cuda.synchronize()
+        for (kind, spec, g, outs, keep), ref in zip(built, alone):
+            got = _read(outs)
+            for name in got:
+                assert np.array_equal(got[name], ref[name]), (kind, name, rep)
+            for t, _ in outs.values():
+                t.fill_(rep)
+        torch.cuda.synchronize()
+    # against the oracle too
+    for (kind, spec, g, outs, keep), ref in zip(built, alone):
+        env = spec.run_oracle()
+        compare(spec, ref, env, phase_names=("ph",), corner=(kind == "corner"))
+    hvx.hvx_release_batch(b)
+
+
+def test_batch_refresh_after_swap(ctx):
+    import torch
+    w, h = 1500, 90
+    a = synth.edge_image(w, h, seed=1)
+    bimg = synth.edge_image(w, h, seed=2)
+    spec = gs.edge_spec(a, phase=True)
+    g, outs, keep, imgs = _build(ctx, spec)
+    other, t2 = device_image(ctx, bimg, hvx.HVX_DF_U8, seed=9)
+    b = hvx.hvx_batch_create(ctx, [g])
+    stream = torch.cuda.current_stream().cuda_stream
+    hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+    torch.cuda.synchronize()
+    compare(spec, _read(outs), spec.run_oracle(), phase_names=("ph",))
+    hvx.hvx_image_swap_ptr(imgs["in"], t2.data_ptr(), t2.stride(0), ctx=ctx)
+    hvx.hvx_batch_refresh(b, ctx=ctx)
+    hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+    torch.cuda.synchronize()
+    spec2 = gs.edge_spec(bimg, phase=True)
+    compare(spec2, _read(outs), spec2.run_oracle(), phase_names=("ph",))
+    hvx.hvx_release_batch(b)
+    # the one-shot form
+    hvx.hvx_process_batch(ctx, [g], stream)
+    compare(spec2, _read(outs), spec2.run_oracle(), phase_names=("ph",))
+
+
+def _templates(ctx, sizes):
+    """Verified templates for the three served kinds at each size."""
+    out = {}
+    keep = []
+    for (w, h) in sizes:
+        for kind in ("sobel_edge", "harris", "uyvy_gauss5"):
+            if kind == "uyvy_gauss5":
+                spec = gs.uyvy_gauss5_spec(synth.uyvy_image(w, h, seed=w))
+            elif kind == "harris":
+                spec = gs.corner_spec(synth.corner_image(w, h, seed=w))
+            else:
+                spec = gs.edge_spec(synth.edge_image(w, h, seed=w))
+            g, outs, k, imgs = _build(ctx, spec)
+            keep.append((outs, k))
+            out[(kind, w, h)] = g
+    return out, keep
+
+
+def _host_frames(kind, w, h, seed):
+    if kind == "uyvy_gauss5":
+        f = synth.uyvy_image(w, h, seed=seed)
+        spec = gs.uyvy_gauss5_spec(f)
+    elif kind == "harris":
+        f = synth.corner_image(w, h, seed=seed)
+        spec = gs.corner_spec(f)
+    else:
+        f = synth.edge_image(w, h, seed=seed)
+        spec = gs.edge_spec(f)
+    return f, spec
+
+
+@pytest.mark.parametrize("mode", [hvx.HVX_SERVER_CONTINUOUS, hvx.HVX_SERVER_PLAIN])
+def test_server_results_alone_equals_mix(ctx, mode):
+    import torch
+    sizes = [(64, 48), (322, 101), (640, 480)]
+    templ, keep = _templates(ctx, sizes)
+    budget = 3 << 20  # binds: a 640x480 request needs ~0.6 MB
+    s = hvx.hvx_server_create(ctx, mode, budget, 4, 2)
+    reqs = {}
+    rng = np.random.default_rng(3)
+    for tag in range(36):
+        kind = ("sobel_edge", "harris", "uyvy_gauss5")[tag % 3]
+        w, h = sizes[int(rng.integers(0, len(sizes)))]
+        f, spec = _host_frames(kind, w, h, seed=100 + tag)
+        src = torch.from_numpy(np.ascontiguousarray(f)).pin_memory()
+        dst = torch.full((h, w), 7, dtype=torch.uint8).pin_memory()
+        reqs[tag] = (kind, spec, src, dst)
+        if tag == 13:
+            hvx.hvx_server_inject_failure(s, tag)
+        log("submit %d %s %dx%d" % (tag, kind, w, h))
+        hvx.hvx_server_submit(s, templ[(kind, w, h)], src.data_ptr(), src.stride(0), dst.data_ptr(),
+                              dst.stride(0), tag, ctx=ctx)
+        if tag % 5 == 0:
+            time.sleep(0.002)
+    hvx.hvx_server_drain(s, ctx=ctx)
+    done = hvx.hvx_server_poll(s, 1000, ctx=ctx)
+    assert sorted(t for t, _, _ in done) == list(range(36))
+    assert hvx.hvx_server_stats(s, 2) <= budget  # peak device bytes
+    assert hvx.hvx_server_stats(s, 5) == 0  # everything released
+    for tag, st, lat in done:
+        kind, spec, src, dst = reqs[tag]
+        if tag == 13:
+            assert st == hvx.HVX_ERROR_DEVICE
+            continue
+        assert st == 0 and lat > 0
+        env = spec.run_oracle()
+        compare(spec, {"out": dst.numpy()}, env, corner=(kind == "harris"))
+    if mode == hvx.HVX_SERVER_CONTINUOUS:
+        assert hvx.hvx_server_stats(s, 4) <= 36  # requests were packed into shared device steps
+    hvx.hvx_release_server(s)
+
+
+def test_server_limits(ctx):
+    with pytest.raises(hvx.HvxError) as e:
+        hvx.hvx_server_create(ctx, hvx.HVX_SERVER_CONTINUOUS, 0, 4, 2)
+    assert e.value.status == hvx.HVX_ERROR_NO_MEMORY
+    templ, keep = _templates(ctx, [(640, 480)])
+    s = hvx.hvx_server_create(ctx, hvx.HVX_SERVER_CONTINUOUS, 1 << 16, 4, 2)
+    import torch
+    src = torch.zeros((480, 640), dtype=torch.uint8).pin_memory()
+    dst = torch.zeros((480, 640), dtype=torch.uint8).pin_memory()
+    with pytest.raises(hvx.HvxError) as e:
+        hvx.hvx_server_submit(s, templ[("sobel_edge", 640, 480)], src.data_ptr(), 640, dst.data_ptr(), 640, 1,
+                              ctx=ctx)
+    assert e.value.status == hvx.HVX_ERROR_NO_MEMORY
+    hvx.hvx_release_server(s)
