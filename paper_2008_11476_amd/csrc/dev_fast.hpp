@@ -2,10 +2,11 @@
 //
 // Work decomposition: one wave (64 lanes) owns a vertical strip of the image
 // and a band of output rows.  Lane l covers 16 consecutive pixels starting at
-// x = strip * 992 + 16 * (l - 1); lanes 1..62 produce output, lanes 0 and 63
-// only supply halo pixels to their neighbours.  The wave streams its band top
-// to bottom, keeping the few rows each stencil needs in registers, so every
-// input byte is read from HBM once and every intermediate stays in VGPRs.
+// x = strip * 960 + 16 * (l - 1); lanes 1..60 produce output, lanes 0 and 61
+// only supply halo pixels to their neighbours (lanes 62 and 63 idle).  The
+// wave streams its band top to bottom, keeping the few rows each stencil
+// needs in registers, so every input byte is read from HBM once and every
+// intermediate stays in VGPRs.
 //
 // Pixel layout in registers: the 16 pixels of a lane are held as 8 packed
 // 16-bit pairs, P[k] = (pixel k) | (pixel k+8) << 16.  With this layout the
@@ -97,7 +98,7 @@ __device__ __forceinline__ Lanes make_lanes(const StripGrid& g, int strip) {
   L.xs = strip * kStripPx + (L.lane - 1) * kLanePx;
   const int wr = (g.w + 15) & ~15;
   L.xl = min(max(L.xs, 0), wr - 16);
-  L.store = L.lane >= 1 && L.lane <= 62 && L.xs >= 0 && L.xs < g.w;
+  L.store = L.lane >= 1 && L.lane <= kOutLanes && L.xs >= 0 && L.xs < g.w;
   L.m = g.w & 15;
   L.mL = L.xs == 0 ? 0x0000FFFFu : 0u;
   L.mR = (L.m == 0 && L.xs + 16 == g.w) ? 0xFFFF0000u : 0u;
@@ -208,7 +209,9 @@ __device__ __forceinline__ int phase_level(int gx, int gy) {
 // Sobel/magnitude/threshold row y.  All (1 2 1) sums are formed from pairwise
 // sums shared between neighbouring rows or pixels (a + 2b + c = (a+b) + (b+c)).
 // The loop is unrolled by six so that every rotating row buffer (periods two
-// and three) is renamed statically, and input rows are loaded two rows ahead.
+// and three) is renamed statically, and each input row is loaded one row
+// ahead (deeper prefetch measured no faster and costs the registers that
+// hold a fourth wave per SIMD).
 template <bool PHASE, bool HEDGE>
 struct EdgeStream {
   const EdgeDesc& d;
@@ -224,7 +227,7 @@ struct EdgeStream {
   u32 tr[2][8];   // in(y) + in(y+1)
   u32 gr[3][8];   // Gaussian rows y-1, y, y+1
   u32 sr[2][8];   // G(y-1) + G(y)
-  u32x4 raw[3];   // prefetched input rows
+  u32x4 raw[2];   // input rows y+2 (in use) and y+3 (in flight)
 
   __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip) : d(d_) {
     L = make_lanes(d.g, strip);
@@ -293,16 +296,20 @@ struct EdgeStream {
       }
       if (L.store) __builtin_nontemporal_store(po, (u32x4*)(phb + (size_t)y * d.phase_pitch));
     }
-    // magnitude + threshold as one integer test: gx^2 + gy^2 > T
+    // magnitude + threshold as one integer test: gx^2 + gy^2 > T, i.e. the
+    // sign of gx^2 + gy^2 + thr_not.  v_mad_i32_i16 multiplies the selected
+    // signed 16-bit halves of its sources into a 32-bit sum (op_sel picks
+    // the high halves), so each pixel takes two instructions and no repacking.
     u32 r[16];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const u32 lo = perm(gy[k], gx[k], 0x05040100u);  // (gx_k, gy_k)
-      const u32 hi = perm(gy[k], gx[k], 0x07060302u);  // (gx_k+8, gy_k+8)
-      r[k] = (u32)__builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, lo), __builtin_bit_cast(s16x2, lo), d.thr_not,
-                                         false);
-      r[k + 8] = (u32)__builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, hi), __builtin_bit_cast(s16x2, hi),
-                                             d.thr_not, false);
+      int t0, t1, r0, r1;
+      asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(t0) : "v"(gx[k]), "s"(d.thr_not));
+      asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(r0) : "v"(gy[k]), "v"(t0));
+      asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(t1) : "v"(gx[k]), "s"(d.thr_not));
+      asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(r1) : "v"(gy[k]), "v"(t1));
+      r[k] = (u32)r0;
+      r[k + 8] = (u32)r1;
     }
     u32x4 o;
     // mask bytes are 0xFF where the sum is below the bound (no edge);
@@ -326,8 +333,8 @@ struct EdgeStream {
     u32(&g1)[8] = gr[(J + 2) % 3];
     u32(&s0)[8] = sr[J % 2];
     u32(&s1)[8] = sr[(J + 1) % 2];
-    const u32x4 cur = raw[J % 3];
-    raw[(J + 2) % 3] = load(y + 4);  // two rows ahead
+    const u32x4 cur = raw[J % 2];
+    raw[(J + 1) % 2] = load(y + 3);  // one row ahead
     if (y + 1 < H) {
       unpk(cur, y + 2, in2);
       u32 v[8];
@@ -359,7 +366,6 @@ struct EdgeStream {
     unpk(load(y0), y0, c);
     unpk(load(y0 + 1), y0 + 1, e);
     raw[0] = load(y0 + 2);
-    raw[1] = load(y0 + 3);
     u32 v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = add2(add2(b[k], c[k]), add2(c[k], e[k]));

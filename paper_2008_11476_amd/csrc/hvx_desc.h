@@ -84,10 +84,13 @@ struct IOTable {
 
 // ---- fast fused kernels -------------------------------------------------------
 // Work decomposition shared by the register-streaming kernels: a wave owns a
-// vertical strip of 62 * 16 output columns (plus one halo lane on each side)
-// and a band of `rows` output rows, streamed top to bottom.
+// vertical strip of 60 * 16 output columns (plus one halo lane on each side)
+// and a band of `rows` output rows, streamed top to bottom.  960 columns keep
+// every strip's rows 64-byte aligned; misaligned 992-column strips streamed
+// about 15% slower on the HBM.
 constexpr int kLanePx = 16;
-constexpr int kStripPx = 62 * kLanePx;
+constexpr int kOutLanes = 60;
+constexpr int kStripPx = kOutLanes * kLanePx;
 
 struct StripGrid {
   int32_t w, h;

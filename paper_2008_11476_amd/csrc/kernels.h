@@ -17,7 +17,7 @@ hipError_t launch_gauss5(const Gauss5Desc& d, bool xcd, hipStream_t s);
 hipError_t launch_batch(const BatchImage* imgs, const uint16_t* item_img, int total, unsigned* counter, int grid,
                         bool persistent, int kinds, hipStream_t s);
 int batch_waves_per_cu(int kinds);
-int kind_bit(int kind);
+int kind_bit(const BatchImage& bi);
 // bytes of the zero-initialised counter block the persistent batch kernel needs
 size_t batch_counter_bytes();
 

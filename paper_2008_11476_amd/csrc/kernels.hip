@@ -52,15 +52,15 @@ __global__ __launch_bounds__(64) void k_gauss5(const Gauss5Desc d, int xcd) {
 // group's counters, so the next launch (or graph replay) starts from zero.
 constexpr int kCtrStride = 32;  // counters 128 bytes apart
 
-// KS: the set of kinds a batch holds (bit 1 edge, 2 corner, 4 Gaussian5x5);
-// only those bodies are compiled into the batch kernel, so a batch of one
-// kind keeps that kind's register budget and occupancy.
+// KS: the set of kinds a batch holds (bit 1 edge, 2 corner, 4 Gaussian5x5,
+// 8 edge with phase); only those bodies are compiled into the batch kernel,
+// so a batch of one kind keeps that kind's register budget and occupancy.
 template <int KS>
 __device__ __forceinline__ void run_item(const BatchImage& bi, int local) {
-  if ((KS & 1) && bi.kind == FK_EDGE) {
+  if ((KS & 9) && bi.kind == FK_EDGE) {
     const EdgeDesc& d = bi.d.e;
-    if (d.phase) edge_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
-    else edge_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
+    if ((KS & 8) && d.phase) edge_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
+    else if (KS & 1) edge_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
   } else if ((KS & 2) && bi.kind == FK_CORNER) {
     const CornerDesc& d = bi.d.c;
     corner_item(d, local % d.g.nstrips, local / d.g.nstrips);
@@ -169,12 +169,21 @@ hipError_t launch_batch(const BatchImage* imgs, const uint16_t* item_img, int to
     case 1: launch_batch_ks<1>(imgs, item_img, total, counter, grid, persistent, s); break;
     case 2: launch_batch_ks<2>(imgs, item_img, total, counter, grid, persistent, s); break;
     case 4: launch_batch_ks<4>(imgs, item_img, total, counter, grid, persistent, s); break;
-    default: launch_batch_ks<7>(imgs, item_img, total, counter, grid, persistent, s); break;
+    case 8: launch_batch_ks<8>(imgs, item_img, total, counter, grid, persistent, s); break;
+    case 7: launch_batch_ks<7>(imgs, item_img, total, counter, grid, persistent, s); break;
+    default: launch_batch_ks<15>(imgs, item_img, total, counter, grid, persistent, s); break;
   }
   return hipGetLastError();
 }
 
-int kind_bit(int kind) { return kind == FK_EDGE ? 1 : kind == FK_CORNER ? 2 : kind == FK_GAUSS5 ? 4 : 0; }
+int kind_bit(const BatchImage& bi) {
+  switch (bi.kind) {
+    case FK_EDGE: return bi.d.e.phase ? 8 : 1;
+    case FK_CORNER: return 2;
+    case FK_GAUSS5: return 4;
+    default: return 0;
+  }
+}
 
 size_t batch_counter_bytes() { return 16 * kCtrStride * sizeof(unsigned); }
 
@@ -185,7 +194,9 @@ int batch_waves_per_cu(int kinds) {
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<1>, 64, 0); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<2>, 64, 0); break;
     case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<4>, 64, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<7>, 64, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<8>, 64, 0); break;
+    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<7>, 64, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<15>, 64, 0); break;
   }
   if (e != hipSuccess || blocks <= 0) blocks = 8;
   return blocks;

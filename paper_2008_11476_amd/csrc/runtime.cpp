@@ -342,7 +342,7 @@ static hvx_status batch_build(Batch* b) {
   }
   b->total = first;
   b->kinds = 0;
-  for (const BatchImage& bi : b->imgs) b->kinds |= kind_bit(bi.kind);
+  for (const BatchImage& bi : b->imgs) b->kinds |= kind_bit(bi);
   b->grid = std::max(1, std::min(b->total, c->num_cus * batch_waves_per_cu(b->kinds)));
   if (!b->imgs.empty()) {
     if (hipMalloc((void**)&b->d_imgs, b->imgs.size() * sizeof(BatchImage)) != hipSuccess ||

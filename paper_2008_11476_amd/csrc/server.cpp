@@ -234,7 +234,7 @@ static bool launch_step(Server* sv, StreamSlot& sl, std::vector<Request*>& reqs)
     if (hipMemcpyAsync(sl.d_items, sl.h_items, nitems * sizeof(uint16_t), hipMemcpyHostToDevice, s) != hipSuccess)
       return false;
     int kinds = 0;
-    for (const BatchImage& bi : imgs) kinds |= kind_bit(bi.kind);
+    for (const BatchImage& bi : imgs) kinds |= kind_bit(bi);
     const int grid = std::max(1, std::min((int)nitems, sv->ctx->num_cus * batch_waves_per_cu(kinds)));
     if (launch_batch(sl.d_imgs, sl.d_items, (int)nitems, sl.d_counter, grid, true, kinds, s) != hipSuccess)
       return false;
