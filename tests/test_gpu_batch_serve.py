@@ -78,7 +78,8 @@ def _read(outs):
     return {k: t.cpu().numpy()[:, :w] for k, (t, w) in outs.items()}
 
 
-def test_batch_equals_alone_and_oracle(ctx):
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_batch_equals_alone_and_oracle(ctx, persistent):
     import torch
     specs = _mixed_specs()
     built = []
@@ -95,6 +96,7 @@ def test_batch_equals_alone_and_oracle(ctx):
             t.fill_(0x5A)
     torch.cuda.synchronize()
     b = hvx.hvx_batch_create(ctx, [x[2] for x in built])
+    hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, persistent)
     assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) >= 2  # persistent launch + separate graphs
     stream = torch.cuda.current_stream().cuda_stream
     for rep in range(3):  # capture, then replays with eager work in between
