@@ -1,15 +1,17 @@
-"""Benchmark: the fused OpenVX-style edge graph on 4K frames, one MI355X.
+"""Benchmark: the fused OpenVX-style Sobel-edge graph with its Phase branch on
+4K frames, one MI355X.
 
-One step = one execution of the verified edge graph (Gaussian3x3 -> Sobel3x3
--> Magnitude -> Threshold at 100, REPLICATE borders) over a batch of F
-distinct 3840x2160 U8 frames resident in HBM (>= 1 GiB of distinct buffers,
-so the 256 MB last-level cache cannot serve them), issued as one persistent
-batch launch replayed from a captured HIP graph.  value = MPix/s of the whole
-job.  The JSON line also reports the roofline of that kernel, the CPU oracle
-on a bounded sample, and context measurements under "extras": single-frame
-latency, the +Phase graph at 4K and 8K, CONSTANT(0) borders, node-by-node
-(unfused) execution, the corner graph at 1080p, the 256-image mixed batch and
-the serving loop against plain per-request execution.
+One step = one execution of the verified graph Gaussian3x3 -> Sobel3x3 ->
+{Magnitude -> Threshold at 100, Phase} (REPLICATE borders; two U8 outputs)
+over F distinct 3840x2160 U8 frames resident in HBM (3 B/px, >= 1.5 GB of
+distinct buffers, so the 256 MB last-level cache cannot serve them), issued
+as one batch launch replayed from a captured HIP graph.  value = MPix/s of
+the whole job.  The JSON line also reports the roofline of that kernel, the
+CPU oracle on a bounded sample, and context measurements under "extras": the
+same graph without Phase (2 B/px), 8K frames, CONSTANT(0) borders,
+single-frame latency, node-by-node (unfused) execution, the corner graph at
+1080p, the 256-image mixed batch and the serving loop against plain
+per-request execution.
 """
 from __future__ import annotations
 
@@ -36,7 +38,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "dev_fast.hpp", "dev_generic.hpp", "hvx_desc.h"):
+    for f in ("kernels.hip", "dev_fast.hpp", "dev_generic.hpp", "dev_phase.hpp", "hvx_desc.h"):
         with open(os.path.join(ROOT, "paper_2008_11476_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -169,36 +171,38 @@ def extras(hvx, torch, ctx, quick=False):
         res[name] = d
         log(name, json.dumps(d))
 
+    # the same graph without the Phase branch (2 B/px), 64 4K frames
+    r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 20, 3)
+    rec("edge_4k_batch64", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
+                            "hbm_frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "ms": round(r["ms"], 4),
+                            "rows": r["rows"], "batch_mode_ms": r["per_mode"]})
     # single 4K frame, one launch per frame (latency view)
     inp, out = make_frames(hvx, torch, 3840, 2160, 1, n_out=2)
-    g = edge_graph(hvx, ctx, inp[0][1], out[0])
+    g = edge_graph(hvx, ctx, inp[0][1], out[0], phase=True)
     hvx.hvx_graph_autotune(g, stream, 5, ctx=ctx)
     ms, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(g, stream, ctx=ctx), 50, 5)
-    rec("edge_4k_single_frame", {"us_per_frame": round(ms * 1e3, 2), "mpix_s": round(8.2944 / (ms / 1e3), 1),
+    rec("edge_phase_4k_single_frame", {"us_per_frame": round(ms * 1e3, 2), "mpix_s": round(8.2944 / (ms / 1e3), 1),
                                  "rows_per_item": hvx.hvx_graph_query(g, hvx.HVX_QUERY_ROWS_PER_ITEM)})
-    # node by node (fusion off): five kernels, intermediates in HBM
-    gu = edge_graph(hvx, ctx, inp[0][1], out[0], fusion=False)
+    # node by node (fusion off): six kernels, intermediates in HBM
+    gu = edge_graph(hvx, ctx, inp[0][1], out[0], phase=True, fusion=False)
     ms_u, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(gu, stream, ctx=ctx), 20, 3)
     hbm_u = hvx.hvx_graph_query(gu, hvx.HVX_QUERY_HBM_BYTES)
-    rec("edge_4k_unfused", {"us_per_frame": round(ms_u * 1e3, 2), "mpix_s": round(8.2944 / (ms_u / 1e3), 1),
+    rec("edge_phase_4k_unfused", {"us_per_frame": round(ms_u * 1e3, 2), "mpix_s": round(8.2944 / (ms_u / 1e3), 1),
                             "kernels": hvx.hvx_graph_query(gu, hvx.HVX_QUERY_NUM_KERNELS),
                             "hbm_bytes_per_frame": hbm_u, "gbs": round(hbm_u / (ms_u / 1e3) / 1e9, 1),
                             "fused_speedup_single_frame": round(ms_u / ms, 2)})
     for x in (g, gu):
         hvx.hvx_release_graph(x)
     del inp, out
-    # +Phase at 4K and 8K, CONSTANT(0) borders
-    r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 10, 2, phase=True)
-    rec("edge_phase_4k_batch64", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
-                                  "ms": round(r["ms"], 3), "rows": r["rows"], "batch_mode_ms": r["per_mode"]})
+    # 8K frames, CONSTANT(0) borders
     r = edge_batch(hvx, torch, ctx, 7680, 4320, 16, 10, 2, phase=True)
     rec("edge_phase_8k_batch16", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
                                   "ms": round(r["ms"], 3), "rows": r["rows"], "batch_mode_ms": r["per_mode"]})
     r = edge_batch(hvx, torch, ctx, 7680, 4320, 16, 10, 2)
     rec("edge_8k_batch16", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
                             "ms": round(r["ms"], 3), "rows": r["rows"], "batch_mode_ms": r["per_mode"]})
-    r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 10, 2, border=(hvx.HVX_BORDER_CONSTANT, 0))
-    rec("edge_4k_constant0_batch64", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
+    r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 10, 2, phase=True, border=(hvx.HVX_BORDER_CONSTANT, 0))
+    rec("edge_phase_4k_constant0_batch64", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
                                       "ms": round(r["ms"], 3)})
     # corner graph at 1080p: single frame and 32-frame batch
     inp, out = make_frames(hvx, torch, 1920, 1080, 32)
@@ -412,21 +416,21 @@ def main():
     W, H = 3840, 2160
     copy_ref = copy_calibration(torch)
     log("plain device copy:", copy_ref)
-    log("edge graph: %d x %dx%d frames per step, %d steps" % (args.frames, W, H, args.steps))
-    r = edge_batch(hvx, torch, ctx, W, H, args.frames, args.steps, args.warmup)
+    log("edge+phase graph: %d x %dx%d frames per step, %d steps" % (args.frames, W, H, args.steps))
+    r = edge_batch(hvx, torch, ctx, W, H, args.frames, args.steps, args.warmup, phase=True)
     ms = r["ms"]
-    kernel = "hvx::k_batch_direct<1>" if r["mode"] == "direct" else "hvx::k_batch<1>"
+    kernel = "hvx::k_batch_direct<8>" if r["mode"] == "direct" else "hvx::k_batch<8>"
     # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter
     # summary, used only while it matches the kernel sources and launch shape
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "edge_4k_batch_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", "edge_phase_4k_batch_traffic.json")
     if os.path.exists(tfile):
         t = json.load(open(tfile))
         if (t.get("kernel_hash") == kernel_source_hash() and t.get("kernel") == kernel
                 and t.get("rows_per_item") == r["per_mode"]["rows_per_item"]):
             traffic = t.get("bytes_per_launch")
     out = {
-        "metric": "fused-graph MPix/s (4K Sobel-edge) + % HBM peak; served p50/p99 vs plain",
+        "metric": "fused-graph MPix/s + % HBM peak (4K Sobel); served p50/p99 latency vs plain",
         "value": round(r["mpix_s"], 1),
         "unit": "MPix/s",
         "n_gpus": 1,
@@ -438,8 +442,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic (seeded uniform U8 + 8 filled rectangles)",
-        "config": {"workload": "sobel_edge_4k_batch", "graph": "Gaussian3x3->Sobel3x3->Magnitude->Threshold(100)",
-                   "border": "replicate", "width": W, "height": H, "frames_per_step": args.frames,
+        "config": {"workload": "sobel_edge_phase_4k_batch64",
+                   "graph": "Gaussian3x3->Sobel3x3->{Magnitude->Threshold(100), Phase}",
+                   "border": "replicate", "outputs": "edge map U8 + phase U8", "width": W, "height": H, "frames_per_step": args.frames,
                    "rows_per_item": r["per_mode"]["rows_per_item"],
                    "launch": "%s batch kernel, HIP-graph replay" % r["mode"],
                    "batch_mode_ms": r["per_mode"]},
@@ -449,7 +454,7 @@ def main():
                      "alg_bytes_per_launch": r["alg_bytes"],
                      "avg_launch_ms": round(ms, 4), "plain_copy_gbs": copy_ref["gbs"]},
     }
-    log("headline: %.1f MPix/s, %.1f GB/s (%.1f%% of peak), %.3f ms/step, host %.3f ms/step" % (
+    log("headline (edge+phase): %.1f MPix/s, %.1f GB/s (%.1f%% of peak), %.3f ms/step, host %.3f ms/step" % (
         r["mpix_s"], r["gbs"], 100 * r["gbs"] / HBM_PEAK_GBS, ms, r["ms_host"]))
     if not args.no_extras:
         try:

@@ -143,6 +143,8 @@ hvx_status hvx_convolution_create(hvx_context ctx, uint32_t cols, uint32_t rows,
 
 /* ---- graph and nodes ---------------------------------------------------- */
 
+/* An empty graph in `ctx` (the graph object of Section 3.1).
+ * INVALID_REFERENCE for a bad context, INVALID_PARAMETERS for a NULL out. */
 hvx_status hvx_graph_create(hvx_context ctx, hvx_graph* out);
 
 /* Node constructors.  Each adds one OpenVX function node to the graph and
@@ -155,7 +157,8 @@ hvx_status hvx_graph_create(hvx_context ctx, hvx_graph* out);
  *  box5x5_f32       F32 -> F32: unnormalised 5x5 window sum.
  *  sobel3x3         U8 -> S16 gx (right minus left), S16 gy (bottom minus top),
  *                   (1 2 1) smoothing across; either output may be NULL.
- *  magnitude        S16,S16 -> S16: sqrt(gx^2+gy^2) rounded to nearest, saturated.
+ *  magnitude        S16,S16 -> S16: sqrt(gx^2+gy^2) rounded half up (no ties occur
+ *                   for integer sums), saturated to 32767.
  *  phase            S16,S16 -> U8: atan2(gy,gx) in [0,2pi) scaled to 256 levels,
  *                   rounded, modulo 256 (within 1 level of the exact value).
  *  add              U8/S16 -> U8/S16 with HVX_POLICY_SATURATE or _WRAP.
@@ -187,6 +190,9 @@ hvx_status hvx_convolve_node(hvx_graph g, hvx_image in, hvx_convolution conv, hv
  * value is read as the input's element type (0..255 for U8). */
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value);
 
+/* Set one HVX_OPT_* option (the optimisations of Section 5.2 can be turned
+ * off one by one); the graph is un-verified.  INVALID_PARAMETERS for an
+ * unknown option or a negative tile. */
 hvx_status hvx_graph_set_option(hvx_graph g, int option, int64_t value);
 
 /* Verify and plan: checks (parameters, formats, sizes, single writer per
@@ -201,6 +207,8 @@ hvx_status hvx_graph_process(hvx_graph g);
 hvx_status hvx_graph_schedule(hvx_graph g, void* hip_stream);
 /* Wait for the work last scheduled for this graph. */
 hvx_status hvx_graph_wait(hvx_graph g);
+/* Read one HVX_QUERY_* value of the verified plan.  NOT_VERIFIED before
+ * verification, INVALID_PARAMETERS for an unknown attribute. */
 hvx_status hvx_graph_query(hvx_graph g, int attr, int64_t* out);
 
 /* Time candidate launch configurations of the verified graph on the device
@@ -213,11 +221,14 @@ hvx_status hvx_context_load_tune_cache(hvx_context ctx, const char* path);
 
 /* ---- batches: many verified graphs in one persistent launch ------------- */
 
-/* Build a batch over n verified graphs (any mix of kinds and sizes).  Work
- * items of all graphs go into one work list consumed by one persistent
- * kernel through an atomic counter; the launch is captured once into a HIP
- * graph and replayed.  Graphs keep their image pointers as of this call or
- * of the last hvx_batch_refresh. */
+/* Build a batch over n verified graphs (any mix of kinds and sizes).  The
+ * work items of every graph whose plan is one hand-fused kernel go into one
+ * flat work list run by a single launch (see HVX_BATCH_PERSISTENT); other
+ * graphs are launched after it with their own plans.  The launches are
+ * captured once into a HIP graph and replayed.  Graphs keep their image
+ * pointers as of this call or of the last hvx_batch_refresh.  Graphs not yet
+ * verified are verified here (their verification status on failure);
+ * NOT_SUPPORTED above 65535 single-launch graphs. */
 hvx_status hvx_batch_create(hvx_context ctx, const hvx_graph* graphs, uint32_t n, hvx_batch* out);
 /* Re-read the graphs' image pointers (after hvx_image_swap_ptr). */
 hvx_status hvx_batch_refresh(hvx_batch b);
@@ -225,7 +236,10 @@ hvx_status hvx_batch_refresh(hvx_batch b);
 hvx_status hvx_batch_schedule(hvx_batch b, void* hip_stream);
 /* One-shot form: create, schedule, and release once the stream is done. */
 hvx_status hvx_process_batch(hvx_context ctx, const hvx_graph* graphs, uint32_t n, void* hip_stream);
-hvx_status hvx_batch_query(hvx_batch b, int attr, int64_t* out); /* HVX_QUERY_ALG_BYTES, _NUM_KERNELS */
+/* HVX_QUERY_ALG_BYTES (bytes one schedule must move), _NUM_KERNELS (launches
+ * per schedule), _NUM_OPS (work items of the single launch), _ROWS_PER_ITEM
+ * (rows per work item chosen for the batch, 0 = each graph's own). */
+hvx_status hvx_batch_query(hvx_batch b, int attr, int64_t* out);
 /* Batch options.  HVX_BATCH_PERSISTENT (default 1): a grid sized to the
  * machine pulls chunks of work items from per-XCD atomic counters; 0: one
  * wave per work item.  HVX_BATCH_USE_GRAPH (default 1): capture the launches
@@ -269,6 +283,13 @@ hvx_status hvx_server_inject_failure(hvx_server s, uint64_t tag);
 
 /* ---- release ------------------------------------------------------------ */
 
+/* Each release invalidates the handle and sets *ref = NULL (explicit
+ * release, Section 3.1).  A graph waits for its scheduled work first, a
+ * batch for its last launch, a server drains its requests.  An image or
+ * convolution still wired into a node of a live graph stays alive until that
+ * graph (or the context) is released; a node's handle can be dropped at any
+ * time, the node itself lives as long as its graph.  INVALID_PARAMETERS for a
+ * NULL ref, INVALID_REFERENCE for a handle already released. */
 hvx_status hvx_release_graph(hvx_graph* g);
 hvx_status hvx_release_image(hvx_image* img);
 hvx_status hvx_release_node(hvx_node* node);

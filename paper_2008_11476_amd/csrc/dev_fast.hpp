@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dev_phase.hpp"
 #include "hvx_desc.h"
 
 namespace hvx {
@@ -187,24 +188,6 @@ __device__ __forceinline__ void extend(u32 p[8], Ext& e, const Lanes& L, bool re
 
 // ---- Gaussian 3x3 -> Sobel 3x3 -> Magnitude -> Threshold (+ Phase) ----------
 
-// Phase in 1/256 turns from an octant reduction and the arctangent
-// approximation atan(z) ~ (pi/4) z + 0.273 z (1 - z) on [0, 1]
-// (S. Rajan, S. Wang, R. Inkol, A. Joyal, "Efficient approximations for the
-// arctangent function", IEEE Signal Processing Magazine 23(3), 2006), whose
-// error is below 0.004 rad (0.16 of one level), so the rounded result is
-// within one level of the rounded exact angle.
-__device__ __forceinline__ int phase_level(int gx, int gy) {
-  const float kA = 0.273f * 128.0f / 3.14159265358979f;
-  float ax = fabsf((float)gx), ay = fabsf((float)gy);
-  float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
-  float z = mn * __builtin_amdgcn_rcpf(fmaxf(mx, 1.0f));
-  float a = z * fmaf(-kA, z, 32.0f + kA);
-  float t = ay > ax ? 64.0f - a : a;
-  t = gx < 0 ? 128.0f - t : t;
-  t = gy < 0 ? 256.0f - t : t;
-  return ((int)(t + 0.5f)) & 255;
-}
-
 // One wave streams its band: at output row y it finishes Gaussian row y+1 and
 // Sobel/magnitude/threshold row y.  All (1 2 1) sums are formed from pairwise
 // sums shared between neighbouring rows or pixels (a + 2b + c = (a+b) + (b+c)).
@@ -216,7 +199,7 @@ template <bool PHASE, bool HEDGE>
 struct EdgeStream {
   const EdgeDesc& d;
   Lanes L;
-  int H, y1;
+  int H;
   bool repl0, repl1;
   u32 cin, cv0, cg, cs1;
   const uint8_t* inb;
@@ -277,23 +260,18 @@ struct EdgeStream {
       gy[k] = add2(eu[k], eu[k + 1]);
     }
     if (PHASE) {
-      // four output bytes at a time (pixels 4j..4j+3), with scheduling
-      // barriers so that only one group's temporaries are live at once
+      // levels of pixels k and k+8 in the low bytes of lv[k]'s halves; output
+      // word j holds pixels 4j .. 4j+3
+      u32 lv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lv[k] = phase_pair(gx[k], gy[k]);
       u32x4 po;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        u32 word = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int k = (j & 1) * 4 + i;  // register
-          const bool hi = j >= 2;         // half
-          const int a = hi ? ((int)gx[k]) >> 16 : (int)(short)(gx[k] & 0xFFFF);
-          const int b = hi ? ((int)gy[k]) >> 16 : (int)(short)(gy[k] & 0xFFFF);
-          word |= (u32)phase_level(a, b) << (8 * i);
-        }
-        po[j] = word;
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      const u32 a01 = perm(lv[1], lv[0], 0x06020400u), a23 = perm(lv[3], lv[2], 0x06020400u);
+      const u32 a45 = perm(lv[5], lv[4], 0x06020400u), a67 = perm(lv[7], lv[6], 0x06020400u);
+      po.x = perm(a23, a01, 0x05040100u);
+      po.y = perm(a67, a45, 0x05040100u);
+      po.z = perm(a23, a01, 0x07060302u);
+      po.w = perm(a67, a45, 0x07060302u);
       if (L.store) __builtin_nontemporal_store(po, (u32x4*)(phb + (size_t)y * d.phase_pitch));
     }
     // magnitude + threshold as one integer test: gx^2 + gy^2 > T, i.e. the
@@ -357,8 +335,8 @@ struct EdgeStream {
     }
     emit(y, sv, dv);
   }
-  __device__ __forceinline__ void run(int y0, int y1_) {
-    y1 = y1_;
+  // Output rows [y0, y1), top to bottom.
+  __device__ __forceinline__ void run(int y0, int y1) {
     // prologue: G(y0-1), G(y0) and the pairwise state for row y0
     u32 a[8], b[8], c[8], e[8];
     unpk(load(y0 - 2), y0 - 2, a);

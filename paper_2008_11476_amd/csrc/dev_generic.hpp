@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dev_phase.hpp"
+
 #include "hvx_desc.h"
 
 namespace hvx {
@@ -151,10 +153,16 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
       return (int)min(m, 32767u);
     }
     case OP_PHASE: {
+      // the fused kernels' phase function; S16 gradients beyond 1023 are
+      // first scaled down by a common power of two (the angle depends on
+      // their ratio only; the truncation moves it by under 0.1 level)
       int a = rd(t, o, o.in[0], x, y), b = rd(t, o, o.in[1], x, y);
-      float th = atan2f((float)b, (float)a);  // (-pi, pi]
-      if (th < 0.f) th += 6.28318530717958647692f;
-      return ((int)floorf(th * (128.0f / 3.14159265358979323846f) + 0.5f)) & 255;
+      const int ua = a < 0 ? -a : a, ub = b < 0 ? -b : b;
+      const int m = ua > ub ? ua : ub;
+      const int sh = m >= 1024 ? 22 - __clz(m) : 0;
+      const int sa = ua >> sh, sb = ub >> sh;
+      const uint32_t ga = (uint32_t)(uint16_t)(a < 0 ? -sa : sa), gb = (uint32_t)(uint16_t)(b < 0 ? -sb : sb);
+      return (int)(phase_pair(ga, gb) & 0xFF);
     }
     case OP_THRESHOLD: {
       const GVal& iv = P.vals[o.in[0]];

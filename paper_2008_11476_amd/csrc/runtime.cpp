@@ -512,8 +512,28 @@ hvx_status hvx_batch_autotune(hvx_batch hb, void* stream, int iters) {
         for (auto& x : o) cur.push_back(std::move(x));
       }
       if (s) break;
-      if (ref.empty()) ref.swap(cur);
-      else if (cur != ref) s = set_error(b->ctx, HVX_ERROR_DEVICE, "batch candidate rows=%d changed the output", rows);
+      if (ref.empty()) {
+        ref.swap(cur);
+      } else if (cur != ref) {
+        // name the first differing output byte and how many differ
+        size_t which = 0, first = 0, count = 0;
+        for (size_t i = 0; i < ref.size() && i < cur.size(); ++i) {
+          if (ref[i] == cur[i]) continue;
+          for (size_t j = 0; j < ref[i].size() && j < cur[i].size(); ++j) {
+            if (ref[i][j] == cur[i][j]) continue;
+            if (count == 0) {
+              which = i;
+              first = j;
+            }
+            ++count;
+          }
+        }
+        s = set_error(b->ctx, HVX_ERROR_DEVICE,
+                      "batch candidate rows=%d persistent=%d changed the output: %zu bytes differ, first in output "
+                      "%zu at byte %zu (%u instead of %u)",
+                      rows, pers, count, which, first, count ? (unsigned)cur[which][first] : 0u,
+                      count ? (unsigned)ref[which][first] : 0u);
+      }
       cur.clear();
       if (s) break;
       (void)hipEventRecord(e0, st);

@@ -178,6 +178,8 @@ def test_edge_unfused_and_generic_match(ctx, w, h):
     compare(spec, unf, env, phase_names=("ph",))
     compare(spec, gen, env, phase_names=("ph",))
     assert np.array_equal(unf["out"], fast["out"]) and np.array_equal(gen["out"], fast["out"])
+    # one phase function serves every kernel: Phase is bitwise equal too
+    assert np.array_equal(unf["ph"], fast["ph"]) and np.array_equal(gen["ph"], fast["ph"])
 
 
 @pytest.mark.parametrize("w,h", [(1, 1), (2, 3), (17, 9), (100, 37), (993, 21), (2000, 70)])
