@@ -111,9 +111,16 @@ def gauss5_graph(hvx, ctx, inp_view, outs, uyvy=False, w=None):
     return g
 
 
-def time_region(torch, fn, steps, warmup):
-    """fn() `warmup` times, then `steps` timed calls: events on the current
-    stream (the stream the kernels go to) and the host clock."""
+def time_region(torch, fn, steps, warmup, spin_ms=150.0):
+    """fn() repeated for `spin_ms` of wall time (the GPU leaves its idle
+    clocks only under sustained load), then `warmup` more times, then `steps`
+    timed calls: events on the current stream (the stream the kernels go to)
+    and the host clock."""
+    t_end = time.perf_counter() + spin_ms / 1e3
+    while time.perf_counter() < t_end:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -129,12 +136,16 @@ def time_region(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps, (t1 - t0) * 1e3 / steps
 
 
-def batch_run(hvx, torch, ctx, graphs, steps, warmup, modes=("persistent", "direct")):
-    """Tune the batch's rows per work item, then time it in each launch mode;
-    returns the fastest (ms, host ms, algorithmic bytes, mode, {mode: ms})."""
+def batch_run(hvx, torch, ctx, graphs, steps, warmup, modes=("persistent", "direct"), rows=None):
+    """Tune the batch's rows per work item (or pin them to `rows`), then time
+    it in each launch mode; returns the fastest (ms, host ms, algorithmic
+    bytes, mode, {mode: ms})."""
     stream = torch.cuda.current_stream().cuda_stream
     b = hvx.hvx_batch_create(ctx, graphs)
-    hvx.hvx_batch_autotune(b, stream, 2, ctx=ctx)
+    if rows is None:
+        hvx.hvx_batch_autotune(b, stream, 2, ctx=ctx)
+    else:
+        hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_ROWS, rows, ctx=ctx)
     alg = hvx.hvx_batch_query(b, hvx.HVX_QUERY_ALG_BYTES)
     per_mode = {"rows_per_item": hvx.hvx_batch_query(b, hvx.HVX_QUERY_ROWS_PER_ITEM),
                 "work_items": hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_OPS)}
@@ -149,10 +160,11 @@ def batch_run(hvx, torch, ctx, graphs, steps, warmup, modes=("persistent", "dire
     return best[0], best[1], alg, best[2], per_mode
 
 
-def edge_batch(hvx, torch, ctx, w, h, nframes, steps, warmup, phase=False, border=None):
+def edge_batch(hvx, torch, ctx, w, h, nframes, steps, warmup, phase=False, border=None, rows=None,
+               modes=("persistent", "direct")):
     inp, out = make_frames(hvx, torch, w, h, nframes, n_out=2 if phase else 1)
     graphs = [edge_graph(hvx, ctx, inp[i][1], out[i], phase=phase, border=border) for i in range(nframes)]
-    ms, ms_host, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, steps, warmup)
+    ms, ms_host, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, steps, warmup, modes=modes, rows=rows)
     for g in graphs:
         hvx.hvx_release_graph(g)
     del inp, out
@@ -401,6 +413,10 @@ def main():
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rows", type=int, default=None,
+                    help="pin the headline batch to this many rows per work item (default: tune)")
+    ap.add_argument("--mode", choices=("auto", "direct", "persistent"), default="auto",
+                    help="headline launch mode (default: time both, keep the faster)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path: images and requests shard with "
@@ -417,7 +433,9 @@ def main():
     copy_ref = copy_calibration(torch)
     log("plain device copy:", copy_ref)
     log("edge+phase graph: %d x %dx%d frames per step, %d steps" % (args.frames, W, H, args.steps))
-    r = edge_batch(hvx, torch, ctx, W, H, args.frames, args.steps, args.warmup, phase=True)
+    modes = ("persistent", "direct") if args.mode == "auto" else (args.mode,)
+    r = edge_batch(hvx, torch, ctx, W, H, args.frames, args.steps, args.warmup, phase=True, rows=args.rows,
+                   modes=modes)
     ms = r["ms"]
     kernel = "hvx::k_batch_direct<8>" if r["mode"] == "direct" else "hvx::k_batch<8>"
     # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter

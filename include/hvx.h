@@ -243,9 +243,15 @@ hvx_status hvx_batch_query(hvx_batch b, int attr, int64_t* out);
 /* Batch options.  HVX_BATCH_PERSISTENT (default 1): a grid sized to the
  * machine pulls chunks of work items from per-XCD atomic counters; 0: one
  * wave per work item.  HVX_BATCH_USE_GRAPH (default 1): capture the launches
- * once into a HIP graph and replay it.  Changing an option drops the capture. */
+ * once into a HIP graph and replay it.  HVX_BATCH_ROWS (default 0): rows per
+ * work item for every image of the single launch (1..65535), 0 = each
+ * graph's own; it is what hvx_batch_autotune sets, and setting it pins a
+ * launch shape (e.g. a tuned one) without re-tuning.  Changing an option
+ * drops the capture; INVALID_PARAMETERS for an unknown option or a value out
+ * of range. */
 #define HVX_BATCH_PERSISTENT 1
 #define HVX_BATCH_USE_GRAPH 2
+#define HVX_BATCH_ROWS 3
 hvx_status hvx_batch_set_option(hvx_batch b, int option, int64_t value);
 /* Time candidate rows-per-work-item settings (shared by all images) and both
  * launch modes on the device (`iters` timed runs each; outputs of the first

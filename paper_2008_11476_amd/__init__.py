@@ -36,7 +36,7 @@ HVX_OPT_FUSION, HVX_OPT_DCE, HVX_OPT_TILE, HVX_OPT_SPECIALIZE, HVX_OPT_XCD_REMAP
  HVX_QUERY_HBM_BYTES, HVX_QUERY_KERNEL_KIND, HVX_QUERY_SCRATCH_BYTES, HVX_QUERY_OP_LIVE_MASK,
  HVX_QUERY_ROWS_PER_ITEM) = range(1, 11)
 HVX_SERVER_CONTINUOUS, HVX_SERVER_PLAIN = 0, 1
-HVX_BATCH_PERSISTENT, HVX_BATCH_USE_GRAPH = 1, 2
+HVX_BATCH_PERSISTENT, HVX_BATCH_USE_GRAPH, HVX_BATCH_ROWS = 1, 2, 3
 
 BYTES_PER_PIXEL = {HVX_DF_U8: 1, HVX_DF_S16: 2, HVX_DF_S32: 4, HVX_DF_F32: 4, HVX_DF_UYVY: 2}
 

@@ -362,17 +362,20 @@ struct EdgeStream {
       tr[0][k] = add2(c[k], e[k]);
       sr[0][k] = add2(gr[0][k], gr[1][k]);
     }
-    for (int y = y0; y < y1; y += 6) {
+    // counted loop over the band's rows (measured faster than a loop on y)
+    const int n = y1 - y0;
+    for (int i = 0; i < n; i += 6) {
+      const int y = y0 + i;
       step<0>(y);
-      if (y + 1 >= y1) break;
+      if (i + 1 >= n) break;
       step<1>(y + 1);
-      if (y + 2 >= y1) break;
+      if (i + 2 >= n) break;
       step<2>(y + 2);
-      if (y + 3 >= y1) break;
+      if (i + 3 >= n) break;
       step<3>(y + 3);
-      if (y + 4 >= y1) break;
+      if (i + 4 >= n) break;
       step<4>(y + 4);
-      if (y + 5 >= y1) break;
+      if (i + 5 >= n) break;
       step<5>(y + 5);
     }
   }

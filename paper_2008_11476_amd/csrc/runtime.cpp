@@ -478,7 +478,7 @@ hvx_status hvx_batch_query(hvx_batch hb, int attr, int64_t* out) {
 }
 
 // Outputs of the first and last graph of a batch (the tuner's equality check).
-static hvx_status read_outputs(Graph* g, std::vector<std::vector<uint8_t>>* out);
+static hvx_status read_outputs(Graph* g, hipStream_t st, std::vector<std::vector<uint8_t>>* out);
 
 hvx_status hvx_batch_autotune(hvx_batch hb, void* stream, int iters) {
   if (!registry_check(hb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
@@ -507,7 +507,7 @@ hvx_status hvx_batch_autotune(hvx_batch hb, void* stream, int iters) {
       if (s) break;
       for (Graph* g : {b->graphs.front(), b->graphs.back()}) {
         std::vector<std::vector<uint8_t>> o;
-        s = read_outputs(g, &o);
+        s = read_outputs(g, st, &o);
         if (s) break;
         for (auto& x : o) cur.push_back(std::move(x));
       }
@@ -571,6 +571,10 @@ hvx_status hvx_batch_set_option(hvx_batch hb, int option, int64_t value) {
   switch (option) {
     case HVX_BATCH_PERSISTENT: b->persistent = value != 0; break;
     case HVX_BATCH_USE_GRAPH: b->use_graph = value != 0; break;
+    case HVX_BATCH_ROWS:
+      if (value < 0 || value > 65535) return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "rows %lld", (long long)value);
+      b->rows_override = (int)value;
+      return batch_build(b);
     default: return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown batch option %d", option);
   }
   return HVX_SUCCESS;
@@ -604,7 +608,8 @@ hvx_status hvx_process_batch(hvx_context ctx, const hvx_graph* graphs, uint32_t 
 
 // ---- autotuning -----------------------------------------------------------------
 
-static hvx_status read_outputs(Graph* g, std::vector<std::vector<uint8_t>>* out) {
+static hvx_status read_outputs(Graph* g, hipStream_t st, std::vector<std::vector<uint8_t>>* out) {
+  // copies ordered after the work on `st` and complete before returning
   out->clear();
   const Plan& p = *g->plan;
   for (size_t v = 0; v < p.vals.size(); ++v) {
@@ -612,7 +617,9 @@ static hvx_status read_outputs(Graph* g, std::vector<std::vector<uint8_t>>* out)
     if (val.is_virtual || val.producer < 0 || !p.ops[val.producer].live) continue;
     size_t row = (size_t)val.w * df_bytes(val.df);
     std::vector<uint8_t> buf(row * val.h);
-    if (hipMemcpy2D(buf.data(), row, val.img->ptr, val.img->pitch, row, val.h, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy2DAsync(buf.data(), row, val.img->ptr, val.img->pitch, row, val.h, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
       return set_error(g->ctx, HVX_ERROR_DEVICE, "autotune readback failed");
     out->push_back(std::move(buf));
   }
@@ -648,7 +655,7 @@ hvx_status hvx_graph_autotune(hvx_graph hg, void* stream, int iters) {
       gr.xcd = xcd;
       s = schedule_graph(g, st);  // warm-up, also the output check
       if (!s && hipStreamSynchronize(st) != hipSuccess) s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune sync failed");
-      if (!s) s = read_outputs(g, ref.empty() ? &ref : &cur);
+      if (!s) s = read_outputs(g, st, ref.empty() ? &ref : &cur);
       if (!s && !cur.empty() && cur != ref)
         s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune candidate rows=%d xcd=%d changed the output", rows, xcd);
       cur.clear();

@@ -117,6 +117,34 @@ def test_batch_equals_alone_and_oracle(ctx, persistent):
     hvx.hvx_release_batch(b)
 
 
+def test_batch_rows_option(ctx):
+    """Pinned rows per work item (any value, ragged bands included) give the
+    oracle's result in both launch modes; out-of-range values are rejected."""
+    import torch
+    w, h = 2100, 77
+    a = synth.edge_image(w, h, seed=3)
+    spec = gs.edge_spec(a, phase=True)
+    env = spec.run_oracle()
+    g, outs, keep, imgs = _build(ctx, spec)
+    b = hvx.hvx_batch_create(ctx, [g])
+    stream = torch.cuda.current_stream().cuda_stream
+    for rows in (1, 5, 32, 200):
+        for pers in (1, 0):
+            log("batch rows=%d persistent=%d" % (rows, pers))
+            hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_ROWS, rows, ctx=ctx)
+            hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, pers, ctx=ctx)
+            assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_ROWS_PER_ITEM) == rows
+            for t, _ in outs.values():
+                t.fill_(0x5A)
+            hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+            torch.cuda.synchronize()
+            compare(spec, _read(outs), env, phase_names=("ph",))
+    for bad in (-1, 65536):
+        with pytest.raises(hvx.HvxError):
+            hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_ROWS, bad, ctx=ctx)
+    hvx.hvx_release_batch(b)
+
+
 def test_batch_refresh_after_swap(ctx):
     import torch
     w, h = 1500, 90
