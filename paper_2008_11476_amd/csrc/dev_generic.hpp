@@ -79,18 +79,70 @@ __device__ __forceinline__ uint32_t isqrt_u32(uint32_t s) {
 __device__ __forceinline__ int sat_u8(int v) { return min(max(v, 0), 255); }
 __device__ __forceinline__ int sat_s16(int v) { return min(max(v, -32768), 32767); }
 
+__host__ __device__ inline bool is_point_op(int kind) {
+  return kind == OP_CHANNEL_Y || kind == OP_MAGNITUDE || kind == OP_PHASE || kind == OP_THRESHOLD ||
+         kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS;
+}
+
+// A point operator (Section 4) on one pixel: a, b, c are its input elements
+// (int bits; F32 as bit patterns; a UYVY input as its 16-bit U/V,Y pair),
+// `in_f32` says whether the first input is F32.  Returns the output element.
+__device__ __forceinline__ int point_eval(const GOp& o, int out_df, bool in_f32, int a, int b, int c) {
+  switch (o.kind) {
+    case OP_CHANNEL_Y: return (a >> 8) & 0xFF;
+    case OP_MAGNITUDE: {
+      uint32_t sq = (uint32_t)(a * a) + (uint32_t)(b * b);
+      uint32_t q = isqrt_u32(sq);
+      uint32_t m = q + ((sq - q * q) > q ? 1u : 0u);
+      return (int)min(m, 32767u);
+    }
+    case OP_PHASE: {
+      // the fused kernels' phase function; S16 gradients beyond 1023 are
+      // first scaled down by a common power of two (the angle depends on
+      // their ratio only; the truncation moves it by under 0.1 level)
+      const int ua = a < 0 ? -a : a, ub = b < 0 ? -b : b;
+      const int m = ua > ub ? ua : ub;
+      const int sh = m >= 1024 ? 22 - __clz(m) : 0;
+      const int sa = ua >> sh, sb = ub >> sh;
+      const uint32_t ga = (uint32_t)(uint16_t)(a < 0 ? -sa : sa), gb = (uint32_t)(uint16_t)(b < 0 ? -sb : sb);
+      return (int)(phase_pair(ga, gb) & 0xFF);
+    }
+    case OP_THRESHOLD: {
+      bool hit = in_f32 ? (__int_as_float(a) > o.pf) : (a >= o.p2);
+      return hit ? o.p0 : o.p1;
+    }
+    case OP_ADD: {
+      int sm = a + b;
+      if (out_df == DF_U8) return o.p0 == 0 ? sat_u8(sm) : (sm & 0xFF);
+      return o.p0 == 0 ? sat_s16(sm) : (int)(int16_t)(uint16_t)(sm & 0xFFFF);
+    }
+    case OP_MULF: return __float_as_int((float)a * (float)b);
+    case OP_HARRIS: {
+      float sxx = __int_as_float(a), syy = __int_as_float(b), sxy = __int_as_float(c);
+      float det = sxx * syy - sxy * sxy;
+      float tr = sxx + syy;
+      return __float_as_int(det - o.pf * tr * tr);
+    }
+  }
+  return 0;
+}
+
 // Evaluate operator `o` at (x, y).  Returns the output element as int bits
 // (F32 outputs as their bit pattern).
-__device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, int y) {
-  const GProg& P = *t.P;
+// A local operator (Section 4) at one pixel.  rd(dx, dy) returns its input
+// at offset (dx, dy) from that pixel, border rule applied (int bits; F32 as
+// bit patterns).  The Convolve mask is walked over the full 5 x 5 extent with
+// the cells outside cols x rows skipped, so that every window offset is a
+// compile-time constant.
+template <class RD>
+__device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd) {
   switch (o.kind) {
-    case OP_CHANNEL_Y: return (rd(t, o, o.in[0], x, y) >> 8) & 0xFF;
     case OP_GAUSS3: {
       int s = 0;
 #pragma unroll
       for (int j = -1; j <= 1; ++j) {
         const int wj = j == 0 ? 2 : 1;
-        int r = rd(t, o, o.in[0], x - 1, y + j) + 2 * rd(t, o, o.in[0], x, y + j) + rd(t, o, o.in[0], x + 1, y + j);
+        int r = rd(-1, j) + 2 * rd(0, j) + rd(1, j);
         s += wj * r;
       }
       return s >> 4;
@@ -102,7 +154,7 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
       for (int j = -2; j <= 2; ++j) {
         int r = 0;
 #pragma unroll
-        for (int i = -2; i <= 2; ++i) r += wt[i + 2] * rd(t, o, o.in[0], x + i, y + j);
+        for (int i = -2; i <= 2; ++i) r += wt[i + 2] * rd(i, j);
         s += wt[j + 2] * r;
       }
       return s >> 8;
@@ -112,7 +164,7 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
 #pragma unroll
       for (int j = -1; j <= 1; ++j)
 #pragma unroll
-        for (int i = -1; i <= 1; ++i) s += rd(t, o, o.in[0], x + i, y + j);
+        for (int i = -1; i <= 1; ++i) s += rd(i, j);
       return s / 9;
     }
     case OP_BOX5F: {
@@ -122,7 +174,7 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
       for (int j = -2; j <= 2; ++j) {
         float r = 0.f;
 #pragma unroll
-        for (int i = -2; i <= 2; ++i) r += rdf(t, o, o.in[0], x + i, y + j);
+        for (int i = -2; i <= 2; ++i) r += __int_as_float(rd(i, j));
         s += r;
       }
       return __float_as_int(s);
@@ -132,7 +184,7 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
 #pragma unroll
       for (int j = -1; j <= 1; ++j) {
         const int wj = j == 0 ? 2 : 1;
-        s += wj * (rd(t, o, o.in[0], x + 1, y + j) - rd(t, o, o.in[0], x - 1, y + j));
+        s += wj * (rd(1, j) - rd(-1, j));
       }
       return s;
     }
@@ -141,61 +193,50 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
 #pragma unroll
       for (int i = -1; i <= 1; ++i) {
         const int wi = i == 0 ? 2 : 1;
-        s += wi * (rd(t, o, o.in[0], x + i, y + 1) - rd(t, o, o.in[0], x + i, y - 1));
+        s += wi * (rd(i, 1) - rd(i, -1));
       }
       return s;
-    }
-    case OP_MAGNITUDE: {
-      int a = rd(t, o, o.in[0], x, y), b = rd(t, o, o.in[1], x, y);
-      uint32_t s = (uint32_t)(a * a) + (uint32_t)(b * b);
-      uint32_t q = isqrt_u32(s);
-      uint32_t m = q + ((s - q * q) > q ? 1u : 0u);
-      return (int)min(m, 32767u);
-    }
-    case OP_PHASE: {
-      // the fused kernels' phase function; S16 gradients beyond 1023 are
-      // first scaled down by a common power of two (the angle depends on
-      // their ratio only; the truncation moves it by under 0.1 level)
-      int a = rd(t, o, o.in[0], x, y), b = rd(t, o, o.in[1], x, y);
-      const int ua = a < 0 ? -a : a, ub = b < 0 ? -b : b;
-      const int m = ua > ub ? ua : ub;
-      const int sh = m >= 1024 ? 22 - __clz(m) : 0;
-      const int sa = ua >> sh, sb = ub >> sh;
-      const uint32_t ga = (uint32_t)(uint16_t)(a < 0 ? -sa : sa), gb = (uint32_t)(uint16_t)(b < 0 ? -sb : sb);
-      return (int)(phase_pair(ga, gb) & 0xFF);
-    }
-    case OP_THRESHOLD: {
-      const GVal& iv = P.vals[o.in[0]];
-      int v = rd(t, o, o.in[0], x, y);
-      bool hit = iv.df == DF_F32 ? (__int_as_float(v) > o.pf) : (v >= o.p2);
-      return hit ? o.p0 : o.p1;
-    }
-    case OP_ADD: {
-      int s = rd(t, o, o.in[0], x, y) + rd(t, o, o.in[1], x, y);
-      int odf = P.vals[o.out].df;
-      if (odf == DF_U8) return o.p0 == 0 ? sat_u8(s) : (s & 0xFF);
-      return o.p0 == 0 ? sat_s16(s) : (int)(int16_t)(uint16_t)(s & 0xFFFF);
-    }
-    case OP_MULF: {
-      float a = (float)rd(t, o, o.in[0], x, y), b = (float)rd(t, o, o.in[1], x, y);
-      return __float_as_int(a * b);
-    }
-    case OP_HARRIS: {
-      float sxx = rdf(t, o, o.in[0], x, y), syy = rdf(t, o, o.in[1], x, y), sxy = rdf(t, o, o.in[2], x, y);
-      float det = sxx * syy - sxy * sxy;
-      float tr = sxx + syy;
-      return __float_as_int(det - o.pf * tr * tr);
     }
     case OP_CONVOLVE: {
       const int cols = o.p0, rows = o.p1, rx = cols / 2, ry = rows / 2;
       int s = 0;
-      for (int j = -ry; j <= ry; ++j)
-        for (int i = -rx; i <= rx; ++i) s += o.mask[(j + ry) * cols + (i + rx)] * rd(t, o, o.in[0], x - i, y - j);
+#pragma unroll
+      for (int j = -2; j <= 2; ++j)
+#pragma unroll
+        for (int i = -2; i <= 2; ++i)
+          if (i >= -rx && i <= rx && j >= -ry && j <= ry)
+            s += o.mask[(j + ry) * cols + (i + rx)] * rd(-i, -j);
       int q = s >= 0 ? (s >> o.p2) : -((-s) >> o.p2);  // divide by 2^p2 toward zero
-      return P.vals[o.out].df == DF_U8 ? sat_u8(q) : sat_s16(q);
+      return out_df == DF_U8 ? sat_u8(q) : sat_s16(q);
     }
   }
   return 0;
+}
+
+__host__ __device__ inline int local_radius(int kind) {
+  return (kind == OP_GAUSS5 || kind == OP_BOX5F || kind == OP_CONVOLVE) ? 2 : 1;
+}
+
+// reads value `vi` of a tile as operator `o` sees it
+struct TileRd {
+  const TileCtx* t;
+  const GOp* o;
+  int vi, x, y;
+  __device__ __forceinline__ int operator()(int dx, int dy) const { return rd(*t, *o, vi, x + dx, y + dy); }
+};
+
+// Evaluate operator `o` at (x, y) inside a tile.  Returns the output element
+// as int bits (F32 outputs as their bit pattern).
+__device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, int y) {
+  const GProg& P = *t.P;
+  if (is_point_op(o.kind)) {
+    const int a = rd(t, o, o.in[0], x, y);
+    const int b = o.in[1] >= 0 ? rd(t, o, o.in[1], x, y) : 0;
+    const int c = o.in[2] >= 0 ? rd(t, o, o.in[2], x, y) : 0;
+    return point_eval(o, P.vals[o.out].df, P.vals[o.in[0]].df == DF_F32, a, b, c);
+  }
+  const int vi = o.in[0];
+  return local_eval(o, P.vals[o.out].df, TileRd{&t, &o, vi, x, y});
 }
 
 // One tile of a generic program.  `lds` holds P.lds_words words.
@@ -218,10 +259,10 @@ __device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_
     if (cw <= 0 || ch <= 0) continue;
     const void* base = io.ptr[v.io];
     const int64_t pitch = io.pitch[v.io];
-    for (int i = threadIdx.x; i < cw * ch; i += NT) {
-      const int yy = cy0 + i / cw, xx = cx0 + i % cw;
-      lds[v.lds + (yy - y0) * rw + (xx - x0)] = gload(v.df, base, pitch, xx, yy);
-    }
+    // rows spread over groups of 64 threads, columns over the lanes
+    for (int yy = cy0 + (int)(threadIdx.x >> 6); yy < cy1; yy += NT / 64)
+      for (int xx = cx0 + (int)(threadIdx.x & 63); xx < cx1; xx += 64)
+        lds[v.lds + (yy - y0) * rw + (xx - x0)] = gload(v.df, base, pitch, xx, yy);
   }
   __syncthreads();
   for (int oi = 0; oi < P.nops; ++oi) {
@@ -237,16 +278,182 @@ __device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_
     void* gbase = ov.store ? io.ptr[ov.io] : nullptr;
     const int64_t gpitch = ov.store ? io.pitch[ov.io] : 0;
     if (cw > 0 && ch > 0) {
-      for (int i = threadIdx.x; i < cw * ch; i += NT) {
-        const int yy = cy0 + i / cw, xx = cx0 + i % cw;
-        const int r = eval_op(t, o, xx, yy);
-        if (dst) dst[(yy - y0) * rw + (xx - x0)] = r;
-        if (gbase && xx >= t.tx0 && xx < t.tx0 + P.tw && yy >= t.ty0 && yy < t.ty0 + P.th)
-          gstore(ov.df, gbase, gpitch, xx, yy, r);
-      }
+      for (int yy = cy0 + (int)(threadIdx.x >> 6); yy < cy1; yy += NT / 64)
+        for (int xx = cx0 + (int)(threadIdx.x & 63); xx < cx1; xx += 64) {
+          const int r = eval_op(t, o, xx, yy);
+          if (dst) dst[(yy - y0) * rw + (xx - x0)] = r;
+          if (gbase && xx >= t.tx0 && xx < t.tx0 + P.tw && yy >= t.ty0 && yy < t.ty0 + P.th)
+            gstore(ov.df, gbase, gpitch, xx, yy, r);
+        }
     }
     __syncthreads();
   }
+}
+
+// ---- one point operator over a whole image ----------------------------------
+// A group that is a single point operator needs no tile or halo: each thread
+// reads four consecutive pixels of each input with one vector load, applies
+// the operator, and writes four pixels with one vector store (per-element
+// accesses only in the last, partial group of a row).
+
+__device__ __forceinline__ void load4(int df, const uint8_t* row, int x, int W, int v[4]) {
+  if (x + 3 < W) {
+    switch (df) {
+      case DF_U8: {
+        const uint32_t r = *(const uint32_t*)(row + x);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = (r >> (8 * k)) & 0xFF;
+        return;
+      }
+      case DF_S16: {
+        const uint2 r = *(const uint2*)(row + 2 * x);
+        v[0] = (int)(int16_t)(r.x & 0xFFFF);
+        v[1] = ((int)r.x) >> 16;
+        v[2] = (int)(int16_t)(r.y & 0xFFFF);
+        v[3] = ((int)r.y) >> 16;
+        return;
+      }
+      case DF_UYVY: {
+        const uint2 r = *(const uint2*)(row + 2 * x);
+        v[0] = r.x & 0xFFFF;
+        v[1] = r.x >> 16;
+        v[2] = r.y & 0xFFFF;
+        v[3] = r.y >> 16;
+        return;
+      }
+      default: {
+        const uint4 r = *(const uint4*)(row + 4 * x);
+        v[0] = (int)r.x;
+        v[1] = (int)r.y;
+        v[2] = (int)r.z;
+        v[3] = (int)r.w;
+        return;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = x + k < W ? gload(df, row, 0, x + k, 0) : 0;
+}
+
+__device__ __forceinline__ void store4(int df, uint8_t* row, int x, int W, const int v[4]) {
+  if (x + 3 < W) {
+    switch (df) {
+      case DF_U8:
+        *(uint32_t*)(row + x) = (uint32_t)(v[0] & 0xFF) | (uint32_t)(v[1] & 0xFF) << 8 |
+                                (uint32_t)(v[2] & 0xFF) << 16 | (uint32_t)(v[3] & 0xFF) << 24;
+        return;
+      case DF_S16:
+        *(uint2*)(row + 2 * x) = make_uint2((uint32_t)(v[0] & 0xFFFF) | (uint32_t)v[1] << 16,
+                                            (uint32_t)(v[2] & 0xFFFF) | (uint32_t)v[3] << 16);
+        return;
+      default:
+        *(uint4*)(row + 4 * x) = make_uint4((uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]);
+        return;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (x + k < W) gstore(df, row, 0, x + k, 0, v[k]);
+}
+
+// 256 threads cover 1024 pixels of one row; block b handles row b / bx of
+// the ceil(W / 1024) = bx blocks per row.
+__device__ __forceinline__ void point_image(const GProg& P, const IOTable& io) {
+  const GOp& o = P.ops[0];
+  const int W = P.w, H = P.h;
+  const int bx = (W + 1023) >> 10;
+  const int y = blockIdx.x / bx;
+  const int x = ((blockIdx.x - y * bx) * 256 + (int)threadIdx.x) * 4;
+  if (y >= H || x >= W) return;
+  int a[4][4] = {};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (o.in[i] < 0) continue;
+    const GVal& v = P.vals[o.in[i]];
+    load4(v.df, (const uint8_t*)io.ptr[v.io] + (size_t)y * io.pitch[v.io], x, W, a[i]);
+  }
+  const GVal& ov = P.vals[o.out];
+  const bool in_f32 = P.vals[o.in[0]].df == DF_F32;
+  int r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = point_eval(o, ov.df, in_f32, a[0][k], a[1][k], a[2][k]);
+  store4(ov.df, (uint8_t*)io.ptr[ov.io] + (size_t)y * io.pitch[ov.io], x, W, r);
+}
+
+// ---- one local operator over a whole image ----------------------------------
+// A group that is a single local operator reads its input straight from
+// global memory: each thread produces four consecutive pixels of one row
+// from a window of (2R+1) rows x 12 columns (the aligned 4-pixel groups left
+// of, at and right of its own), fetched with three vector loads per row;
+// neighbouring threads' windows overlap in the caches, so HBM sees each input
+// row about once.  Windows that leave the image take the border rule per
+// element.
+
+// reads the window of local_image around output pixel x0 + K: every index
+// is a compile-time constant once inlined, so the window stays in VGPRs
+template <int R, int K>
+struct WinRd {
+  const int (*w)[12];
+  __device__ __forceinline__ int operator()(int dx, int dy) const { return w[R + dy][4 + K + dx]; }
+};
+
+template <int R, bool F32>
+__device__ __forceinline__ void local_image(const GProg& P, const IOTable& io) {
+  const GOp& o = P.ops[0];
+  const int W = P.w, H = P.h;
+  const int bx = (W + 1023) >> 10;
+  const int y = blockIdx.x / bx;
+  const int x0 = ((blockIdx.x - y * bx) * 256 + (int)threadIdx.x) * 4;
+  if (y >= H || x0 >= W) return;
+  const GVal& iv = P.vals[o.in[0]];
+  const GVal& ov = P.vals[o.out];
+  const uint8_t* base = (const uint8_t*)io.ptr[iv.io];
+  const int64_t pitch = io.pitch[iv.io];
+  int win[2 * R + 1][12];  // columns x0-4 .. x0+7
+  const bool inside = x0 >= 4 && x0 + 8 <= W && y >= R && y + R < H;
+  if (inside) {
+#pragma unroll
+    for (int j = 0; j < 2 * R + 1; ++j) {
+      const uint8_t* row = base + (size_t)(y - R + j) * pitch;
+      if (F32) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const uint4 v = *(const uint4*)(row + 4 * (x0 - 4 + 4 * q));
+          win[j][4 * q] = (int)v.x;
+          win[j][4 * q + 1] = (int)v.y;
+          win[j][4 * q + 2] = (int)v.z;
+          win[j][4 * q + 3] = (int)v.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const uint32_t v = *(const uint32_t*)(row + x0 - 4 + 4 * q);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) win[j][4 * q + k] = (v >> (8 * k)) & 0xFF;
+        }
+      }
+    }
+  } else {
+    const bool cst = o.border == B_CONSTANT;
+    const int cval = F32 ? __float_as_int(o.cf) : o.cint;
+#pragma unroll
+    for (int j = 0; j < 2 * R + 1; ++j)
+#pragma unroll
+      for (int k = 4 - R; k < 8 + R; ++k) {
+        int xx = x0 - 4 + k, yy = y - R + j;
+        const bool out = xx < 0 || yy < 0 || xx >= W || yy >= H;
+        xx = min(max(xx, 0), W - 1);
+        yy = min(max(yy, 0), H - 1);
+        const int v = gload(iv.df, base, pitch, xx, yy);
+        win[j][k] = (out && cst) ? cval : v;
+      }
+  }
+  int r[4];
+  r[0] = local_eval(o, ov.df, WinRd<R, 0>{win});
+  r[1] = local_eval(o, ov.df, WinRd<R, 1>{win});
+  r[2] = local_eval(o, ov.df, WinRd<R, 2>{win});
+  r[3] = local_eval(o, ov.df, WinRd<R, 3>{win});
+  store4(ov.df, (uint8_t*)io.ptr[ov.io] + (size_t)y * io.pitch[ov.io], x0, W, r);
 }
 
 }  // namespace hvx

@@ -47,11 +47,12 @@ constexpr unsigned short kRcpMagic = 0x779C;
 // phase levels in the low bytes of the two halves.
 __device__ __forceinline__ uint32_t phase_pair(uint32_t gx, uint32_t gy) {
   const i16x2 x = __builtin_bit_cast(i16x2, gx), y = __builtin_bit_cast(i16x2, gy);
-  const i16x2 z0 = {0, 0}, one = {1, 1};
+  const i16x2 z0 = {0, 0};
   const i16x2 ax = __builtin_elementwise_max(x, z0 - x);
   const i16x2 ay = __builtin_elementwise_max(y, z0 - y);
   const i16x2 mn = __builtin_elementwise_min(ax, ay);
-  const i16x2 mx = __builtin_elementwise_max(__builtin_elementwise_max(ax, ay), one);
+  // mx = 0 needs no guard: the reciprocal estimate of 0 is finite, so z = 0
+  const i16x2 mx = __builtin_elementwise_max(ax, ay);
   const w16x2 bias = {0x6400, 0x6400};
   const h16x2 k1024 = {(_Float16)1024.0f, (_Float16)1024.0f};
   const h16x2 fmn = __builtin_bit_cast(h16x2, __builtin_bit_cast(w16x2, mn) + bias) - k1024;

@@ -24,6 +24,15 @@ __global__ __launch_bounds__(256) void k_generic(const GProg* __restrict__ P, co
   generic_tile<256>(*P, io, blockIdx.x, lds);
 }
 
+__global__ __launch_bounds__(256) void k_point(const GProg* __restrict__ P, const IOTable io) {
+  point_image(*P, io);
+}
+
+template <int R, bool F32>
+__global__ __launch_bounds__(256) void k_local(const GProg* __restrict__ P, const IOTable io) {
+  local_image<R, F32>(*P, io);
+}
+
 template <bool PHASE>
 __global__ __launch_bounds__(64) void k_edge(const EdgeDesc d, int xcd) {
   const int item = xcd ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -120,6 +129,28 @@ __global__ __launch_bounds__(64) void k_batch_direct(const BatchImage* __restric
 // ---- host launchers ---------------------------------------------------------
 
 hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& io, hipStream_t s) {
+  if (P.nops == 1 && is_point_op(P.ops[0].kind)) {
+    const long long blocks = (long long)((P.w + 1023) >> 10) * P.h;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_point, dim3((unsigned)blocks), dim3(256), 0, s, dev_prog, io);
+    return hipGetLastError();
+  }
+  const int in_df = P.nops == 1 && P.ops[0].in[0] >= 0 ? P.vals[P.ops[0].in[0]].df : -1;
+  if (P.nops == 1 && (in_df == DF_U8 || in_df == DF_F32)) {
+    const GOp& o = P.ops[0];
+    const long long blocks = (long long)((P.w + 1023) >> 10) * P.h;
+    if (blocks <= 0) return hipSuccess;
+    const bool f32 = in_df == DF_F32;
+    const dim3 g((unsigned)blocks), b(256);
+    if (local_radius(o.kind) == 1) {
+      if (f32) hipLaunchKernelGGL((k_local<1, true>), g, b, 0, s, dev_prog, io);
+      else hipLaunchKernelGGL((k_local<1, false>), g, b, 0, s, dev_prog, io);
+    } else {
+      if (f32) hipLaunchKernelGGL((k_local<2, true>), g, b, 0, s, dev_prog, io);
+      else hipLaunchKernelGGL((k_local<2, false>), g, b, 0, s, dev_prog, io);
+    }
+    return hipGetLastError();
+  }
   const int tiles = P.tiles_x * P.tiles_y;
   if (tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_generic, dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
