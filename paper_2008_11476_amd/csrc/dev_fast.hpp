@@ -623,24 +623,27 @@ struct St {
   int c0, c1;
 };
 
-__device__ __forceinline__ void load_row(const St& s, int y, int a[4]) {
+// The lane's four input pixels of row y as packed bytes (the border constant
+// outside the image under CONSTANT); kept packed so that the three rows a
+// gradient row needs cost three registers.
+__device__ __forceinline__ u32 load_row(const St& s, int y) {
   const int H = s.d->g.h;
   const int yc = min(max(y, 0), H - 1);
   u32 r = __builtin_nontemporal_load((const u32*)(s.inb + (size_t)yc * s.d->in_pitch));
   if (!s.repl0 && (y < 0 || y >= H)) r = 0x01010101u * (u32)s.c0;
-  a[0] = r & 0xFF;
-  a[1] = (r >> 8) & 0xFF;
-  a[2] = (r >> 16) & 0xFF;
-  a[3] = r >> 24;
+  return r;
 }
 
+__device__ __forceinline__ int byte_of(u32 r, int k) { return (int)((r >> (8 * k)) & 0xFF); }
+
 // Horizontal 5-sums of the three products at in-image row r (rows r-1, r, r+1 given).
-__device__ __forceinline__ void hsums(const St& s, const int a[4], const int b[4], const int c[4], int h[3][4]) {
+__device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3][4]) {
   int sv[4], dv[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    sv[k] = a[k] + 2 * b[k] + c[k];
-    dv[k] = c[k] - a[k];
+    const int ak = byte_of(a, k), bk = byte_of(b, k), ck = byte_of(c, k);
+    sv[k] = ak + 2 * bk + ck;
+    dv[k] = ck - ak;
   }
   int es[8], ed[8];
   extend4<1>(sv, es, s.L, s.repl0, 4 * s.c0);
@@ -683,39 +686,30 @@ __device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int 
   const int y1 = min(y0 + d.g.rows, H);
 
   // input rows r-1, r, r+1 for the next gradient row r = nr
-  int ia[4], ib[4], ic[4];
   int nr = max(y0 - 2, 0);
-  load_row(s, nr - 1, ia);
-  load_row(s, nr, ib);
-  load_row(s, nr + 1, ic);
+  u32 ia = load_row(s, nr - 1), ib = load_row(s, nr), ic = load_row(s, nr + 1);
   // H rows of the product planes; row y of the box needs rows y-2..y+2
   int ring[5][3][4];
-  int last[3][4];  // most recent in-image H row (for REPLICATE below the image)
-  auto next_h = [&](int r, int out[3][4]) {
-    if (r < 0 || r >= H) {
-      // rows outside the image: border of the box filters' input
+  // H row r into out; `prev` holds H row r-1 (rows below the image repeat it
+  // under REPLICATE, so no separate copy of the last in-image row is kept)
+  auto next_h = [&](int r, int out[3][4], const int prev[3][4]) {
+    if (r >= H) {
+      // rows below the image: border of the box filters' input
 #pragma unroll
       for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) out[q][k] = s.repl1 ? last[q][k] : 5 * s.c1;
+        for (int k = 0; k < 4; ++k) out[q][k] = s.repl1 ? prev[q][k] : 5 * s.c1;
       return;
     }
     hsums(s, ia, ib, ic, out);
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) last[q][k] = out[q][k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      ia[k] = ib[k];
-      ib[k] = ic[k];
-    }
-    load_row(s, r + 2, ic);
+    ia = ib;
+    ib = ic;
+    ic = load_row(s, r + 2);
   };
   // prologue: rows y0-2 .. y0+2; above the image REPLICATE needs row 0 first
   if (y0 - 2 < 0) {
     int h0[3][4];
-    next_h(0, h0);  // computes row 0 and sets `last`
+    next_h(0, h0, h0);  // row 0 (H >= 1, so never below the image)
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
       const int r = y0 - 2 + j;
@@ -730,12 +724,13 @@ __device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int 
 #pragma unroll
           for (int k = 0; k < 4; ++k) ring[j][q][k] = h0[q][k];
       } else {
-        next_h(r, ring[j]);
+        next_h(r, ring[j], ring[j - 1]);  // r > 0 here, so j >= 1
       }
     }
   } else {
+    next_h(y0 - 2, ring[0], ring[0]);  // y0 - 2 < H
 #pragma unroll
-    for (int j = 0; j < 5; ++j) next_h(y0 - 2 + j, ring[j]);
+    for (int j = 1; j < 5; ++j) next_h(y0 - 2 + j, ring[j], ring[j - 1]);
   }
   int v[3][4];
 #pragma unroll
@@ -765,7 +760,7 @@ __device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int 
       if (y + j < y1) {
         emit(y + j);
         int hn[3][4];
-        next_h(y + j + 3, hn);
+        next_h(y + j + 3, hn, ring[(j + 4) % 5]);
 #pragma unroll
         for (int q = 0; q < 3; ++q)
 #pragma unroll

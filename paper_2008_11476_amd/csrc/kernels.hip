@@ -62,8 +62,9 @@ __global__ __launch_bounds__(64) void k_gauss5(const Gauss5Desc d, int xcd) {
 constexpr int kCtrStride = 32;  // counters 128 bytes apart
 
 // KS: the set of kinds a batch holds (bit 1 edge, 2 corner, 4 Gaussian5x5,
-// 8 edge with phase); only those bodies are compiled into the batch kernel,
-// so a batch of one kind keeps that kind's register budget and occupancy.
+// 8 edge with phase, 16 Gaussian5x5 of UYVY luma); only those bodies are
+// compiled into the batch kernel, so a batch of one kind keeps that kind's
+// register budget and occupancy.
 template <int KS>
 __device__ __forceinline__ void run_item(const BatchImage& bi, int local) {
   if ((KS & 9) && bi.kind == FK_EDGE) {
@@ -73,10 +74,10 @@ __device__ __forceinline__ void run_item(const BatchImage& bi, int local) {
   } else if ((KS & 2) && bi.kind == FK_CORNER) {
     const CornerDesc& d = bi.d.c;
     corner_item(d, local % d.g.nstrips, local / d.g.nstrips);
-  } else if ((KS & 4) && bi.kind == FK_GAUSS5) {
+  } else if ((KS & 20) && bi.kind == FK_GAUSS5) {
     const Gauss5Desc& d = bi.d.g5;
-    if (d.uyvy) gauss5_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
-    else gauss5_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
+    if ((KS & 16) && d.uyvy) gauss5_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
+    else if (KS & 4) gauss5_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
   }
 }
 
@@ -201,8 +202,10 @@ hipError_t launch_batch(const BatchImage* imgs, const uint16_t* item_img, int to
     case 2: launch_batch_ks<2>(imgs, item_img, total, counter, grid, persistent, s); break;
     case 4: launch_batch_ks<4>(imgs, item_img, total, counter, grid, persistent, s); break;
     case 8: launch_batch_ks<8>(imgs, item_img, total, counter, grid, persistent, s); break;
+    case 16: launch_batch_ks<16>(imgs, item_img, total, counter, grid, persistent, s); break;
     case 7: launch_batch_ks<7>(imgs, item_img, total, counter, grid, persistent, s); break;
-    default: launch_batch_ks<15>(imgs, item_img, total, counter, grid, persistent, s); break;
+    case 19: launch_batch_ks<19>(imgs, item_img, total, counter, grid, persistent, s); break;
+    default: launch_batch_ks<31>(imgs, item_img, total, counter, grid, persistent, s); break;
   }
   return hipGetLastError();
 }
@@ -211,7 +214,7 @@ int kind_bit(const BatchImage& bi) {
   switch (bi.kind) {
     case FK_EDGE: return bi.d.e.phase ? 8 : 1;
     case FK_CORNER: return 2;
-    case FK_GAUSS5: return 4;
+    case FK_GAUSS5: return bi.d.g5.uyvy ? 16 : 4;
     default: return 0;
   }
 }
@@ -226,8 +229,10 @@ int batch_waves_per_cu(int kinds) {
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<2>, 64, 0); break;
     case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<4>, 64, 0); break;
     case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<8>, 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<16>, 64, 0); break;
     case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<7>, 64, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<15>, 64, 0); break;
+    case 19: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<19>, 64, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<31>, 64, 0); break;
   }
   if (e != hipSuccess || blocks <= 0) blocks = 8;
   return blocks;
