@@ -429,6 +429,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     ctx = hvx.hvx_context_create(0)
+    # a stream of our own (default priority): the null stream cannot be
+    # captured, so batches would run as plain launches there
+    work = torch.cuda.Stream()
+    with torch.cuda.stream(work):
+        run(args, torch, hvx, ctx)
+    hvx.hvx_context_release(ctx)
+
+
+def run(args, torch, hvx, ctx):
     W, H = 3840, 2160
     copy_ref = copy_calibration(torch)
     log("plain device copy:", copy_ref)
@@ -484,7 +493,6 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W, H)
         log("cpu baseline:", out["cpu_baseline"])
-    hvx.hvx_context_release(ctx)
     print(json.dumps(out), flush=True)
 
 

@@ -425,6 +425,8 @@ hvx_status hvx_batch_schedule(hvx_batch hb, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hvx_status st = ensure_device(b->ctx);
   if (st) return st;
+  if (b->total == 0 && b->separate.empty()) return HVX_SUCCESS;  // nothing to launch
+  // the legacy null stream cannot be captured: there the launches are plain
   if (b->use_graph && s != nullptr) {
     if (!b->exec) {
       // capture once: the persistent launch plus the launches of any graph

@@ -98,7 +98,8 @@ def test_batch_equals_alone_and_oracle(ctx, persistent):
     b = hvx.hvx_batch_create(ctx, [x[2] for x in built])
     hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, persistent)
     assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) >= 2  # persistent launch + separate graphs
-    stream = torch.cuda.current_stream().cuda_stream
+    side = torch.cuda.Stream()  # capturable (the null stream is not)
+    stream = side.cuda_stream
     for rep in range(3):  # capture, then replays with eager work in between
         log("batch replay %d" % rep)
         hvx.hvx_batch_schedule(b, stream, ctx=ctx)
@@ -127,7 +128,8 @@ def test_batch_rows_option(ctx):
     env = spec.run_oracle()
     g, outs, keep, imgs = _build(ctx, spec)
     b = hvx.hvx_batch_create(ctx, [g])
-    stream = torch.cuda.current_stream().cuda_stream
+    side = torch.cuda.Stream()  # capturable (the null stream is not)
+    stream = side.cuda_stream
     for rows in (1, 5, 32, 200):
         for pers in (1, 0):
             log("batch rows=%d persistent=%d" % (rows, pers))
@@ -136,6 +138,7 @@ def test_batch_rows_option(ctx):
             assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_ROWS_PER_ITEM) == rows
             for t, _ in outs.values():
                 t.fill_(0x5A)
+            torch.cuda.synchronize()
             hvx.hvx_batch_schedule(b, stream, ctx=ctx)
             torch.cuda.synchronize()
             compare(spec, _read(outs), env, phase_names=("ph",))
@@ -154,7 +157,8 @@ def test_batch_refresh_after_swap(ctx):
     g, outs, keep, imgs = _build(ctx, spec)
     other, t2 = device_image(ctx, bimg, hvx.HVX_DF_U8, seed=9)
     b = hvx.hvx_batch_create(ctx, [g])
-    stream = torch.cuda.current_stream().cuda_stream
+    side = torch.cuda.Stream()  # capturable (the null stream is not)
+    stream = side.cuda_stream
     hvx.hvx_batch_schedule(b, stream, ctx=ctx)
     torch.cuda.synchronize()
     compare(spec, _read(outs), spec.run_oracle(), phase_names=("ph",))

@@ -55,7 +55,8 @@ def _run_modes(ctx, graphs, outs, check):
     gets the per-image outputs of the first mode, and the second mode must
     reproduce them byte for byte."""
     import torch
-    stream = torch.cuda.current_stream().cuda_stream
+    side = torch.cuda.Stream()  # capturable (the null stream is not)
+    stream = side.cuda_stream
     b = hvx.hvx_batch_create(ctx, graphs)
     hvx.hvx_batch_autotune(b, stream, 1, ctx=ctx)
     log("batch tuned: rows %d, %d work items" % (hvx.hvx_batch_query(b, hvx.HVX_QUERY_ROWS_PER_ITEM),
@@ -203,3 +204,49 @@ def test_multiply_f32_exact(ctx):
     log("multiply f32")
     got, _ = run_spec(spec, ctx, fusion=False)
     assert np.array_equal(got["out"], env["out"].astype(np.float32))
+
+
+# ---- extremes of the accepted sizes ----------------------------------------------
+
+@pytest.mark.parametrize("w,h", [(65536, 3), (3, 65536), (65535, 2)])
+def test_edge_phase_extreme_shapes(ctx, w, h):
+    """Widest and tallest images the API accepts (65536), through the fused
+    edge+phase kernel and through the node-by-node path."""
+    img = synth.edge_image(w, h, seed=w % 97 + h)
+    spec = gs.edge_spec(img, phase=True)
+    env = spec.run_oracle()
+    log("edge extreme %dx%d" % (w, h))
+    got, g = run_spec(spec, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_KERNEL_KIND) == 1
+    compare(spec, got, env, phase_names=("ph",))
+    unf, _ = run_spec(spec, ctx, fusion=False)
+    compare(spec, unf, env, phase_names=("ph",))
+
+
+def test_empty_and_generic_only_batches(ctx):
+    """A batch of no graphs is a no-op; a batch whose graphs all need the
+    generic kernels has no single launch and runs them one after another."""
+    import torch
+    side = torch.cuda.Stream()  # capturable (the null stream is not)
+    stream = side.cuda_stream
+    b = hvx.hvx_batch_create(ctx, [])
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_OPS) == 0
+    hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+    torch.cuda.synchronize()
+    hvx.hvx_release_batch(b)
+    img = synth.edge_image(333, 41, seed=8)
+    spec = gs.Spec([gs.N("box3x3", ["in"], ["b"]), gs.N("add", ["in", "b"], ["out"], params={"policy": "wrap"})],
+                   {"in": img}, {"out": np.uint8})
+    graphs, outs, keep = _build_batch(ctx, [spec, spec])
+    b = hvx.hvx_batch_create(ctx, graphs)
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_OPS) == 0
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) == 2
+    log("generic-only batch")
+    hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+    torch.cuda.synchronize()
+    env = spec.run_oracle()
+    for o in outs:
+        compare(spec, {"out": o["out"][0][:, :o["out"][1]].cpu().numpy()}, env)
+    hvx.hvx_release_batch(b)
+    for g in graphs:
+        hvx.hvx_release_graph(g)
