@@ -5,7 +5,7 @@ One step = one execution of the verified graph Gaussian3x3 -> Sobel3x3 ->
 {Magnitude -> Threshold at 100, Phase} (REPLICATE borders; two U8 outputs)
 over F distinct 3840x2160 U8 frames resident in HBM (3 B/px, >= 1.5 GB of
 distinct buffers, so the 256 MB last-level cache cannot serve them), issued
-as one batch launch replayed from a captured HIP graph.  value = MPix/s of
+as one batch launch (a single kernel, so no HIP graph).  value = MPix/s of
 the whole job.  The JSON line also reports the roofline of that kernel, the
 CPU oracle on a bounded sample, and context measurements under "extras": the
 same graph without Phase (2 B/px), 8K frames, CONSTANT(0) borders,
@@ -473,7 +473,7 @@ def run(args, torch, hvx, ctx):
                    "graph": "Gaussian3x3->Sobel3x3->{Magnitude->Threshold(100), Phase}",
                    "border": "replicate", "outputs": "edge map U8 + phase U8", "width": W, "height": H, "frames_per_step": args.frames,
                    "rows_per_item": r["per_mode"]["rows_per_item"],
-                   "launch": "%s batch kernel, HIP-graph replay" % r["mode"],
+                   "launch": "%s batch kernel, one launch per step" % r["mode"],
                    "batch_mode_ms": r["per_mode"]},
         "roofline": {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,

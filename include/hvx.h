@@ -242,8 +242,9 @@ hvx_status hvx_process_batch(hvx_context ctx, const hvx_graph* graphs, uint32_t 
 hvx_status hvx_batch_query(hvx_batch b, int attr, int64_t* out);
 /* Batch options.  HVX_BATCH_PERSISTENT (default 1): a grid sized to the
  * machine pulls chunks of work items from per-XCD atomic counters; 0: one
- * wave per work item.  HVX_BATCH_USE_GRAPH (default 1): capture the launches
- * once into a HIP graph and replay it.  HVX_BATCH_ROWS (default 0): rows per
+ * wave per work item.  HVX_BATCH_USE_GRAPH (default 1): when a schedule
+ * takes more than one launch, capture them once into a HIP graph and replay
+ * it (a single launch, or the legacy null stream, is launched plainly).  HVX_BATCH_ROWS (default 0): rows per
  * work item for every image of the single launch (1..65535), 0 = each
  * graph's own; it is what hvx_batch_autotune sets, and setting it pins a
  * launch shape (e.g. a tuned one) without re-tuning.  Changing an option

@@ -364,6 +364,14 @@ static hvx_status batch_build(Batch* b) {
   return HVX_SUCCESS;
 }
 
+// kernel launches of one schedule: the single batch launch plus the plans of
+// the graphs it cannot hold
+static int64_t batch_launches(const Batch* b) {
+  int64_t k = b->total > 0 ? 1 : 0;
+  for (Graph* g : b->separate) k += (int64_t)g->plan->groups.size();
+  return k;
+}
+
 static hvx_status batch_enqueue(Batch* b, hipStream_t s) {
   if (b->total > 0) {
     hipError_t e = launch_batch(b->d_imgs, b->d_item_img, b->total, b->d_counter, b->grid, b->persistent, b->kinds, s);
@@ -425,9 +433,11 @@ hvx_status hvx_batch_schedule(hvx_batch hb, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hvx_status st = ensure_device(b->ctx);
   if (st) return st;
-  if (b->total == 0 && b->separate.empty()) return HVX_SUCCESS;  // nothing to launch
-  // the legacy null stream cannot be captured: there the launches are plain
-  if (b->use_graph && s != nullptr) {
+  const int64_t launches = batch_launches(b);
+  if (launches == 0) return HVX_SUCCESS;  // nothing to launch
+  // A graph pays off only for several launches (a replay costs more than one
+  // plain launch), and the legacy null stream cannot be captured at all.
+  if (b->use_graph && s != nullptr && launches > 1) {
     if (!b->exec) {
       // capture once: the persistent launch plus the launches of any graph
       // that is not expressible as batch work items
@@ -466,12 +476,7 @@ hvx_status hvx_batch_query(hvx_batch hb, int attr, int64_t* out) {
   if (!out) return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "null output");
   switch (attr) {
     case HVX_QUERY_ALG_BYTES: *out = b->alg_bytes; break;
-    case HVX_QUERY_NUM_KERNELS: {
-      int64_t k = b->total > 0 ? 1 : 0;
-      for (Graph* g : b->separate) k += (int64_t)g->plan->groups.size();
-      *out = k;
-      break;
-    }
+    case HVX_QUERY_NUM_KERNELS: *out = batch_launches(b); break;
     case HVX_QUERY_NUM_OPS: *out = b->total; break;  // work items of the persistent launch
     case HVX_QUERY_ROWS_PER_ITEM: *out = b->rows_override; break;  // 0: each graph's own
     default: return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown batch query %d", attr);
