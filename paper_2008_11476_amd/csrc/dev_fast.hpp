@@ -40,6 +40,20 @@ __device__ __forceinline__ u32 alignbit16(u32 hi, u32 lo) { return __builtin_amd
 // without a source reads 0, which only halo lanes ever see)
 __device__ __forceinline__ u32 from_left(u32 v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
 __device__ __forceinline__ u32 from_right(u32 v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
+// The same shifts kept as separate v_mov_b32_dpp instructions (the empty asm
+// stops the compiler from folding them into the consuming add or subtract).
+// Folded into v_add_u32_dpp / v_subrev_u32_dpp with wave_shr:1, they gave
+// wrong corner-kernel results on gfx950 in every lane.
+__device__ __forceinline__ u32 from_left_mov(u32 v) {
+  u32 r = from_left(v);
+  asm("" : "+v"(r));
+  return r;
+}
+__device__ __forceinline__ u32 from_right_mov(u32 v) {
+  u32 r = from_right(v);
+  asm("" : "+v"(r));
+  return r;
+}
 __device__ __forceinline__ u32 bfi(u32 mask, u32 a, u32 b) { return (mask & a) | (~mask & b); }
 
 __device__ __forceinline__ u32 add2(u32 a, u32 b) {
@@ -573,13 +587,15 @@ __device__ __forceinline__ Lanes4 make_lanes(const StripGrid& g, int strip) {
   return L;
 }
 
-__device__ __forceinline__ int ileft(int v) { return (int)from_left((u32)v); }
-__device__ __forceinline__ int iright(int v) { return (int)from_right((u32)v); }
+__device__ __forceinline__ int ileft(int v) { return (int)from_left_mov((u32)v); }
+__device__ __forceinline__ int iright(int v) { return (int)from_right_mov((u32)v); }
 
 // e[0..7] = values at x-2, x-1, x..x+3, x+4, x+5 after the border rule.
-template <int R>
+// HEDGE: the strip touches the left or right image edge; other strips need
+// no border work at all.
+template <int R, bool HEDGE>
 __device__ __forceinline__ void extend4(int p[4], int e[8], const Lanes4& L, bool repl, int c) {
-  if (L.edgeR && L.m != 0) {
+  if (HEDGE && L.edgeR && L.m != 0) {
     const int last = L.m == 1 ? p[0] : (L.m == 2 ? p[1] : p[2]);
     const int f = repl ? last : c;
 #pragma unroll
@@ -598,12 +614,12 @@ __device__ __forceinline__ void extend4(int p[4], int e[8], const Lanes4& L, boo
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) e[k + 2] = p[k];
-  if (L.edgeL && L.mL) {
+  if (HEDGE && L.edgeL && L.mL) {
     const int f = repl ? p[0] : c;
     e[1] = f;
     if (R >= 2) e[0] = f;
   }
-  if (L.edgeR) {
+  if (HEDGE && L.edgeR) {
     if (L.mR) {
       const int f = repl ? p[3] : c;
       e[6] = f;
@@ -637,6 +653,7 @@ __device__ __forceinline__ u32 load_row(const St& s, int y) {
 __device__ __forceinline__ int byte_of(u32 r, int k) { return (int)((r >> (8 * k)) & 0xFF); }
 
 // Horizontal 5-sums of the three products at in-image row r (rows r-1, r, r+1 given).
+template <bool HEDGE>
 __device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3][4]) {
   int sv[4], dv[4];
 #pragma unroll
@@ -646,8 +663,8 @@ __device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3]
     dv[k] = ck - ak;
   }
   int es[8], ed[8];
-  extend4<1>(sv, es, s.L, s.repl0, 4 * s.c0);
-  extend4<1>(dv, ed, s.L, s.repl0, 0);
+  extend4<1, HEDGE>(sv, es, s.L, s.repl0, 4 * s.c0);
+  extend4<1, HEDGE>(dv, ed, s.L, s.repl0, 0);
   int p[3][4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -660,7 +677,7 @@ __device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3]
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     int e[8];
-    extend4<2>(p[q], e, s.L, s.repl1, s.c1);
+    extend4<2, HEDGE>(p[q], e, s.L, s.repl1, s.c1);
     const int t01 = e[0] + e[1], t23 = e[2] + e[3], t45 = e[4] + e[5], t67 = e[6] + e[7];
     h[q][0] = t01 + t23 + e[4];
     h[q][1] = e[1] + t23 + t45;
@@ -671,11 +688,12 @@ __device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3]
 
 }  // namespace corner
 
-__device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int band) {
+template <bool HEDGE>
+__device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::Lanes4& lanes, int band) {
   using namespace corner;
   St s;
   s.d = &d;
-  s.L = corner::make_lanes(d.g, strip);
+  s.L = lanes;
   s.inb = d.in + s.L.xl;
   s.repl0 = d.b0 != B_CONSTANT;
   s.repl1 = d.b1 != B_CONSTANT;
@@ -701,7 +719,7 @@ __device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int 
         for (int k = 0; k < 4; ++k) out[q][k] = s.repl1 ? prev[q][k] : 5 * s.c1;
       return;
     }
-    hsums(s, ia, ib, ic, out);
+    hsums<HEDGE>(s, ia, ib, ic, out);
     ia = ib;
     ib = ic;
     ic = load_row(s, r + 2);
@@ -771,6 +789,12 @@ __device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int 
       }
     }
   }
+}
+
+__device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int band) {
+  const corner::Lanes4 L = corner::make_lanes(d.g, strip);
+  if (L.edgeL || L.edgeR) corner_band<true>(d, L, band);
+  else corner_band<false>(d, L, band);
 }
 
 }  // namespace hvx
