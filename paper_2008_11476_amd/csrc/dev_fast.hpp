@@ -706,6 +706,12 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
   // input rows r-1, r, r+1 for the next gradient row r = nr
   int nr = max(y0 - 2, 0);
   u32 ia = load_row(s, nr - 1), ib = load_row(s, nr), ic = load_row(s, nr + 1);
+  // the next kPf input rows, loaded ahead: a row is four bytes per lane, so
+  // a deep queue costs few registers and hides the load latency
+  constexpr int kPf = 3;
+  u32 pf[kPf];
+#pragma unroll
+  for (int k = 0; k < kPf; ++k) pf[k] = load_row(s, nr + 2 + k);
   // H rows of the product planes; row y of the box needs rows y-2..y+2
   int ring[5][3][4];
   // H row r into out; `prev` holds H row r-1 (rows below the image repeat it
@@ -722,7 +728,10 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
     hsums<HEDGE>(s, ia, ib, ic, out);
     ia = ib;
     ib = ic;
-    ic = load_row(s, r + 2);
+    ic = pf[0];
+#pragma unroll
+    for (int k = 0; k + 1 < kPf; ++k) pf[k] = pf[k + 1];
+    pf[kPf - 1] = load_row(s, r + 2 + kPf);
   };
   // prologue: rows y0-2 .. y0+2; above the image REPLICATE needs row 0 first
   if (y0 - 2 < 0) {
