@@ -232,7 +232,7 @@ def extras(hvx, torch, ctx, quick=False):
         hvx.hvx_release_graph(x)
     del inp, out
     torch.cuda.empty_cache()
-    # mixed batch: 256 images of random sizes and kinds in one persistent launch
+    # mixed batch: 256 images of random sizes and kinds in one launch
     shapes = synth.batch_shapes(256, seed=0)
     keep, graphs = [], []
     total_px = 0

@@ -219,7 +219,7 @@ hvx_status hvx_graph_autotune(hvx_graph g, void* hip_stream, int iters);
 hvx_status hvx_context_save_tune_cache(hvx_context ctx, const char* path);
 hvx_status hvx_context_load_tune_cache(hvx_context ctx, const char* path);
 
-/* ---- batches: many verified graphs in one persistent launch ------------- */
+/* ---- batches: many verified graphs in one kernel launch ----------------- */
 
 /* Build a batch over n verified graphs (any mix of kinds and sizes).  The
  * work items of every graph whose plan is one hand-fused kernel go into one

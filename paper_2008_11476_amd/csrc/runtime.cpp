@@ -270,7 +270,7 @@ struct Batch : Object {
   hipGraphExec_t exec = nullptr;
   int64_t alg_bytes = 0;
   int rows_override = 0;  // rows per work item for every image (0: each graph's own)
-  int kinds = 0;          // bit set of the kinds in the persistent launch
+  int kinds = 0;          // bit set of the kinds in the single batch launch
   void* last_stream = nullptr;
   bool scheduled = false;
 };
@@ -439,7 +439,7 @@ hvx_status hvx_batch_schedule(hvx_batch hb, void* stream) {
   // plain launch), and the legacy null stream cannot be captured at all.
   if (b->use_graph && s != nullptr && launches > 1) {
     if (!b->exec) {
-      // capture once: the persistent launch plus the launches of any graph
+      // capture once: the batch launch plus the launches of any graph
       // that is not expressible as batch work items
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
       if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "begin capture: %s", hipGetErrorString(e));
@@ -477,7 +477,7 @@ hvx_status hvx_batch_query(hvx_batch hb, int attr, int64_t* out) {
   switch (attr) {
     case HVX_QUERY_ALG_BYTES: *out = b->alg_bytes; break;
     case HVX_QUERY_NUM_KERNELS: *out = batch_launches(b); break;
-    case HVX_QUERY_NUM_OPS: *out = b->total; break;  // work items of the persistent launch
+    case HVX_QUERY_NUM_OPS: *out = b->total; break;  // work items of the single batch launch
     case HVX_QUERY_ROWS_PER_ITEM: *out = b->rows_override; break;  // 0: each graph's own
     default: return set_error(b->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown batch query %d", attr);
   }

@@ -3,7 +3,7 @@
 // CONTINUOUS mode: a worker thread admits queued requests in arrival order
 // while their device buffers fit in the HBM budget and a slot is free, packs
 // every admitted request into one device step (host-to-device copies, one
-// persistent batch launch over all their work items, device-to-host copies)
+// batch launch over all their work items, device-to-host copies)
 // on a stream with no step in flight, and retires steps as their completion
 // events fire.  With n_streams >= 2, requests that arrive while a step runs
 // start in a new step that overlaps it on the device.
@@ -103,7 +103,6 @@ struct StreamSlot {
   hipEvent_t done = nullptr;
   BatchImage* d_imgs = nullptr;
   uint16_t* d_items = nullptr;
-  unsigned* d_counter = nullptr;
   BatchImage* h_imgs = nullptr;  // pinned staging
   uint16_t* h_items = nullptr;
   size_t cap_imgs = 0, cap_items = 0;
@@ -133,7 +132,6 @@ struct Server : Object {
   int64_t submitted = 0, completed = 0, steps = 0;
   bool stop = false;
   std::thread worker;
-  int grid = 1;
 };
 
 static bool batchable(const Graph* g) {
@@ -235,8 +233,9 @@ static bool launch_step(Server* sv, StreamSlot& sl, std::vector<Request*>& reqs)
       return false;
     int kinds = 0;
     for (const BatchImage& bi : imgs) kinds |= kind_bit(bi);
-    const int grid = std::max(1, std::min((int)nitems, sv->ctx->num_cus * batch_waves_per_cu(kinds)));
-    if (launch_batch(sl.d_imgs, sl.d_items, (int)nitems, sl.d_counter, grid, true, kinds, s) != hipSuccess)
+    // one wave per work item (the direct form measured faster than the
+    // persistent one on every batch shape served here)
+    if (launch_batch(sl.d_imgs, sl.d_items, (int)nitems, nullptr, 1, false, kinds, s) != hipSuccess)
       return false;
   }
   for (Request* r : live) {
@@ -336,7 +335,6 @@ void destroy_server_object(Object* o) {
     if (sl.s) (void)hipStreamDestroy(sl.s);
     if (sl.d_imgs) (void)hipFree(sl.d_imgs);
     if (sl.d_items) (void)hipFree(sl.d_items);
-    if (sl.d_counter) (void)hipFree(sl.d_counter);
     if (sl.h_imgs) (void)hipHostFree(sl.h_imgs);
     if (sl.h_items) (void)hipHostFree(sl.h_items);
   }
@@ -378,16 +376,12 @@ hvx_status hvx_server_create(hvx_context ctx, int mode, size_t budget, uint32_t 
   for (StreamSlot& sl : sv->slots) {
     // default priority streams only
     if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc((void**)&sl.d_counter, batch_counter_bytes()) != hipSuccess ||
-        hipMemset(sl.d_counter, 0, batch_counter_bytes()) != hipSuccess) {
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
       registry_add(sv);
       destroy_server_object(sv);
       return set_error(c, HVX_ERROR_DEVICE, "server stream setup failed");
     }
   }
-  (void)hipDeviceSynchronize();
-  sv->grid = c->num_cus * batch_waves_per_cu(7);
   registry_add(sv);
   {
     std::lock_guard<std::recursive_mutex> l(c->mu);
@@ -410,6 +404,8 @@ hvx_status hvx_server_submit(hvx_server hs, hvx_graph templ, const void* in, siz
   }
   if (!batchable(g))
     return set_error(sv->ctx, HVX_ERROR_NOT_SUPPORTED, "template must be a single fused kernel of a served kind");
+  if (g->plan->groups[0].inputs.size() != 1 || g->plan->groups[0].outputs.size() != 1)
+    return set_error(sv->ctx, HVX_ERROR_NOT_SUPPORTED, "template must have one input and one output image");
   if (!in || !out) return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "null host buffer");
   const Group& gr = g->plan->groups[0];
   Request* r = new Request();

@@ -1,4 +1,4 @@
-"""GPU tests of batched execution (one persistent launch over many graphs,
+"""GPU tests of batched execution (one kernel launch over many graphs,
 replayed from a captured HIP graph) and of the serving loop: every result
 must equal the same graph run alone, and the oracle."""
 import time
@@ -97,7 +97,7 @@ def test_batch_equals_alone_and_oracle(ctx, persistent):
     torch.cuda.synchronize()
     b = hvx.hvx_batch_create(ctx, [x[2] for x in built])
     hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, persistent)
-    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) >= 2  # persistent launch + separate graphs
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) >= 2  # the batch launch + separate graphs
     side = torch.cuda.Stream()  # capturable (the null stream is not)
     stream = side.cuda_stream
     for rep in range(3):  # capture, then replays with eager work in between
@@ -259,4 +259,24 @@ def test_server_limits(ctx):
         hvx.hvx_server_submit(s, templ[("sobel_edge", 640, 480)], src.data_ptr(), 640, dst.data_ptr(), 640, 1,
                               ctx=ctx)
     assert e.value.status == hvx.HVX_ERROR_NO_MEMORY
+    hvx.hvx_release_server(s)
+
+
+def test_server_rejects_unservable_templates(ctx):
+    """Only single-kernel templates with one input and one output image are
+    served: an edge graph with its Phase output, or a graph that needs the
+    generic kernels, is refused at submission."""
+    import torch
+    w, h = 256, 64
+    img = synth.edge_image(w, h, seed=2)
+    s = hvx.hvx_server_create(ctx, hvx.HVX_SERVER_CONTINUOUS, 64 << 20, 4, 2)
+    src = torch.zeros((h, w), dtype=torch.uint8).pin_memory()
+    dst = torch.zeros((h, w), dtype=torch.uint8).pin_memory()
+    for spec in (gs.edge_spec(img, phase=True),
+                 gs.Spec([gs.N("box3x3", ["in"], ["out"])], {"in": img}, {"out": np.uint8})):
+        g, outs, keep, imgs = _build(ctx, spec)
+        with pytest.raises(hvx.HvxError) as e:
+            hvx.hvx_server_submit(s, g, src.data_ptr(), w, dst.data_ptr(), w, 7, ctx=ctx)
+        assert e.value.status == hvx.HVX_ERROR_NOT_SUPPORTED
+        hvx.hvx_release_graph(g)
     hvx.hvx_release_server(s)
