@@ -639,18 +639,38 @@ struct St {
   int c0, c1;
 };
 
-// The lane's four input pixels of row y as packed bytes (the border constant
-// outside the image under CONSTANT); kept packed so that the three rows a
-// gradient row needs cost three registers.
-__device__ __forceinline__ u32 load_row(const St& s, int y) {
-  const int H = s.d->g.h;
-  const int yc = min(max(y, 0), H - 1);
-  u32 r = __builtin_nontemporal_load((const u32*)(s.inb + (size_t)yc * s.d->in_pitch));
-  if (!s.repl0 && (y < 0 || y >= H)) r = 0x01010101u * (u32)s.c0;
-  return r;
-}
-
 __device__ __forceinline__ int byte_of(u32 r, int k) { return (int)((r >> (8 * k)) & 0xFF); }
+
+// Input rows travel through a queue of kQ rows in this wave's LDS, filled by
+// direct-to-LDS loads (64 lanes x 4 bytes per row): the loads run kQ rows
+// ahead without holding VGPRs.  The compiler does not track these loads
+// against the LDS reads, so the waits are explicit: before a row is read,
+// at most kQ - 1 vector-memory operations may still be outstanding (they
+// complete in issue order, stores included, so the row's load is done), and
+// the read itself completes before its slot is refilled.
+constexpr int kQ = 8;
+
+struct RowQueue {
+  u32* buf;  // kQ x 64 dwords of LDS
+  const uint8_t* src;
+  int64_t pitch;
+  int H, base, lane;
+  bool repl;
+  u32 fill;
+  __device__ __forceinline__ void issue(int y) {
+    const int yc = min(max(y, 0), H - 1);
+    __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)yc * pitch),
+                                     (__attribute__((address_space(3))) void*)(buf + ((y - base) & (kQ - 1)) * 64), 4,
+                                     0, 0);
+  }
+  __device__ __forceinline__ u32 take(int y) {
+    asm volatile("s_waitcnt vmcnt(7)" ::: "memory");  // kQ - 1
+    u32 r = buf[((y - base) & (kQ - 1)) * 64 + lane];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (!repl && (y < 0 || y >= H)) r = fill;
+    return r;
+  }
+};
 
 // Horizontal 5-sums of the three products at in-image row r (rows r-1, r, r+1 given).
 template <bool HEDGE>
@@ -689,7 +709,7 @@ __device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3]
 }  // namespace corner
 
 template <bool HEDGE>
-__device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::Lanes4& lanes, int band) {
+__device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::Lanes4& lanes, int band, u32* qbuf) {
   using namespace corner;
   St s;
   s.d = &d;
@@ -703,15 +723,18 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
   const int y0 = band * d.g.rows;
   const int y1 = min(y0 + d.g.rows, H);
 
-  // input rows r-1, r, r+1 for the next gradient row r = nr
+  // input rows r-1, r, r+1 for the next gradient row r = nr, then rows
+  // further down through the LDS queue
   int nr = max(y0 - 2, 0);
-  u32 ia = load_row(s, nr - 1), ib = load_row(s, nr), ic = load_row(s, nr + 1);
-  // the next kPf input rows, loaded ahead: a row is four bytes per lane, so
-  // a deep queue costs few registers and hides the load latency
-  constexpr int kPf = 3;
-  u32 pf[kPf];
+  RowQueue q{qbuf, s.inb, d.in_pitch, H, nr - 1, s.L.lane, s.repl0, 0x01010101u * (u32)s.c0};
 #pragma unroll
-  for (int k = 0; k < kPf; ++k) pf[k] = load_row(s, nr + 2 + k);
+  for (int k = 0; k < kQ; ++k) q.issue(nr - 1 + k);
+  u32 ia = q.take(nr - 1);
+  q.issue(nr - 1 + kQ);
+  u32 ib = q.take(nr);
+  q.issue(nr + kQ);
+  u32 ic = q.take(nr + 1);
+  q.issue(nr + 1 + kQ);
   // H rows of the product planes; row y of the box needs rows y-2..y+2
   int ring[5][3][4];
   // H row r into out; `prev` holds H row r-1 (rows below the image repeat it
@@ -728,10 +751,8 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
     hsums<HEDGE>(s, ia, ib, ic, out);
     ia = ib;
     ib = ic;
-    ic = pf[0];
-#pragma unroll
-    for (int k = 0; k + 1 < kPf; ++k) pf[k] = pf[k + 1];
-    pf[kPf - 1] = load_row(s, r + 2 + kPf);
+    ic = q.take(r + 2);
+    q.issue(r + 2 + kQ);
   };
   // prologue: rows y0-2 .. y0+2; above the image REPLICATE needs row 0 first
   if (y0 - 2 < 0) {
@@ -801,9 +822,12 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
 }
 
 __device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int band) {
+  __shared__ u32 qbuf[corner::kQ * 64];
   const corner::Lanes4 L = corner::make_lanes(d.g, strip);
-  if (L.edgeL || L.edgeR) corner_band<true>(d, L, band);
-  else corner_band<false>(d, L, band);
+  if (L.edgeL || L.edgeR) corner_band<true>(d, L, band, qbuf);
+  else corner_band<false>(d, L, band, qbuf);
+  // no load into the queue may still be in flight when the wave moves on
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 }  // namespace hvx
