@@ -502,7 +502,7 @@ hvx_status hvx_batch_autotune(hvx_batch hb, void* stream, int iters) {
   int best_rows = b->rows_override;
   bool best_persistent = b->persistent;
   hvx_status s = HVX_SUCCESS;
-  static const int cand_rows[] = {0, 8, 16, 32, 64, 128};
+  static const int cand_rows[] = {0, 8, 16, 24, 32, 40, 48, 64, 128};
   for (int rows : cand_rows) {
     b->rows_override = rows;
     s = batch_build(b);
