@@ -216,6 +216,35 @@ def extras(hvx, torch, ctx, quick=False):
     r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 10, 2, phase=True, border=(hvx.HVX_BORDER_CONSTANT, 0))
     rec("edge_phase_4k_constant0_batch64", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
                                       "ms": round(r["ms"], 3)})
+    # Gaussian5x5 on 64 4K frames: U8 input (2 B/px) and UYVY input (3 B/px)
+    for uyvy in (False, True):
+        W4, H4, n = 3840, 2160, 64
+        ins, outs = [], []
+        for i in range(n):
+            if uyvy:
+                ib, iv = hvx.alloc_image(H4, W4, hvx.HVX_DF_UYVY)
+                if i < 4:
+                    iv.copy_(torch.from_numpy(synth.uyvy_image(W4, H4, seed=i)))
+                else:
+                    iv.copy_(ins[i % 4][1] ^ ((i // 4) * 37 % 256))
+            else:
+                ib, iv = hvx.alloc_image(H4, W4, hvx.HVX_DF_U8)
+                if i < 4:
+                    iv.copy_(torch.from_numpy(synth.edge_image(W4, H4, seed=i)))
+                else:
+                    iv.copy_(ins[i % 4][1] ^ ((i // 4) * 37 % 256))
+            ins.append((ib, iv))
+            outs.append([hvx.alloc_image(H4, W4, hvx.HVX_DF_U8)])
+        graphs = [gauss5_graph(hvx, ctx, ins[i][1], outs[i], uyvy=uyvy, w=W4) for i in range(n)]
+        ms, _, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, 10, 2)
+        rec("uyvy_gauss5_4k_batch64" if uyvy else "gauss5_4k_batch64",
+            {"mpix_s": round(n * W4 * H4 / 1e6 / (ms / 1e3), 1), "alg_gbs": round(alg / (ms / 1e3) / 1e9, 1),
+             "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms, 4),
+             "batch_mode_ms": per_mode})
+        for x in graphs:
+            hvx.hvx_release_graph(x)
+        del ins, outs
+        torch.cuda.empty_cache()
     # corner graph at 1080p: single frame and 32-frame batch
     inp, out = make_frames(hvx, torch, 1920, 1080, 32)
     graphs = [corner_graph(hvx, ctx, inp[i][1], out[i]) for i in range(32)]
