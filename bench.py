@@ -28,8 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# 32-bit VALU lane operations per second: 256 CUs x 64 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD per 4 cycles
+VALU_SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
 
 
 def log(*a):
@@ -485,6 +486,18 @@ def run(args, torch, hvx, ctx):
         if (t.get("kernel_hash") == kernel_source_hash() and t.get("kernel") == kernel
                 and t.get("rows_per_item") == r["per_mode"]["rows_per_item"]):
             traffic = t.get("bytes_per_launch")
+    # VALU instructions per launch from the committed SQ counter summary (same
+    # kernel sources and launch shape only): the share of the machine's VALU
+    # issue slots the timed launches used, 1024 SIMDs x one wave64
+    # instruction per 4 cycles at 2.4 GHz
+    valu_frac = None
+    vfile = os.path.join(ROOT, "profiles", "edge_phase_4k_batch_valu.json")
+    if os.path.exists(vfile):
+        v = json.load(open(vfile))
+        if (v.get("kernel_hash") == kernel_source_hash() and v.get("kernel") == kernel
+                and v.get("rows_per_item") == r["per_mode"]["rows_per_item"]):
+            slots = VALU_SIMDS * (ms * 1e-3) * CLOCK_HZ / 4
+            valu_frac = round(v["valu_insts_per_launch"] / slots, 4)
     out = {
         "metric": "fused-graph MPix/s + % HBM peak (4K Sobel); served p50/p99 latency vs plain",
         "value": round(r["mpix_s"], 1),
@@ -508,7 +521,8 @@ def run(args, torch, hvx, ctx):
                      "frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kernel, "work_items": r["per_mode"]["work_items"],
                      "alg_bytes_per_launch": r["alg_bytes"],
-                     "avg_launch_ms": round(ms, 4), "plain_copy_gbs": copy_ref["gbs"]},
+                     "avg_launch_ms": round(ms, 4), "plain_copy_gbs": copy_ref["gbs"],
+                     "valu_issue_frac": valu_frac},
     }
     log("headline (edge+phase): %.1f MPix/s, %.1f GB/s (%.1f%% of peak), %.3f ms/step, host %.3f ms/step" % (
         r["mpix_s"], r["gbs"], 100 * r["gbs"] / HBM_PEAK_GBS, ms, r["ms_host"]))
