@@ -35,6 +35,26 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32 perm(u32 hi, u32 lo, u32 sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
+
+// Row access at base + y * pitch + off, off being the lane's byte offset.
+// GLOBAL issues global (address space 1) instead of flat instructions; the
+// choice changes only where the compiler places its memory waits, and was
+// measured per kernel (flat for the edge streams, global for the Gaussian5x5
+// streams, a few percent each way).
+typedef __attribute__((address_space(1))) const u32x4 g_cu32x4;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+template <bool GLOBAL>
+__device__ __forceinline__ u32x4 load_row16(const uint8_t* base, int64_t pitch, int y, u32 off) {
+  const uint8_t* p = base + off + (size_t)((int64_t)y * pitch);
+  if (GLOBAL) return __builtin_nontemporal_load((g_cu32x4*)p);
+  return __builtin_nontemporal_load((const u32x4*)p);
+}
+template <bool GLOBAL>
+__device__ __forceinline__ void store_row16(uint8_t* base, int64_t pitch, int y, u32 off, u32x4 v) {
+  uint8_t* p = base + off + (size_t)((int64_t)y * pitch);
+  if (GLOBAL) __builtin_nontemporal_store(v, (g_u32x4*)p);
+  else __builtin_nontemporal_store(v, (u32x4*)p);
+}
 __device__ __forceinline__ u32 alignbit16(u32 hi, u32 lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }
 // lane i receives lane i-1's value / lane i+1's value (whole-wave shifts; the lane
 // without a source reads 0, which only halo lanes ever see)
@@ -216,9 +236,15 @@ struct EdgeStream {
   int H;
   bool repl0, repl1;
   u32 cin, cv0, cg, cs1;
-  const uint8_t* inb;
-  uint8_t* outb;
-  uint8_t* phb;
+  // image bases and pitches copied out of the descriptor (wave-uniform, so
+  // row addresses are scalar arithmetic) and the lane's byte offsets
+  const uint8_t* in0;
+  uint8_t* out0;
+  uint8_t* ph0;
+  int64_t ip, op, pp;
+  u32 lin, lout;
+  int thr;
+  u32 tv4, x4;
   // rotating state
   u32 inr[2][8];  // input row y+1 (role alternates)
   u32 tr[2][8];   // in(y) + in(y+1)
@@ -236,13 +262,21 @@ struct EdgeStream {
     cv0 = (4 * c0) | ((4 * c0) << 16);
     cg = c1 | (c1 << 16);
     cs1 = (4 * c1) | ((4 * c1) << 16);
-    inb = d.in + L.xl;
-    outb = d.out + L.xs;
-    phb = PHASE ? d.phase + L.xs : nullptr;
+    in0 = d.in;
+    out0 = d.out;
+    ph0 = PHASE ? d.phase : nullptr;
+    ip = d.in_pitch;
+    op = d.out_pitch;
+    pp = PHASE ? d.phase_pitch : 0;
+    lin = (u32)L.xl;
+    lout = (u32)L.xs;  // wraps for the left halo lane, which never stores
+    thr = d.thr_not;
+    tv4 = d.tv4;
+    x4 = d.tv4 ^ d.fv4;
   }
   __device__ __forceinline__ u32x4 load(int y) const {
     const int yc = min(max(y, 0), H - 1);
-    return __builtin_nontemporal_load((const u32x4*)(inb + (size_t)yc * d.in_pitch));
+    return load_row16<false>(in0, ip, yc, lin);
   }
   __device__ __forceinline__ void unpk(u32x4 r, int y, u32 p[8]) const {
     unpack16(r, p);
@@ -286,7 +320,7 @@ struct EdgeStream {
       po.y = perm(a67, a45, 0x05040100u);
       po.z = perm(a23, a01, 0x07060302u);
       po.w = perm(a67, a45, 0x07060302u);
-      if (L.store) __builtin_nontemporal_store(po, (u32x4*)(phb + (size_t)y * d.phase_pitch));
+      if (L.store) store_row16<false>(ph0, pp, y, lout, po);
     }
     // magnitude + threshold as one integer test: gx^2 + gy^2 > T, i.e. the
     // sign of gx^2 + gy^2 + thr_not.  v_mad_i32_i16 multiplies the selected
@@ -296,9 +330,9 @@ struct EdgeStream {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       int t0, t1, r0, r1;
-      asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(t0) : "v"(gx[k]), "s"(d.thr_not));
+      asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(t0) : "v"(gx[k]), "s"(thr));
       asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(r0) : "v"(gy[k]), "v"(t0));
-      asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(t1) : "v"(gx[k]), "s"(d.thr_not));
+      asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(t1) : "v"(gx[k]), "s"(thr));
       asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(r1) : "v"(gy[k]), "v"(t1));
       r[k] = (u32)r0;
       r[k + 8] = (u32)r1;
@@ -306,12 +340,11 @@ struct EdgeStream {
     u32x4 o;
     // mask bytes are 0xFF where the sum is below the bound (no edge);
     // out = tv ^ (mask & (tv ^ fv)) picks fv there and tv elsewhere
-    const u32 x4 = d.tv4 ^ d.fv4;
-    o.x = d.tv4 ^ ((perm(r[1], r[0], 0x0c0c0b09u) | perm(r[3], r[2], 0x0b090c0cu)) & x4);
-    o.y = d.tv4 ^ ((perm(r[5], r[4], 0x0c0c0b09u) | perm(r[7], r[6], 0x0b090c0cu)) & x4);
-    o.z = d.tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
-    o.w = d.tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
-    if (L.store) __builtin_nontemporal_store(o, (u32x4*)(outb + (size_t)y * d.out_pitch));
+    o.x = tv4 ^ ((perm(r[1], r[0], 0x0c0c0b09u) | perm(r[3], r[2], 0x0b090c0cu)) & x4);
+    o.y = tv4 ^ ((perm(r[5], r[4], 0x0c0c0b09u) | perm(r[7], r[6], 0x0b090c0cu)) & x4);
+    o.z = tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
+    o.w = tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
+    if (L.store) store_row16<false>(out0, op, y, lout, o);
   }
   // Output row y; J is the phase of y in the six-row unrolled sequence.
   template <int J>
@@ -419,8 +452,11 @@ struct G5Stream {
   int H;
   bool repl;
   u32 cin, cv;
-  const uint8_t* inb;
-  uint8_t* outb;
+  // wave-uniform bases and pitches, lane byte offsets
+  const uint8_t* in0;
+  uint8_t* out0;
+  int64_t ip, op;
+  u32 lin, lout;
   u32 rr[2][8];  // last input row
   u32 p1[2][8];  // level-1 vertical sums (rows y, y+1) ...
   u32 p2[2][8];
@@ -434,14 +470,17 @@ struct G5Stream {
     const u32 c = (u32)d.c0 & 0xFF;
     cin = c | (c << 16);
     cv = (16 * c) | ((16 * c) << 16);
-    inb = d.in + (UYVY ? 2 * L.xl : L.xl);
-    outb = d.out + L.xs;
+    in0 = d.in;
+    out0 = d.out;
+    ip = d.in_pitch;
+    op = d.out_pitch;
+    lin = (u32)(UYVY ? 2 * L.xl : L.xl);
+    lout = (u32)L.xs;  // wraps for the left halo lane, which never stores
   }
   __device__ __forceinline__ void load(int y, u32x4 r[2]) const {
     const int yc = min(max(y, 0), H - 1);
-    const uint8_t* row = inb + (size_t)yc * d.in_pitch;
-    r[0] = __builtin_nontemporal_load((const u32x4*)row);
-    if (UYVY) r[1] = __builtin_nontemporal_load((const u32x4*)(row + 16));
+    r[0] = load_row16<true>(in0, ip, yc, lin);
+    if (UYVY) r[1] = load_row16<true>(in0, ip, yc, lin + 16);
   }
   __device__ __forceinline__ void unpk(const u32x4 r[2], int y, u32 p[8]) const {
     if (UYVY) {
@@ -476,7 +515,7 @@ struct G5Stream {
     u32 o[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) o[k] = shr2(add2(c[k], c[k + 1]), 8);
-    if (L.store) __builtin_nontemporal_store(pack16(o), (u32x4*)(outb + (size_t)y * d.out_pitch));
+    if (L.store) store_row16<true>(out0, op, y, lout, pack16(o));
   }
   // output row y: the new input row is y+2
   template <int J>
@@ -787,7 +826,14 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
     for (int k = 0; k < 4; ++k)
       v[q][k] = ring[0][q][k] + ring[1][q][k] + ring[2][q][k] + ring[3][q][k] + ring[4][q][k];
 
-  uint8_t* outb = d.out + s.L.xs;
+  // descriptor fields the row loop needs, read once (the stores could alias
+  // the descriptor as far as the compiler knows, which would make it reload
+  // them every row)
+  uint8_t* const out0 = d.out;
+  const int64_t op = d.out_pitch;
+  const u32 lout = (u32)s.L.xs;  // wraps for the left halo lane, which never stores
+  const float kk = d.k, thr = d.thr;
+  const u32 tv = d.tv4 & 0xFFu, fv = d.fv4 & 0xFFu;
   auto emit = [&](int y) {
     u32 o = 0;
 #pragma unroll
@@ -795,10 +841,10 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
       const float sxx = (float)v[0][k], syy = (float)v[1][k], sxy = (float)v[2][k];
       const float det = fmaf(sxx, syy, -sxy * sxy);
       const float tr = sxx + syy;
-      const float r = fmaf(-d.k * tr, tr, det);
-      o |= (r > d.thr ? (d.tv4 & 0xFFu) : (d.fv4 & 0xFFu)) << (8 * k);
+      const float r = fmaf(-kk * tr, tr, det);
+      o |= (r > thr ? tv : fv) << (8 * k);
     }
-    if (s.L.store) __builtin_nontemporal_store(o, (u32*)(outb + (size_t)y * d.out_pitch));
+    if (s.L.store) __builtin_nontemporal_store(o, (u32*)(out0 + lout + (size_t)((int64_t)y * op)));
   };
   // unrolled by the ring length so that every ring slot index is a
   // compile-time constant; each step is guarded by a uniform branch

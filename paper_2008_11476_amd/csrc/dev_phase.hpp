@@ -12,19 +12,25 @@
 //
 // Two pixels (the two 16-bit halves of a register) are handled per
 // instruction, in half precision:
-//  - |g| <= 1023 is turned into an exact half by adding the bit pattern of
-//    1024.0 and subtracting 1024.0;
-//  - 1 / mx starts from the bit-pattern estimate K - bits(mx) and takes one
-//    Newton step, folded into z = (mn r)(2 - mx r);
-//  - z (c0 - c1 z) + 1024 is rounded once by the last fused multiply-add to
-//    the half grid around 1024 (spacing 1), so the low byte of its bit
-//    pattern is alpha rounded to a whole level (1024.0 is 0x6400);
+//  - an integer m < 2048 read as a half is the subnormal m * 2^-24 (exact),
+//    so mn needs no conversion and mx one exact multiply, F = mx * 2^-9
+//    (half-precision subnormals are kept, the default mode of HIP kernels);
+//  - R ~ 64 / F starts from a bit-pattern estimate K - bits(F) and takes one
+//    Newton step; with the scalings above, zz = (mn R) (128 - F R) is z / 8;
+//  - 8 z (c0 - c1 z) + 1024, written zz (8 c0 - 64 c1 zz) + 1024, is rounded
+//    once by the last fused multiply-add to the half grid around 1024
+//    (spacing 1), so the low byte of its bit pattern is alpha rounded to a
+//    whole level (1024.0 is 0x6400);
 //  - the octant (|gy| > |gx|, gx < 0, gy < 0) selects, by a byte permute
 //    from two 8-entry tables, whether alpha is negated and which multiple of
 //    64 levels is added; negation is xor 0xFF plus one, folded into the added
 //    constant.  Only the low byte of each half is meaningful (arithmetic
-//    modulo 256 is the wrap of the level circle).
-// Over every (gx, gy) in [-1020, 1020]^2 the octant angle is within 0.71 of
+//    modulo 256 is the wrap of the level circle);
+//  - the table index is built from bits 13..15 of gx, gy and |gx| - |gy|:
+//    values within [-1024, 1023] repeat their sign in bits 10..15, so
+//    bit 15 of gy, bit 14 of gx ^ gy and bit 13 of gx ^ gy ^ d carry the three
+//    octant bits in an invertible code, and one 16-bit shift brings them down.
+// Over every (gx, gy) in [-1023, 1023]^2 the octant angle is within 0.71 of
 // the exact alpha, so the level is within one of round(exact level).  Inputs
 // must satisfy |g| <= 1023; larger S16 values are scaled by the caller.
 #pragma once
@@ -37,11 +43,12 @@ typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 typedef short i16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short w16x2 __attribute__((ext_vector_type(2)));
 
-// byte tables indexed by the octant code o = s1 | s2 << 1 | s3 << 2
-// (s1: |gy| > |gx|, s2: gx < 0, s3: gy < 0)
-constexpr uint32_t kPhaseNegLo = 0x00FFFF00u, kPhaseNegHi = 0xFF0000FFu;  // 0xFF: alpha negated
-constexpr uint32_t kPhaseAddLo = 0x40814100u, kPhaseAddHi = 0xC180C001u;  // 64 q (+1 when negated)
-constexpr unsigned short kRcpMagic = 0x779C;
+// byte tables indexed by the code c = p | (s2 ^ s3) << 1 | s3 << 2 with
+// p = s1 ^ s2 ^ s3 (s1: |gy| > |gx|, s2: gx < 0, s3: gy < 0)
+constexpr uint32_t kPhaseNegLo = 0xFF00FF00u, kPhaseNegHi = 0xFF00FF00u;  // 0xFF: alpha negated
+constexpr uint32_t kPhaseAddLo = 0x81404100u, kPhaseAddHi = 0x01C0C180u;  // 64 q (+1 when negated)
+// reciprocal estimate 2^6 / F ~ bits^-1(kRcpMagic - bits(F)), in 16-bit wrap-around
+constexpr unsigned short kRcpMagic = 0x8F9C;
 
 // gx, gy: two signed 16-bit gradients each (|g| <= 1023).  Returns the two
 // phase levels in the low bytes of the two halves.
@@ -51,23 +58,25 @@ __device__ __forceinline__ uint32_t phase_pair(uint32_t gx, uint32_t gy) {
   const i16x2 ax = __builtin_elementwise_max(x, z0 - x);
   const i16x2 ay = __builtin_elementwise_max(y, z0 - y);
   const i16x2 mn = __builtin_elementwise_min(ax, ay);
-  // mx = 0 needs no guard: the reciprocal estimate of 0 is finite, so z = 0
+  // mx = 0 needs no guard: the estimate for F = 0 is finite, so zz = 0
   const i16x2 mx = __builtin_elementwise_max(ax, ay);
-  const w16x2 bias = {0x6400, 0x6400};
-  const h16x2 k1024 = {(_Float16)1024.0f, (_Float16)1024.0f};
-  const h16x2 fmn = __builtin_bit_cast(h16x2, __builtin_bit_cast(w16x2, mn) + bias) - k1024;
-  const h16x2 fmx = __builtin_bit_cast(h16x2, __builtin_bit_cast(w16x2, mx) + bias) - k1024;
+  const h16x2 k32768 = {(_Float16)32768.0f, (_Float16)32768.0f};
+  const h16x2 F = __builtin_bit_cast(h16x2, mx) * k32768;  // mx 2^-9
   const w16x2 magic = {kRcpMagic, kRcpMagic};
-  const h16x2 r = __builtin_bit_cast(h16x2, magic - __builtin_bit_cast(w16x2, fmx));
-  const h16x2 two = {(_Float16)2.0f, (_Float16)2.0f};
-  const h16x2 e = __builtin_elementwise_fma(-fmx, r, two);
-  const h16x2 z = (fmn * r) * e;
-  const h16x2 c0 = {(_Float16)43.125f, (_Float16)43.125f}, c1 = {(_Float16)11.125f, (_Float16)11.125f};
-  const h16x2 p = __builtin_elementwise_fma(-c1, z, c0);
-  const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(z, p, k1024));
-  const uint32_t d = __builtin_bit_cast(uint32_t, ax - ay);  // sign bit set where |gy| > |gx|
-  const uint32_t o = ((d >> 15) & 0x00010001u) | ((gx >> 14) & 0x00020002u) | ((gy >> 13) & 0x00040004u) |
-                     0x0C000C00u;
+  const h16x2 R = __builtin_bit_cast(h16x2, magic - __builtin_bit_cast(w16x2, F));
+  const h16x2 k128 = {(_Float16)128.0f, (_Float16)128.0f};
+  const h16x2 E = __builtin_elementwise_fma(-F, R, k128);
+  const h16x2 zz = (__builtin_bit_cast(h16x2, mn) * R) * E;
+  const h16x2 c0 = {(_Float16)345.0f, (_Float16)345.0f}, c1 = {(_Float16)712.0f, (_Float16)712.0f};
+  const h16x2 p = __builtin_elementwise_fma(-c1, zz, c0);
+  const h16x2 k1024 = {(_Float16)1024.0f, (_Float16)1024.0f};
+  const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(zz, p, k1024));
+  const uint32_t d = __builtin_bit_cast(uint32_t, ax - ay);  // sign where |gy| > |gx|
+  // t = gy ^ (gx & bits 13,14) ^ (d & bit 13), as two three-input bit operations
+  // (truth table 0x78 is s0 ^ (s1 & s2))
+  const uint32_t t = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_bitop3_b32(gy, gx, 0x60006000u, 0x78), d,
+                                                 0x20002000u, 0x78);
+  const uint32_t o = __builtin_bit_cast(uint32_t, __builtin_bit_cast(w16x2, t) >> (unsigned short)13);
   const uint32_t neg = __builtin_amdgcn_perm(kPhaseNegHi, kPhaseNegLo, o);
   const uint32_t add = __builtin_amdgcn_perm(kPhaseAddHi, kPhaseAddLo, o);
   return (a ^ neg) + add;
