@@ -229,7 +229,9 @@ __device__ __forceinline__ void extend(u32 p[8], Ext& e, const Lanes& L, bool re
 // and three) is renamed statically, and each input row is loaded one row
 // ahead (deeper prefetch measured no faster and costs the registers that
 // hold a fourth wave per SIMD).
-template <bool PHASE, bool HEDGE>
+// WIDE selects the 32-bit magnitude test; otherwise the bound fits the
+// saturating 16-bit test (thr_not >= -32768).
+template <bool PHASE, bool HEDGE, bool WIDE>
 struct EdgeStream {
   const EdgeDesc& d;
   Lanes L;
@@ -244,6 +246,7 @@ struct EdgeStream {
   int64_t ip, op, pp;
   u32 lin, lout;
   int thr;
+  u32 thr2;  // thr_not in both halves (16-bit test)
   u32 tv4, x4;
   // rotating state
   u32 inr[2][8];  // input row y+1 (role alternates)
@@ -271,6 +274,7 @@ struct EdgeStream {
     lin = (u32)L.xl;
     lout = (u32)L.xs;  // wraps for the left halo lane, which never stores
     thr = d.thr_not;
+    thr2 = ((u32)d.thr_not & 0xFFFFu) * 0x10001u;
     tv4 = d.tv4;
     x4 = d.tv4 ^ d.fv4;
   }
@@ -323,27 +327,50 @@ struct EdgeStream {
       if (L.store) store_row16<false>(ph0, pp, y, lout, po);
     }
     // magnitude + threshold as one integer test: gx^2 + gy^2 > T, i.e. the
-    // sign of gx^2 + gy^2 + thr_not.  v_mad_i32_i16 multiplies the selected
-    // signed 16-bit halves of its sources into a 32-bit sum (op_sel picks
-    // the high halves), so each pixel takes two instructions and no repacking.
-    u32 r[16];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      int t0, t1, r0, r1;
-      asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(t0) : "v"(gx[k]), "s"(thr));
-      asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(r0) : "v"(gy[k]), "v"(t0));
-      asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(t1) : "v"(gx[k]), "s"(thr));
-      asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(r1) : "v"(gy[k]), "v"(t1));
-      r[k] = (u32)r0;
-      r[k + 8] = (u32)r1;
-    }
+    // sign of gx^2 + gy^2 + thr_not (thr_not = -T - 1); mask bytes are 0xFF
+    // where that sum is negative (no edge), and out = tv ^ (mask & (tv ^ fv))
+    // picks fv there and tv elsewhere.
     u32x4 o;
-    // mask bytes are 0xFF where the sum is below the bound (no edge);
-    // out = tv ^ (mask & (tv ^ fv)) picks fv there and tv elsewhere
-    o.x = tv4 ^ ((perm(r[1], r[0], 0x0c0c0b09u) | perm(r[3], r[2], 0x0b090c0cu)) & x4);
-    o.y = tv4 ^ ((perm(r[5], r[4], 0x0c0c0b09u) | perm(r[7], r[6], 0x0b090c0cu)) & x4);
-    o.z = tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
-    o.w = tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
+    if (!WIDE) {
+      // v_pk_mad_i16 with clamp forms each full product and sum before it
+      // saturates to 16 bits.  gx^2 + thr_not cannot saturate low
+      // (thr_not >= -32768), and a saturated value keeps its sign, so bit
+      // 15 of each half of m is the sign of the exact sum.
+      u32 m[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        u32 t;
+        asm("v_pk_mad_i16 %0, %1, %1, %2 clamp" : "=v"(t) : "v"(gx[k]), "s"(thr2));
+        asm("v_pk_mad_i16 %0, %1, %1, %2 clamp" : "=v"(m[k]) : "v"(gy[k]), "v"(t));
+      }
+      // byte permute selectors 8..11 replicate bit 15 / 31 of the sources:
+      // a01 = masks of pixels 0, 1, 8, 9
+      const u32 a01 = perm(m[1], m[0], 0x0B090A08u), a23 = perm(m[3], m[2], 0x0B090A08u);
+      const u32 a45 = perm(m[5], m[4], 0x0B090A08u), a67 = perm(m[7], m[6], 0x0B090A08u);
+      o.x = tv4 ^ (perm(a23, a01, 0x05040100u) & x4);
+      o.y = tv4 ^ (perm(a67, a45, 0x05040100u) & x4);
+      o.z = tv4 ^ (perm(a23, a01, 0x07060302u) & x4);
+      o.w = tv4 ^ (perm(a67, a45, 0x07060302u) & x4);
+    } else {
+      // v_mad_i32_i16 multiplies the selected signed 16-bit halves of its
+      // sources into a 32-bit sum (op_sel picks the high halves), so each
+      // pixel takes two instructions and no repacking.
+      u32 r[16];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        int t0, t1, r0, r1;
+        asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(t0) : "v"(gx[k]), "s"(thr));
+        asm("v_mad_i32_i16 %0, %1, %1, %2" : "=v"(r0) : "v"(gy[k]), "v"(t0));
+        asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(t1) : "v"(gx[k]), "s"(thr));
+        asm("v_mad_i32_i16 %0, %1, %1, %2 op_sel:[1,1,0,0]" : "=v"(r1) : "v"(gy[k]), "v"(t1));
+        r[k] = (u32)r0;
+        r[k + 8] = (u32)r1;
+      }
+      o.x = tv4 ^ ((perm(r[1], r[0], 0x0c0c0b09u) | perm(r[3], r[2], 0x0b090c0cu)) & x4);
+      o.y = tv4 ^ ((perm(r[5], r[4], 0x0c0c0b09u) | perm(r[7], r[6], 0x0b090c0cu)) & x4);
+      o.z = tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
+      o.w = tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
+    }
     if (L.store) store_row16<false>(out0, op, y, lout, o);
   }
   // Output row y; J is the phase of y in the six-row unrolled sequence.
@@ -432,11 +459,16 @@ template <bool PHASE>
 __device__ __forceinline__ void edge_item(const EdgeDesc& d, int strip, int band) {
   const int y0 = band * d.g.rows;
   const int y1 = min(y0 + d.g.rows, d.g.h);
-  if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
-    EdgeStream<PHASE, true> s(d, strip);
+  if (d.thr_not < -32768) {
+    // bounds above 32767 (thresholds of 181 and more): the 32-bit test, with
+    // the border-aware stream on every strip
+    EdgeStream<PHASE, true, true> s(d, strip);
+    s.run(y0, y1);
+  } else if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
+    EdgeStream<PHASE, true, false> s(d, strip);
     s.run(y0, y1);
   } else {
-    EdgeStream<PHASE, false> s(d, strip);
+    EdgeStream<PHASE, false, false> s(d, strip);
     s.run(y0, y1);
   }
 }

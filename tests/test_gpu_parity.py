@@ -157,13 +157,17 @@ def test_edge_fused_borders(ctx, b0, b1):
         compare(spec, got, env, phase_names=("ph",))
 
 
-@pytest.mark.parametrize("thresh", [-1, 0, 1, 99.5, 100, 1442, 1443, 40000])
-def test_edge_thresholds(ctx, thresh):
+@pytest.mark.parametrize("thresh", [-1, 0, 1, 99.5, 100, 180, 180.5, 181, 1442, 1443, 40000])
+@pytest.mark.parametrize("phase", [False, True])
+def test_edge_thresholds(ctx, thresh, phase):
+    """Bounds u(u-1) up to 32767 (threshold below 181) take the fused
+    kernel's saturating 16-bit magnitude test, larger ones the 32-bit test;
+    both sides of that switch and the extremes."""
     img = synth.edge_image(300, 40, seed=12)
-    spec = gs.edge_spec(img, thresh=thresh)
-    log("edge threshold %s" % thresh)
+    spec = gs.edge_spec(img, thresh=thresh, phase=phase)
+    log("edge threshold %s phase %s" % (thresh, phase))
     got, _ = run_spec(spec, ctx)
-    compare(spec, got, spec.run_oracle())
+    compare(spec, got, spec.run_oracle(), phase_names=("ph",) if phase else ())
 
 
 @pytest.mark.parametrize("w,h", [(64, 48), (1003, 67)])
