@@ -226,9 +226,19 @@ __device__ __forceinline__ void extend(u32 p[8], Ext& e, const Lanes& L, bool re
 // Sobel/magnitude/threshold row y.  All (1 2 1) sums are formed from pairwise
 // sums shared between neighbouring rows or pixels (a + 2b + c = (a+b) + (b+c)).
 // The loop is unrolled by six so that every rotating row buffer (periods two
-// and three) is renamed statically, and each input row is loaded one row
-// ahead (deeper prefetch measured no faster and costs the registers that
-// hold a fourth wave per SIMD).
+// and three) is renamed statically.  Input rows arrive through a queue of
+// kEQ rows in the wave's LDS (1 KB per row), filled by direct-to-LDS loads
+// kEQ rows ahead, so the prefetch holds no registers.  The compiler does not
+// track these loads against the LDS reads; the waits are explicit and count
+// every vector-memory operation issued after a row's load (the counter
+// drains in issue order, stores included).
+constexpr int kEQ = 4;
+
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
 // WIDE selects the 32-bit magnitude test; otherwise the bound fits the
 // saturating 16-bit test (thr_not >= -32768).
 template <bool PHASE, bool HEDGE, bool WIDE>
@@ -253,9 +263,10 @@ struct EdgeStream {
   u32 tr[2][8];   // in(y) + in(y+1)
   u32 gr[3][8];   // Gaussian rows y-1, y, y+1
   u32 sr[2][8];   // G(y-1) + G(y)
-  u32x4 raw[2];   // input rows y+2 (in use) and y+3 (in flight)
+  u32x4* q;       // LDS queue, kEQ rows x 64 lanes; row r in slot (r - qbase) mod kEQ
+  int qbase, yb0, yb1;
 
-  __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip) : d(d_) {
+  __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip, u32x4* qbuf) : d(d_), q(qbuf) {
     L = make_lanes(d.g, strip);
     H = d.g.h;
     repl0 = d.b0 != B_CONSTANT;
@@ -278,9 +289,32 @@ struct EdgeStream {
     tv4 = d.tv4;
     x4 = d.tv4 ^ d.fv4;
   }
-  __device__ __forceinline__ u32x4 load(int y) const {
-    const int yc = min(max(y, 0), H - 1);
-    return load_row16<false>(in0, ip, yc, lin);
+  // direct-to-LDS load of input row r (clamped to the image) into its slot
+  __device__ __forceinline__ void issue(int r) const {
+    const int rc = min(max(r, 0), H - 1);
+    __builtin_amdgcn_global_load_lds((const void*)(in0 + lin + (size_t)((int64_t)rc * ip)),
+                                     (__attribute__((address_space(3))) void*)(q + ((r - qbase) & (kEQ - 1)) * 64),
+                                     16, 0, 0);
+  }
+  // row r from its slot; the read completes before the slot is refilled
+  __device__ __forceinline__ u32x4 read(int r) const {
+    const u32x4 v = q[((r - qbase) & (kEQ - 1)) * 64 + L.lane];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    return v;
+  }
+  // Wait for input row y+2, read at output row y.  After its load were
+  // issued: the later loads of rows y+3 .. y+5, except those past the band's
+  // last input row y1+1, which are never issued, and the stores of the rows
+  // y0 .. y-1 that followed it (at most four rows, S stores each).  Waiting
+  // until no more than that many operations are outstanding leaves row y+2
+  // complete; the count is rounded down to one of four immediates.
+  __device__ __forceinline__ void wait_row(int y) const {
+    constexpr int S = PHASE ? 2 : 1;
+    const int n = min(y - yb0, 4) * S + 3 - min(max(y + 4 - yb1, 0), 3);
+    if (n >= 3 + 4 * S) wait_vmem<3 + 4 * S>();
+    else if (n >= 4 * S) wait_vmem<4 * S>();
+    else if (n >= 3) wait_vmem<3>();
+    else wait_vmem<0>();
   }
   __device__ __forceinline__ void unpk(u32x4 r, int y, u32 p[8]) const {
     unpack16(r, p);
@@ -324,7 +358,7 @@ struct EdgeStream {
       po.y = perm(a67, a45, 0x05040100u);
       po.z = perm(a23, a01, 0x07060302u);
       po.w = perm(a67, a45, 0x07060302u);
-      if (L.store) store_row16<false>(ph0, pp, y, lout, po);
+      if (L.store) store_row16<true>(ph0, pp, y, lout, po);
     }
     // magnitude + threshold as one integer test: gx^2 + gy^2 > T, i.e. the
     // sign of gx^2 + gy^2 + thr_not (thr_not = -T - 1); mask bytes are 0xFF
@@ -371,7 +405,7 @@ struct EdgeStream {
       o.z = tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
       o.w = tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
     }
-    if (L.store) store_row16<false>(out0, op, y, lout, o);
+    if (L.store) store_row16<true>(out0, op, y, lout, o);
   }
   // Output row y; J is the phase of y in the six-row unrolled sequence.
   template <int J>
@@ -385,8 +419,9 @@ struct EdgeStream {
     u32(&g1)[8] = gr[(J + 2) % 3];
     u32(&s0)[8] = sr[J % 2];
     u32(&s1)[8] = sr[(J + 1) % 2];
-    const u32x4 cur = raw[J % 2];
-    raw[(J + 1) % 2] = load(y + 3);  // one row ahead
+    wait_row(y);
+    const u32x4 cur = read(y + 2);
+    if (y + 6 <= yb1 + 1) issue(y + 6);  // into the slot just read
     if (y + 1 < H) {
       unpk(cur, y + 2, in2);
       u32 v[8];
@@ -412,12 +447,20 @@ struct EdgeStream {
   // Output rows [y0, y1), top to bottom.
   __device__ __forceinline__ void run(int y0, int y1) {
     // prologue: G(y0-1), G(y0) and the pairwise state for row y0
+    qbase = y0 - 2;
+    yb0 = y0;
+    yb1 = y1;
+#pragma unroll
+    for (int k = 0; k < kEQ; ++k) issue(y0 - 2 + k);
+    wait_vmem<0>();
     u32 a[8], b[8], c[8], e[8];
-    unpk(load(y0 - 2), y0 - 2, a);
-    unpk(load(y0 - 1), y0 - 1, b);
-    unpk(load(y0), y0, c);
-    unpk(load(y0 + 1), y0 + 1, e);
-    raw[0] = load(y0 + 2);
+    unpk(read(y0 - 2), y0 - 2, a);
+    unpk(read(y0 - 1), y0 - 1, b);
+    unpk(read(y0), y0, c);
+    unpk(read(y0 + 1), y0 + 1, e);
+    // rows y0+2 .. y0+5 into the slots just read
+#pragma unroll
+    for (int k = 0; k < kEQ; ++k) issue(y0 + 2 + k);
     u32 v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = add2(add2(b[k], c[k]), add2(c[k], e[k]));
@@ -457,20 +500,23 @@ struct EdgeStream {
 
 template <bool PHASE>
 __device__ __forceinline__ void edge_item(const EdgeDesc& d, int strip, int band) {
+  __shared__ u32x4 eq[kEQ * 64];
   const int y0 = band * d.g.rows;
   const int y1 = min(y0 + d.g.rows, d.g.h);
   if (d.thr_not < -32768) {
     // bounds above 32767 (thresholds of 181 and more): the 32-bit test, with
     // the border-aware stream on every strip
-    EdgeStream<PHASE, true, true> s(d, strip);
+    EdgeStream<PHASE, true, true> s(d, strip, eq);
     s.run(y0, y1);
   } else if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
-    EdgeStream<PHASE, true, false> s(d, strip);
+    EdgeStream<PHASE, true, false> s(d, strip, eq);
     s.run(y0, y1);
   } else {
-    EdgeStream<PHASE, false, false> s(d, strip);
+    EdgeStream<PHASE, false, false> s(d, strip, eq);
     s.run(y0, y1);
   }
+  // no load into the queue may still be in flight when the wave moves on
+  wait_vmem<0>();
 }
 
 // ---- Gaussian 5x5 (optionally of the luma of a UYVY frame) -----------------
