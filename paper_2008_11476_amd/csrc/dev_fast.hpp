@@ -220,18 +220,19 @@ __device__ __forceinline__ void extend(u32 p[8], Ext& e, const Lanes& L, bool re
   }
 }
 
-// ---- Gaussian 3x3 -> Sobel 3x3 -> Magnitude -> Threshold (+ Phase) ----------
-
-// One wave streams its band: at output row y it finishes Gaussian row y+1 and
-// Sobel/magnitude/threshold row y.  All (1 2 1) sums are formed from pairwise
-// sums shared between neighbouring rows or pixels (a + 2b + c = (a+b) + (b+c)).
-// The loop is unrolled by six so that every rotating row buffer (periods two
-// and three) is renamed statically.  Input rows arrive through a queue of
-// kEQ rows in the wave's LDS (1 KB per row), filled by direct-to-LDS loads
-// kEQ rows ahead, so the prefetch holds no registers.  The compiler does not
-// track these loads against the LDS reads; the waits are explicit and count
-// every vector-memory operation issued after a row's load (the counter
-// drains in issue order, stores included).
+// ---- input row queue in LDS -------------------------------------------------
+// The row streams read input row y+2 at output row y.  Rows travel through a
+// queue of kEQ rows in the wave's LDS (NB x 16 bytes per lane and row),
+// filled by direct-to-LDS loads kEQ rows ahead, so the prefetch holds no
+// registers.  The compiler does not track these loads against the LDS
+// reads, so the waits are explicit.  The vector-memory counter drains in
+// issue order, stores included; a row is complete once no more operations
+// are outstanding than were issued after its last load:
+//  - the loads of rows y+3 .. y+5 (NB each), except those past the band's
+//    last input row y1+1, which are never issued;
+//  - the stores (S per output row) of the rows y0 .. y-1 issued after it,
+//    at most four rows' worth.
+// The count is rounded down to one of four immediates.
 constexpr int kEQ = 4;
 
 template <int N>
@@ -239,6 +240,67 @@ __device__ __forceinline__ void wait_vmem() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
+template <int NB, int S>
+struct LdsRows {
+  u32x4* q;  // kEQ x NB x 64 entries; row r in slot (r - qbase) mod kEQ
+  const uint8_t* base;
+  int64_t pitch;
+  u32 lin;  // lane byte offset
+  int H, lane, qbase, y0, y1;
+
+  // direct-to-LDS load of input row r (clamped to the image) into its slot
+  __device__ __forceinline__ void issue(int r) const {
+    const int rc = min(max(r, 0), H - 1);
+    const uint8_t* src = base + lin + (size_t)((int64_t)rc * pitch);
+    u32x4* slot = q + ((r - qbase) & (kEQ - 1)) * (64 * NB);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      __builtin_amdgcn_global_load_lds((const void*)(src + 16 * b),
+                                       (__attribute__((address_space(3))) void*)(slot + 64 * b), 16, 0, 0);
+  }
+  // row r from its slot; the read completes before the slot is refilled
+  __device__ __forceinline__ void read(int r, u32x4 v[NB]) const {
+    const u32x4* slot = q + ((r - qbase) & (kEQ - 1)) * (64 * NB) + lane;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[b] = slot[64 * b];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+  // band [b0, b1): load input rows b0-2 .. b0+1, wait for them
+  __device__ __forceinline__ void start(int b0, int b1) {
+    qbase = b0 - 2;
+    y0 = b0;
+    y1 = b1;
+#pragma unroll
+    for (int k = 0; k < kEQ; ++k) issue(b0 - 2 + k);
+    wait_vmem<0>();
+  }
+  // after the first four rows are read: rows b0+2 .. b0+5 into their slots
+  __device__ __forceinline__ void refill() const {
+#pragma unroll
+    for (int k = 0; k < kEQ; ++k) issue(y0 + 2 + k);
+  }
+  // at output row y: wait for row y+2, read it, queue row y+6
+  __device__ __forceinline__ void take(int y, u32x4 v[NB]) const {
+    constexpr int F = 4 * S + 3 * NB;
+    constexpr int X = 4 * S > 3 * NB ? 4 * S : 3 * NB, Y = 4 * S > 3 * NB ? 3 * NB : 4 * S;
+    const int n = min(y - y0, 4) * S + NB * (3 - min(max(y + 4 - y1, 0), 3));
+    if (n >= F) wait_vmem<F>();
+    else if (n >= X) wait_vmem<X>();
+    else if (n >= Y) wait_vmem<Y>();
+    else wait_vmem<0>();
+    read(y + 2, v);
+    if (y + 6 <= y1 + 1) issue(y + 6);
+  }
+};
+
+// ---- Gaussian 3x3 -> Sobel 3x3 -> Magnitude -> Threshold (+ Phase) ----------
+
+// One wave streams its band: at output row y it finishes Gaussian row y+1 and
+// Sobel/magnitude/threshold row y.  All (1 2 1) sums are formed from pairwise
+// sums shared between neighbouring rows or pixels (a + 2b + c = (a+b) + (b+c)).
+// The loop is unrolled by six so that every rotating row buffer (periods two
+// and three) is renamed statically.  Input rows arrive through an LdsRows
+// queue.
 // WIDE selects the 32-bit magnitude test; otherwise the bound fits the
 // saturating 16-bit test (thr_not >= -32768).
 template <bool PHASE, bool HEDGE, bool WIDE>
@@ -263,10 +325,9 @@ struct EdgeStream {
   u32 tr[2][8];   // in(y) + in(y+1)
   u32 gr[3][8];   // Gaussian rows y-1, y, y+1
   u32 sr[2][8];   // G(y-1) + G(y)
-  u32x4* q;       // LDS queue, kEQ rows x 64 lanes; row r in slot (r - qbase) mod kEQ
-  int qbase, yb0, yb1;
+  LdsRows<1, PHASE ? 2 : 1> rows;  // input rows (one 16-byte load per row; 1 or 2 stores)
 
-  __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip, u32x4* qbuf) : d(d_), q(qbuf) {
+  __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip, u32x4* lds) : d(d_) {
     L = make_lanes(d.g, strip);
     H = d.g.h;
     repl0 = d.b0 != B_CONSTANT;
@@ -288,33 +349,12 @@ struct EdgeStream {
     thr2 = ((u32)d.thr_not & 0xFFFFu) * 0x10001u;
     tv4 = d.tv4;
     x4 = d.tv4 ^ d.fv4;
-  }
-  // direct-to-LDS load of input row r (clamped to the image) into its slot
-  __device__ __forceinline__ void issue(int r) const {
-    const int rc = min(max(r, 0), H - 1);
-    __builtin_amdgcn_global_load_lds((const void*)(in0 + lin + (size_t)((int64_t)rc * ip)),
-                                     (__attribute__((address_space(3))) void*)(q + ((r - qbase) & (kEQ - 1)) * 64),
-                                     16, 0, 0);
-  }
-  // row r from its slot; the read completes before the slot is refilled
-  __device__ __forceinline__ u32x4 read(int r) const {
-    const u32x4 v = q[((r - qbase) & (kEQ - 1)) * 64 + L.lane];
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    return v;
-  }
-  // Wait for input row y+2, read at output row y.  After its load were
-  // issued: the later loads of rows y+3 .. y+5, except those past the band's
-  // last input row y1+1, which are never issued, and the stores of the rows
-  // y0 .. y-1 that followed it (at most four rows, S stores each).  Waiting
-  // until no more than that many operations are outstanding leaves row y+2
-  // complete; the count is rounded down to one of four immediates.
-  __device__ __forceinline__ void wait_row(int y) const {
-    constexpr int S = PHASE ? 2 : 1;
-    const int n = min(y - yb0, 4) * S + 3 - min(max(y + 4 - yb1, 0), 3);
-    if (n >= 3 + 4 * S) wait_vmem<3 + 4 * S>();
-    else if (n >= 4 * S) wait_vmem<4 * S>();
-    else if (n >= 3) wait_vmem<3>();
-    else wait_vmem<0>();
+    rows.q = lds;
+    rows.base = in0;
+    rows.pitch = ip;
+    rows.lin = lin;
+    rows.H = H;
+    rows.lane = L.lane;
   }
   __device__ __forceinline__ void unpk(u32x4 r, int y, u32 p[8]) const {
     unpack16(r, p);
@@ -419,9 +459,8 @@ struct EdgeStream {
     u32(&g1)[8] = gr[(J + 2) % 3];
     u32(&s0)[8] = sr[J % 2];
     u32(&s1)[8] = sr[(J + 1) % 2];
-    wait_row(y);
-    const u32x4 cur = read(y + 2);
-    if (y + 6 <= yb1 + 1) issue(y + 6);  // into the slot just read
+    u32x4 cur;
+    rows.take(y, &cur);
     if (y + 1 < H) {
       unpk(cur, y + 2, in2);
       u32 v[8];
@@ -447,20 +486,18 @@ struct EdgeStream {
   // Output rows [y0, y1), top to bottom.
   __device__ __forceinline__ void run(int y0, int y1) {
     // prologue: G(y0-1), G(y0) and the pairwise state for row y0
-    qbase = y0 - 2;
-    yb0 = y0;
-    yb1 = y1;
-#pragma unroll
-    for (int k = 0; k < kEQ; ++k) issue(y0 - 2 + k);
-    wait_vmem<0>();
+    rows.start(y0, y1);
     u32 a[8], b[8], c[8], e[8];
-    unpk(read(y0 - 2), y0 - 2, a);
-    unpk(read(y0 - 1), y0 - 1, b);
-    unpk(read(y0), y0, c);
-    unpk(read(y0 + 1), y0 + 1, e);
-    // rows y0+2 .. y0+5 into the slots just read
-#pragma unroll
-    for (int k = 0; k < kEQ; ++k) issue(y0 + 2 + k);
+    u32x4 t;
+    rows.read(y0 - 2, &t);
+    unpk(t, y0 - 2, a);
+    rows.read(y0 - 1, &t);
+    unpk(t, y0 - 1, b);
+    rows.read(y0, &t);
+    unpk(t, y0, c);
+    rows.read(y0 + 1, &t);
+    unpk(t, y0 + 1, e);
+    rows.refill();
     u32 v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = add2(add2(b[k], c[k]), add2(c[k], e[k]));
@@ -498,21 +535,24 @@ struct EdgeStream {
   }
 };
 
+// LDS the item functions need, in 16-byte units (the kernels provide one
+// buffer of the largest size among the kinds they run)
+constexpr int kEdgeLds = kEQ * 64;
+
 template <bool PHASE>
-__device__ __forceinline__ void edge_item(const EdgeDesc& d, int strip, int band) {
-  __shared__ u32x4 eq[kEQ * 64];
+__device__ __forceinline__ void edge_item(const EdgeDesc& d, int strip, int band, u32x4* lds) {
   const int y0 = band * d.g.rows;
   const int y1 = min(y0 + d.g.rows, d.g.h);
   if (d.thr_not < -32768) {
     // bounds above 32767 (thresholds of 181 and more): the 32-bit test, with
     // the border-aware stream on every strip
-    EdgeStream<PHASE, true, true> s(d, strip, eq);
+    EdgeStream<PHASE, true, true> s(d, strip, lds);
     s.run(y0, y1);
   } else if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
-    EdgeStream<PHASE, true, false> s(d, strip, eq);
+    EdgeStream<PHASE, true, false> s(d, strip, lds);
     s.run(y0, y1);
   } else {
-    EdgeStream<PHASE, false, false> s(d, strip, eq);
+    EdgeStream<PHASE, false, false> s(d, strip, lds);
     s.run(y0, y1);
   }
   // no load into the queue may still be in flight when the wave moves on
@@ -539,9 +579,9 @@ struct G5Stream {
   u32 p1[2][8];  // level-1 vertical sums (rows y, y+1) ...
   u32 p2[2][8];
   u32 p3[2][8];
-  u32x4 raw[3][2];
+  LdsRows<UYVY ? 2 : 1, 1> rows;  // input rows (UYVY: 32 bytes per lane)
 
-  __device__ __forceinline__ G5Stream(const Gauss5Desc& d_, int strip) : d(d_) {
+  __device__ __forceinline__ G5Stream(const Gauss5Desc& d_, int strip, u32x4* lds) : d(d_) {
     L = make_lanes(d.g, strip);
     H = d.g.h;
     repl = d.b0 != B_CONSTANT;
@@ -554,11 +594,12 @@ struct G5Stream {
     op = d.out_pitch;
     lin = (u32)(UYVY ? 2 * L.xl : L.xl);
     lout = (u32)L.xs;  // wraps for the left halo lane, which never stores
-  }
-  __device__ __forceinline__ void load(int y, u32x4 r[2]) const {
-    const int yc = min(max(y, 0), H - 1);
-    r[0] = load_row16<true>(in0, ip, yc, lin);
-    if (UYVY) r[1] = load_row16<true>(in0, ip, yc, lin + 16);
+    rows.q = lds;
+    rows.base = in0;
+    rows.pitch = ip;
+    rows.lin = lin;
+    rows.H = H;
+    rows.lane = L.lane;
   }
   __device__ __forceinline__ void unpk(const u32x4 r[2], int y, u32 p[8]) const {
     if (UYVY) {
@@ -606,8 +647,8 @@ struct G5Stream {
     u32(&b1)[8] = p2[(J + 1) % 2];
     u32(&c0)[8] = p3[J % 2];
     u32(&c1)[8] = p3[(J + 1) % 2];
-    u32x4 cur[2] = {raw[J % 3][0], raw[J % 3][1]};
-    load(y + 4, raw[(J + 2) % 3]);
+    u32x4 cur[2];
+    rows.take(y, cur);
     unpk(cur, y + 2, r1);
     u32 v[8];
 #pragma unroll
@@ -622,12 +663,13 @@ struct G5Stream {
   __device__ __forceinline__ void run(int y0, int y1) {
     u32 q[4][8];
     u32x4 t[2];
+    rows.start(y0, y1);
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      load(y0 - 2 + j, t);
+      rows.read(y0 - 2 + j, t);
       unpk(t, y0 - 2 + j, q[j]);
     }
-    load(y0 + 2, raw[0]);
-    load(y0 + 3, raw[1]);
+    rows.refill();
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const u32 s01 = add2(q[0][k], q[1][k]), s12 = add2(q[1][k], q[2][k]), s23 = add2(q[2][k], q[3][k]);
@@ -653,16 +695,21 @@ struct G5Stream {
 };
 
 template <bool UYVY>
-__device__ __forceinline__ void gauss5_item(const Gauss5Desc& d, int strip, int band) {
+constexpr int kGauss5Lds = kEQ * 64 * (UYVY ? 2 : 1);
+
+template <bool UYVY>
+__device__ __forceinline__ void gauss5_item(const Gauss5Desc& d, int strip, int band, u32x4* lds) {
   const int y0 = band * d.g.rows;
   const int y1 = min(y0 + d.g.rows, d.g.h);
   if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
-    G5Stream<UYVY, true> s(d, strip);
+    G5Stream<UYVY, true> s(d, strip, lds);
     s.run(y0, y1);
   } else {
-    G5Stream<UYVY, false> s(d, strip);
+    G5Stream<UYVY, false> s(d, strip, lds);
     s.run(y0, y1);
   }
+  // no load into the queue may still be in flight when the wave moves on
+  wait_vmem<0>();
 }
 
 // ---- Sobel 3x3 -> products -> Box5x5 (x3) -> corner response -> Threshold ----
@@ -945,8 +992,10 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
   }
 }
 
-__device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int band) {
-  __shared__ u32 qbuf[corner::kQ * 64];
+constexpr int kCornerLds = corner::kQ * 64 / 4;
+
+__device__ __forceinline__ void corner_item(const CornerDesc& d, int strip, int band, u32x4* lds) {
+  u32* qbuf = (u32*)lds;
   const corner::Lanes4 L = corner::make_lanes(d.g, strip);
   if (L.edgeL || L.edgeR) corner_band<true>(d, L, band, qbuf);
   else corner_band<false>(d, L, band, qbuf);

@@ -35,19 +35,22 @@ __global__ __launch_bounds__(256) void k_local(const GProg* __restrict__ P, cons
 
 template <bool PHASE>
 __global__ __launch_bounds__(64) void k_edge(const EdgeDesc d, int xcd) {
+  __shared__ u32x4 lds[kEdgeLds];
   const int item = xcd ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x;
-  edge_item<PHASE>(d, item % d.g.nstrips, item / d.g.nstrips);
+  edge_item<PHASE>(d, item % d.g.nstrips, item / d.g.nstrips, lds);
 }
 
 __global__ __launch_bounds__(64) void k_corner(const CornerDesc d, int xcd) {
+  __shared__ u32x4 lds[kCornerLds];
   const int item = xcd ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x;
-  corner_item(d, item % d.g.nstrips, item / d.g.nstrips);
+  corner_item(d, item % d.g.nstrips, item / d.g.nstrips, lds);
 }
 
 template <bool UYVY>
 __global__ __launch_bounds__(64) void k_gauss5(const Gauss5Desc d, int xcd) {
+  __shared__ u32x4 lds[kGauss5Lds<UYVY>];
   const int item = xcd ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x;
-  gauss5_item<UYVY>(d, item % d.g.nstrips, item / d.g.nstrips);
+  gauss5_item<UYVY>(d, item % d.g.nstrips, item / d.g.nstrips, lds);
 }
 
 // Persistent batch kernel.  The flat work list is cut into 8 contiguous
@@ -65,34 +68,41 @@ constexpr int kCtrStride = 32;  // counters 128 bytes apart
 // 8 edge with phase, 16 Gaussian5x5 of UYVY luma); only those bodies are
 // compiled into the batch kernel, so a batch of one kind keeps that kind's
 // register budget and occupancy.
+// LDS of a batch kernel: the largest need among its kinds (one item at a time)
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <int KS>
-__device__ __forceinline__ void run_item(const BatchImage& bi, int local) {
+constexpr int kBatchLds = cmax(cmax((KS & 9) ? kEdgeLds : 1, (KS & 2) ? kCornerLds : 1),
+                               cmax((KS & 4) ? kGauss5Lds<false> : 1, (KS & 16) ? kGauss5Lds<true> : 1));
+
+template <int KS>
+__device__ __forceinline__ void run_item(const BatchImage& bi, int local, u32x4* lds) {
   if ((KS & 9) && bi.kind == FK_EDGE) {
     const EdgeDesc& d = bi.d.e;
-    if ((KS & 8) && d.phase) edge_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
-    else if (KS & 1) edge_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
+    if ((KS & 8) && d.phase) edge_item<true>(d, local % d.g.nstrips, local / d.g.nstrips, lds);
+    else if (KS & 1) edge_item<false>(d, local % d.g.nstrips, local / d.g.nstrips, lds);
   } else if ((KS & 2) && bi.kind == FK_CORNER) {
     const CornerDesc& d = bi.d.c;
-    corner_item(d, local % d.g.nstrips, local / d.g.nstrips);
+    corner_item(d, local % d.g.nstrips, local / d.g.nstrips, lds);
   } else if ((KS & 20) && bi.kind == FK_GAUSS5) {
     const Gauss5Desc& d = bi.d.g5;
-    if ((KS & 16) && d.uyvy) gauss5_item<true>(d, local % d.g.nstrips, local / d.g.nstrips);
-    else if (KS & 4) gauss5_item<false>(d, local % d.g.nstrips, local / d.g.nstrips);
+    if ((KS & 16) && d.uyvy) gauss5_item<true>(d, local % d.g.nstrips, local / d.g.nstrips, lds);
+    else if (KS & 4) gauss5_item<false>(d, local % d.g.nstrips, local / d.g.nstrips, lds);
   }
 }
 
 template <int KS>
 __device__ __forceinline__ void run_flat(const BatchImage* __restrict__ imgs, const uint16_t* __restrict__ item_img,
-                                         int item) {
+                                         int item, u32x4* lds) {
   const int im = item_img[item];
   const BatchImage& bi = imgs[im];
-  run_item<KS>(bi, item - bi.first_item);
+  run_item<KS>(bi, item - bi.first_item, lds);
 }
 
 template <int KS>
-__global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ imgs,
+__global__ __launch_bounds__(64, 4) void k_batch(const BatchImage* __restrict__ imgs,
                                               const uint16_t* __restrict__ item_img, int total, int chunk,
                                               unsigned* __restrict__ counter) {
+  __shared__ u32x4 lds[kBatchLds<KS>];
   const int lane = threadIdx.x & 63;
   const int grp = blockIdx.x & 7;
   const int begin = (int)((long long)total * grp / 8), end = (int)((long long)total * (grp + 1) / 8);
@@ -105,7 +115,7 @@ __global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ img
     unsigned nxt = 0;
     if (lane == 0) nxt = atomicAdd(next, (unsigned)chunk);
     const int stop = min(base + chunk, end);
-    for (int item = base; item < stop; ++item) run_flat<KS>(imgs, item_img, item);
+    for (int item = base; item < stop; ++item) run_flat<KS>(imgs, item_img, item, lds);
     base = begin + __builtin_amdgcn_readfirstlane((int)nxt);
   }
   if (lane == 0) {
@@ -122,9 +132,10 @@ __global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ img
 template <int KS>
 __global__ __launch_bounds__(64) void k_batch_direct(const BatchImage* __restrict__ imgs,
                                                      const uint16_t* __restrict__ item_img, int total) {
+  __shared__ u32x4 lds[kBatchLds<KS>];
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= total) return;
-  run_flat<KS>(imgs, item_img, item);
+  run_flat<KS>(imgs, item_img, item, lds);
 }
 
 // ---- host launchers ---------------------------------------------------------
