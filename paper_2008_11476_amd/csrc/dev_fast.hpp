@@ -222,27 +222,27 @@ __device__ __forceinline__ void extend(u32 p[8], Ext& e, const Lanes& L, bool re
 
 // ---- input row queue in LDS -------------------------------------------------
 // The row streams read input row y+2 at output row y.  Rows travel through a
-// queue of kEQ rows in the wave's LDS (NB x 16 bytes per lane and row),
-// filled by direct-to-LDS loads kEQ rows ahead, so the prefetch holds no
-// registers.  The compiler does not track these loads against the LDS
-// reads, so the waits are explicit.  The vector-memory counter drains in
-// issue order, stores included; a row is complete once no more operations
-// are outstanding than were issued after its last load:
-//  - the loads of rows y+3 .. y+5 (NB each), except those past the band's
+// queue of Q rows in the wave's LDS (NB x 16 bytes per lane and row), filled
+// by direct-to-LDS loads Q rows ahead, so the prefetch holds no registers.
+// The compiler does not track these loads against the LDS reads, so the
+// waits are explicit.  The vector-memory counter drains in issue order,
+// stores included; a row is complete once no more operations are
+// outstanding than were issued after its last load:
+//  - the loads of rows y+3 .. y+Q+1 (NB each), except those past the band's
 //    last input row y1+1, which are never issued;
 //  - the stores (S per output row) of the rows y0 .. y-1 issued after it,
-//    at most four rows' worth.
+//    at most Q rows' worth.
 // The count is rounded down to one of four immediates.
-constexpr int kEQ = 4;
-
 template <int N>
 __device__ __forceinline__ void wait_vmem() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-template <int NB, int S>
+template <int NB, int S, int Q>
 struct LdsRows {
-  u32x4* q;  // kEQ x NB x 64 entries; row r in slot (r - qbase) mod kEQ
+  static_assert(Q >= 4 && (Q & (Q - 1)) == 0, "queue of a power of two rows, at least 4");
+  static constexpr int kLds = Q * 64 * NB;  // 16-byte entries
+  u32x4* q;  // row r in slot (r - qbase) mod Q
   const uint8_t* base;
   int64_t pitch;
   u32 lin;  // lane byte offset
@@ -252,7 +252,7 @@ struct LdsRows {
   __device__ __forceinline__ void issue(int r) const {
     const int rc = min(max(r, 0), H - 1);
     const uint8_t* src = base + lin + (size_t)((int64_t)rc * pitch);
-    u32x4* slot = q + ((r - qbase) & (kEQ - 1)) * (64 * NB);
+    u32x4* slot = q + ((r - qbase) & (Q - 1)) * (64 * NB);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       __builtin_amdgcn_global_load_lds((const void*)(src + 16 * b),
@@ -260,38 +260,42 @@ struct LdsRows {
   }
   // row r from its slot; the read completes before the slot is refilled
   __device__ __forceinline__ void read(int r, u32x4 v[NB]) const {
-    const u32x4* slot = q + ((r - qbase) & (kEQ - 1)) * (64 * NB) + lane;
+    const u32x4* slot = q + ((r - qbase) & (Q - 1)) * (64 * NB) + lane;
 #pragma unroll
     for (int b = 0; b < NB; ++b) v[b] = slot[64 * b];
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   }
-  // band [b0, b1): load input rows b0-2 .. b0+1, wait for them
+  // band [b0, b1): load input rows b0-2 .. b0+Q-3, wait for the first four
   __device__ __forceinline__ void start(int b0, int b1) {
     qbase = b0 - 2;
     y0 = b0;
     y1 = b1;
 #pragma unroll
-    for (int k = 0; k < kEQ; ++k) issue(b0 - 2 + k);
-    wait_vmem<0>();
+    for (int k = 0; k < Q; ++k) issue(b0 - 2 + k);
+    wait_vmem<NB*(Q - 4)>();
   }
-  // after the first four rows are read: rows b0+2 .. b0+5 into their slots
+  // after the first four rows are read: rows b0+Q-2 .. b0+Q+1 into their slots
   __device__ __forceinline__ void refill() const {
 #pragma unroll
-    for (int k = 0; k < kEQ; ++k) issue(y0 + 2 + k);
+    for (int k = 0; k < 4; ++k) issue(y0 + Q - 2 + k);
   }
-  // at output row y: wait for row y+2, read it, queue row y+6
+  // at output row y: wait for row y+2, read it, queue row y+Q+2
   __device__ __forceinline__ void take(int y, u32x4 v[NB]) const {
-    constexpr int F = 4 * S + 3 * NB;
-    constexpr int X = 4 * S > 3 * NB ? 4 * S : 3 * NB, Y = 4 * S > 3 * NB ? 3 * NB : 4 * S;
-    const int n = min(y - y0, 4) * S + NB * (3 - min(max(y + 4 - y1, 0), 3));
+    constexpr int F = Q * S + (Q - 1) * NB;
+    constexpr int A = Q * S, B = (Q - 1) * NB;
+    constexpr int X = A > B ? A : B, Y = A > B ? B : A;
+    const int n = min(y - y0, Q) * S + NB * (Q - 1 - min(max(y + Q - y1, 0), Q - 1));
     if (n >= F) wait_vmem<F>();
     else if (n >= X) wait_vmem<X>();
     else if (n >= Y) wait_vmem<Y>();
     else wait_vmem<0>();
     read(y + 2, v);
-    if (y + 6 <= y1 + 1) issue(y + 6);
+    if (y + Q + 2 <= y1 + 1) issue(y + Q + 2);
   }
 };
+
+// queue depths (rows): 16 waves of a CU hold at most 160 KB of LDS
+constexpr int kEdgeQ = 4, kGauss5Q = 4, kUyvyQ = 4;
 
 // ---- Gaussian 3x3 -> Sobel 3x3 -> Magnitude -> Threshold (+ Phase) ----------
 
@@ -325,7 +329,7 @@ struct EdgeStream {
   u32 tr[2][8];   // in(y) + in(y+1)
   u32 gr[3][8];   // Gaussian rows y-1, y, y+1
   u32 sr[2][8];   // G(y-1) + G(y)
-  LdsRows<1, PHASE ? 2 : 1> rows;  // input rows (one 16-byte load per row; 1 or 2 stores)
+  LdsRows<1, PHASE ? 2 : 1, kEdgeQ> rows;  // input rows (one 16-byte load per row; 1 or 2 stores)
 
   __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip, u32x4* lds) : d(d_) {
     L = make_lanes(d.g, strip);
@@ -537,7 +541,7 @@ struct EdgeStream {
 
 // LDS the item functions need, in 16-byte units (the kernels provide one
 // buffer of the largest size among the kinds they run)
-constexpr int kEdgeLds = kEQ * 64;
+constexpr int kEdgeLds = kEdgeQ * 64;
 
 template <bool PHASE>
 __device__ __forceinline__ void edge_item(const EdgeDesc& d, int strip, int band, u32x4* lds) {
@@ -579,7 +583,7 @@ struct G5Stream {
   u32 p1[2][8];  // level-1 vertical sums (rows y, y+1) ...
   u32 p2[2][8];
   u32 p3[2][8];
-  LdsRows<UYVY ? 2 : 1, 1> rows;  // input rows (UYVY: 32 bytes per lane)
+  LdsRows<UYVY ? 2 : 1, 1, UYVY ? kUyvyQ : kGauss5Q> rows;  // input rows (UYVY: 32 bytes per lane)
 
   __device__ __forceinline__ G5Stream(const Gauss5Desc& d_, int strip, u32x4* lds) : d(d_) {
     L = make_lanes(d.g, strip);
@@ -695,7 +699,7 @@ struct G5Stream {
 };
 
 template <bool UYVY>
-constexpr int kGauss5Lds = kEQ * 64 * (UYVY ? 2 : 1);
+constexpr int kGauss5Lds = UYVY ? kUyvyQ * 128 : kGauss5Q * 64;
 
 template <bool UYVY>
 __device__ __forceinline__ void gauss5_item(const Gauss5Desc& d, int strip, int band, u32x4* lds) {
