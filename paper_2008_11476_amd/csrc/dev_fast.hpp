@@ -812,10 +812,14 @@ __device__ __forceinline__ int byte_of(u32 r, int k) { return (int)((r >> (8 * k
 // Input rows travel through a queue of kQ rows in this wave's LDS, filled by
 // direct-to-LDS loads (64 lanes x 4 bytes per row): the loads run kQ rows
 // ahead without holding VGPRs.  The compiler does not track these loads
-// against the LDS reads, so the waits are explicit: before a row is read,
-// at most kQ - 1 vector-memory operations may still be outstanding (they
-// complete in issue order, stores included, so the row's load is done), and
-// the read itself completes before its slot is refilled.
+// against the LDS reads, so the waits are explicit, and the read completes
+// before its slot is refilled.  Vector-memory operations complete in issue
+// order, stores included.  A row's load is followed by the loads of the
+// next kQ - 1 rows (every take issues one, clamped rows included) and by
+// the output stores made since: one per output row between the take that
+// issued it and the take that reads it, kQ in the steady state, fewer while
+// the band starts (the first takes fill the ring, with no store between).
+// The wait lets that many operations remain outstanding, rounded down.
 constexpr int kQ = 8;
 
 struct RowQueue {
@@ -825,6 +829,7 @@ struct RowQueue {
   int H, base, lane;
   bool repl;
   u32 fill;
+  int stores;  // output rows stored so far in the band
   __device__ __forceinline__ void issue(int y) {
     const int yc = min(max(y, 0), H - 1);
     __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)yc * pitch),
@@ -832,7 +837,10 @@ struct RowQueue {
                                      0, 0);
   }
   __device__ __forceinline__ u32 take(int y) {
-    asm volatile("s_waitcnt vmcnt(7)" ::: "memory");  // kQ - 1
+    static_assert(kQ == 8, "wait counts below assume eight rows");
+    if (stores >= 8) asm volatile("s_waitcnt vmcnt(15)" ::: "memory");
+    else if (stores >= 4) asm volatile("s_waitcnt vmcnt(11)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(7)" ::: "memory");
     u32 r = buf[((y - base) & (kQ - 1)) * 64 + lane];
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     if (!repl && (y < 0 || y >= H)) r = fill;
@@ -894,7 +902,7 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
   // input rows r-1, r, r+1 for the next gradient row r = nr, then rows
   // further down through the LDS queue
   int nr = max(y0 - 2, 0);
-  RowQueue q{qbuf, s.inb, d.in_pitch, H, nr - 1, s.L.lane, s.repl0, 0x01010101u * (u32)s.c0};
+  RowQueue q{qbuf, s.inb, d.in_pitch, H, nr - 1, s.L.lane, s.repl0, 0x01010101u * (u32)s.c0, 0};
 #pragma unroll
   for (int k = 0; k < kQ; ++k) q.issue(nr - 1 + k);
   u32 ia = q.take(nr - 1);
@@ -974,6 +982,7 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
       o |= (r > thr ? tv : fv) << (8 * k);
     }
     if (s.L.store) __builtin_nontemporal_store(o, (u32*)(out0 + lout + (size_t)((int64_t)y * op)));
+    ++q.stores;
   };
   // unrolled by the ring length so that every ring slot index is a
   // compile-time constant; each step is guarded by a uniform branch
