@@ -36,25 +36,26 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32 perm(u32 hi, u32 lo, u32 sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
 
-// Row access at base + y * pitch + off, off being the lane's byte offset.
-// GLOBAL issues global (address space 1) instead of flat instructions; the
-// choice changes only where the compiler places its memory waits, and was
-// measured per kernel (flat for the edge streams, global for the Gaussian5x5
-// streams, a few percent each way).
-typedef __attribute__((address_space(1))) const u32x4 g_cu32x4;
+// Images are in global memory (address space 1): global rather than flat
+// instructions.
 typedef __attribute__((address_space(1))) u32x4 g_u32x4;
-template <bool GLOBAL>
-__device__ __forceinline__ u32x4 load_row16(const uint8_t* base, int64_t pitch, int y, u32 off) {
-  const uint8_t* p = base + off + (size_t)((int64_t)y * pitch);
-  if (GLOBAL) return __builtin_nontemporal_load((g_cu32x4*)p);
-  return __builtin_nontemporal_load((const u32x4*)p);
+
+// The start of a row is the same in every lane.  Reading it back through
+// readfirstlane keeps the row arithmetic on the scalar unit; with the lane's
+// 32-bit byte offset redefined in the same block (keep_vgpr, an empty asm),
+// the access takes the scalar-base global form and costs no vector address
+// arithmetic.
+__device__ __forceinline__ uintptr_t uniform_addr(uintptr_t a) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  return ((uintptr_t)hi << 32) | lo;
 }
-template <bool GLOBAL>
-__device__ __forceinline__ void store_row16(uint8_t* base, int64_t pitch, int y, u32 off, u32x4 v) {
-  uint8_t* p = base + off + (size_t)((int64_t)y * pitch);
-  if (GLOBAL) __builtin_nontemporal_store(v, (g_u32x4*)p);
-  else __builtin_nontemporal_store(v, (u32x4*)p);
+__device__ __forceinline__ void keep_vgpr(u32& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void store_row16_uniform(uint8_t* base, int64_t pitch, int y, u32 off, u32x4 v) {
+  const uintptr_t row = uniform_addr((uintptr_t)base + (uintptr_t)((int64_t)y * pitch));
+  __builtin_nontemporal_store(v, (g_u32x4*)(row + off));
 }
+
 __device__ __forceinline__ u32 alignbit16(u32 hi, u32 lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }
 // lane i receives lane i-1's value / lane i+1's value (whole-wave shifts; the lane
 // without a source reads 0, which only halo lanes ever see)
@@ -251,11 +252,11 @@ struct LdsRows {
   // direct-to-LDS load of input row r (clamped to the image) into its slot
   __device__ __forceinline__ void issue(int r) const {
     const int rc = min(max(r, 0), H - 1);
-    const uint8_t* src = base + lin + (size_t)((int64_t)rc * pitch);
+    const uintptr_t row = uniform_addr((uintptr_t)base + (uintptr_t)((int64_t)rc * pitch));
     u32x4* slot = q + ((r - qbase) & (Q - 1)) * (64 * NB);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      __builtin_amdgcn_global_load_lds((const void*)(src + 16 * b),
+      __builtin_amdgcn_global_load_lds((const void*)(row + lin + 16 * b),
                                        (__attribute__((address_space(3))) void*)(slot + 64 * b), 16, 0, 0);
   }
   // row r from its slot; the read completes before the slot is refilled
@@ -280,7 +281,8 @@ struct LdsRows {
     for (int k = 0; k < 4; ++k) issue(y0 + Q - 2 + k);
   }
   // at output row y: wait for row y+2, read it, queue row y+Q+2
-  __device__ __forceinline__ void take(int y, u32x4 v[NB]) const {
+  __device__ __forceinline__ void take(int y, u32x4 v[NB]) {
+    keep_vgpr(lin);
     constexpr int F = Q * S + (Q - 1) * NB;
     constexpr int A = Q * S, B = (Q - 1) * NB;
     constexpr int X = A > B ? A : B, Y = A > B ? B : A;
@@ -402,7 +404,7 @@ struct EdgeStream {
       po.y = perm(a67, a45, 0x05040100u);
       po.z = perm(a23, a01, 0x07060302u);
       po.w = perm(a67, a45, 0x07060302u);
-      if (L.store) store_row16<true>(ph0, pp, y, lout, po);
+      if (L.store) store_row16_uniform(ph0, pp, y, lout, po);
     }
     // magnitude + threshold as one integer test: gx^2 + gy^2 > T, i.e. the
     // sign of gx^2 + gy^2 + thr_not (thr_not = -T - 1); mask bytes are 0xFF
@@ -449,7 +451,7 @@ struct EdgeStream {
       o.z = tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
       o.w = tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
     }
-    if (L.store) store_row16<true>(out0, op, y, lout, o);
+    if (L.store) store_row16_uniform(out0, op, y, lout, o);
   }
   // Output row y; J is the phase of y in the six-row unrolled sequence.
   template <int J>
@@ -465,6 +467,7 @@ struct EdgeStream {
     u32(&s1)[8] = sr[(J + 1) % 2];
     u32x4 cur;
     rows.take(y, &cur);
+    keep_vgpr(lout);
     if (y + 1 < H) {
       unpk(cur, y + 2, in2);
       u32 v[8];
@@ -638,7 +641,7 @@ struct G5Stream {
     u32 o[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) o[k] = shr2(add2(c[k], c[k + 1]), 8);
-    if (L.store) store_row16<true>(out0, op, y, lout, pack16(o));
+    if (L.store) store_row16_uniform(out0, op, y, lout, pack16(o));
   }
   // output row y: the new input row is y+2
   template <int J>
@@ -653,6 +656,7 @@ struct G5Stream {
     u32(&c1)[8] = p3[(J + 1) % 2];
     u32x4 cur[2];
     rows.take(y, cur);
+    keep_vgpr(lout);
     unpk(cur, y + 2, r1);
     u32 v[8];
 #pragma unroll
