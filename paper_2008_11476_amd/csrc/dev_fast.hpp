@@ -995,15 +995,17 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
     for (int j = 0; j < 5; ++j) {
       if (y + j < y1) {
         emit(y + j);
-        int hn[3][4];
-        next_h(y + j + 3, hn, ring[(j + 4) % 5]);
+        // the oldest row leaves the running sums, and its slot takes the new
+        // row in place (no copy between registers)
 #pragma unroll
         for (int q = 0; q < 3; ++q)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            v[q][k] += hn[q][k] - ring[j][q][k];
-            ring[j][q][k] = hn[q][k];
-          }
+          for (int k = 0; k < 4; ++k) v[q][k] -= ring[j][q][k];
+        next_h(y + j + 3, ring[j], ring[(j + 4) % 5]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[q][k] += ring[j][q][k];
       }
     }
   }

@@ -148,6 +148,44 @@ def test_batch_rows_option(ctx):
     hvx.hvx_release_batch(b)
 
 
+@pytest.mark.parametrize("kind", ["edge", "edge_phase_constant", "gauss5", "uyvy_gauss5", "corner"])
+def test_batch_short_bands_every_stream(ctx, kind):
+    """Bands of 1 to 9 rows (shorter than the row queue and its prologue),
+    on a frame whose height leaves a ragged last band, through each fused
+    stream in both launch modes: the explicit memory waits of the row queues
+    have their start and end cases here."""
+    import torch
+    w, h = 1100, 37
+    if kind == "edge":
+        spec = gs.edge_spec(synth.edge_image(w, h, seed=21))
+    elif kind == "edge_phase_constant":
+        spec = gs.edge_spec(synth.edge_image(w, h, seed=22), phase=True, b0=("constant", 9), b1=("constant", 0))
+    elif kind == "gauss5":
+        spec = gs.gauss5_spec(synth.edge_image(w, h, seed=23), b=("constant", 200))
+    elif kind == "uyvy_gauss5":
+        spec = gs.uyvy_gauss5_spec(synth.uyvy_image(w, h, seed=24))
+    else:
+        spec = gs.corner_spec(synth.corner_image(w, h, seed=25))
+    env = spec.run_oracle()
+    g, outs, keep, imgs = _build(ctx, spec)
+    b = hvx.hvx_batch_create(ctx, [g])
+    side = torch.cuda.Stream()
+    stream = side.cuda_stream
+    for rows in (1, 2, 3, 4, 5, 6, 7, 9):
+        for pers in (0, 1):
+            log("short bands %s rows=%d persistent=%d" % (kind, rows, pers))
+            hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_ROWS, rows, ctx=ctx)
+            hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, pers, ctx=ctx)
+            for t, _ in outs.values():
+                t.fill_(0x5A)
+            torch.cuda.synchronize()
+            hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+            torch.cuda.synchronize()
+            compare(spec, _read(outs), env, phase_names=("ph",), corner=(kind == "corner"))
+    hvx.hvx_release_batch(b)
+    hvx.hvx_release_graph(g)
+
+
 def test_batch_refresh_after_swap(ctx):
     import torch
     w, h = 1500, 90
