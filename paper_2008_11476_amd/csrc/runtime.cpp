@@ -487,6 +487,37 @@ hvx_status hvx_batch_query(hvx_batch hb, int attr, int64_t* out) {
 // Outputs of the first and last graph of a batch (the tuner's equality check).
 static hvx_status read_outputs(Graph* g, hipStream_t st, std::vector<std::vector<uint8_t>>* out);
 
+// Rows per work item that make the single launch a whole number of rounds
+// of resident waves (2, 3, 4, 6 or 8 rounds): the smallest rows whose item
+// count fits, so the last round is as full as the batch allows.
+static std::vector<int> balanced_rows(const Batch* b) {
+  std::vector<std::pair<int64_t, int64_t>> sh;  // strips and height of each image
+  for (const BatchImage& bi : b->imgs) {
+    const StripGrid& g = bi.kind == FK_EDGE ? bi.d.e.g : bi.kind == FK_CORNER ? bi.d.c.g : bi.d.g5.g;
+    sh.push_back({g.nstrips, g.h});
+  }
+  std::vector<int> out;
+  if (sh.empty()) return out;
+  const int64_t slots = (int64_t)b->ctx->num_cus * batch_waves_per_cu(b->kinds);
+  auto items = [&](int64_t r) {
+    int64_t n = 0;
+    for (const auto& x : sh) n += x.first * ((x.second + r - 1) / r);
+    return n;
+  };
+  for (int rounds : {2, 3, 4, 6, 8}) {
+    const int64_t cap = rounds * slots;
+    if (items(65535) > cap) continue;
+    int lo = 1, hi = 65535;  // items() does not increase with the rows
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (items(mid) <= cap) hi = mid;
+      else lo = mid + 1;
+    }
+    out.push_back(lo);
+  }
+  return out;
+}
+
 hvx_status hvx_batch_autotune(hvx_batch hb, void* stream, int iters) {
   if (!registry_check(hb, T_BATCH)) return HVX_ERROR_INVALID_REFERENCE;
   Batch* b = (Batch*)hb;
@@ -502,7 +533,9 @@ hvx_status hvx_batch_autotune(hvx_batch hb, void* stream, int iters) {
   int best_rows = b->rows_override;
   bool best_persistent = b->persistent;
   hvx_status s = HVX_SUCCESS;
-  static const int cand_rows[] = {0, 8, 16, 24, 32, 40, 48, 64, 128};
+  std::vector<int> cand_rows = {0, 8, 16, 24, 32, 40, 48, 64, 128};
+  for (int r : balanced_rows(b))
+    if (std::find(cand_rows.begin(), cand_rows.end(), r) == cand_rows.end()) cand_rows.push_back(r);
   for (int rows : cand_rows) {
     b->rows_override = rows;
     s = batch_build(b);
