@@ -478,14 +478,15 @@ def run(args, torch, hvx, ctx):
     ms = r["ms"]
     kernel = "hvx::k_batch_direct<8>" if r["mode"] == "direct" else "hvx::k_batch<8>"
     # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter
-    # summary, used only while it matches the kernel sources and launch shape
+    # summary (one entry per profiled rows-per-item shape), used only while it
+    # matches the kernel sources and the tuned launch shape
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "edge_phase_4k_batch_traffic.json")
+    rows_key = str(r["per_mode"]["rows_per_item"])
     if os.path.exists(tfile):
         t = json.load(open(tfile))
-        if (t.get("kernel_hash") == kernel_source_hash() and t.get("kernel") == kernel
-                and t.get("rows_per_item") == r["per_mode"]["rows_per_item"]):
-            traffic = t.get("bytes_per_launch")
+        if t.get("kernel_hash") == kernel_source_hash() and t.get("kernel") == kernel:
+            traffic = t.get("shapes", {}).get(rows_key, {}).get("bytes_per_launch")
     # VALU instructions per launch from the committed SQ counter summary (same
     # kernel sources and launch shape only): the share of the machine's VALU
     # issue slots the timed launches used, 1024 SIMDs x one wave64
@@ -494,10 +495,12 @@ def run(args, torch, hvx, ctx):
     vfile = os.path.join(ROOT, "profiles", "edge_phase_4k_batch_valu.json")
     if os.path.exists(vfile):
         v = json.load(open(vfile))
-        if (v.get("kernel_hash") == kernel_source_hash() and v.get("kernel") == kernel
-                and v.get("rows_per_item") == r["per_mode"]["rows_per_item"]):
+        insts = None
+        if v.get("kernel_hash") == kernel_source_hash() and v.get("kernel") == kernel:
+            insts = v.get("shapes", {}).get(rows_key, {}).get("valu_insts_per_launch")
+        if insts:
             slots = VALU_SIMDS * (ms * 1e-3) * CLOCK_HZ / 4
-            valu_frac = round(v["valu_insts_per_launch"] / slots, 4)
+            valu_frac = round(insts / slots, 4)
     out = {
         "metric": "fused-graph MPix/s + % HBM peak (4K Sobel); served p50/p99 latency vs plain",
         "value": round(r["mpix_s"], 1),
