@@ -852,28 +852,80 @@ struct RowQueue {
   }
 };
 
-// Horizontal 5-sums of the three products at in-image row r (rows r-1, r, r+1 given).
+// The lane's four pixels x0..x3 of an input row as two registers of 16-bit
+// pairs: even (x0, x2) and odd (x1, x3).
+__device__ __forceinline__ u32 even_pair(u32 r) { return perm(0u, r, 0x0C020C00u); }
+__device__ __forceinline__ u32 odd_pair(u32 r) { return perm(0u, r, 0x0C030C01u); }
+// a + 2 b + c on 16-bit pairs (one packed multiply-add; the inline constant 2
+// sits in the low half, which op_sel_hi feeds to both halves)
+__device__ __forceinline__ u32 sum121(u32 a, u32 b, u32 c) {
+  u32 r;
+  asm("v_pk_mad_u16 %0, %1, 2, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(b), "v"(add2(a, c)));
+  return r;
+}
+// signed 16-bit half h0 of a times half h1 of b (0 low, 1 high), into 32 bits
+template <int H0, int H1>
+__device__ __forceinline__ int mul_half(u32 a, u32 b) {
+  int r;
+  if (H0 == 0 && H1 == 0) asm("v_mad_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  else if (H0 == 1 && H1 == 1) asm("v_mad_i32_i16 %0, %1, %2, 0 op_sel:[1,1,0,0]" : "=v"(r) : "v"(a), "v"(b));
+  else if (H0 == 1) asm("v_mad_i32_i16 %0, %1, %2, 0 op_sel:[1,0,0,0]" : "=v"(r) : "v"(a), "v"(b));
+  else asm("v_mad_i32_i16 %0, %1, %2, 0 op_sel:[0,1,0,0]" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Horizontal 5-sums of the three products at in-image row r (rows r-1, r, r+1
+// given).  The Sobel part runs on 16-bit pairs (two pixels per instruction):
+// sv = a + 2b + c and dv = c - a per column, their left and right neighbours
+// by wave shifts and v_alignbit, the border of the Sobel's input applied to
+// those neighbour columns (a column of border pixels has sv = 4c, dv = 0).
 template <bool HEDGE>
 __device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3][4]) {
-  int sv[4], dv[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int ak = byte_of(a, k), bk = byte_of(b, k), ck = byte_of(c, k);
-    sv[k] = ak + 2 * bk + ck;
-    dv[k] = ck - ak;
+  const Lanes4& L = s.L;
+  u32 s0 = sum121(even_pair(a), even_pair(b), even_pair(c));  // sv (x0, x2)
+  u32 s1 = sum121(odd_pair(a), odd_pair(b), odd_pair(c));     // sv (x1, x3)
+  u32 d0 = sub2(even_pair(c), even_pair(a));                  // dv (x0, x2)
+  u32 d1 = sub2(odd_pair(c), odd_pair(a));                    // dv (x1, x3)
+  const u32 cs = (u32)(4 * s.c0) * 0x10001u;  // sv of a border column, both halves
+  if (HEDGE && L.edgeR && L.m != 0 && L.mRag) {
+    // the pixel just past W (position m of the ragged lane) becomes the border
+    if (L.m == 1) {
+      s1 = bfi(0x0000FFFFu, s.repl0 ? s0 : cs, s1);
+      d1 = bfi(0x0000FFFFu, s.repl0 ? d0 : 0u, d1);
+    } else if (L.m == 2) {
+      s0 = s.repl0 ? perm(s1, s0, 0x05040100u) : bfi(0xFFFF0000u, cs, s0);
+      d0 = s.repl0 ? perm(d1, d0, 0x05040100u) : (d0 & 0x0000FFFFu);
+    } else {
+      s1 = bfi(0xFFFF0000u, s.repl0 ? s0 : cs, s1);
+      d1 = bfi(0xFFFF0000u, s.repl0 ? d0 : 0u, d1);
+    }
   }
-  int es[8], ed[8];
-  extend4<1, HEDGE>(sv, es, s.L, s.repl0, 4 * s.c0);
-  extend4<1, HEDGE>(dv, ed, s.L, s.repl0, 0);
+  // columns x-1, x1 and x2, x4 around the lane
+  u32 ls = alignbit16(s1, from_left_mov(s1)), rs = alignbit16(from_right_mov(s0), s0);
+  u32 ld = alignbit16(d1, from_left_mov(d1)), rd = alignbit16(from_right_mov(d0), d0);
+  if (HEDGE && L.edgeL && L.mL) {  // x-1 left of the image
+    ls = bfi(0x0000FFFFu, s.repl0 ? s0 : cs, ls);
+    ld = bfi(0x0000FFFFu, s.repl0 ? d0 : 0u, ld);
+  }
+  if (HEDGE && L.edgeR && L.mR) {  // x4 right of the image (W % 4 == 0)
+    rs = bfi(0xFFFF0000u, s.repl0 ? s1 : cs, rs);
+    rd = bfi(0xFFFF0000u, s.repl0 ? d1 : 0u, rd);
+  }
+  const u32 gx0 = sub2(s1, ls), gx1 = sub2(rs, s0);          // gx (x0, x2), (x1, x3)
+  const u32 gy0 = sum121(ld, d0, d1), gy1 = sum121(d0, d1, rd);  // gy (x0, x2), (x1, x3)
   int p[3][4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int gx = es[k + 3] - es[k + 1];
-    const int gy = ed[k + 1] + 2 * ed[k + 2] + ed[k + 3];
-    p[0][k] = __mul24(gx, gx);
-    p[1][k] = __mul24(gy, gy);
-    p[2][k] = __mul24(gx, gy);
-  }
+  p[0][0] = mul_half<0, 0>(gx0, gx0);
+  p[0][1] = mul_half<0, 0>(gx1, gx1);
+  p[0][2] = mul_half<1, 1>(gx0, gx0);
+  p[0][3] = mul_half<1, 1>(gx1, gx1);
+  p[1][0] = mul_half<0, 0>(gy0, gy0);
+  p[1][1] = mul_half<0, 0>(gy1, gy1);
+  p[1][2] = mul_half<1, 1>(gy0, gy0);
+  p[1][3] = mul_half<1, 1>(gy1, gy1);
+  p[2][0] = mul_half<0, 0>(gx0, gy0);
+  p[2][1] = mul_half<0, 0>(gx1, gy1);
+  p[2][2] = mul_half<1, 1>(gx0, gy0);
+  p[2][3] = mul_half<1, 1>(gx1, gy1);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     int e[8];
