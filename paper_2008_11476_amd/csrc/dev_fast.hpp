@@ -1026,17 +1026,22 @@ __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::L
   const int64_t op = d.out_pitch;
   const u32 lout = (u32)s.L.xs;  // wraps for the left halo lane, which never stores
   const float kk = d.k, thr = d.thr;
-  const u32 tv = d.tv4 & 0xFFu, fv = d.fv4 & 0xFFu;
+  const u32 fv4 = d.fv4, x4 = d.tv4 ^ d.fv4;
   auto emit = [&](int y) {
-    u32 o = 0;
+    // thr - R = thr + Sxy^2 + k (Sxx + Syy)^2 - Sxx Syy in three fused
+    // multiply-adds; its sign bit is set exactly where R > thr (equality
+    // gives +0)
+    u32 t[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const float sxx = (float)v[0][k], syy = (float)v[1][k], sxy = (float)v[2][k];
-      const float det = fmaf(sxx, syy, -sxy * sxy);
       const float tr = sxx + syy;
-      const float r = fmaf(-kk * tr, tr, det);
-      o |= (r > thr ? tv : fv) << (8 * k);
+      t[k] = __float_as_uint(fmaf(-sxx, syy, fmaf(kk * tr, tr, fmaf(sxy, sxy, thr))));
     }
+    // byte permute selectors 9 and 11 replicate bit 31 of the low and high
+    // source: mask bytes 0xFF where R > thr, which pick tv over fv
+    const u32 m = perm(t[1], t[0], 0x0C0C0B09u) | perm(t[3], t[2], 0x0B090C0Cu);
+    const u32 o = fv4 ^ (m & x4);
     if (s.L.store) __builtin_nontemporal_store(o, (u32*)(out0 + lout + (size_t)((int64_t)y * op)));
     ++q.stores;
   };
