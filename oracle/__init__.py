@@ -31,7 +31,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BORDERS = {"undefined": 0, "constant": 1, "replicate": 2}
 
 # Window radius of each local operator (point operators have radius 0).
-RADIUS = {"gaussian3x3": 1, "gaussian5x5": 2, "box3x3": 1, "sobel3x3": 1, "box5x5_f32": 2}
+RADIUS = {"gaussian3x3": 1, "gaussian5x5": 2, "box3x3": 1, "sobel3x3": 1, "box5x5_f32": 2, "dilate3x3": 1,
+          "erode3x3": 1, "median3x3": 1}
 
 _lib = None
 
@@ -92,6 +93,21 @@ def gaussian5x5(img, border="replicate", c=0):
 
 def box3x3(img, border="replicate", c=0):
     return _local_u8("orc_box3x3", img, border, c)
+
+
+def dilate3x3(img, border="replicate", c=0):
+    """Table 2 local operator, MAX over the 3x3 window."""
+    return _local_u8("orc_dilate3x3", img, border, c)
+
+
+def erode3x3(img, border="replicate", c=0):
+    """Table 2 local operator, MIN over the 3x3 window."""
+    return _local_u8("orc_erode3x3", img, border, c)
+
+
+def median3x3(img, border="replicate", c=0):
+    """Table 2 local operator, MEDIAN of the 3x3 window."""
+    return _local_u8("orc_median3x3", img, border, c)
 
 
 def sobel3x3(img, border="replicate", c=0):
@@ -237,6 +253,12 @@ def _run_node(n: Node, env: dict):
         res = [gaussian5x5(ins[0], b, c)]
     elif n.op == "box3x3":
         res = [box3x3(ins[0], b, c)]
+    elif n.op == "dilate3x3":
+        res = [dilate3x3(ins[0], b, c)]
+    elif n.op == "erode3x3":
+        res = [erode3x3(ins[0], b, c)]
+    elif n.op == "median3x3":
+        res = [median3x3(ins[0], b, c)]
     elif n.op == "sobel3x3":
         res = list(sobel3x3(ins[0], b, c))
     elif n.op == "magnitude":

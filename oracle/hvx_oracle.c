@@ -210,6 +210,55 @@ void orc_box3x3(const uint8_t* in, uint8_t* out, int w, int h, int border, int c
     }
 }
 
+/* Dilate 3x3 / Erode 3x3 (Table 2, local operators with a MAX / MIN
+ * reduction): the largest / smallest of the 9 window pixels. */
+void orc_dilate3x3(const uint8_t* in, uint8_t* out, int w, int h, int border, int c) {
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < w; ++x) {
+      int64_t m = 0;
+      for (int j = -1; j <= 1; ++j)
+        for (int i = -1; i <= 1; ++i) {
+          int64_t v = fetch_u8(in, w, h, x + i, y + j, border, c);
+          if (v > m) m = v;
+        }
+      out[(size_t)y * w + x] = (uint8_t)m;
+    }
+}
+
+void orc_erode3x3(const uint8_t* in, uint8_t* out, int w, int h, int border, int c) {
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < w; ++x) {
+      int64_t m = 255;
+      for (int j = -1; j <= 1; ++j)
+        for (int i = -1; i <= 1; ++i) {
+          int64_t v = fetch_u8(in, w, h, x + i, y + j, border, c);
+          if (v < m) m = v;
+        }
+      out[(size_t)y * w + x] = (uint8_t)m;
+    }
+}
+
+/* Median 3x3 (Table 2, local operator with a MEDIAN reduction): the 9
+ * window pixels sorted ascending (insertion sort), the fifth one. */
+void orc_median3x3(const uint8_t* in, uint8_t* out, int w, int h, int border, int c) {
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < w; ++x) {
+      int64_t v[9];
+      int n = 0;
+      for (int j = -1; j <= 1; ++j)
+        for (int i = -1; i <= 1; ++i) {
+          int64_t t = fetch_u8(in, w, h, x + i, y + j, border, c);
+          int k = n++;
+          while (k > 0 && v[k - 1] > t) {
+            v[k] = v[k - 1];
+            --k;
+          }
+          v[k] = t;
+        }
+      out[(size_t)y * w + x] = (uint8_t)v[4];
+    }
+}
+
 /* Sobel 3x3 gradients of a U8 image.  x grows to the right, y downwards.
  * gx = (right column - left column) weighted (1 2 1) along y;
  * gy = (bottom row - top row) weighted (1 2 1) along x.

@@ -56,6 +56,43 @@ def test_gaussian_box_vs_scipy(w, h, border, c):
 
 @pytest.mark.parametrize("w,h", SIZES)
 @pytest.mark.parametrize("border,c", BORDERS)
+def test_dilate_erode_median_vs_scipy(w, h, border, c):
+    """Grey dilation, erosion and the median filter of scipy.ndimage over the
+    3x3 window, with the same border extension."""
+    img = synth.uniform_u8(w, h, seed=w * 7 + h)
+    mode, cval = _nd_mode(border, c)
+    kw = dict(size=(3, 3), mode=mode, cval=cval)
+    assert np.array_equal(oracle.dilate3x3(img, border, c), nd.grey_dilation(img, **kw))
+    assert np.array_equal(oracle.erode3x3(img, border, c), nd.grey_erosion(img, **kw))
+    assert np.array_equal(oracle.median3x3(img, border, c), nd.median_filter(img, **kw))
+
+
+def test_dilate_erode_median_brute_force_and_order():
+    """Brute force over explicit windows on a small image, and the order
+    erode <= median <= dilate with equality on a constant image."""
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, size=(6, 7)).astype(np.uint8)
+    pad = np.pad(img.astype(np.int64), 1, mode="edge")
+    win = np.stack([pad[j:j + 6, i:i + 7] for j in range(3) for i in range(3)])
+    assert np.array_equal(oracle.dilate3x3(img), win.max(0))
+    assert np.array_equal(oracle.erode3x3(img), win.min(0))
+    assert np.array_equal(oracle.median3x3(img), np.sort(win, axis=0)[4])
+    big = synth.uniform_u8(40, 30, seed=5)
+    e, m, d = oracle.erode3x3(big), oracle.median3x3(big), oracle.dilate3x3(big)
+    assert np.all(e <= m) and np.all(m <= d) and np.all(e <= big) and np.all(big <= d)
+    const = np.full((5, 9), 77, np.uint8)
+    for f in (oracle.erode3x3, oracle.median3x3, oracle.dilate3x3):
+        assert np.array_equal(f(const, "constant", 77), const)
+    # a lone bright pixel grows to a 3x3 square under dilation, vanishes under
+    # erosion and the median
+    dot = np.zeros((7, 7), np.uint8)
+    dot[3, 3] = 200
+    assert oracle.dilate3x3(dot)[2:5, 2:5].min() == 200 and oracle.dilate3x3(dot).sum() == 9 * 200
+    assert oracle.erode3x3(dot).max() == 0 and oracle.median3x3(dot).max() == 0
+
+
+@pytest.mark.parametrize("w,h", SIZES)
+@pytest.mark.parametrize("border,c", BORDERS)
 def test_sobel_vs_scipy_sobel(w, h, border, c):
     img = synth.uniform_u8(w, h, seed=w * 7 + h)
     mode, cval = _nd_mode(border, c)
