@@ -154,6 +154,9 @@ hvx_status hvx_graph_create(hvx_context ctx, hvx_graph* out);
  *  gaussian3x3      U8 -> U8: sum of (1 2 1)x(1 2 1)-weighted window, >> 4.
  *  gaussian5x5      U8 -> U8: sum of (1 4 6 4 1)^2-weighted window, >> 8.
  *  box3x3           U8 -> U8: window sum / 9, floor.
+ *  dilate3x3        U8 -> U8: largest pixel of the 3x3 window.
+ *  erode3x3         U8 -> U8: smallest pixel of the 3x3 window.
+ *  median3x3        U8 -> U8: median (fifth smallest) of the 3x3 window.
  *  box5x5_f32       F32 -> F32: unnormalised 5x5 window sum.
  *  sobel3x3         U8 -> S16 gx (right minus left), S16 gy (bottom minus top),
  *                   (1 2 1) smoothing across; either output may be NULL.
@@ -174,6 +177,10 @@ hvx_status hvx_channel_extract_node(hvx_graph g, hvx_image uyvy, int channel, hv
 hvx_status hvx_gaussian3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
 hvx_status hvx_gaussian5x5_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
 hvx_status hvx_box3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
+/* Table 2 local operators with a MAX / MIN / MEDIAN reduction over the window */
+hvx_status hvx_dilate3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
+hvx_status hvx_erode3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
+hvx_status hvx_median3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
 hvx_status hvx_box5x5_f32_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
 hvx_status hvx_sobel3x3_node(hvx_graph g, hvx_image in, hvx_image gx, hvx_image gy, hvx_node* node_out);
 hvx_status hvx_magnitude_node(hvx_graph g, hvx_image gx, hvx_image gy, hvx_image out, hvx_node* node_out);

@@ -76,6 +76,9 @@ def _load():
         "hvx_gaussian3x3_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_gaussian5x5_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_box3x3_node": [_vp, _vp, _vp, _P(_vp)],
+        "hvx_dilate3x3_node": [_vp, _vp, _vp, _P(_vp)],
+        "hvx_erode3x3_node": [_vp, _vp, _vp, _P(_vp)],
+        "hvx_median3x3_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -222,6 +225,18 @@ def hvx_gaussian5x5_node(g, i, o, ctx=None):
 
 def hvx_box3x3_node(g, i, o, ctx=None):
     return _node("hvx_box3x3_node", ctx, g, i, o)
+
+
+def hvx_dilate3x3_node(g, i, o, ctx=None):
+    return _node("hvx_dilate3x3_node", ctx, g, i, o)
+
+
+def hvx_erode3x3_node(g, i, o, ctx=None):
+    return _node("hvx_erode3x3_node", ctx, g, i, o)
+
+
+def hvx_median3x3_node(g, i, o, ctx=None):
+    return _node("hvx_median3x3_node", ctx, g, i, o)
 
 
 def hvx_box5x5_f32_node(g, i, o, ctx=None):

@@ -396,6 +396,18 @@ hvx_status hvx_gaussian5x5_node(hvx_graph g, hvx_image in, hvx_image out, hvx_no
 hvx_status hvx_box3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* no) {
   return add_node(g, NK_BOX3, {in}, {out}, 1, no, nullptr);
 }
+
+hvx_status hvx_dilate3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* no) {
+  return add_node(g, NK_DILATE3, {in}, {out}, 1, no, nullptr);
+}
+
+hvx_status hvx_erode3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* no) {
+  return add_node(g, NK_ERODE3, {in}, {out}, 1, no, nullptr);
+}
+
+hvx_status hvx_median3x3_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* no) {
+  return add_node(g, NK_MEDIAN3, {in}, {out}, 1, no, nullptr);
+}
 hvx_status hvx_box5x5_f32_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* no) {
   return add_node(g, NK_BOX5F, {in}, {out}, 1, no, nullptr);
 }

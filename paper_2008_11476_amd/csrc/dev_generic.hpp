@@ -167,6 +167,31 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
         for (int i = -1; i <= 1; ++i) s += rd(i, j);
       return s / 9;
     }
+    case OP_DILATE3:
+    case OP_ERODE3: {
+      const bool mx = o.kind == OP_DILATE3;
+      int m = rd(0, 0);
+#pragma unroll
+      for (int j = -1; j <= 1; ++j)
+#pragma unroll
+        for (int i = -1; i <= 1; ++i) m = mx ? max(m, rd(i, j)) : min(m, rd(i, j));
+      return m;
+    }
+    case OP_MEDIAN3: {
+      // Sorting each row of the window and then each column leaves the
+      // median of the nine on the anti-diagonal: the largest row minimum,
+      // the median of the row medians and the smallest row maximum.
+      int lo = 0, md[3], hi = 255;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int a = rd(-1, j - 1), b = rd(0, j - 1), c = rd(1, j - 1);
+        lo = max(lo, min(a, min(b, c)));
+        md[j] = max(min(a, b), min(max(a, b), c));
+        hi = min(hi, max(a, max(b, c)));
+      }
+      const int mm = max(min(md[0], md[1]), min(max(md[0], md[1]), md[2]));
+      return max(min(lo, mm), min(max(lo, mm), hi));
+    }
     case OP_BOX5F: {
       // fixed order: each row left to right, rows top to bottom
       float s = 0.f;

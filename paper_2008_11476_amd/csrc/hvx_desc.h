@@ -22,6 +22,9 @@ enum OpKind : int32_t {
   OP_HARRIS,
   OP_THRESHOLD,
   OP_CONVOLVE,
+  OP_DILATE3,  // Table 2 local operators with MAX / MIN / MEDIAN reductions
+  OP_ERODE3,
+  OP_MEDIAN3,
 };
 
 // Element formats (same numbering as the public HVX_DF_* constants).

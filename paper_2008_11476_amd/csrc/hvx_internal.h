@@ -45,6 +45,9 @@ enum NodeKind : int32_t {
   NK_GAUSS3,
   NK_GAUSS5,
   NK_BOX3,
+  NK_DILATE3,
+  NK_ERODE3,
+  NK_MEDIAN3,
   NK_BOX5F,
   NK_SOBEL3,
   NK_MAGNITUDE,

@@ -31,6 +31,9 @@ static int op_radius(const LOp& o, int* rx, int* ry) {
   switch (o.kind) {
     case OP_GAUSS3:
     case OP_BOX3:
+    case OP_DILATE3:
+    case OP_ERODE3:
+    case OP_MEDIAN3:
     case OP_SOBEL_X:
     case OP_SOBEL_Y: r = 1; break;
     case OP_GAUSS5:
@@ -80,6 +83,9 @@ static const char* node_name(int kind) {
     case NK_GAUSS3: return "Gaussian3x3";
     case NK_GAUSS5: return "Gaussian5x5";
     case NK_BOX3: return "Box3x3";
+    case NK_DILATE3: return "Dilate3x3";
+    case NK_ERODE3: return "Erode3x3";
+    case NK_MEDIAN3: return "Median3x3";
     case NK_BOX5F: return "Box5x5F32";
     case NK_SOBEL3: return "Sobel3x3";
     case NK_MAGNITUDE: return "Magnitude";
@@ -491,6 +497,9 @@ hvx_status verify_graph(Graph* g) {
       case NK_GAUSS3:
       case NK_GAUSS5:
       case NK_BOX3:
+      case NK_DILATE3:
+      case NK_ERODE3:
+      case NK_MEDIAN3:
         if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
         s = bind_output(g, p, nout[i][0], DF_U8, w, h, nn);
         break;
@@ -576,6 +585,9 @@ hvx_status verify_graph(Graph* g) {
       case NK_GAUSS3: emit(OP_GAUSS3, nin[i], nout[i][0]); break;
       case NK_GAUSS5: emit(OP_GAUSS5, nin[i], nout[i][0]); break;
       case NK_BOX3: emit(OP_BOX3, nin[i], nout[i][0]); break;
+      case NK_DILATE3: emit(OP_DILATE3, nin[i], nout[i][0]); break;
+      case NK_ERODE3: emit(OP_ERODE3, nin[i], nout[i][0]); break;
+      case NK_MEDIAN3: emit(OP_MEDIAN3, nin[i], nout[i][0]); break;
       case NK_BOX5F: emit(OP_BOX5F, nin[i], nout[i][0]); break;
       case NK_SOBEL3:  // two parallel local operators
         if (nout[i][0] >= 0) emit(OP_SOBEL_X, nin[i], nout[i][0]);

@@ -27,7 +27,7 @@ def ctx():
 
 # ---- single operators, node by node (generic tile kernel) ------------------
 
-LOCAL_U8 = ["gaussian3x3", "gaussian5x5", "box3x3"]
+LOCAL_U8 = ["gaussian3x3", "gaussian5x5", "box3x3", "dilate3x3", "erode3x3", "median3x3"]
 SIZES = [(1, 1), (2, 3), (7, 5), (17, 13), (67, 45), (300, 70)]
 
 
@@ -40,6 +40,26 @@ def test_local_u8(ctx, op, w, h, border):
     spec = gs.Spec([gs.N(op, ["in"], ["out"], *border)], {"in": img}, {"out": np.uint8})
     got, _ = run_spec(spec, ctx, fusion=False, specialize=False)
     compare(spec, got, spec.run_oracle())
+
+
+@pytest.mark.parametrize("border", [("replicate", 0), ("constant", 30), ("undefined", 0)])
+@pytest.mark.parametrize("w,h", [(301, 77), (64, 9)])
+def test_morphology_chain_fused(ctx, border, w, h):
+    """Gaussian3x3 -> Median3x3 -> Dilate3x3 -> Erode3x3 -> Threshold as one
+    fused kernel (intermediates in LDS, borders node by node), the median also
+    as an output; against the oracle and the unfused path."""
+    img = synth.edge_image(w, h, seed=w + h)
+    spec = gs.Spec([gs.N("gaussian3x3", ["in"], ["g"], *border), gs.N("median3x3", ["g"], ["m"], *border),
+                    gs.N("dilate3x3", ["m"], ["d"], *border), gs.N("erode3x3", ["d"], ["e"], *border),
+                    gs.N("threshold", ["e"], ["out"], params={"thresh": 100})],
+                   {"in": img}, {"m": np.uint8, "out": np.uint8})
+    env = spec.run_oracle()
+    log("morphology chain %dx%d %s" % (w, h, border))
+    got, g = run_spec(spec, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    compare(spec, got, env)
+    unf, _ = run_spec(spec, ctx, fusion=False)
+    compare(spec, unf, env)
 
 
 @pytest.mark.parametrize("w,h", SIZES)
