@@ -27,17 +27,34 @@
 #define ORC_BORDER_UNDEFINED 0
 #define ORC_BORDER_CONSTANT 1
 #define ORC_BORDER_REPLICATE 2
+#define ORC_BORDER_MIRROR 3
 
 /* ---- border fetch (one per input element type) ------------------------- */
 /* REPLICATE: nearest in-image pixel.  CONSTANT: the constant outside.
+ * MIRROR: the image reflected about its first and last pixel (reflect-101:
+ * ... c b | a b c ... x y | x w ...), repeated as often as needed; a single
+ * row or column repeats its pixel.
  * UNDEFINED: the result there is unspecified; the replicated value is used so
  * that the computation is defined, and callers exclude those pixels. */
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+static int mirror_index(int x, int n) {
+  if (n == 1) return 0;
+  while (x < 0 || x >= n) {
+    if (x < 0) x = -x;
+    if (x >= n) x = 2 * (n - 1) - x;
+  }
+  return x;
+}
+
 static int64_t fetch_u8(const uint8_t* img, int w, int h, int x, int y, int border, int64_t c) {
   if (x < 0 || y < 0 || x >= w || y >= h) {
     if (border == ORC_BORDER_CONSTANT) return c;
+    if (border == ORC_BORDER_MIRROR) {
+      x = mirror_index(x, w);
+      y = mirror_index(y, h);
+    }
     x = clampi(x, 0, w - 1);
     y = clampi(y, 0, h - 1);
   }
@@ -47,6 +64,10 @@ static int64_t fetch_u8(const uint8_t* img, int w, int h, int x, int y, int bord
 static int64_t fetch_s16(const int16_t* img, int w, int h, int x, int y, int border, int64_t c) {
   if (x < 0 || y < 0 || x >= w || y >= h) {
     if (border == ORC_BORDER_CONSTANT) return c;
+    if (border == ORC_BORDER_MIRROR) {
+      x = mirror_index(x, w);
+      y = mirror_index(y, h);
+    }
     x = clampi(x, 0, w - 1);
     y = clampi(y, 0, h - 1);
   }
@@ -56,6 +77,10 @@ static int64_t fetch_s16(const int16_t* img, int w, int h, int x, int y, int bor
 static double fetch_f64(const double* img, int w, int h, int x, int y, int border, double c) {
   if (x < 0 || y < 0 || x >= w || y >= h) {
     if (border == ORC_BORDER_CONSTANT) return c;
+    if (border == ORC_BORDER_MIRROR) {
+      x = mirror_index(x, w);
+      y = mirror_index(y, h);
+    }
     x = clampi(x, 0, w - 1);
     y = clampi(y, 0, h - 1);
   }

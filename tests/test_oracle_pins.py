@@ -15,10 +15,12 @@ import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 SIZES = [(1, 1), (2, 3), (3, 2), (7, 5), (17, 13), (33, 4)]
-BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("constant", 255)]
+BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("constant", 255), ("mirror", 0)]
 
 
 def _nd_mode(border, c):
+    if border == "mirror":
+        return "mirror", 0  # scipy's reflect-101 extension
     return ("nearest", 0) if border == "replicate" else ("constant", c)
 
 
