@@ -73,6 +73,9 @@ typedef int32_t hvx_status;
 #define HVX_BORDER_UNDEFINED 0 /* output pixels whose window leaves the image are unspecified */
 #define HVX_BORDER_CONSTANT 1  /* pixels outside the image read as the constant */
 #define HVX_BORDER_REPLICATE 2 /* pixels outside the image read as the nearest edge pixel */
+#define HVX_BORDER_MIRROR 3    /* the image reflected about its first and last pixel (reflect-101),
+                                  repeated; a one-pixel axis repeats its pixel.  Graphs using it
+                                  run on the generic kernels. */
 
 #define HVX_POLICY_SATURATE 0
 #define HVX_POLICY_WRAP 1

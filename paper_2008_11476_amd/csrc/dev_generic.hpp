@@ -49,12 +49,29 @@ struct TileCtx {
   int tx0, ty0;
 };
 
-// Read value `vi` at (x, y) as seen by operator `o` (border applied).
+// Position read for x outside [0, n) under the MIRROR border: reflected
+// about the first and last pixel (period 2 (n - 1)); a one-pixel axis
+// repeats its pixel.
+__device__ __forceinline__ int mirror_pos(int x, int n) {
+  if (n == 1) return 0;
+  const int per = 2 * (n - 1);
+  x %= per;
+  if (x < 0) x += per;
+  return x < n ? x : per - x;
+}
+
+// Read value `vi` at (x, y) as seen by operator `o` (border applied).  A
+// mirrored position lies within the operator's radius of the image edge,
+// inside the tile's extent of the value.
 __device__ __forceinline__ int rd(const TileCtx& t, const GOp& o, int vi, int x, int y) {
   const GProg& P = *t.P;
   const GVal& v = P.vals[vi];
   if (x < 0 || y < 0 || x >= P.w || y >= P.h) {
     if (o.border == B_CONSTANT) return v.df == DF_F32 ? __float_as_int(o.cf) : o.cint;
+    if (o.border == B_MIRROR) {
+      x = mirror_pos(x, P.w);
+      y = mirror_pos(y, P.h);
+    }
     x = min(max(x, 0), P.w - 1);
     y = min(max(y, 0), P.h - 1);
   }
@@ -467,6 +484,10 @@ __device__ __forceinline__ void local_image(const GProg& P, const IOTable& io) {
       for (int k = 4 - R; k < 8 + R; ++k) {
         int xx = x0 - 4 + k, yy = y - R + j;
         const bool out = xx < 0 || yy < 0 || xx >= W || yy >= H;
+        if (out && o.border == B_MIRROR) {
+          xx = (xx < 0 || xx >= W) ? mirror_pos(xx, W) : xx;
+          yy = (yy < 0 || yy >= H) ? mirror_pos(yy, H) : yy;
+        }
         xx = min(max(xx, 0), W - 1);
         yy = min(max(yy, 0), H - 1);
         const int v = gload(iv.df, base, pitch, xx, yy);

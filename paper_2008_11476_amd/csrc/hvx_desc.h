@@ -29,7 +29,7 @@ enum OpKind : int32_t {
 
 // Element formats (same numbering as the public HVX_DF_* constants).
 enum Df : int32_t { DF_VIRT = 0, DF_U8 = 1, DF_S16 = 2, DF_S32 = 3, DF_F32 = 4, DF_UYVY = 5 };
-enum Border : int32_t { B_UNDEFINED = 0, B_CONSTANT = 1, B_REPLICATE = 2 };
+enum Border : int32_t { B_UNDEFINED = 0, B_CONSTANT = 1, B_REPLICATE = 2, B_MIRROR = 3 };
 
 inline int df_bytes(int df) {
   switch (df) {

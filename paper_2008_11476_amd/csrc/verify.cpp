@@ -125,6 +125,14 @@ static int producer_in(const Plan& p, int v, const std::set<int>& ops) {
 }
 
 // Gaussian3x3 -> SobelX, SobelY -> Magnitude -> Threshold (+ Phase(gx, gy)).
+// The hand-fused kernels implement the UNDEFINED, CONSTANT and REPLICATE
+// borders; a group with a MIRROR border runs on the generic kernels.
+static bool fast_borders(const Plan& p, const Group& gr) {
+  for (int o : gr.ops)
+    if (p.ops[o].border == B_MIRROR) return false;
+  return true;
+}
+
 static bool match_edge(const Plan& p, const Group& gr, int* in_v, int* out_v, int* ph_v) {
   if (gr.ops.size() != 5 && gr.ops.size() != 6) return false;
   std::set<int> ops(gr.ops.begin(), gr.ops.end());
@@ -709,8 +717,8 @@ hvx_status verify_graph(Graph* g) {
   std::vector<Group> final_groups;
   for (auto& gr : p.groups) {
     int a, b, c;
-    bool fast = g->opt_specialize && (match_edge(p, gr, &a, &b, &c) || match_corner(p, gr, &a, &b) ||
-                                      match_gauss5(p, gr, &a, &b));
+    bool fast = g->opt_specialize && fast_borders(p, gr) &&
+                (match_edge(p, gr, &a, &b, &c) || match_corner(p, gr, &a, &b) || match_gauss5(p, gr, &a, &b));
     std::string why;
     if (!fast && gr.ops.size() > 1) {
       Group probe = gr;
@@ -733,7 +741,7 @@ hvx_status verify_graph(Graph* g) {
   for (auto& gr : p.groups) {
     int in_v = -1, out_v = -1, aux = -1;
     gr.kind = FK_GENERIC;
-    if (g->opt_specialize) {
+    if (g->opt_specialize && fast_borders(p, gr)) {
       if (match_edge(p, gr, &in_v, &out_v, &aux)) gr.kind = FK_EDGE;
       else if (match_corner(p, gr, &in_v, &out_v)) gr.kind = FK_CORNER;
       else if (match_gauss5(p, gr, &in_v, &out_v)) gr.kind = FK_GAUSS5;

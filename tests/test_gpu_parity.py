@@ -13,7 +13,8 @@ from tests.gpu_util import compare, log, run_spec
 
 pytestmark = pytest.mark.gpu
 
-BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("undefined", 0)]
+# MIRROR last: the slices BORDERS[:2] / [:3] keep the modes the hand-fused kernels implement
+BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("undefined", 0), ("mirror", 0)]
 
 
 @pytest.fixture(scope="module")
@@ -42,7 +43,7 @@ def test_local_u8(ctx, op, w, h, border):
     compare(spec, got, spec.run_oracle())
 
 
-@pytest.mark.parametrize("border", [("replicate", 0), ("constant", 30), ("undefined", 0)])
+@pytest.mark.parametrize("border", [("replicate", 0), ("constant", 30), ("undefined", 0), ("mirror", 0)])
 @pytest.mark.parametrize("w,h", [(301, 77), (64, 9)])
 def test_morphology_chain_fused(ctx, border, w, h):
     """Gaussian3x3 -> Median3x3 -> Dilate3x3 -> Erode3x3 -> Threshold as one
@@ -228,6 +229,20 @@ def test_uyvy_gauss5_fused(ctx, w, h, border):
     compare(spec, got, spec.run_oracle())
     got2, _ = run_spec(spec, ctx, fusion=False)
     compare(spec, got2, spec.run_oracle())
+
+
+@pytest.mark.parametrize("w,h", [(2, 2), (3, 5), (130, 41)])
+@pytest.mark.parametrize("fusion", [True, False])
+def test_corner_mirror(ctx, w, h, fusion):
+    """The corner graph with MIRROR borders runs on the generic kernels (the
+    F32 Box5x5 reads mirrored F32 products)."""
+    img = synth.corner_image(w, h, seed=w + 1)
+    spec = gs.corner_spec(img, b0=("mirror", 0), b1=("mirror", 0))
+    env = spec.run_oracle()
+    log("corner mirror %dx%d fusion=%s" % (w, h, fusion))
+    got, g = run_spec(spec, ctx, fusion=fusion)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_KERNEL_KIND) == 0
+    compare(spec, got, env, corner=True)
 
 
 @pytest.mark.parametrize("w,h", [(13, 11), (200, 60), (1003, 45)])
