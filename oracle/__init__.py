@@ -110,6 +110,23 @@ def median3x3(img, border="replicate", c=0):
     return _local_u8("orc_median3x3", img, border, c)
 
 
+NONLINEAR = {"median": 0, "min": 1, "max": 2}
+
+
+def nonlinear(img, mask, func, border="replicate", c=0):
+    """Table 2 local operator: median / min / max over the window pixels
+    where `mask` (odd rows x cols, at most 9x9) is nonzero."""
+    img = _c(img, np.uint8)
+    mask = _c((np.asarray(mask) != 0).astype(np.uint8), np.uint8)
+    rows, cols = mask.shape
+    if rows % 2 == 0 or cols % 2 == 0 or rows > 9 or cols > 9 or not mask.any():
+        raise ValueError("mask must be odd-sized, at most 9x9, with a nonzero entry")
+    out = np.empty(img.shape, np.uint8)
+    lib().orc_nonlinear(_p(img), _p(mask), cols, rows, NONLINEAR[func], _p(out), img.shape[1], img.shape[0],
+                        BORDERS[border], int(c))
+    return out
+
+
 def sobel3x3(img, border="replicate", c=0):
     img = _c(img, np.uint8)
     h, w = img.shape
@@ -277,6 +294,8 @@ def _run_node(n: Node, env: dict):
         res = [harris_response(ins[0], ins[1], ins[2], p.get("k", 0.04))]
     elif n.op == "convolve":
         res = [convolve(ins[0], p["coeffs"], p["scale"], p.get("out_dtype", "u8"), b, c)]
+    elif n.op == "nonlinear":
+        res = [nonlinear(ins[0], p["mask"], p["func"], b, c)]
     else:
         raise ValueError("unknown op " + n.op)
     for name, val in zip(n.outputs, res):
@@ -294,8 +313,8 @@ def run(graph: Graph, inputs: dict) -> dict:
 
 
 def _radius(n: Node) -> tuple:
-    if n.op == "convolve":
-        rows, cols = np.asarray(n.params["coeffs"]).shape
+    if n.op in ("convolve", "nonlinear"):
+        rows, cols = np.asarray(n.params["coeffs" if n.op == "convolve" else "mask"]).shape
         return cols // 2, rows // 2
     r = RADIUS.get(n.op, 0)
     return r, r

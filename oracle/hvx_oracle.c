@@ -284,6 +284,33 @@ void orc_median3x3(const uint8_t* in, uint8_t* out, int w, int h, int border, in
     }
 }
 
+/* NonLinearFilter (Table 2, local operator): over the window pixels where
+ * the cols x rows mask (row-major, centred) is nonzero, the median, the
+ * minimum or the maximum (func 0, 1, 2).  The median of n values is the one
+ * at index n / 2 of the ascending order (the upper one when n is even). */
+void orc_nonlinear(const uint8_t* in, const uint8_t* mask, int cols, int rows, int func, uint8_t* out, int w, int h,
+                   int border, int c) {
+  const int rx = cols / 2, ry = rows / 2;
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < w; ++x) {
+      int64_t v[81];
+      int n = 0;
+      for (int j = -ry; j <= ry; ++j)
+        for (int i = -rx; i <= rx; ++i) {
+          if (!mask[(j + ry) * cols + (i + rx)]) continue;
+          int64_t t = fetch_u8(in, w, h, x + i, y + j, border, c);
+          int k = n++;
+          while (k > 0 && v[k - 1] > t) {
+            v[k] = v[k - 1];
+            --k;
+          }
+          v[k] = t;
+        }
+      int64_t r = func == 1 ? v[0] : (func == 2 ? v[n - 1] : v[n / 2]);
+      out[(size_t)y * w + x] = (uint8_t)r;
+    }
+}
+
 /* Sobel 3x3 gradients of a U8 image.  x grows to the right, y downwards.
  * gx = (right column - left column) weighted (1 2 1) along y;
  * gy = (bottom row - top row) weighted (1 2 1) along x.

@@ -804,7 +804,6 @@ __device__ __forceinline__ void extend4(int p[4], int e[8], const Lanes4& L, boo
 }
 
 struct St {
-  const CornerDesc* d;
   Lanes4 L;
   const uint8_t* inb;
   bool repl0, repl1;
@@ -944,7 +943,6 @@ template <bool HEDGE>
 __device__ __forceinline__ void corner_band(const CornerDesc& d, const corner::Lanes4& lanes, int band, u32* qbuf) {
   using namespace corner;
   St s;
-  s.d = &d;
   s.L = lanes;
   s.inb = d.in + s.L.xl;
   s.repl0 = d.b0 != B_CONSTANT;

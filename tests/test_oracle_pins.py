@@ -69,6 +69,28 @@ def test_dilate_erode_median_vs_scipy(w, h, border, c):
     assert np.array_equal(oracle.median3x3(img, border, c), nd.median_filter(img, **kw))
 
 
+PATTERNS = {"box3": np.ones((3, 3)), "cross3": np.array([[0, 1, 0], [1, 1, 1], [0, 1, 0]]),
+            "disk5": np.array([[0, 1, 1, 1, 0]] + [[1] * 5] * 3 + [[0, 1, 1, 1, 0]]),
+            "custom5x3": np.array([[1, 0, 0, 1, 1], [0, 1, 1, 0, 1], [1, 1, 0, 0, 0]]),
+            "pair1x3": np.array([[1, 0, 1]])}
+
+
+@pytest.mark.parametrize("pattern", sorted(PATTERNS))
+@pytest.mark.parametrize("border,c", BORDERS)
+def test_nonlinear_vs_scipy(pattern, border, c):
+    """NonLinearFilter over a mask against scipy.ndimage's rank filters with
+    the same footprint (median: rank n // 2, which scipy's median filter uses)."""
+    img = synth.uniform_u8(23, 17, seed=len(pattern) + c)
+    m = PATTERNS[pattern]
+    mode, cval = _nd_mode(border, c)
+    kw = dict(footprint=m != 0, mode=mode, cval=cval)
+    assert np.array_equal(oracle.nonlinear(img, m, "min", border, c), nd.minimum_filter(img, **kw))
+    assert np.array_equal(oracle.nonlinear(img, m, "max", border, c), nd.maximum_filter(img, **kw))
+    assert np.array_equal(oracle.nonlinear(img, m, "median", border, c), nd.median_filter(img, **kw))
+    if pattern == "box3":
+        assert np.array_equal(oracle.nonlinear(img, m, "median", border, c), oracle.median3x3(img, border, c))
+
+
 def test_dilate_erode_median_brute_force_and_order():
     """Brute force over explicit windows on a small image, and the order
     erode <= median <= dilate with equality on a constant image."""
