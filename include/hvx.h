@@ -160,6 +160,9 @@ hvx_status hvx_graph_create(hvx_context ctx, hvx_graph* out);
  *  dilate3x3        U8 -> U8: largest pixel of the 3x3 window.
  *  erode3x3         U8 -> U8: smallest pixel of the 3x3 window.
  *  median3x3        U8 -> U8: median (fifth smallest) of the 3x3 window.
+ *  nonlinear_filter U8 -> U8: median, minimum or maximum of the window pixels
+ *                   selected by a mask; the median of n pixels is the one at
+ *                   index n / 2 of their ascending order.
  *  box5x5_f32       F32 -> F32: unnormalised 5x5 window sum.
  *  sobel3x3         U8 -> S16 gx (right minus left), S16 gy (bottom minus top),
  *                   (1 2 1) smoothing across; either output may be NULL.
@@ -195,6 +198,15 @@ hvx_status hvx_harris_response_node(hvx_graph g, hvx_image sxx, hvx_image syy, h
 hvx_status hvx_threshold_node(hvx_graph g, hvx_image in, double value, uint8_t true_v, uint8_t false_v,
                               hvx_image out, hvx_node* node_out);
 hvx_status hvx_convolve_node(hvx_graph g, hvx_image in, hvx_convolution conv, hvx_image out, hvx_node* node_out);
+/* NonLinearFilter (Table 2 local operator).  `mask` is cols x rows bytes,
+ * row-major, centred on the output pixel (odd sizes up to 5x5, at least one
+ * nonzero entry: INVALID_DIMENSION / INVALID_PARAMETERS otherwise); nonzero
+ * entries select window pixels.  The mask is copied. */
+#define HVX_NONLINEAR_MEDIAN 0
+#define HVX_NONLINEAR_MIN 1
+#define HVX_NONLINEAR_MAX 2
+hvx_status hvx_nonlinear_filter_node(hvx_graph g, int function, hvx_image in, uint32_t cols, uint32_t rows,
+                                     const uint8_t* mask, hvx_image out, hvx_node* node_out);
 
 /* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the
  * value is read as the input's element type (0..255 for U8). */

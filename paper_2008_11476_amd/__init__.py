@@ -79,6 +79,7 @@ def _load():
         "hvx_dilate3x3_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_erode3x3_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_median3x3_node": [_vp, _vp, _vp, _P(_vp)],
+        "hvx_nonlinear_filter_node": [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _P(_vp)],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -237,6 +238,18 @@ def hvx_erode3x3_node(g, i, o, ctx=None):
 
 def hvx_median3x3_node(g, i, o, ctx=None):
     return _node("hvx_median3x3_node", ctx, g, i, o)
+
+
+HVX_NONLINEAR_MEDIAN, HVX_NONLINEAR_MIN, HVX_NONLINEAR_MAX = 0, 1, 2
+
+
+def hvx_nonlinear_filter_node(g, function, i, mask, o, ctx=None):
+    """`mask`: 2-D array (rows x cols, odd, at most 5x5); nonzero entries
+    select window pixels."""
+    import numpy as np
+    m = np.ascontiguousarray((np.asarray(mask) != 0).astype(np.uint8))
+    rows, cols = m.shape
+    return _node("hvx_nonlinear_filter_node", ctx, g, function, i, cols, rows, m.ctypes.data_as(_vp), o)
 
 
 def hvx_box5x5_f32_node(g, i, o, ctx=None):

@@ -467,6 +467,34 @@ hvx_status hvx_convolve_node(hvx_graph g, hvx_image in, hvx_convolution conv, hv
   return s;
 }
 
+hvx_status hvx_nonlinear_filter_node(hvx_graph g, int function, hvx_image in, uint32_t cols, uint32_t rows,
+                                     const uint8_t* mask, hvx_image out, hvx_node* no) {
+  Graph* gg = as<Graph>(g, T_GRAPH);
+  if (!gg) return HVX_ERROR_INVALID_REFERENCE;
+  if (function < HVX_NONLINEAR_MEDIAN || function > HVX_NONLINEAR_MAX)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown nonlinear function %d", function);
+  if (cols < 1 || rows < 1 || cols > 5 || rows > 5 || !(cols & 1) || !(rows & 1))
+    return set_error(gg->ctx, HVX_ERROR_INVALID_DIMENSION, "mask must be odd-sized, at most 5x5 (got %ux%u)", cols,
+                     rows);
+  if (!mask) return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "null mask");
+  bool any = false;
+  for (uint32_t k = 0; k < cols * rows; ++k) any |= mask[k] != 0;
+  if (!any) return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "mask has no nonzero entry");
+  Node* n = nullptr;
+  hvx_status s = add_node(g, NK_NONLINEAR, {in}, {out}, 1, no, &n);
+  if (s) return s;
+  n->policy = function;
+  n->own_mask.type = T_CONV;
+  n->own_mask.ctx = gg->ctx;
+  n->own_mask.cols = cols;
+  n->own_mask.rows = rows;
+  n->own_mask.scale = 1;
+  n->own_mask.coeffs.resize(cols * rows);
+  for (uint32_t k = 0; k < cols * rows; ++k) n->own_mask.coeffs[k] = mask[k] != 0;
+  n->conv = &n->own_mask;
+  return HVX_SUCCESS;
+}
+
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value) {
   Node* n = as<Node>(node, T_NODE);
   if (!n) return HVX_ERROR_INVALID_REFERENCE;

@@ -151,7 +151,52 @@ __device__ __forceinline__ int point_eval(const GOp& o, int out_df, bool in_f32,
 // bit patterns).  The Convolve mask is walked over the full 5 x 5 extent with
 // the cells outside cols x rows skipped, so that every window offset is a
 // compile-time constant.
+// NonLinearFilter at one pixel (see OP_NONLINEAR).
 template <class RD>
+__device__ __forceinline__ int nonlinear_eval(const GOp& o, const RD& rd) {
+    // the p0 x p1 mask selects window pixels (nonzero entries); p2: 0 the
+    // median, 1 the minimum, 2 the maximum of them.  The median of n
+    // pixels is the one at index n / 2 of their ascending order: a pixel
+    // with at most n / 2 selected pixels below it and more than n / 2 at
+    // or below it.
+    const int cols = o.p0, rows = o.p1, rx = cols / 2, ry = rows / 2;
+    int v[25];
+    uint32_t sel = 0;
+#pragma unroll
+    for (int j = -2; j <= 2; ++j)
+#pragma unroll
+      for (int i = -2; i <= 2; ++i) {
+        const int k = (j + 2) * 5 + (i + 2);
+        v[k] = 0;
+        if (i >= -rx && i <= rx && j >= -ry && j <= ry && o.mask[(j + ry) * cols + (i + rx)] != 0) {
+          v[k] = rd(i, j);
+          sel |= 1u << k;
+        }
+      }
+    if (o.p2 != 0) {
+      int m = o.p2 == 1 ? 255 : 0;
+#pragma unroll
+      for (int k = 0; k < 25; ++k)
+        if ((sel >> k) & 1) m = o.p2 == 1 ? min(m, v[k]) : max(m, v[k]);
+      return m;
+    }
+    const int half = __popc(sel) / 2;
+    int r = 0;
+#pragma unroll
+    for (int a = 0; a < 25; ++a) {
+      int below = 0, upto = 0;
+#pragma unroll
+      for (int b = 0; b < 25; ++b) {
+        const int in = (sel >> b) & 1;
+        below += in & (v[b] < v[a] ? 1 : 0);
+        upto += in & (v[b] <= v[a] ? 1 : 0);
+      }
+      if (((sel >> a) & 1) && below <= half && half < upto) r = v[a];
+    }
+    return r;
+}
+
+template <bool NL, class RD>
 __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd) {
   switch (o.kind) {
     case OP_GAUSS3: {
@@ -209,6 +254,11 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
       const int mm = max(min(md[0], md[1]), min(max(md[0], md[1]), md[2]));
       return max(min(lo, mm), min(max(lo, mm), hi));
     }
+    case OP_NONLINEAR:
+      // compiled only into the kernels built for it: its window and counters
+      // would otherwise set the register budget of every generic kernel
+      if constexpr (NL) return nonlinear_eval(o, rd);
+      break;
     case OP_BOX5F: {
       // fixed order: each row left to right, rows top to bottom
       float s = 0.f;
@@ -256,7 +306,7 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
 }
 
 __host__ __device__ inline int local_radius(int kind) {
-  return (kind == OP_GAUSS5 || kind == OP_BOX5F || kind == OP_CONVOLVE) ? 2 : 1;
+  return (kind == OP_GAUSS5 || kind == OP_BOX5F || kind == OP_CONVOLVE || kind == OP_NONLINEAR) ? 2 : 1;
 }
 
 // reads value `vi` of a tile as operator `o` sees it
@@ -269,6 +319,7 @@ struct TileRd {
 
 // Evaluate operator `o` at (x, y) inside a tile.  Returns the output element
 // as int bits (F32 outputs as their bit pattern).
+template <bool NL>
 __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, int y) {
   const GProg& P = *t.P;
   if (is_point_op(o.kind)) {
@@ -278,11 +329,11 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
     return point_eval(o, P.vals[o.out].df, P.vals[o.in[0]].df == DF_F32, a, b, c);
   }
   const int vi = o.in[0];
-  return local_eval(o, P.vals[o.out].df, TileRd{&t, &o, vi, x, y});
+  return local_eval<NL>(o, P.vals[o.out].df, TileRd{&t, &o, vi, x, y});
 }
 
 // One tile of a generic program.  `lds` holds P.lds_words words.
-template <int NT>
+template <int NT, bool NL>
 __device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_t* lds) {
   TileCtx t;
   t.P = &P;
@@ -322,7 +373,7 @@ __device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_
     if (cw > 0 && ch > 0) {
       for (int yy = cy0 + (int)(threadIdx.x >> 6); yy < cy1; yy += NT / 64)
         for (int xx = cx0 + (int)(threadIdx.x & 63); xx < cx1; xx += 64) {
-          const int r = eval_op(t, o, xx, yy);
+          const int r = eval_op<NL>(t, o, xx, yy);
           if (dst) dst[(yy - y0) * rw + (xx - x0)] = r;
           if (gbase && xx >= t.tx0 && xx < t.tx0 + P.tw && yy >= t.ty0 && yy < t.ty0 + P.th)
             gstore(ov.df, gbase, gpitch, xx, yy, r);
@@ -439,7 +490,7 @@ struct WinRd {
   __device__ __forceinline__ int operator()(int dx, int dy) const { return w[R + dy][4 + K + dx]; }
 };
 
-template <int R, bool F32>
+template <int R, bool F32, bool NL>
 __device__ __forceinline__ void local_image(const GProg& P, const IOTable& io) {
   const GOp& o = P.ops[0];
   const int W = P.w, H = P.h;
@@ -495,10 +546,10 @@ __device__ __forceinline__ void local_image(const GProg& P, const IOTable& io) {
       }
   }
   int r[4];
-  r[0] = local_eval(o, ov.df, WinRd<R, 0>{win});
-  r[1] = local_eval(o, ov.df, WinRd<R, 1>{win});
-  r[2] = local_eval(o, ov.df, WinRd<R, 2>{win});
-  r[3] = local_eval(o, ov.df, WinRd<R, 3>{win});
+  r[0] = local_eval<NL>(o, ov.df, WinRd<R, 0>{win});
+  r[1] = local_eval<NL>(o, ov.df, WinRd<R, 1>{win});
+  r[2] = local_eval<NL>(o, ov.df, WinRd<R, 2>{win});
+  r[3] = local_eval<NL>(o, ov.df, WinRd<R, 3>{win});
   store4(ov.df, (uint8_t*)io.ptr[ov.io] + (size_t)y * io.pitch[ov.io], x0, W, r);
 }
 

@@ -25,6 +25,7 @@ enum OpKind : int32_t {
   OP_DILATE3,  // Table 2 local operators with MAX / MIN / MEDIAN reductions
   OP_ERODE3,
   OP_MEDIAN3,
+  OP_NONLINEAR,  // median / min / max over a mask (p0 x p1, p2: 0 median, 1 min, 2 max)
 };
 
 // Element formats (same numbering as the public HVX_DF_* constants).

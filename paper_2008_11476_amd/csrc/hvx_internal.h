@@ -48,6 +48,7 @@ enum NodeKind : int32_t {
   NK_DILATE3,
   NK_ERODE3,
   NK_MEDIAN3,
+  NK_NONLINEAR,
   NK_BOX5F,
   NK_SOBEL3,
   NK_MAGNITUDE,
@@ -72,6 +73,7 @@ struct Node : Object {
   float k = 0.04f;
   Conv* conv = nullptr;
   int channel = 0;
+  Conv own_mask;  // NonLinearFilter: the node's own copy of its mask (conv points here)
 };
 
 // ---- lowered graph and plan -------------------------------------------------

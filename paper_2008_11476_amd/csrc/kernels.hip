@@ -19,18 +19,21 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
 // The program lives in device memory: the interpreter indexes its value and
 // operator tables with wave-uniform indices (scalar loads), which a by-value
 // kernel argument would turn into a private (scratch) copy.
+// NL: the program holds a NonLinearFilter (its evaluation is compiled only
+// into these variants, which carry its registers)
+template <bool NL>
 __global__ __launch_bounds__(256) void k_generic(const GProg* __restrict__ P, const IOTable io) {
   extern __shared__ int32_t lds[];
-  generic_tile<256>(*P, io, blockIdx.x, lds);
+  generic_tile<256, NL>(*P, io, blockIdx.x, lds);
 }
 
 __global__ __launch_bounds__(256) void k_point(const GProg* __restrict__ P, const IOTable io) {
   point_image(*P, io);
 }
 
-template <int R, bool F32>
+template <int R, bool F32, bool NL>
 __global__ __launch_bounds__(256) void k_local(const GProg* __restrict__ P, const IOTable io) {
-  local_image<R, F32>(*P, io);
+  local_image<R, F32, NL>(*P, io);
 }
 
 template <bool PHASE>
@@ -154,18 +157,23 @@ hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& 
     if (blocks <= 0) return hipSuccess;
     const bool f32 = in_df == DF_F32;
     const dim3 g((unsigned)blocks), b(256);
-    if (local_radius(o.kind) == 1) {
-      if (f32) hipLaunchKernelGGL((k_local<1, true>), g, b, 0, s, dev_prog, io);
-      else hipLaunchKernelGGL((k_local<1, false>), g, b, 0, s, dev_prog, io);
+    if (o.kind == OP_NONLINEAR) {  // U8 only, mask up to 5x5
+      hipLaunchKernelGGL((k_local<2, false, true>), g, b, 0, s, dev_prog, io);
+    } else if (local_radius(o.kind) == 1) {
+      if (f32) hipLaunchKernelGGL((k_local<1, true, false>), g, b, 0, s, dev_prog, io);
+      else hipLaunchKernelGGL((k_local<1, false, false>), g, b, 0, s, dev_prog, io);
     } else {
-      if (f32) hipLaunchKernelGGL((k_local<2, true>), g, b, 0, s, dev_prog, io);
-      else hipLaunchKernelGGL((k_local<2, false>), g, b, 0, s, dev_prog, io);
+      if (f32) hipLaunchKernelGGL((k_local<2, true, false>), g, b, 0, s, dev_prog, io);
+      else hipLaunchKernelGGL((k_local<2, false, false>), g, b, 0, s, dev_prog, io);
     }
     return hipGetLastError();
   }
   const int tiles = P.tiles_x * P.tiles_y;
   if (tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_generic, dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
+  bool nl = false;
+  for (int i = 0; i < P.nops; ++i) nl |= P.ops[i].kind == OP_NONLINEAR;
+  if (nl) hipLaunchKernelGGL((k_generic<true>), dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
+  else hipLaunchKernelGGL((k_generic<false>), dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
   return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ static int op_radius(const LOp& o, int* rx, int* ry) {
     case OP_GAUSS5:
     case OP_BOX5F: r = 2; break;
     case OP_CONVOLVE:
+    case OP_NONLINEAR:
       *rx = (int)o.conv->cols / 2;
       *ry = (int)o.conv->rows / 2;
       return std::max(*rx, *ry);
@@ -86,6 +87,7 @@ static const char* node_name(int kind) {
     case NK_DILATE3: return "Dilate3x3";
     case NK_ERODE3: return "Erode3x3";
     case NK_MEDIAN3: return "Median3x3";
+    case NK_NONLINEAR: return "NonLinearFilter";
     case NK_BOX5F: return "Box5x5F32";
     case NK_SOBEL3: return "Sobel3x3";
     case NK_MAGNITUDE: return "Magnitude";
@@ -380,6 +382,12 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
       }
       case OP_ADD: q.p0 = o.policy; break;
       case OP_HARRIS: q.pf = o.k; break;
+      case OP_NONLINEAR:
+        q.p0 = (int)o.conv->cols;
+        q.p1 = (int)o.conv->rows;
+        q.p2 = o.policy;
+        for (size_t k = 0; k < o.conv->coeffs.size(); ++k) q.mask[k] = o.conv->coeffs[k];
+        break;
       case OP_CONVOLVE: {
         q.p0 = (int)o.conv->cols;
         q.p1 = (int)o.conv->rows;
@@ -508,6 +516,7 @@ hvx_status verify_graph(Graph* g) {
       case NK_DILATE3:
       case NK_ERODE3:
       case NK_MEDIAN3:
+      case NK_NONLINEAR:
         if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
         s = bind_output(g, p, nout[i][0], DF_U8, w, h, nn);
         break;
@@ -596,6 +605,7 @@ hvx_status verify_graph(Graph* g) {
       case NK_DILATE3: emit(OP_DILATE3, nin[i], nout[i][0]); break;
       case NK_ERODE3: emit(OP_ERODE3, nin[i], nout[i][0]); break;
       case NK_MEDIAN3: emit(OP_MEDIAN3, nin[i], nout[i][0]); break;
+      case NK_NONLINEAR: emit(OP_NONLINEAR, nin[i], nout[i][0]); break;
       case NK_BOX5F: emit(OP_BOX5F, nin[i], nout[i][0]); break;
       case NK_SOBEL3:  // two parallel local operators
         if (nout[i][0] >= 0) emit(OP_SOBEL_X, nin[i], nout[i][0]);

@@ -78,6 +78,9 @@ def build_hvx(spec: Spec, ctx, images: dict):
             h = hvx.hvx_box3x3_node(g, a[0], o[0], ctx=ctx)
         elif n.op in ("dilate3x3", "erode3x3", "median3x3"):
             h = getattr(hvx, "hvx_%s_node" % n.op)(g, a[0], o[0], ctx=ctx)
+        elif n.op == "nonlinear":
+            fn = {"median": hvx.HVX_NONLINEAR_MEDIAN, "min": hvx.HVX_NONLINEAR_MIN, "max": hvx.HVX_NONLINEAR_MAX}
+            h = hvx.hvx_nonlinear_filter_node(g, fn[p["func"]], a[0], p["mask"], o[0], ctx=ctx)
         elif n.op == "box5x5_f32":
             h = hvx.hvx_box5x5_f32_node(g, a[0], o[0], ctx=ctx)
         elif n.op == "sobel3x3":

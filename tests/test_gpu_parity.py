@@ -43,6 +43,49 @@ def test_local_u8(ctx, op, w, h, border):
     compare(spec, got, spec.run_oracle())
 
 
+NL_MASKS = {"box3": np.ones((3, 3)), "cross3": np.array([[0, 1, 0], [1, 1, 1], [0, 1, 0]]),
+            "disk5": np.array([[0, 1, 1, 1, 0]] + [[1] * 5] * 3 + [[0, 1, 1, 1, 0]]),
+            "custom5x3": np.array([[1, 0, 0, 1, 1], [0, 1, 1, 0, 1], [1, 1, 0, 0, 0]]),
+            "pair1x3": np.array([[1, 0, 1]])}
+
+
+@pytest.mark.parametrize("mask", sorted(NL_MASKS))
+@pytest.mark.parametrize("func", ["median", "min", "max"])
+@pytest.mark.parametrize("border", BORDERS)
+def test_nonlinear_filter(ctx, mask, func, border):
+    """NonLinearFilter, node by node (one-operator kernel) and fused behind a
+    Gaussian3x3 with a Threshold after it (generic tile kernel)."""
+    w, h = 67, 45
+    img = synth.edge_image(w, h, seed=len(mask) + len(func))
+    m = NL_MASKS[mask]
+    log("nonlinear %s %s %s" % (mask, func, border))
+    one = gs.Spec([gs.N("nonlinear", ["in"], ["out"], *border, params={"mask": m, "func": func})],
+                  {"in": img}, {"out": np.uint8})
+    got, _ = run_spec(one, ctx, fusion=False)
+    compare(one, got, one.run_oracle())
+    chain = gs.Spec([gs.N("gaussian3x3", ["in"], ["g"], *border),
+                     gs.N("nonlinear", ["g"], ["f"], *border, params={"mask": m, "func": func}),
+                     gs.N("threshold", ["f"], ["out"], params={"thresh": 110})],
+                    {"in": img}, {"f": np.uint8, "out": np.uint8})
+    got, g = run_spec(chain, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    compare(chain, got, chain.run_oracle())
+
+
+def test_nonlinear_filter_rejects_bad_masks(ctx):
+    g = hvx.hvx_graph_create(ctx)
+    ab, av = hvx.alloc_image(8, 8, hvx.HVX_DF_U8)
+    ob, ov = hvx.alloc_image(8, 8, hvx.HVX_DF_U8)
+    a = hvx.image_from_tensor(ctx, av, hvx.HVX_DF_U8)
+    o = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
+    for bad in (np.ones((2, 3)), np.ones((7, 7)), np.zeros((3, 3))):
+        with pytest.raises(hvx.HvxError):
+            hvx.hvx_nonlinear_filter_node(g, hvx.HVX_NONLINEAR_MEDIAN, a, bad, o, ctx=ctx)
+    with pytest.raises(hvx.HvxError):
+        hvx.hvx_nonlinear_filter_node(g, 3, a, np.ones((3, 3)), o, ctx=ctx)
+    hvx.hvx_release_graph(g)
+
+
 @pytest.mark.parametrize("border", [("replicate", 0), ("constant", 30), ("undefined", 0), ("mirror", 0)])
 @pytest.mark.parametrize("w,h", [(301, 77), (64, 9)])
 def test_morphology_chain_fused(ctx, border, w, h):
