@@ -113,6 +113,18 @@ def median3x3(img, border="replicate", c=0):
 NONLINEAR = {"median": 0, "min": 1, "max": 2}
 
 
+def nonmax(img, win=3, border="replicate", c=0):
+    """Table 2 local operator NonMaxSuppression over a win x win window (win
+    3 or 5) of a U8 or S16 image (see orc_nonmax)."""
+    img = np.ascontiguousarray(img)
+    if img.dtype not in (np.uint8, np.int16) or win not in (3, 5):
+        raise ValueError("U8 or S16 input, window 3 or 5")
+    out = np.empty_like(img)
+    lib().orc_nonmax(_p(img), _p(out), int(img.dtype == np.int16), int(win), img.shape[1], img.shape[0],
+                     BORDERS[border], int(c))
+    return out
+
+
 def nonlinear(img, mask, func, border="replicate", c=0):
     """Table 2 local operator: median / min / max over the window pixels
     where `mask` (odd rows x cols, at most 9x9) is nonzero."""
@@ -296,6 +308,8 @@ def _run_node(n: Node, env: dict):
         res = [convolve(ins[0], p["coeffs"], p["scale"], p.get("out_dtype", "u8"), b, c)]
     elif n.op == "nonlinear":
         res = [nonlinear(ins[0], p["mask"], p["func"], b, c)]
+    elif n.op == "nonmax":
+        res = [nonmax(ins[0], p.get("win", 3), b, c)]
     else:
         raise ValueError("unknown op " + n.op)
     for name, val in zip(n.outputs, res):
@@ -316,6 +330,9 @@ def _radius(n: Node) -> tuple:
     if n.op in ("convolve", "nonlinear"):
         rows, cols = np.asarray(n.params["coeffs" if n.op == "convolve" else "mask"]).shape
         return cols // 2, rows // 2
+    if n.op == "nonmax":
+        r = n.params.get("win", 3) // 2
+        return r, r
     r = RADIUS.get(n.op, 0)
     return r, r
 

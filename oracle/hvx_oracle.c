@@ -311,6 +311,31 @@ void orc_nonlinear(const uint8_t* in, const uint8_t* mask, int cols, int rows, i
     }
 }
 
+/* NonMaxSuppression (Table 2, local operator) over a win x win window of a
+ * U8 (s16 == 0) or S16 image: the pixel is kept where every window pixel
+ * before it in raster order is smaller and every one after it is not larger,
+ * otherwise it becomes the format's minimum (0, -32768).  Of a plateau of
+ * equal maxima the first pixel in raster order is kept. */
+void orc_nonmax(const void* in, void* out, int s16, int win, int w, int h, int border, int c) {
+  const int r = win / 2;
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < w; ++x) {
+      int64_t p = s16 ? fetch_s16((const int16_t*)in, w, h, x, y, border, c)
+                      : fetch_u8((const uint8_t*)in, w, h, x, y, border, c);
+      int keep = 1;
+      for (int j = -r; j <= r; ++j)
+        for (int i = -r; i <= r; ++i) {
+          if (i == 0 && j == 0) continue;
+          int64_t q = s16 ? fetch_s16((const int16_t*)in, w, h, x + i, y + j, border, c)
+                          : fetch_u8((const uint8_t*)in, w, h, x + i, y + j, border, c);
+          int before = j < 0 || (j == 0 && i < 0);
+          if (before ? q >= p : q > p) keep = 0;
+        }
+      if (s16) ((int16_t*)out)[(size_t)y * w + x] = (int16_t)(keep ? p : -32768);
+      else ((uint8_t*)out)[(size_t)y * w + x] = (uint8_t)(keep ? p : 0);
+    }
+}
+
 /* Sobel 3x3 gradients of a U8 image.  x grows to the right, y downwards.
  * gx = (right column - left column) weighted (1 2 1) along y;
  * gy = (bottom row - top row) weighted (1 2 1) along x.

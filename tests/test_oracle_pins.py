@@ -91,6 +91,45 @@ def test_nonlinear_vs_scipy(pattern, border, c):
         assert np.array_equal(oracle.nonlinear(img, m, "median", border, c), oracle.median3x3(img, border, c))
 
 
+@pytest.mark.parametrize("win", [3, 5])
+@pytest.mark.parametrize("border,c", [("constant", -32768), ("replicate", 0), ("mirror", 0)])
+def test_nonmax_distinct_values_equals_strict_local_maxima(win, border, c):
+    """With all values distinct (a permutation in S16) and none equal to the
+    constant border, a pixel is kept exactly where it is the maximum of its
+    window (scipy's maximum filter), except where the border mode maps a
+    window position before it in raster order onto the pixel itself: that
+    copy ties, and a tie before the pixel suppresses it.  Replicate does so on
+    row 0 and column 0; reflect-101 on row 1 and column 1 for a 5x5 window."""
+    rng = np.random.default_rng(win)
+    h, w = 29, 31
+    img = (rng.permutation(h * w) - 400).astype(np.int16).reshape(h, w)
+    mode, cval = _nd_mode(border, c)
+    keep = img == nd.maximum_filter(img, size=win, mode=mode, cval=cval)
+    yy, xx = np.mgrid[0:h, 0:w]
+    if border == "replicate":
+        keep &= (yy != 0) & (xx != 0)
+    if border == "mirror" and win == 5:
+        keep &= (yy != 1) & (xx != 1)
+    assert np.array_equal(oracle.nonmax(img, win, border, c), np.where(keep, img, np.int16(-32768)))
+
+
+def test_nonmax_plateaus_keep_their_first_pixel():
+    """A plateau of equal maxima keeps only its first pixel in raster order;
+    a lone peak survives, everything else takes the format's minimum."""
+    img = np.zeros((7, 9), np.uint8)
+    img[2, 3:6] = 50       # a horizontal plateau: keep (2, 3)
+    img[4:6, 1] = 80       # a vertical plateau: keep (4, 1)
+    img[5, 7] = 90         # a lone peak
+    got = oracle.nonmax(img, 3, "constant", 0)
+    kept = np.argwhere(got != 0).tolist()
+    assert kept == [[2, 3], [4, 1], [5, 7]]
+    assert got[2, 3] == 50 and got[4, 1] == 80 and got[5, 7] == 90
+    const = np.full((4, 5), 9, np.uint8)
+    assert np.argwhere(oracle.nonmax(const, 5, "constant", 0) != 0).tolist() == [[0, 0]]
+    s = np.full((3, 3), -5, np.int16)
+    assert oracle.nonmax(s, 3, "constant", -32768)[0, 0] == -5 and (oracle.nonmax(s, 3, "constant", -32768) == -32768).sum() == 8
+
+
 def test_dilate_erode_median_brute_force_and_order():
     """Brute force over explicit windows on a small image, and the order
     erode <= median <= dilate with equality on a constant image."""
