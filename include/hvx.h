@@ -207,6 +207,17 @@ hvx_status hvx_convolve_node(hvx_graph g, hvx_image in, hvx_convolution conv, hv
 #define HVX_NONLINEAR_MAX 2
 hvx_status hvx_nonlinear_filter_node(hvx_graph g, int function, hvx_image in, uint32_t cols, uint32_t rows,
                                      const uint8_t* mask, hvx_image out, hvx_node* node_out);
+/* NonMaxSuppression (Table 2 local operator), U8 -> U8 or S16 -> S16 over a
+ * win_size x win_size window (3 or 5; INVALID_PARAMETERS otherwise).  A pixel
+ * is kept where every window pixel before it in raster order is smaller and
+ * every one after it is not larger; elsewhere the output is the format's
+ * minimum (0, -32768).  Of a plateau of equal maxima only the first pixel in
+ * raster order survives.  Window positions outside the image are read
+ * through the node's border mode, and a border copy of the pixel itself
+ * counts like any other position (so under REPLICATE row 0 and column 0 are
+ * always suppressed). */
+hvx_status hvx_non_max_suppression_node(hvx_graph g, hvx_image in, uint32_t win_size, hvx_image out,
+                                        hvx_node* node_out);
 
 /* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the
  * value is read as the input's element type (0..255 for U8). */

@@ -80,6 +80,7 @@ def _load():
         "hvx_erode3x3_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_median3x3_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_nonlinear_filter_node": [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _P(_vp)],
+        "hvx_non_max_suppression_node": [_vp, _vp, ctypes.c_uint32, _vp, _P(_vp)],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -250,6 +251,10 @@ def hvx_nonlinear_filter_node(g, function, i, mask, o, ctx=None):
     m = np.ascontiguousarray((np.asarray(mask) != 0).astype(np.uint8))
     rows, cols = m.shape
     return _node("hvx_nonlinear_filter_node", ctx, g, function, i, cols, rows, m.ctypes.data_as(_vp), o)
+
+
+def hvx_non_max_suppression_node(g, i, win_size, o, ctx=None):
+    return _node("hvx_non_max_suppression_node", ctx, g, i, win_size, o)
 
 
 def hvx_box5x5_f32_node(g, i, o, ctx=None):

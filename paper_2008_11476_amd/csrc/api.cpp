@@ -495,6 +495,17 @@ hvx_status hvx_nonlinear_filter_node(hvx_graph g, int function, hvx_image in, ui
   return HVX_SUCCESS;
 }
 
+hvx_status hvx_non_max_suppression_node(hvx_graph g, hvx_image in, uint32_t win_size, hvx_image out, hvx_node* no) {
+  Graph* gg = as<Graph>(g, T_GRAPH);
+  if (!gg) return HVX_ERROR_INVALID_REFERENCE;
+  if (win_size != 3 && win_size != 5)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "window size must be 3 or 5 (got %u)", win_size);
+  Node* n = nullptr;
+  hvx_status s = add_node(g, NK_NONMAX, {in}, {out}, 1, no, &n);
+  if (!s) n->policy = (int)win_size;
+  return s;
+}
+
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value) {
   Node* n = as<Node>(node, T_NODE);
   if (!n) return HVX_ERROR_INVALID_REFERENCE;

@@ -259,6 +259,23 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
       // would otherwise set the register budget of every generic kernel
       if constexpr (NL) return nonlinear_eval(o, rd);
       break;
+    case OP_NONMAX: {
+      // kept where every window pixel before it in raster order is smaller
+      // and every one after it is not larger: the largest of each group
+      // decides.  Window positions are read through the border rule, so a
+      // border copy of the pixel itself counts like any other position.
+      const int r = o.p0, p = rd(0, 0);
+      int before = -65536, after = -65536;
+#pragma unroll
+      for (int j = -2; j <= 0; ++j)
+#pragma unroll
+        for (int i = -2; i <= 2; ++i) {
+          if (j == 0 && i >= 0) continue;
+          if (i >= -r && i <= r && j >= -r) before = max(before, rd(i, j));
+          if (i >= -r && i <= r && j >= -r) after = max(after, rd(-i, -j));
+        }
+      return before < p && after <= p ? p : (out_df == DF_U8 ? 0 : -32768);
+    }
     case OP_BOX5F: {
       // fixed order: each row left to right, rows top to bottom
       float s = 0.f;
@@ -306,7 +323,9 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
 }
 
 __host__ __device__ inline int local_radius(int kind) {
-  return (kind == OP_GAUSS5 || kind == OP_BOX5F || kind == OP_CONVOLVE || kind == OP_NONLINEAR) ? 2 : 1;
+  return (kind == OP_GAUSS5 || kind == OP_BOX5F || kind == OP_CONVOLVE || kind == OP_NONLINEAR || kind == OP_NONMAX)
+             ? 2
+             : 1;
 }
 
 // reads value `vi` of a tile as operator `o` sees it

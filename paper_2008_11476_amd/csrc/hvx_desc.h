@@ -26,6 +26,7 @@ enum OpKind : int32_t {
   OP_ERODE3,
   OP_MEDIAN3,
   OP_NONLINEAR,  // median / min / max over a mask (p0 x p1, p2: 0 median, 1 min, 2 max)
+  OP_NONMAX,     // NonMaxSuppression over a (2 p0 + 1)^2 window, U8 or S16
 };
 
 // Element formats (same numbering as the public HVX_DF_* constants).

@@ -49,6 +49,7 @@ enum NodeKind : int32_t {
   NK_ERODE3,
   NK_MEDIAN3,
   NK_NONLINEAR,
+  NK_NONMAX,
   NK_BOX5F,
   NK_SOBEL3,
   NK_MAGNITUDE,

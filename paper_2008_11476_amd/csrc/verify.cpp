@@ -38,6 +38,7 @@ static int op_radius(const LOp& o, int* rx, int* ry) {
     case OP_SOBEL_Y: r = 1; break;
     case OP_GAUSS5:
     case OP_BOX5F: r = 2; break;
+    case OP_NONMAX: r = o.policy / 2; break;  // the window size
     case OP_CONVOLVE:
     case OP_NONLINEAR:
       *rx = (int)o.conv->cols / 2;
@@ -88,6 +89,7 @@ static const char* node_name(int kind) {
     case NK_ERODE3: return "Erode3x3";
     case NK_MEDIAN3: return "Median3x3";
     case NK_NONLINEAR: return "NonLinearFilter";
+    case NK_NONMAX: return "NonMaxSuppression";
     case NK_BOX5F: return "Box5x5F32";
     case NK_SOBEL3: return "Sobel3x3";
     case NK_MAGNITUDE: return "Magnitude";
@@ -382,6 +384,7 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
       }
       case OP_ADD: q.p0 = o.policy; break;
       case OP_HARRIS: q.pf = o.k; break;
+      case OP_NONMAX: q.p0 = o.policy / 2; break;
       case OP_NONLINEAR:
         q.p0 = (int)o.conv->cols;
         q.p1 = (int)o.conv->rows;
@@ -520,6 +523,10 @@ hvx_status verify_graph(Graph* g) {
         if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
         s = bind_output(g, p, nout[i][0], DF_U8, w, h, nn);
         break;
+      case NK_NONMAX:
+        if (!need(nin[i][0], {DF_U8, DF_S16})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8/S16 input", nn);
+        s = bind_output(g, p, nout[i][0], p.vals[nin[i][0]].df, w, h, nn);
+        break;
       case NK_BOX5F:
         if (!need(nin[i][0], {DF_F32})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs an F32 input", nn);
         s = bind_output(g, p, nout[i][0], DF_F32, w, h, nn);
@@ -606,6 +613,7 @@ hvx_status verify_graph(Graph* g) {
       case NK_ERODE3: emit(OP_ERODE3, nin[i], nout[i][0]); break;
       case NK_MEDIAN3: emit(OP_MEDIAN3, nin[i], nout[i][0]); break;
       case NK_NONLINEAR: emit(OP_NONLINEAR, nin[i], nout[i][0]); break;
+      case NK_NONMAX: emit(OP_NONMAX, nin[i], nout[i][0]); break;
       case NK_BOX5F: emit(OP_BOX5F, nin[i], nout[i][0]); break;
       case NK_SOBEL3:  // two parallel local operators
         if (nout[i][0] >= 0) emit(OP_SOBEL_X, nin[i], nout[i][0]);

@@ -86,6 +86,68 @@ def test_nonlinear_filter_rejects_bad_masks(ctx):
     hvx.hvx_release_graph(g)
 
 
+@pytest.mark.parametrize("win", [3, 5])
+@pytest.mark.parametrize("border", BORDERS)
+@pytest.mark.parametrize("w,h", [(67, 45), (5, 3), (1100, 19)])
+def test_nonmax_u8(ctx, win, border, w, h):
+    """NonMaxSuppression on U8, node by node (one-operator kernel) on a
+    smoothed edge image (plateaus) and on four-level noise (ties everywhere),
+    and fused behind a Gaussian3x3 with its output also thresholded (generic
+    tile kernel)."""
+    log("nonmax u8 win %d %s %dx%d" % (win, border, w, h))
+    for img in (synth.edge_image(w, h, seed=win + w), synth.uniform_u8(w, h, seed=win + h) // 64):
+        one = gs.Spec([gs.N("nonmax", ["in"], ["out"], *border, params={"win": win})], {"in": img},
+                      {"out": np.uint8})
+        got, _ = run_spec(one, ctx, fusion=False)
+        compare(one, got, one.run_oracle())
+    img = synth.edge_image(w, h, seed=win)
+    chain = gs.Spec([gs.N("gaussian3x3", ["in"], ["g"], *border),
+                     gs.N("nonmax", ["g"], ["n"], *border, params={"win": win}),
+                     gs.N("threshold", ["n"], ["out"], params={"thresh": 90})],
+                    {"in": img}, {"n": np.uint8, "out": np.uint8})
+    got, g = run_spec(chain, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    compare(chain, got, chain.run_oracle())
+
+
+@pytest.mark.parametrize("win", [3, 5])
+@pytest.mark.parametrize("border", [("replicate", 0), ("constant", -7), ("constant", 0), ("undefined", 0),
+                                    ("mirror", 0)])
+def test_nonmax_s16(ctx, win, border):
+    """NonMaxSuppression on S16: on the Sobel gx of an edge image, fused with
+    the Sobel into one kernel and node by node, and on narrow-range S16 noise
+    (many ties, negative values)."""
+    w, h = 131, 37
+    log("nonmax s16 win %d %s" % (win, border))
+    img = synth.edge_image(w, h, seed=win)
+    spec = gs.Spec([gs.N("sobel3x3", ["in"], ["gx", None]),
+                    gs.N("nonmax", ["gx"], ["out"], *border, params={"win": win})],
+                   {"in": img}, {"out": np.int16})
+    env = spec.run_oracle()
+    got, g = run_spec(spec, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    compare(spec, got, env)
+    unf, _ = run_spec(spec, ctx, fusion=False)
+    compare(spec, unf, env)
+    noise = synth.uniform_s16(w, h, seed=win, lo=-12, hi=3)
+    one = gs.Spec([gs.N("nonmax", ["in"], ["out"], *border, params={"win": win})], {"in": noise},
+                  {"out": np.int16})
+    got, _ = run_spec(one, ctx, fusion=False)
+    compare(one, got, one.run_oracle())
+
+
+def test_nonmax_rejects_bad_windows(ctx):
+    g = hvx.hvx_graph_create(ctx)
+    ab, av = hvx.alloc_image(8, 8, hvx.HVX_DF_U8)
+    ob, ov = hvx.alloc_image(8, 8, hvx.HVX_DF_U8)
+    a = hvx.image_from_tensor(ctx, av, hvx.HVX_DF_U8)
+    o = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
+    for bad in (0, 1, 4, 7):
+        with pytest.raises(hvx.HvxError):
+            hvx.hvx_non_max_suppression_node(g, a, bad, o, ctx=ctx)
+    hvx.hvx_release_graph(g)
+
+
 @pytest.mark.parametrize("border", [("replicate", 0), ("constant", 30), ("undefined", 0), ("mirror", 0)])
 @pytest.mark.parametrize("w,h", [(301, 77), (64, 9)])
 def test_morphology_chain_fused(ctx, border, w, h):
