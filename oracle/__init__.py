@@ -28,7 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hvx_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-BORDERS = {"undefined": 0, "constant": 1, "replicate": 2, "mirror": 3}
+BORDERS = {"undefined": 0, "constant": 1, "replicate": 2, "mirror": 3, "repeat": 4}
 
 # Window radius of each local operator (point operators have radius 0).
 RADIUS = {"gaussian3x3": 1, "gaussian5x5": 2, "box3x3": 1, "sobel3x3": 1, "box5x5_f32": 2, "dilate3x3": 1,

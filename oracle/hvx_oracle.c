@@ -28,12 +28,15 @@
 #define ORC_BORDER_CONSTANT 1
 #define ORC_BORDER_REPLICATE 2
 #define ORC_BORDER_MIRROR 3
+#define ORC_BORDER_REPEAT 4
 
 /* ---- border fetch (one per input element type) ------------------------- */
 /* REPLICATE: nearest in-image pixel.  CONSTANT: the constant outside.
  * MIRROR: the image reflected about its first and last pixel (reflect-101:
  * ... c b | a b c ... x y | x w ...), repeated as often as needed; a single
  * row or column repeats its pixel.
+ * REPEAT: the image tiled periodically in both directions, so position x
+ * reads pixel x mod n (the non-negative remainder).
  * UNDEFINED: the result there is unspecified; the replicated value is used so
  * that the computation is defined, and callers exclude those pixels. */
 
@@ -48,12 +51,21 @@ static int mirror_index(int x, int n) {
   return x;
 }
 
+static int repeat_index(int x, int n) {
+  int r = x % n;
+  return r < 0 ? r + n : r;
+}
+
 static int64_t fetch_u8(const uint8_t* img, int w, int h, int x, int y, int border, int64_t c) {
   if (x < 0 || y < 0 || x >= w || y >= h) {
     if (border == ORC_BORDER_CONSTANT) return c;
     if (border == ORC_BORDER_MIRROR) {
       x = mirror_index(x, w);
       y = mirror_index(y, h);
+    }
+    if (border == ORC_BORDER_REPEAT) {
+      x = repeat_index(x, w);
+      y = repeat_index(y, h);
     }
     x = clampi(x, 0, w - 1);
     y = clampi(y, 0, h - 1);
@@ -68,6 +80,10 @@ static int64_t fetch_s16(const int16_t* img, int w, int h, int x, int y, int bor
       x = mirror_index(x, w);
       y = mirror_index(y, h);
     }
+    if (border == ORC_BORDER_REPEAT) {
+      x = repeat_index(x, w);
+      y = repeat_index(y, h);
+    }
     x = clampi(x, 0, w - 1);
     y = clampi(y, 0, h - 1);
   }
@@ -80,6 +96,10 @@ static double fetch_f64(const double* img, int w, int h, int x, int y, int borde
     if (border == ORC_BORDER_MIRROR) {
       x = mirror_index(x, w);
       y = mirror_index(y, h);
+    }
+    if (border == ORC_BORDER_REPEAT) {
+      x = repeat_index(x, w);
+      y = repeat_index(y, h);
     }
     x = clampi(x, 0, w - 1);
     y = clampi(y, 0, h - 1);

@@ -15,12 +15,14 @@ import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 SIZES = [(1, 1), (2, 3), (3, 2), (7, 5), (17, 13), (33, 4)]
-BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("constant", 255), ("mirror", 0)]
+BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("constant", 255), ("mirror", 0), ("repeat", 0)]
 
 
 def _nd_mode(border, c):
     if border == "mirror":
         return "mirror", 0  # scipy's reflect-101 extension
+    if border == "repeat":
+        return "wrap", 0  # scipy's periodic extension
     return ("nearest", 0) if border == "replicate" else ("constant", c)
 
 
@@ -92,7 +94,7 @@ def test_nonlinear_vs_scipy(pattern, border, c):
 
 
 @pytest.mark.parametrize("win", [3, 5])
-@pytest.mark.parametrize("border,c", [("constant", -32768), ("replicate", 0), ("mirror", 0)])
+@pytest.mark.parametrize("border,c", [("constant", -32768), ("replicate", 0), ("mirror", 0), ("repeat", 0)])
 def test_nonmax_distinct_values_equals_strict_local_maxima(win, border, c):
     """With all values distinct (a permutation in S16) and none equal to the
     constant border, a pixel is kept exactly where it is the maximum of its
@@ -411,3 +413,22 @@ def test_cycle_rejected():
     g.add("gaussian3x3", ["b"], ["a"])
     with pytest.raises(ValueError):
         oracle.run(g, {})
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 3), (2, 3), (4, 2), (3, 7)])
+def test_repeat_border_on_images_smaller_than_the_window(h, w):
+    """REPEAT tiles the image periodically, also when the window wraps
+    around more than once: the 5x5 Gaussian and Box3x3 equal plain windowed
+    sums over numpy's periodic padding, and the wrapped window of NonMax
+    sees copies of the pixel itself on one-pixel axes."""
+    rng = np.random.default_rng(h * 10 + w)
+    img = rng.integers(0, 256, size=(h, w), dtype=np.uint8)
+    pad = np.pad(img.astype(np.int64), 2, mode="wrap")
+    b = np.array([1, 4, 6, 4, 1])
+    g = sum(b[j] * b[i] * pad[j:j + h, i:i + w] for j in range(5) for i in range(5)) >> 8
+    assert np.array_equal(oracle.gaussian5x5(img, "repeat"), g)
+    box = sum(pad[1 + j:1 + j + h, 1 + i:1 + i + w] for j in range(3) for i in range(3)) // 9
+    assert np.array_equal(oracle.box3x3(img, "repeat"), box)
+    if w == 1:  # the position left of the pixel is the pixel itself
+        assert np.all(oracle.nonmax(img, 3, "repeat") == 0)
+
