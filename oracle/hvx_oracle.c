@@ -56,19 +56,24 @@ static int repeat_index(int x, int n) {
   return r < 0 ? r + n : r;
 }
 
+/* The in-image position read for (x, y) outside the image under MIRROR,
+ * REPEAT, REPLICATE or UNDEFINED. */
+static void outside_pos(int border, int w, int h, int* x, int* y) {
+  if (border == ORC_BORDER_MIRROR) {
+    *x = mirror_index(*x, w);
+    *y = mirror_index(*y, h);
+  } else if (border == ORC_BORDER_REPEAT) {
+    *x = repeat_index(*x, w);
+    *y = repeat_index(*y, h);
+  }
+  *x = clampi(*x, 0, w - 1);
+  *y = clampi(*y, 0, h - 1);
+}
+
 static int64_t fetch_u8(const uint8_t* img, int w, int h, int x, int y, int border, int64_t c) {
   if (x < 0 || y < 0 || x >= w || y >= h) {
     if (border == ORC_BORDER_CONSTANT) return c;
-    if (border == ORC_BORDER_MIRROR) {
-      x = mirror_index(x, w);
-      y = mirror_index(y, h);
-    }
-    if (border == ORC_BORDER_REPEAT) {
-      x = repeat_index(x, w);
-      y = repeat_index(y, h);
-    }
-    x = clampi(x, 0, w - 1);
-    y = clampi(y, 0, h - 1);
+    outside_pos(border, w, h, &x, &y);
   }
   return img[(size_t)y * w + x];
 }
@@ -76,16 +81,7 @@ static int64_t fetch_u8(const uint8_t* img, int w, int h, int x, int y, int bord
 static int64_t fetch_s16(const int16_t* img, int w, int h, int x, int y, int border, int64_t c) {
   if (x < 0 || y < 0 || x >= w || y >= h) {
     if (border == ORC_BORDER_CONSTANT) return c;
-    if (border == ORC_BORDER_MIRROR) {
-      x = mirror_index(x, w);
-      y = mirror_index(y, h);
-    }
-    if (border == ORC_BORDER_REPEAT) {
-      x = repeat_index(x, w);
-      y = repeat_index(y, h);
-    }
-    x = clampi(x, 0, w - 1);
-    y = clampi(y, 0, h - 1);
+    outside_pos(border, w, h, &x, &y);
   }
   return img[(size_t)y * w + x];
 }
@@ -93,16 +89,7 @@ static int64_t fetch_s16(const int16_t* img, int w, int h, int x, int y, int bor
 static double fetch_f64(const double* img, int w, int h, int x, int y, int border, double c) {
   if (x < 0 || y < 0 || x >= w || y >= h) {
     if (border == ORC_BORDER_CONSTANT) return c;
-    if (border == ORC_BORDER_MIRROR) {
-      x = mirror_index(x, w);
-      y = mirror_index(y, h);
-    }
-    if (border == ORC_BORDER_REPEAT) {
-      x = repeat_index(x, w);
-      y = repeat_index(y, h);
-    }
-    x = clampi(x, 0, w - 1);
-    y = clampi(y, 0, h - 1);
+    outside_pos(border, w, h, &x, &y);
   }
   return img[(size_t)y * w + x];
 }
