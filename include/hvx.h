@@ -76,6 +76,10 @@ typedef int32_t hvx_status;
 #define HVX_BORDER_MIRROR 3    /* the image reflected about its first and last pixel (reflect-101),
                                   repeated; a one-pixel axis repeats its pixel.  Graphs using it
                                   run on the generic kernels. */
+#define HVX_BORDER_REPEAT 4    /* the image tiled periodically: position x reads x mod width (same
+                                  for rows).  Graphs using it run on the generic kernels, and a
+                                  fused group in which such a node reads an intermediate of the
+                                  group runs node by node instead. */
 
 #define HVX_POLICY_SATURATE 0
 #define HVX_POLICY_WRAP 1

@@ -28,7 +28,7 @@ HVX_ERROR_NOT_SUPPORTED = -8
 HVX_ERROR_DEVICE = -9
 
 HVX_DF_VIRT, HVX_DF_U8, HVX_DF_S16, HVX_DF_S32, HVX_DF_F32, HVX_DF_UYVY = range(6)
-HVX_BORDER_UNDEFINED, HVX_BORDER_CONSTANT, HVX_BORDER_REPLICATE, HVX_BORDER_MIRROR = range(4)
+HVX_BORDER_UNDEFINED, HVX_BORDER_CONSTANT, HVX_BORDER_REPLICATE, HVX_BORDER_MIRROR, HVX_BORDER_REPEAT = range(5)
 HVX_POLICY_SATURATE, HVX_POLICY_WRAP = 0, 1
 HVX_CHANNEL_Y = 0
 HVX_OPT_FUSION, HVX_OPT_DCE, HVX_OPT_TILE, HVX_OPT_SPECIALIZE, HVX_OPT_XCD_REMAP = 1, 2, 3, 4, 5

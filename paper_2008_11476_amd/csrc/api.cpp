@@ -509,7 +509,8 @@ hvx_status hvx_non_max_suppression_node(hvx_graph g, hvx_image in, uint32_t win_
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value) {
   Node* n = as<Node>(node, T_NODE);
   if (!n) return HVX_ERROR_INVALID_REFERENCE;
-  if (border != B_UNDEFINED && border != B_CONSTANT && border != B_REPLICATE && border != B_MIRROR)
+  if (border != B_UNDEFINED && border != B_CONSTANT && border != B_REPLICATE && border != B_MIRROR &&
+      border != B_REPEAT)
     return set_error(n->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown border mode %d", border);
   n->border = border;
   n->bconst = constant_value;

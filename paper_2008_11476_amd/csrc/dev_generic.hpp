@@ -60,13 +60,22 @@ __device__ __forceinline__ int mirror_pos(int x, int n) {
   return x < n ? x : per - x;
 }
 
+// Position read for x outside [0, n) under the REPEAT border: the image
+// tiled periodically.
+__device__ __forceinline__ int repeat_pos(int x, int n) {
+  const int r = x % n;
+  return r < 0 ? r + n : r;
+}
+
 // Read value `vi` at (x, y) as seen by operator `o` (border applied).  A
 // mirrored position lies within the operator's radius of the image edge,
-// inside the tile's extent of the value.
+// inside the tile's extent of the value.  Under REPEAT the value is a group
+// input whose tile extent outside the image was loaded from the periodic
+// positions, so the position is read as it is.
 __device__ __forceinline__ int rd(const TileCtx& t, const GOp& o, int vi, int x, int y) {
   const GProg& P = *t.P;
   const GVal& v = P.vals[vi];
-  if (x < 0 || y < 0 || x >= P.w || y >= P.h) {
+  if ((x < 0 || y < 0 || x >= P.w || y >= P.h) && o.border != B_REPEAT) {
     if (o.border == B_CONSTANT) return v.df == DF_F32 ? __float_as_int(o.cf) : o.cint;
     if (o.border == B_MIRROR) {
       x = mirror_pos(x, P.w);
@@ -371,6 +380,12 @@ __device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_
     if (cw <= 0 || ch <= 0) continue;
     const void* base = io.ptr[v.io];
     const int64_t pitch = io.pitch[v.io];
+    if (v.wrap) {  // the whole extent, positions outside the image taken periodically
+      for (int yy = y0 + (int)(threadIdx.x >> 6); yy < y0 + P.th + 2 * e; yy += NT / 64)
+        for (int xx = x0 + (int)(threadIdx.x & 63); xx < x0 + rw; xx += 64)
+          lds[v.lds + (yy - y0) * rw + (xx - x0)] = gload(v.df, base, pitch, repeat_pos(xx, W), repeat_pos(yy, H));
+      continue;
+    }
     // rows spread over groups of 64 threads, columns over the lanes
     for (int yy = cy0 + (int)(threadIdx.x >> 6); yy < cy1; yy += NT / 64)
       for (int xx = cx0 + (int)(threadIdx.x & 63); xx < cx1; xx += 64)
@@ -557,6 +572,10 @@ __device__ __forceinline__ void local_image(const GProg& P, const IOTable& io) {
         if (out && o.border == B_MIRROR) {
           xx = (xx < 0 || xx >= W) ? mirror_pos(xx, W) : xx;
           yy = (yy < 0 || yy >= H) ? mirror_pos(yy, H) : yy;
+        }
+        if (out && o.border == B_REPEAT) {
+          xx = repeat_pos(xx, W);
+          yy = repeat_pos(yy, H);
         }
         xx = min(max(xx, 0), W - 1);
         yy = min(max(yy, 0), H - 1);

@@ -31,7 +31,7 @@ enum OpKind : int32_t {
 
 // Element formats (same numbering as the public HVX_DF_* constants).
 enum Df : int32_t { DF_VIRT = 0, DF_U8 = 1, DF_S16 = 2, DF_S32 = 3, DF_F32 = 4, DF_UYVY = 5 };
-enum Border : int32_t { B_UNDEFINED = 0, B_CONSTANT = 1, B_REPLICATE = 2, B_MIRROR = 3 };
+enum Border : int32_t { B_UNDEFINED = 0, B_CONSTANT = 1, B_REPLICATE = 2, B_MIRROR = 3, B_REPEAT = 4 };
 
 inline int df_bytes(int df) {
   switch (df) {
@@ -57,6 +57,7 @@ struct GVal {
   int32_t io;     // index into the I/O table, -1 if the value never touches global memory
   int32_t input;  // 1: read from global memory (a group input)
   int32_t store;  // 1: written to global memory (a group output)
+  int32_t wrap;   // 1: a group input whose halo outside the image holds its periodic copies (REPEAT)
 };
 
 struct GOp {

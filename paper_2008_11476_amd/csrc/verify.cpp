@@ -130,11 +130,27 @@ static int producer_in(const Plan& p, int v, const std::set<int>& ops) {
 
 // Gaussian3x3 -> SobelX, SobelY -> Magnitude -> Threshold (+ Phase(gx, gy)).
 // The hand-fused kernels implement the UNDEFINED, CONSTANT and REPLICATE
-// borders; a group with a MIRROR border runs on the generic kernels.
+// borders; a group with a MIRROR or REPEAT border runs on the generic kernels.
 static bool fast_borders(const Plan& p, const Group& gr) {
   for (int o : gr.ops)
-    if (p.ops[o].border == B_MIRROR) return false;
+    if (p.ops[o].border == B_MIRROR || p.ops[o].border == B_REPEAT) return false;
   return true;
+}
+
+// A local operator with the REPEAT border reads its input at the far side of
+// the image.  A tile holds an intermediate only around itself, so such an
+// operator must read a value that is in memory: a group where it reads one
+// computed inside the group runs node by node.
+static bool repeat_reads_intermediate(const Plan& p, const Group& gr) {
+  std::set<int> ops(gr.ops.begin(), gr.ops.end());
+  for (int o : gr.ops) {
+    const LOp& op = p.ops[o];
+    int rx, ry;
+    if (op.border != B_REPEAT || op_radius(op, &rx, &ry) == 0) continue;
+    for (int k = 0; k < op.nin; ++k)
+      if (producer_in(p, op.in[k], ops) >= 0) return true;
+  }
+  return false;
 }
 
 static bool match_edge(const Plan& p, const Group& gr, int* in_v, int* out_v, int* ph_v) {
@@ -354,6 +370,13 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
     gv.input = std::find(gr.inputs.begin(), gr.inputs.end(), v) != gr.inputs.end();
     gv.store = outset.count(v) ? 1 : 0;
     gv.io = (gv.input || gv.store) ? io++ : -1;
+    gv.wrap = 0;
+    for (int o : gr.ops) {
+      const LOp& op = p.ops[o];
+      int rx, ry;
+      if (gv.input && op.border == B_REPEAT && op_radius(op, &rx, &ry) > 0)
+        for (int k = 0; k < op.nin; ++k) gv.wrap |= op.in[k] == v;
+    }
   }
   for (size_t i = 0; i < gr.ops.size(); ++i) {
     const LOp& o = p.ops[gr.ops[i]];
@@ -740,7 +763,7 @@ hvx_status verify_graph(Graph* g) {
     std::string why;
     if (!fast && gr.ops.size() > 1) {
       Group probe = gr;
-      if (!build_generic(g, p, probe, &why) || probe.footprint > 8) {
+      if (repeat_reads_intermediate(p, gr) || !build_generic(g, p, probe, &why) || probe.footprint > 8) {
         for (int o : gr.ops) {
           Group s;
           s.ops.push_back(o);

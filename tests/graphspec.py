@@ -10,7 +10,8 @@ import oracle
 import paper_2008_11476_amd as hvx
 
 BORDER = {"undefined": hvx.HVX_BORDER_UNDEFINED, "constant": hvx.HVX_BORDER_CONSTANT,
-          "replicate": hvx.HVX_BORDER_REPLICATE, "mirror": hvx.HVX_BORDER_MIRROR}
+          "replicate": hvx.HVX_BORDER_REPLICATE, "mirror": hvx.HVX_BORDER_MIRROR,
+          "repeat": hvx.HVX_BORDER_REPEAT}
 DF_OF_DTYPE = {np.dtype(np.uint8): hvx.HVX_DF_U8, np.dtype(np.int16): hvx.HVX_DF_S16,
                np.dtype(np.float32): hvx.HVX_DF_F32, np.dtype(np.float64): hvx.HVX_DF_F32}
 

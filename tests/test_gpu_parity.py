@@ -13,8 +13,8 @@ from tests.gpu_util import compare, log, run_spec
 
 pytestmark = pytest.mark.gpu
 
-# MIRROR last: the slices BORDERS[:2] / [:3] keep the modes the hand-fused kernels implement
-BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("undefined", 0), ("mirror", 0)]
+# MIRROR and REPEAT last: the slices BORDERS[:2] / [:3] keep the modes the hand-fused kernels implement
+BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("undefined", 0), ("mirror", 0), ("repeat", 0)]
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +68,7 @@ def test_nonlinear_filter(ctx, mask, func, border):
                      gs.N("threshold", ["f"], ["out"], params={"thresh": 110})],
                     {"in": img}, {"f": np.uint8, "out": np.uint8})
     got, g = run_spec(chain, ctx)
-    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == (1 if border[0] != "repeat" else 3)
     compare(chain, got, chain.run_oracle())
 
 
@@ -106,13 +106,13 @@ def test_nonmax_u8(ctx, win, border, w, h):
                      gs.N("threshold", ["n"], ["out"], params={"thresh": 90})],
                     {"in": img}, {"n": np.uint8, "out": np.uint8})
     got, g = run_spec(chain, ctx)
-    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == (1 if border[0] != "repeat" else 3)
     compare(chain, got, chain.run_oracle())
 
 
 @pytest.mark.parametrize("win", [3, 5])
 @pytest.mark.parametrize("border", [("replicate", 0), ("constant", -7), ("constant", 0), ("undefined", 0),
-                                    ("mirror", 0)])
+                                    ("mirror", 0), ("repeat", 0)])
 def test_nonmax_s16(ctx, win, border):
     """NonMaxSuppression on S16: on the Sobel gx of an edge image, fused with
     the Sobel into one kernel and node by node, and on narrow-range S16 noise
@@ -125,7 +125,7 @@ def test_nonmax_s16(ctx, win, border):
                    {"in": img}, {"out": np.int16})
     env = spec.run_oracle()
     got, g = run_spec(spec, ctx)
-    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == (1 if border[0] != "repeat" else 2)
     compare(spec, got, env)
     unf, _ = run_spec(spec, ctx, fusion=False)
     compare(spec, unf, env)
@@ -134,6 +134,31 @@ def test_nonmax_s16(ctx, win, border):
                   {"out": np.int16})
     got, _ = run_spec(one, ctx, fusion=False)
     compare(one, got, one.run_oracle())
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (3, 2), (67, 45), (130, 21)])
+def test_repeat_border_fused_and_split(ctx, w, h):
+    """REPEAT on operators that read the graph input stays fused (the tile
+    loads its halo from the periodic positions); REPEAT on an operator that
+    reads an intermediate splits the group into single operators.  Both
+    against the oracle, on images down to one pixel (windows wrapping more
+    than once)."""
+    img = synth.edge_image(w, h, seed=w * h)
+    rp = ("repeat", 0)
+    fused = gs.Spec([gs.N("gaussian5x5", ["in"], ["g"], *rp), gs.N("box3x3", ["in"], ["b"], *rp),
+                     gs.N("add", ["g", "b"], ["s"]), gs.N("threshold", ["s"], ["out"], params={"thresh": 200})],
+                    {"in": img}, {"s": np.uint8, "out": np.uint8})
+    log("repeat fused %dx%d" % (w, h))
+    got, g = run_spec(fused, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    compare(fused, got, fused.run_oracle())
+    split = gs.Spec([gs.N("gaussian3x3", ["in"], ["g"]), gs.N("dilate3x3", ["g"], ["d"], *rp),
+                     gs.N("sobel3x3", ["d"], ["gx", "gy"], *rp), gs.N("magnitude", ["gx", "gy"], ["out"])],
+                    {"in": img}, {"out": np.int16})
+    log("repeat split %dx%d" % (w, h))
+    got, g = run_spec(split, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 5  # Sobel lowers to two local operators
+    compare(split, got, split.run_oracle())
 
 
 def test_nonmax_rejects_bad_windows(ctx):
@@ -148,7 +173,8 @@ def test_nonmax_rejects_bad_windows(ctx):
     hvx.hvx_release_graph(g)
 
 
-@pytest.mark.parametrize("border", [("replicate", 0), ("constant", 30), ("undefined", 0), ("mirror", 0)])
+@pytest.mark.parametrize("border", [("replicate", 0), ("constant", 30), ("undefined", 0), ("mirror", 0),
+                                    ("repeat", 0)])
 @pytest.mark.parametrize("w,h", [(301, 77), (64, 9)])
 def test_morphology_chain_fused(ctx, border, w, h):
     """Gaussian3x3 -> Median3x3 -> Dilate3x3 -> Erode3x3 -> Threshold as one
@@ -162,7 +188,7 @@ def test_morphology_chain_fused(ctx, border, w, h):
     env = spec.run_oracle()
     log("morphology chain %dx%d %s" % (w, h, border))
     got, g = run_spec(spec, ctx)
-    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == (1 if border[0] != "repeat" else 5)
     compare(spec, got, env)
     unf, _ = run_spec(spec, ctx, fusion=False)
     compare(spec, unf, env)
