@@ -310,6 +310,9 @@ def _run_node(n: Node, env: dict):
         res = [nonlinear(ins[0], p["mask"], p["func"], b, c)]
     elif n.op == "nonmax":
         res = [nonmax(ins[0], p.get("win", 3), b, c)]
+    elif n.op == "custom_point":
+        from . import custom
+        res = [custom.evaluate(p["expr"], ins, p["out_dtype"])]
     else:
         raise ValueError("unknown op " + n.op)
     for name, val in zip(n.outputs, res):

@@ -1,0 +1,133 @@
+"""Oracle for user-defined point nodes (custom OpenVX kernels, Section 5.1).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  The paper lets users
+add their own kernels to a graph as generic nodes, analysed and fused like
+the built-in ones.  Here a user point kernel is an arithmetic expression over
+up to three input images ``a``, ``b``, ``c``; this module evaluates it over
+whole images, independently of the GPU library (its own parser: Python's
+``ast`` restricted to the grammar below).
+
+Grammar: numbers, ``a``/``b``/``c``, unary ``-``, binary ``+ - * /`` with the
+usual precedence and parentheses, and the functions ``min(x, y)``,
+``max(x, y)``, ``abs(x)``, ``clamp(x, lo, hi)`` (= min(max(x, lo), hi)),
+``gt(x, y)`` (1 where x > y, else 0), ``sel(p, x, y)`` (x where p != 0, else
+y) and ``sqrt(x)`` (float kernels only).
+
+Integer kernels (every input U8/S16, output U8/S16) compute in 32-bit two's
+complement: + - * and negation wrap modulo 2^32, / truncates toward zero,
+x / 0 = 0 and the one overflowing quotient (-2^31) / (-1) wraps to -2^31.
+Literals are integers that fit 32 bits.  The result is saturated to the
+output type.  Float kernels (some input F32; the output must then be F32)
+compute in real arithmetic, here float64; IEEE division and square root.
+"""
+from __future__ import annotations
+
+import ast
+
+import numpy as np
+
+FUNCS = {"min": 2, "max": 2, "abs": 1, "clamp": 3, "gt": 2, "sel": 3, "sqrt": 1}
+INPUTS = ("a", "b", "c")
+
+
+def _wrap(x):
+    return ((x + 2 ** 31) % 2 ** 32) - 2 ** 31
+
+
+def check(expr: str, nin: int, is_float: bool):
+    """Raise ValueError unless ``expr`` is in the grammar for ``nin`` inputs."""
+    try:
+        tree = ast.parse(expr, mode="eval")
+    except SyntaxError as e:
+        raise ValueError("syntax error: %s" % e) from None
+
+    def walk(n):
+        if isinstance(n, ast.BinOp):
+            if not isinstance(n.op, (ast.Add, ast.Sub, ast.Mult, ast.Div)):
+                raise ValueError("operator not allowed")
+            walk(n.left)
+            walk(n.right)
+        elif isinstance(n, ast.UnaryOp):
+            if not isinstance(n.op, ast.USub):
+                raise ValueError("unary operator not allowed")
+            walk(n.operand)
+        elif isinstance(n, ast.Call):
+            if not isinstance(n.func, ast.Name) or n.func.id not in FUNCS or n.keywords:
+                raise ValueError("unknown function")
+            if len(n.args) != FUNCS[n.func.id]:
+                raise ValueError("wrong argument count")
+            if n.func.id == "sqrt" and not is_float:
+                raise ValueError("sqrt needs a float kernel")
+            for x in n.args:
+                walk(x)
+        elif isinstance(n, ast.Name):
+            if n.id not in INPUTS[:nin]:
+                raise ValueError("unknown name %s" % n.id)
+        elif isinstance(n, ast.Constant):
+            if isinstance(n.value, bool) or not isinstance(n.value, (int, float)):
+                raise ValueError("bad literal")
+            if not is_float and (not isinstance(n.value, int) or not -2 ** 31 <= n.value < 2 ** 31):
+                raise ValueError("integer kernels take 32-bit integer literals")
+        else:
+            raise ValueError("construct not allowed: %s" % type(n).__name__)
+
+    walk(tree.body)
+    return tree.body
+
+
+def evaluate(expr: str, inputs: list, out_dtype) -> np.ndarray:
+    """Evaluate ``expr`` over the input images (numpy arrays of one shape:
+    uint8 / int16 / float64 standing for F32).  ``out_dtype``: np.uint8,
+    np.int16 or np.float64 (F32 output)."""
+    is_float = any(x.dtype == np.float64 for x in inputs) or np.dtype(out_dtype) == np.float64
+    if is_float and np.dtype(out_dtype) != np.float64:
+        raise ValueError("a float kernel has an F32 output")
+    tree = check(expr, len(inputs), is_float)
+    env = {INPUTS[i]: (x.astype(np.float64) if is_float else x.astype(np.int64)) for i, x in enumerate(inputs)}
+    shape = inputs[0].shape
+
+    def ev(n):
+        if isinstance(n, ast.Constant):
+            return np.full(shape, n.value, np.float64 if is_float else np.int64)
+        if isinstance(n, ast.Name):
+            return env[n.id]
+        if isinstance(n, ast.UnaryOp):
+            v = -ev(n.operand)
+            return v if is_float else _wrap(v)
+        if isinstance(n, ast.BinOp):
+            x, y = ev(n.left), ev(n.right)
+            if isinstance(n.op, ast.Add):
+                r = x + y
+            elif isinstance(n.op, ast.Sub):
+                r = x - y
+            elif isinstance(n.op, ast.Mult):
+                r = x * y
+            elif is_float:
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    r = x / y
+            else:  # truncating division on the exact int64 values, x / 0 = 0
+                q = np.abs(x) // np.where(y == 0, 1, np.abs(y))
+                r = np.where(y == 0, 0, np.where((x < 0) != (y < 0), -q, q))
+            return r if is_float else _wrap(r)
+        f = n.func.id
+        args = [ev(x) for x in n.args]
+        if f == "min":
+            return np.minimum(args[0], args[1])
+        if f == "max":
+            return np.maximum(args[0], args[1])
+        if f == "abs":
+            return np.abs(args[0]) if is_float else _wrap(np.abs(args[0]))
+        if f == "clamp":
+            return np.minimum(np.maximum(args[0], args[1]), args[2])
+        if f == "gt":
+            return (args[0] > args[1]).astype(args[0].dtype)
+        if f == "sel":
+            return np.where(args[0] != 0, args[1], args[2])
+        with np.errstate(invalid="ignore"):
+            return np.sqrt(args[0])
+
+    r = ev(tree)
+    if is_float:
+        return r
+    info = np.iinfo(out_dtype)
+    return np.clip(r, info.min, info.max).astype(out_dtype)
