@@ -223,6 +223,27 @@ hvx_status hvx_nonlinear_filter_node(hvx_graph g, int function, hvx_image in, ui
 hvx_status hvx_non_max_suppression_node(hvx_graph g, hvx_image in, uint32_t win_size, hvx_image out,
                                         hvx_node* node_out);
 
+/* User-defined point kernel (Section 5.1): `expr` computes each output pixel
+ * from the pixels at the same position of 1 to 3 inputs, named a, b, c.  It
+ * is parsed once here (INVALID_PARAMETERS with the position of the error
+ * otherwise), and the node is analysed, dead-code eliminated and fused like
+ * the built-in point operators.  Grammar: integer or decimal literals, a / b
+ * / c, unary -, binary + - * / with the usual precedence, parentheses, and
+ * min(x, y), max(x, y), abs(x), clamp(x, lo, hi) = min(max(x, lo), hi),
+ * gt(x, y) (1 where x > y, else 0), sel(p, x, y) (x where p != 0, else y),
+ * sqrt(x).  At most 32 steps (names, literals and operations), 8 distinct
+ * literals and 8 values pending at once.
+ *   Integer kernel (every input U8/S16, out_format U8 or S16): 32-bit two's
+ *   complement arithmetic; + - * and negation wrap modulo 2^32, / truncates
+ *   toward zero, x / 0 = 0, (-2^31) / (-1) = -2^31; the result saturates to
+ *   the output format.  Literals are integers that fit 32 bits; no sqrt.
+ *   Float kernel (an F32 input or out_format F32; the output must be F32):
+ *   F32 arithmetic with IEEE division and square root.
+ * Format errors are reported by verification (INVALID_FORMAT).  `inputs` is
+ * read during the call only. */
+hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image* inputs, uint32_t num_inputs,
+                                 int out_format, hvx_image out, hvx_node* node_out);
+
 /* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the
  * value is read as the input's element type (0..255 for U8). */
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value);

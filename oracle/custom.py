@@ -77,10 +77,11 @@ def check(expr: str, nin: int, is_float: bool):
 
 def evaluate(expr: str, inputs: list, out_dtype) -> np.ndarray:
     """Evaluate ``expr`` over the input images (numpy arrays of one shape:
-    uint8 / int16 / float64 standing for F32).  ``out_dtype``: np.uint8,
-    np.int16 or np.float64 (F32 output)."""
-    is_float = any(x.dtype == np.float64 for x in inputs) or np.dtype(out_dtype) == np.float64
-    if is_float and np.dtype(out_dtype) != np.float64:
+    uint8 / int16, or a float type standing for F32).  ``out_dtype``:
+    np.uint8, np.int16, or a float type (F32 output, computed in float64)."""
+    f32_out = np.dtype(out_dtype).kind == "f"
+    is_float = any(x.dtype.kind == "f" for x in inputs) or f32_out
+    if is_float and not f32_out:
         raise ValueError("a float kernel has an F32 output")
     tree = check(expr, len(inputs), is_float)
     env = {INPUTS[i]: (x.astype(np.float64) if is_float else x.astype(np.int64)) for i, x in enumerate(inputs)}

@@ -81,6 +81,7 @@ def _load():
         "hvx_median3x3_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_nonlinear_filter_node": [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _P(_vp)],
         "hvx_non_max_suppression_node": [_vp, _vp, ctypes.c_uint32, _vp, _P(_vp)],
+        "hvx_custom_point_node": [_vp, ctypes.c_char_p, _P(_vp), ctypes.c_uint32, ctypes.c_int, _vp, _P(_vp)],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -255,6 +256,13 @@ def hvx_nonlinear_filter_node(g, function, i, mask, o, ctx=None):
 
 def hvx_non_max_suppression_node(g, i, win_size, o, ctx=None):
     return _node("hvx_non_max_suppression_node", ctx, g, i, win_size, o)
+
+
+def hvx_custom_point_node(g, expr, inputs, out_format, o, ctx=None):
+    """User point kernel: `expr` over the images `inputs` (1 to 3, named a,
+    b, c); `out_format` one of HVX_DF_U8 / S16 / F32."""
+    arr = (_vp * len(inputs))(*inputs)
+    return _node("hvx_custom_point_node", ctx, g, expr.encode(), arr, len(inputs), out_format, o)
 
 
 def hvx_box5x5_f32_node(g, i, o, ctx=None):

@@ -506,6 +506,31 @@ hvx_status hvx_non_max_suppression_node(hvx_graph g, hvx_image in, uint32_t win_
   return s;
 }
 
+hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image* inputs, uint32_t num_inputs,
+                                 int out_format, hvx_image out, hvx_node* no) {
+  Graph* gg = as<Graph>(g, T_GRAPH);
+  if (!gg) return HVX_ERROR_INVALID_REFERENCE;
+  if (num_inputs < 1 || num_inputs > 3 || !inputs)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "a user point kernel takes 1 to 3 inputs (got %u)",
+                     num_inputs);
+  if (out_format != HVX_DF_U8 && out_format != HVX_DF_S16 && out_format != HVX_DF_F32)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_FORMAT, "output format must be U8, S16 or F32");
+  ExprProg prog;
+  std::string why = parse_expr(expr, &prog);
+  if (!why.empty()) return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "expression: %s", why.c_str());
+  if (prog.max_input >= (int)num_inputs)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "expression names input %c of %u", 'a' + prog.max_input,
+                     num_inputs);
+  Node* n = nullptr;
+  hvx_status s = num_inputs == 1   ? add_node(g, NK_CUSTOM_POINT, {inputs[0]}, {out}, 1, no, &n)
+                 : num_inputs == 2 ? add_node(g, NK_CUSTOM_POINT, {inputs[0], inputs[1]}, {out}, 1, no, &n)
+                                   : add_node(g, NK_CUSTOM_POINT, {inputs[0], inputs[1], inputs[2]}, {out}, 1, no, &n);
+  if (s) return s;
+  n->expr = std::move(prog);
+  n->out_df = out_format;
+  return HVX_SUCCESS;
+}
+
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value) {
   Node* n = as<Node>(node, T_NODE);
   if (!n) return HVX_ERROR_INVALID_REFERENCE;

@@ -107,7 +107,73 @@ __device__ __forceinline__ int sat_s16(int v) { return min(max(v, -32768), 32767
 
 __host__ __device__ inline bool is_point_op(int kind) {
   return kind == OP_CHANNEL_Y || kind == OP_MAGNITUDE || kind == OP_PHASE || kind == OP_THRESHOLD ||
-         kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS;
+         kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS || kind == OP_EXPR;
+}
+
+// A user point kernel (Section 5.1) at one pixel: its postfix program over
+// the input elements a, b, c (int bits; F32 inputs as bit patterns, marked in
+// o.p2).  Integer kernels compute in 32-bit two's complement: + - * and
+// negation wrap, / truncates toward zero, x / 0 = 0 and INT_MIN / -1 wraps
+// to INT_MIN; the result saturates to the output type.  Float kernels
+// (o.p1) compute in F32 and return F32 bits.  Every lane runs the same
+// program, so the stack position is uniform across the wave.
+__device__ __forceinline__ int expr_eval(const GOp& o, int out_df, int a, int b, int c) {
+  const int n = o.p0;
+  if (o.p1) {
+    float st[kExprStack];
+    int sp = 0;
+    for (int k = 0; k < n; ++k) {
+      const int op = o.code[k] & 0xFF, arg = o.code[k] >> 8;
+      switch (op) {
+        case X_IN: {
+          const int v = arg == 0 ? a : (arg == 1 ? b : c);
+          st[sp++] = ((o.p2 >> arg) & 1) ? __int_as_float(v) : (float)v;
+          break;
+        }
+        case X_CONST: st[sp++] = __int_as_float(o.kc[arg]); break;
+        case X_ADD: --sp; st[sp - 1] = st[sp - 1] + st[sp]; break;
+        case X_SUB: --sp; st[sp - 1] = st[sp - 1] - st[sp]; break;
+        case X_MUL: --sp; st[sp - 1] = st[sp - 1] * st[sp]; break;
+        case X_DIV: --sp; st[sp - 1] = st[sp - 1] / st[sp]; break;
+        case X_NEG: st[sp - 1] = -st[sp - 1]; break;
+        case X_MIN: --sp; st[sp - 1] = fminf(st[sp - 1], st[sp]); break;
+        case X_MAX: --sp; st[sp - 1] = fmaxf(st[sp - 1], st[sp]); break;
+        case X_ABS: st[sp - 1] = fabsf(st[sp - 1]); break;
+        case X_CLAMP: sp -= 2; st[sp - 1] = fminf(fmaxf(st[sp - 1], st[sp]), st[sp + 1]); break;
+        case X_GT: --sp; st[sp - 1] = st[sp - 1] > st[sp] ? 1.f : 0.f; break;
+        case X_SEL: sp -= 2; st[sp - 1] = st[sp - 1] != 0.f ? st[sp] : st[sp + 1]; break;
+        case X_SQRT: st[sp - 1] = __builtin_sqrtf(st[sp - 1]); break;
+      }
+    }
+    return __float_as_int(st[0]);
+  }
+  int st[kExprStack];
+  int sp = 0;
+  for (int k = 0; k < n; ++k) {
+    const int op = o.code[k] & 0xFF, arg = o.code[k] >> 8;
+    switch (op) {
+      case X_IN: st[sp++] = arg == 0 ? a : (arg == 1 ? b : c); break;
+      case X_CONST: st[sp++] = o.kc[arg]; break;
+      case X_ADD: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] + (uint32_t)st[sp]); break;
+      case X_SUB: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] - (uint32_t)st[sp]); break;
+      case X_MUL: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] * (uint32_t)st[sp]); break;
+      case X_DIV: {
+        --sp;
+        const int x = st[sp - 1], y = st[sp];
+        st[sp - 1] = y == 0 ? 0 : (y == -1 ? (int)(0u - (uint32_t)x) : x / y);
+        break;
+      }
+      case X_NEG: st[sp - 1] = (int)(0u - (uint32_t)st[sp - 1]); break;
+      case X_MIN: --sp; st[sp - 1] = min(st[sp - 1], st[sp]); break;
+      case X_MAX: --sp; st[sp - 1] = max(st[sp - 1], st[sp]); break;
+      case X_ABS: st[sp - 1] = st[sp - 1] < 0 ? (int)(0u - (uint32_t)st[sp - 1]) : st[sp - 1]; break;
+      case X_CLAMP: sp -= 2; st[sp - 1] = min(max(st[sp - 1], st[sp]), st[sp + 1]); break;
+      case X_GT: --sp; st[sp - 1] = st[sp - 1] > st[sp] ? 1 : 0; break;
+      case X_SEL: sp -= 2; st[sp - 1] = st[sp - 1] != 0 ? st[sp] : st[sp + 1]; break;
+    }
+  }
+  const int r = st[0];
+  return out_df == DF_U8 ? min(max(r, 0), 255) : min(max(r, -32768), 32767);
 }
 
 // A point operator (Section 4) on one pixel: a, b, c are its input elements
@@ -143,6 +209,7 @@ __device__ __forceinline__ int point_eval(const GOp& o, int out_df, bool in_f32,
       return o.p0 == 0 ? sat_s16(sm) : (int)(int16_t)(uint16_t)(sm & 0xFFFF);
     }
     case OP_MULF: return __float_as_int((float)a * (float)b);
+    case OP_EXPR: return expr_eval(o, out_df, a, b, c);
     case OP_HARRIS: {
       float sxx = __int_as_float(a), syy = __int_as_float(b), sxy = __int_as_float(c);
       float det = sxx * syy - sxy * sxy;

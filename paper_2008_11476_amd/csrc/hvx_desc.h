@@ -27,7 +27,17 @@ enum OpKind : int32_t {
   OP_MEDIAN3,
   OP_NONLINEAR,  // median / min / max over a mask (p0 x p1, p2: 0 median, 1 min, 2 max)
   OP_NONMAX,     // NonMaxSuppression over a (2 p0 + 1)^2 window, U8 or S16
+  OP_EXPR,       // user point kernel (Section 5.1): p0 steps of `code`, p1 = 1 float kernel, p2 bit k: input k F32
 };
+
+// Steps of a user point kernel's postfix program: the low byte is the
+// operation, the high byte its argument (input index, literal index).
+enum ExprOp : int16_t {
+  X_IN = 1, X_CONST, X_ADD, X_SUB, X_MUL, X_DIV, X_NEG, X_MIN, X_MAX, X_ABS, X_CLAMP, X_GT, X_SEL, X_SQRT
+};
+constexpr int kMaxExpr = 32;       // steps
+constexpr int kMaxExprConst = 8;   // distinct literals
+constexpr int kExprStack = 8;      // values on the evaluation stack
 
 // Element formats (same numbering as the public HVX_DF_* constants).
 enum Df : int32_t { DF_VIRT = 0, DF_U8 = 1, DF_S16 = 2, DF_S32 = 3, DF_F32 = 4, DF_UYVY = 5 };
@@ -71,6 +81,8 @@ struct GOp {
   int32_t p0, p1, p2, p3;  // threshold: true, false, integer bound; add: policy; convolve: cols, rows, shift
   float pf;                // corner response k; threshold bound for F32 input
   int16_t mask[kMaxMask];
+  int16_t code[kMaxExpr];      // OP_EXPR program
+  int32_t kc[kMaxExprConst];   // OP_EXPR literals (int32, or F32 bits in a float kernel)
 };
 
 struct GProg {

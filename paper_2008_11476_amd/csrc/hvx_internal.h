@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/hvx.h"
+#include "expr.h"
 #include "hvx_desc.h"
 
 namespace hvx {
@@ -59,6 +60,7 @@ enum NodeKind : int32_t {
   NK_HARRIS,
   NK_THRESHOLD,
   NK_CONVOLVE,
+  NK_CUSTOM_POINT,
 };
 
 struct Node : Object {
@@ -75,6 +77,8 @@ struct Node : Object {
   Conv* conv = nullptr;
   int channel = 0;
   Conv own_mask;  // NonLinearFilter: the node's own copy of its mask (conv points here)
+  ExprProg expr;  // user point kernel
+  int out_df = 0; // user point kernel: declared output format
 };
 
 // ---- lowered graph and plan -------------------------------------------------
@@ -103,6 +107,7 @@ struct LOp {
   int tv = 255, fv = 0, policy = 0;
   float k = 0.04f;
   const Conv* conv = nullptr;
+  const ExprProg* expr = nullptr;
   int rx = 0, ry = 0;
   bool live = true;
 };

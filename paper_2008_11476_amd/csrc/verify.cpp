@@ -90,6 +90,7 @@ static const char* node_name(int kind) {
     case NK_MEDIAN3: return "Median3x3";
     case NK_NONLINEAR: return "NonLinearFilter";
     case NK_NONMAX: return "NonMaxSuppression";
+    case NK_CUSTOM_POINT: return "user point kernel";
     case NK_BOX5F: return "Box5x5F32";
     case NK_SOBEL3: return "Sobel3x3";
     case NK_MAGNITUDE: return "Magnitude";
@@ -408,6 +409,23 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
       case OP_ADD: q.p0 = o.policy; break;
       case OP_HARRIS: q.pf = o.k; break;
       case OP_NONMAX: q.p0 = o.policy / 2; break;
+      case OP_EXPR: {
+        const ExprProg& e = *o.expr;
+        q.p0 = (int)e.code.size();
+        q.p1 = P.vals[q.out].df == DF_F32 ? 1 : 0;
+        q.p2 = 0;
+        for (int k = 0; k < o.nin; ++k) q.p2 |= (P.vals[q.in[k]].df == DF_F32 ? 1 : 0) << k;
+        for (size_t k = 0; k < e.code.size(); ++k) q.code[k] = e.code[k];
+        for (size_t k = 0; k < e.consts.size(); ++k) {
+          if (q.p1) {
+            const float f = (float)e.consts[k];
+            memcpy(&q.kc[k], &f, 4);
+          } else {
+            q.kc[k] = (int32_t)e.consts[k];
+          }
+        }
+        break;
+      }
       case OP_NONLINEAR:
         q.p0 = (int)o.conv->cols;
         q.p1 = (int)o.conv->rows;
@@ -546,6 +564,21 @@ hvx_status verify_graph(Graph* g) {
         if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
         s = bind_output(g, p, nout[i][0], DF_U8, w, h, nn);
         break;
+      case NK_CUSTOM_POINT: {
+        // a float kernel (an F32 input or output) has an F32 output; an
+        // integer kernel uses no sqrt and only 32-bit integer literals
+        bool flt = n->out_df == DF_F32;
+        for (int v : nin[i]) {
+          if (!need(v, {DF_U8, DF_S16, DF_F32})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs U8/S16/F32 inputs", nn);
+          flt |= p.vals[v].df == DF_F32;
+        }
+        if (flt && n->out_df != DF_F32)
+          return err(g, HVX_ERROR_INVALID_FORMAT, "%s: a kernel with an F32 input has an F32 output", nn);
+        if (!flt && (n->expr.needs_float || !n->expr.int_literals_ok))
+          return err(g, HVX_ERROR_INVALID_FORMAT, "%s: sqrt and non-integer literals need a float kernel", nn);
+        s = bind_output(g, p, nout[i][0], n->out_df, w, h, nn);
+        break;
+      }
       case NK_NONMAX:
         if (!need(nin[i][0], {DF_U8, DF_S16})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8/S16 input", nn);
         s = bind_output(g, p, nout[i][0], p.vals[nin[i][0]].df, w, h, nn);
@@ -624,6 +657,7 @@ hvx_status verify_graph(Graph* g) {
       o.policy = n->policy;
       o.k = n->k;
       o.conv = n->conv;
+      o.expr = &n->expr;
       op_radius(o, &o.rx, &o.ry);
       p.ops.push_back(o);
     };
@@ -637,6 +671,7 @@ hvx_status verify_graph(Graph* g) {
       case NK_MEDIAN3: emit(OP_MEDIAN3, nin[i], nout[i][0]); break;
       case NK_NONLINEAR: emit(OP_NONLINEAR, nin[i], nout[i][0]); break;
       case NK_NONMAX: emit(OP_NONMAX, nin[i], nout[i][0]); break;
+      case NK_CUSTOM_POINT: emit(OP_EXPR, nin[i], nout[i][0]); break;
       case NK_BOX5F: emit(OP_BOX5F, nin[i], nout[i][0]); break;
       case NK_SOBEL3:  // two parallel local operators
         if (nout[i][0] >= 0) emit(OP_SOBEL_X, nin[i], nout[i][0]);
