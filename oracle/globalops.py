@@ -1,0 +1,42 @@
+"""Oracle for global operators (Table 2: reductions and histograms).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  A global operator
+reads every pixel of an image and produces a few values, not an image.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def histogram(img: np.ndarray, num_bins: int, offset: int, rng: int) -> np.ndarray:
+    """Counts of a U8 image over ``num_bins`` equal bins of [offset, offset +
+    rng): a pixel v in that interval falls in bin (v - offset) * num_bins //
+    rng; pixels outside it are not counted."""
+    if img.dtype != np.uint8 or not 1 <= num_bins <= 256 or rng < 1 or offset < 0 or offset + rng > 256 \
+            or num_bins > rng:
+        raise ValueError("U8 image, 1 <= num_bins <= range, [offset, offset + range) within 0..256")
+    v = img.astype(np.int64).ravel()
+    inside = (v >= offset) & (v < offset + rng)
+    bins = (v[inside] - offset) * num_bins // rng
+    return np.bincount(bins, minlength=num_bins).astype(np.uint32)
+
+
+def min_max(img: np.ndarray) -> tuple:
+    """Smallest and largest pixel of a U8 or S16 image."""
+    if img.dtype not in (np.uint8, np.int16) or img.size == 0:
+        raise ValueError("non-empty U8 or S16 image")
+    return int(img.min()), int(img.max())
+
+
+def mean_std_dev(img: np.ndarray) -> tuple:
+    """Mean and population standard deviation of a U8 image, from the exact
+    integer sums S1 = sum v and S2 = sum v^2 over N pixels: mean = S1 / N,
+    stddev = sqrt(S2 / N - mean^2), in double precision.  Also returns the
+    sums."""
+    if img.dtype != np.uint8 or img.size == 0:
+        raise ValueError("non-empty U8 image")
+    v = img.astype(np.int64)
+    s1, s2, n = int(v.sum()), int((v * v).sum()), img.size
+    mean = s1 / n
+    var = s2 / n - mean * mean
+    return mean, float(np.sqrt(max(var, 0.0))), s1, s2

@@ -1,0 +1,46 @@
+"""Pins of the global-operator oracle against numpy's own histogram, mean
+and standard deviation, and brute force on tiny images."""
+import numpy as np
+import pytest
+
+from oracle import globalops as G
+
+RNG = np.random.default_rng(9)
+IMG = RNG.integers(0, 256, (37, 53), dtype=np.uint8)
+
+
+@pytest.mark.parametrize("bins,offset,rng", [(256, 0, 256), (16, 0, 256), (10, 20, 200), (1, 0, 256), (7, 100, 21)])
+def test_histogram_matches_numpy_histogram(bins, offset, rng):
+    # numpy's half-open bins on the edges offset + k * rng / bins (exact for these pairs)
+    edges = offset + np.arange(bins + 1) * (rng / bins)
+    want, _ = np.histogram(IMG, bins=edges)
+    last = IMG == offset + rng  # np.histogram closes the last bin; the OpenVX interval is half-open
+    want[-1] -= last.sum() if edges[-1] == offset + rng else 0
+    assert np.array_equal(G.histogram(IMG, bins, offset, rng), want)
+    assert G.histogram(IMG, bins, offset, rng).sum() == ((IMG >= offset) & (IMG < offset + rng)).sum()
+
+
+def test_histogram_brute_force_uneven_bins():
+    img = np.arange(256, dtype=np.uint8).reshape(16, 16)
+    got = G.histogram(img, 3, 10, 10)  # bins of width 10/3: 10..13, 14..16, 17..19
+    assert got.tolist() == [4, 3, 3]
+
+
+def test_min_max_brute_force():
+    for dt, lo, hi in ((np.uint8, 0, 256), (np.int16, -32768, 32768)):
+        img = RNG.integers(lo, hi, (5, 7)).astype(dt)
+        flat = [int(x) for x in img.ravel()]
+        m, M = flat[0], flat[0]
+        for x in flat:
+            m, M = (x if x < m else m), (x if x > M else M)
+        assert G.min_max(img) == (m, M)
+
+
+def test_mean_std_dev_matches_numpy():
+    mean, std, s1, s2 = G.mean_std_dev(IMG)
+    assert mean == pytest.approx(float(np.mean(IMG, dtype=np.float64)), rel=1e-15)
+    assert std == pytest.approx(float(np.std(IMG, dtype=np.float64)), rel=1e-12)
+    const = np.full((3, 4), 77, np.uint8)
+    assert G.mean_std_dev(const)[:2] == (77.0, 0.0)
+    two = np.array([[0, 255]], np.uint8)
+    assert G.mean_std_dev(two)[:2] == (127.5, 127.5)
