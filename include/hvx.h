@@ -244,6 +244,28 @@ hvx_status hvx_non_max_suppression_node(hvx_graph g, hvx_image in, uint32_t win_
 hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image* inputs, uint32_t num_inputs,
                                  int out_format, hvx_image out, hvx_node* node_out);
 
+/* Global operators (Table 2), immediate mode: each call reads the whole
+ * (non-virtual) image and writes its result to caller-owned device memory,
+ * asynchronously on `stream` (NULL: the default stream); the image and the
+ * buffer must stay valid until the stream reaches the call.  The result is
+ * initialised by a kernel in the same stream, so the calls can be captured
+ * into a HIP graph.  Calls that share a result buffer and overlap race.
+ * INVALID_REFERENCE / INVALID_FORMAT / INVALID_PARAMETERS as stated; DEVICE
+ * if a launch fails.
+ *  histogram: U8 image; dev_counts holds num_bins uint32 counts.  A pixel v
+ *    with offset <= v < offset + range falls in bin (v - offset) * num_bins /
+ *    range (integer division); other pixels are not counted.  Needs
+ *    1 <= num_bins <= range and offset + range <= 256.
+ *  min_max: U8 or S16 image; dev_min_max receives {smallest, largest}.
+ *  mean_std_dev: U8 image; dev_result (24 bytes, 8-byte aligned) receives
+ *    the exact sums uint64 S1 = sum v and S2 = sum v^2, then float mean =
+ *    S1 / N and float population standard deviation sqrt(S2 / N - mean^2),
+ *    both formed in double precision. */
+hvx_status hvx_histogram(hvx_context ctx, hvx_image in, uint32_t num_bins, uint32_t offset, uint32_t range,
+                         uint32_t* dev_counts, void* stream);
+hvx_status hvx_min_max(hvx_context ctx, hvx_image in, int32_t* dev_min_max, void* stream);
+hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream);
+
 /* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the
  * value is read as the input's element type (0..255 for U8). */
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value);

@@ -82,6 +82,9 @@ def _load():
         "hvx_nonlinear_filter_node": [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _P(_vp)],
         "hvx_non_max_suppression_node": [_vp, _vp, ctypes.c_uint32, _vp, _P(_vp)],
         "hvx_custom_point_node": [_vp, ctypes.c_char_p, _P(_vp), ctypes.c_uint32, ctypes.c_int, _vp, _P(_vp)],
+        "hvx_histogram": [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp],
+        "hvx_min_max": [_vp, _vp, _vp, _vp],
+        "hvx_mean_std_dev": [_vp, _vp, _vp, _vp],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -263,6 +266,20 @@ def hvx_custom_point_node(g, expr, inputs, out_format, o, ctx=None):
     b, c); `out_format` one of HVX_DF_U8 / S16 / F32."""
     arr = (_vp * len(inputs))(*inputs)
     return _node("hvx_custom_point_node", ctx, g, expr.encode(), arr, len(inputs), out_format, o)
+
+
+def hvx_histogram(ctx, img, num_bins, offset, rng, dev_counts, stream=None):
+    """Global operator: counts of a U8 image into `dev_counts` (device pointer
+    to num_bins uint32), asynchronous on `stream`."""
+    _check(_load().hvx_histogram(ctx, img, num_bins, offset, rng, dev_counts, stream), ctx)
+
+
+def hvx_min_max(ctx, img, dev_min_max, stream=None):
+    _check(_load().hvx_min_max(ctx, img, dev_min_max, stream), ctx)
+
+
+def hvx_mean_std_dev(ctx, img, dev_result, stream=None):
+    _check(_load().hvx_mean_std_dev(ctx, img, dev_result, stream), ctx)
 
 
 def hvx_box5x5_f32_node(g, i, o, ctx=None):

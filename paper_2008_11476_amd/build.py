@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libhvx.so")
 
-SOURCES = ["api.cpp", "verify.cpp", "runtime.cpp", "server.cpp", "expr.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "verify.cpp", "runtime.cpp", "server.cpp", "expr.cpp", "kernels.hip", "global.hip"]
 
 ARCH = os.environ.get("HVX_OFFLOAD_ARCH", "gfx950")
 COMMON = [

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <unordered_map>
 
+#include "global.h"
 #include "hvx_internal.h"
 
 namespace hvx {
@@ -529,6 +530,61 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
   n->expr = std::move(prog);
   n->out_df = out_format;
   return HVX_SUCCESS;
+}
+
+// ---- global operators (immediate mode) ------------------------------------------
+
+static hvx_status global_input(hvx_context ctx, hvx_image in, std::initializer_list<int> dfs, GlobalImg* gi) {
+  Context* c = as<Context>(ctx, T_CONTEXT);
+  if (!c) return HVX_ERROR_INVALID_REFERENCE;
+  Image* im = as<Image>(in, T_IMAGE);
+  if (!im || im->ctx != c) return set_error(c, HVX_ERROR_INVALID_REFERENCE, "invalid image");
+  if (im->is_virtual || !im->ptr) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "image has no device memory");
+  bool ok = false;
+  for (int d : dfs) ok |= im->df == d;
+  if (!ok) return set_error(c, HVX_ERROR_INVALID_FORMAT, "unsupported image format");
+  hvx_status s = ensure_device(c);
+  if (s) return s;
+  gi->base = (const uint8_t*)im->ptr;
+  gi->pitch = (int64_t)im->pitch;
+  gi->w = (int32_t)im->w;
+  gi->h = (int32_t)im->h;
+  gi->bpp = df_bytes(im->df);
+  return HVX_SUCCESS;
+}
+
+static hvx_status launched(hvx_context ctx, hipError_t e) {
+  if (e == hipSuccess) return HVX_SUCCESS;
+  return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+}
+
+hvx_status hvx_histogram(hvx_context ctx, hvx_image in, uint32_t num_bins, uint32_t offset, uint32_t range,
+                         uint32_t* dev_counts, void* stream) {
+  GlobalImg gi;
+  hvx_status s = global_input(ctx, in, {DF_U8}, &gi);
+  if (s) return s;
+  Context* c = as<Context>(ctx, T_CONTEXT);
+  if (!dev_counts) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "null counts buffer");
+  if (num_bins < 1 || num_bins > 256 || range < num_bins || offset + (uint64_t)range > 256)
+    return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "need 1 <= num_bins <= range and offset + range <= 256");
+  return launched(ctx, launch_histogram(gi, (int)num_bins, (int)offset, (int)range, dev_counts, (hipStream_t)stream));
+}
+
+hvx_status hvx_min_max(hvx_context ctx, hvx_image in, int32_t* dev_min_max, void* stream) {
+  GlobalImg gi;
+  hvx_status s = global_input(ctx, in, {DF_U8, DF_S16}, &gi);
+  if (s) return s;
+  if (!dev_min_max) return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "null result buffer");
+  return launched(ctx, launch_min_max(gi, dev_min_max, (hipStream_t)stream));
+}
+
+hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream) {
+  GlobalImg gi;
+  hvx_status s = global_input(ctx, in, {DF_U8}, &gi);
+  if (s) return s;
+  if (!dev_result || ((uintptr_t)dev_result & 7))
+    return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "result buffer null or not 8-byte aligned");
+  return launched(ctx, launch_mean_std_dev(gi, dev_result, (hipStream_t)stream));
 }
 
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value) {

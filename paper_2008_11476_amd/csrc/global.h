@@ -1,0 +1,21 @@
+// Host-side launchers of the global-operator kernels (global.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hvx {
+
+// One image as the global kernels read it: rows of `pitch` bytes (a multiple
+// of 64) from a 16-byte aligned base; `bpp` bytes per element (1 or 2).
+struct GlobalImg {
+  const uint8_t* base;
+  int64_t pitch;
+  int32_t w, h, bpp;
+};
+
+hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int range, uint32_t* counts,
+                            hipStream_t s);
+hipError_t launch_min_max(const GlobalImg& im, int32_t* min_max, hipStream_t s);
+hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s);
+
+}  // namespace hvx

@@ -1,0 +1,171 @@
+// Global operators (Table 2): operators that read every pixel of an image
+// and produce a few values.  Each kernel streams the image once with one
+// 16-byte load per lane per step (a row split into 16-byte chunks across the
+// 256 threads of a work-group, rows strided over the grid), reduces inside
+// the wave with lane exchanges, and combines work-groups with one global
+// atomic per wave (per bin for the histogram).  The caller's result buffer is
+// initialised by a small kernel in the same stream, so the sequence can be
+// captured into a HIP graph.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include "global.h"
+
+namespace hvx {
+
+constexpr int kGThreads = 256;
+
+static int global_grid(const GlobalImg& im) { return im.h < 1024 ? im.h : 1024; }
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t a, uint32_t b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i == 0 ? a : b;
+}
+
+// ---- histogram of a U8 image ------------------------------------------------
+// Bin of value v: (v - offset) * num_bins / range for offset <= v < offset +
+// range, none otherwise; looked up from a 256-entry table in LDS.  Each wave
+// counts into its own LDS sub-histogram (fewer collisions between waves).
+__global__ __launch_bounds__(kGThreads) void k_histogram(GlobalImg im, int num_bins, int offset, int range,
+                                                         uint32_t* __restrict__ counts) {
+  __shared__ uint32_t sub[kGThreads / 64][256];
+  __shared__ int lut[256];
+  const int t = threadIdx.x, wv = t >> 6;
+  for (int k = t; k < (kGThreads / 64) * 256; k += kGThreads) (&sub[0][0])[k] = 0;
+  lut[t] = (t >= offset && t < offset + range) ? (t - offset) * num_bins / range : -1;
+  __syncthreads();
+  const int chunks = (im.w + 15) >> 4;
+  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
+    const uint8_t* row = im.base + (size_t)y * im.pitch;
+    for (int c = t; c < chunks; c += kGThreads) {
+      const uint4 q = *(const uint4*)(row + 16 * c);
+      const int n = min(16, im.w - 16 * c);
+      const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int b = lut[(wd[k >> 2] >> (8 * (k & 3))) & 0xFF];
+        if (k < n && b >= 0) atomicAdd(&sub[wv][b], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = t; b < num_bins; b += kGThreads) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < kGThreads / 64; ++w) s += sub[w][b];
+    if (s) atomicAdd(&counts[b], s);
+  }
+}
+
+hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int range, uint32_t* counts,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((num_bins + 255) / 256), dim3(256), 0, s, counts, num_bins, 0u, 0u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  hipLaunchKernelGGL(k_histogram, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, num_bins, offset, range, counts);
+  return hipGetLastError();
+}
+
+// ---- smallest and largest element of a U8 or S16 image ------------------------
+template <bool S16>
+__global__ __launch_bounds__(kGThreads) void k_min_max(GlobalImg im, int32_t* __restrict__ out) {
+  constexpr int kPer = S16 ? 8 : 16;  // elements per 16-byte chunk
+  int mn = INT_MAX, mx = INT_MIN;
+  const int t = threadIdx.x;
+  const int chunks = (im.w + kPer - 1) / kPer;
+  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
+    const uint8_t* row = im.base + (size_t)y * im.pitch;
+    for (int c = t; c < chunks; c += kGThreads) {
+      const uint4 q = *(const uint4*)(row + 16 * c);
+      const int n = min(kPer, im.w - kPer * c);
+      const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
+        if (k < n) {
+          mn = min(mn, v);
+          mx = max(mx, v);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = min(mn, __shfl_xor(mn, off));
+    mx = max(mx, __shfl_xor(mx, off));
+  }
+  if ((t & 63) == 0) {
+    atomicMin(&out[0], mn);
+    atomicMax(&out[1], mx);
+  }
+}
+
+hipError_t launch_min_max(const GlobalImg& im, int32_t* min_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)min_max, 2, (uint32_t)INT_MAX,
+                     (uint32_t)INT_MIN);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  if (im.bpp == 2) hipLaunchKernelGGL(k_min_max<true>, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, min_max);
+  else hipLaunchKernelGGL(k_min_max<false>, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, min_max);
+  return hipGetLastError();
+}
+
+// ---- mean and standard deviation of a U8 image ----------------------------------
+// Exact sums S1 = sum v and S2 = sum v^2 (64-bit), then one thread forms
+// mean = S1 / N and stddev = sqrt(S2 / N - mean^2) in double precision.
+// result: u64 S1, u64 S2, f32 mean, f32 stddev.
+__global__ __launch_bounds__(kGThreads) void k_sums(GlobalImg im, unsigned long long* __restrict__ sums) {
+  unsigned long long s1 = 0, s2 = 0;
+  const int t = threadIdx.x;
+  const int chunks = (im.w + 15) >> 4;
+  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
+    const uint8_t* row = im.base + (size_t)y * im.pitch;
+    for (int c = t; c < chunks; c += kGThreads) {
+      const uint4 q = *(const uint4*)(row + 16 * c);
+      const int n = min(16, im.w - 16 * c);
+      const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+      uint32_t a = 0, b = 0;  // at most 16 * 255^2 < 2^21
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t v = k < n ? (wd[k >> 2] >> (8 * (k & 3))) & 0xFF : 0u;
+        a += v;
+        b += v * v;
+      }
+      s1 += a;
+      s2 += b;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_xor(s1, off);
+    s2 += __shfl_xor(s2, off);
+  }
+  if ((t & 63) == 0) {
+    atomicAdd(&sums[0], s1);
+    atomicAdd(&sums[1], s2);
+  }
+}
+
+__global__ void k_mean_std_final(unsigned long long* __restrict__ sums, double n) {
+  if (threadIdx.x != 0) return;
+  const double mean = (double)sums[0] / n;
+  const double var = (double)sums[1] / n - mean * mean;
+  float* f = (float*)(sums + 2);
+  f[0] = (float)mean;
+  f[1] = (float)sqrt(var > 0.0 ? var : 0.0);
+}
+
+hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result, 6, 0u, 0u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  hipLaunchKernelGGL(k_sums, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, (unsigned long long*)result);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mean_std_final, dim3(1), dim3(64), 0, s, (unsigned long long*)result,
+                     (double)im.w * (double)im.h);
+  return hipGetLastError();
+}
+
+}  // namespace hvx

@@ -200,3 +200,27 @@ def test_custom_format_errors_at_verify(ctx, expr, in_df, out_df):
     with pytest.raises(hvx.HvxError):
         hvx.hvx_graph_verify(g, ctx=ctx)
     hvx.hvx_release_graph(g)
+
+
+FCHAIN = [(np.outer([1, 4, 6, 4, 1], [1, 4, 6, 4, 1]), 256),      # Gaussian 5x5
+          (np.array([[0, -1, 0], [-1, 5, -1], [0, -1, 0]]), 1),    # sharpen 3x3
+          (np.ones((5, 5), int), 32)]                              # box 5x5, scaled down
+
+
+@pytest.mark.parametrize("w,h", [(640, 480), (131, 29)])
+@pytest.mark.parametrize("border", [("replicate", 0), ("constant", 9), ("mirror", 0)])
+def test_fchain_application(ctx, w, h, border):
+    """FChain (Section 6.1): three convolution nodes in a row, U8 between
+    them, fused into one kernel (footprint 2 + 1 + 2) and node by node."""
+    img = synth.edge_image(w, h, seed=h)
+    names = ["in", "c1", "c2", "out"]
+    nodes = [gs.N("convolve", [names[k]], [names[k + 1]], *border,
+                  params={"coeffs": m, "scale": s, "out_dtype": "u8"}) for k, (m, s) in enumerate(FCHAIN)]
+    spec = gs.Spec(nodes, {"in": img}, {"c1": np.uint8, "c2": np.uint8, "out": np.uint8})
+    env = spec.run_oracle()
+    log("fchain %dx%d %s" % (w, h, border))
+    got, g = run_spec(spec, ctx)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    compare(spec, got, env)
+    unf, _ = run_spec(spec, ctx, fusion=False)
+    compare(spec, unf, env)
