@@ -175,7 +175,7 @@ def edge_batch(hvx, torch, ctx, w, h, nframes, steps, warmup, phase=False, borde
                 rows=per_mode["rows_per_item"], mode=mode, per_mode=per_mode)
 
 
-def extras(hvx, torch, ctx, quick=False):
+def extras(hvx, torch, ctx, quick=False, only_global=False):
     import synth
     res = {}
     stream = torch.cuda.current_stream().cuda_stream
@@ -183,6 +183,10 @@ def extras(hvx, torch, ctx, quick=False):
     def rec(name, d):
         res[name] = d
         log(name, json.dumps(d))
+
+    if only_global:
+        global_ops(hvx, torch, ctx, stream, rec)
+        return res
 
     # the same graph without the Phase branch (2 B/px), 64 4K frames
     r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 20, 3)
@@ -287,9 +291,33 @@ def extras(hvx, torch, ctx, quick=False):
         hvx.hvx_release_graph(x)
     del keep
     torch.cuda.empty_cache()
+    global_ops(hvx, torch, ctx, stream, rec)
     res["serving"] = serving(hvx, torch, ctx)
     log("serving", json.dumps(res["serving"]))
     return res
+
+
+def global_ops(hvx, torch, ctx, stream, rec):
+    """Global operators (Table 2) over one 16384 x 16384 U8 image: one read
+    pass of 268 MB each.  The timed call includes the kernel that initialises
+    the result (and, for mean/stddev, the final kernel)."""
+    gw = gh = 16384
+    gb, gv = hvx.alloc_image(gh, gw, hvx.HVX_DF_U8)
+    gv.copy_(torch.randint(0, 256, (gh, gw), dtype=torch.uint8, device="cuda"))
+    gim = hvx.image_from_tensor(ctx, gv, hvx.HVX_DF_U8)
+    gout = torch.zeros(512, dtype=torch.int64, device="cuda")
+    gops = {"histogram256": lambda: hvx.hvx_histogram(ctx, gim, 256, 0, 256, gout.data_ptr(), stream),
+            "min_max": lambda: hvx.hvx_min_max(ctx, gim, gout.data_ptr(), stream),
+            "mean_std_dev": lambda: hvx.hvx_mean_std_dev(ctx, gim, gout.data_ptr(), stream)}
+    gd = {"image": "16384x16384 U8, uniform random", "alg_bytes": gw * gh}
+    for name, fn in gops.items():
+        ms, _ = time_region(torch, fn, 20, 3)
+        gbs = gw * gh / (ms / 1e3) / 1e9
+        gd[name] = {"ms": round(ms, 4), "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    rec("global_ops_16k", gd)
+    hvx.hvx_release_image(gim)
+    del gb, gv, gout
+    torch.cuda.empty_cache()
 
 
 def serving(hvx, torch, ctx, n_req=240, budget=512 << 20):
@@ -442,6 +470,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--global-ops-only", action="store_true",
+                    help="of the extra measurements, run only the global operators")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rows", type=int, default=None,
                     help="pin the headline batch to this many rows per work item (default: tune)")
@@ -531,7 +561,7 @@ def run(args, torch, hvx, ctx):
         r["mpix_s"], r["gbs"], 100 * r["gbs"] / HBM_PEAK_GBS, ms, r["ms_host"]))
     if not args.no_extras:
         try:
-            out["extras"] = extras(hvx, torch, ctx)
+            out["extras"] = extras(hvx, torch, ctx, only_global=args.global_ops_only)
         except Exception as e:  # context numbers must never cost the headline
             import traceback
             traceback.print_exc()

@@ -1,9 +1,10 @@
 // Global operators (Table 2): operators that read every pixel of an image
-// and produce a few values.  Each kernel streams the image once with one
-// 16-byte load per lane per step (a row split into 16-byte chunks across the
-// 256 threads of a work-group, rows strided over the grid), reduces inside
-// the wave with lane exchanges, and combines work-groups with one global
-// atomic per wave (per bin for the histogram).  The caller's result buffer is
+// and produce a few values.  Each kernel streams the image once in 16-byte
+// chunks (a row split into chunks across the 256 threads of a work-group,
+// four rows a grid size apart loaded together, so that every lane has four
+// independent loads in flight), reduces inside the wave with lane
+// exchanges, and combines work-groups with one global atomic per wave (per
+// bin for the histogram).  The caller's result buffer is
 // initialised by a small kernel in the same stream, so the sequence can be
 // captured into a HIP graph.
 #include <hip/hip_runtime.h>
@@ -16,7 +17,40 @@ namespace hvx {
 
 constexpr int kGThreads = 256;
 
-static int global_grid(const GlobalImg& im) { return im.h < 1024 ? im.h : 1024; }
+// Launch shapes, measured on a 16384 x 16384 image.  The histogram combines
+// work-groups through 256 different counters and runs best on many 256-thread
+// groups with two rows in flight.  Min/max and the sums combine through two
+// words each: same-address atomics serialise, so those kernels reduce a
+// whole 1024-thread group in LDS first and launch one group per CU.
+constexpr int kRThreads = 1024;
+constexpr int kRGroups = 256;
+
+static int global_grid(const GlobalImg& im, int rows_in_flight, int cap) {
+  const int g = (im.h + rows_in_flight - 1) / rows_in_flight;
+  return g < cap ? g : cap;
+}
+
+// Calls f(chunk, valid elements) for every 16-byte chunk of the image
+// (PER elements per chunk) that this thread of an NT-thread group reads.
+// Rows y, y + G, ..., y + (K - 1) G (G the grid size) are loaded together;
+// together the work-groups cover every row once.
+template <int PER, int NT, int K, class F>
+__device__ __forceinline__ void stream_image(const GlobalImg& im, F&& f) {
+  const int G = gridDim.x;
+  const int chunks = (im.w + PER - 1) / PER;
+  for (int y = blockIdx.x; y < im.h; y += K * G) {
+    for (int c = threadIdx.x; c < chunks; c += NT) {
+      uint4 q[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (y + k * G < im.h) q[k] = *(const uint4*)(im.base + (size_t)(y + k * G) * im.pitch + 16 * c);
+      const int n = min(PER, im.w - PER * c);
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (y + k * G < im.h) f(q[k], n);
+    }
+  }
+}
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t a, uint32_t b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -35,20 +69,15 @@ __global__ __launch_bounds__(kGThreads) void k_histogram(GlobalImg im, int num_b
   for (int k = t; k < (kGThreads / 64) * 256; k += kGThreads) (&sub[0][0])[k] = 0;
   lut[t] = (t >= offset && t < offset + range) ? (t - offset) * num_bins / range : -1;
   __syncthreads();
-  const int chunks = (im.w + 15) >> 4;
-  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
-    const uint8_t* row = im.base + (size_t)y * im.pitch;
-    for (int c = t; c < chunks; c += kGThreads) {
-      const uint4 q = *(const uint4*)(row + 16 * c);
-      const int n = min(16, im.w - 16 * c);
-      const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+  uint32_t* mine = sub[wv];
+  stream_image<16, kGThreads, 2>(im, [&](const uint4& q, int n) {
+    const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int b = lut[(wd[k >> 2] >> (8 * (k & 3))) & 0xFF];
-        if (k < n && b >= 0) atomicAdd(&sub[wv][b], 1u);
-      }
+    for (int k = 0; k < 16; ++k) {
+      const int b = lut[(wd[k >> 2] >> (8 * (k & 3))) & 0xFF];
+      if (k < n && b >= 0) atomicAdd(&mine[b], 1u);
     }
-  }
+  });
   __syncthreads();
   for (int b = t; b < num_bins; b += kGThreads) {
     uint32_t s = 0;
@@ -63,41 +92,48 @@ hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int r
   hipLaunchKernelGGL(k_fill_u32, dim3((num_bins + 255) / 256), dim3(256), 0, s, counts, num_bins, 0u, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
-  hipLaunchKernelGGL(k_histogram, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, num_bins, offset, range, counts);
+  hipLaunchKernelGGL(k_histogram, dim3(global_grid(im, 2, 2048)), dim3(kGThreads), 0, s, im, num_bins, offset, range,
+                     counts);
   return hipGetLastError();
 }
 
 // ---- smallest and largest element of a U8 or S16 image ------------------------
 template <bool S16>
-__global__ __launch_bounds__(kGThreads) void k_min_max(GlobalImg im, int32_t* __restrict__ out) {
+__global__ __launch_bounds__(kRThreads) void k_min_max(GlobalImg im, int32_t* __restrict__ out) {
   constexpr int kPer = S16 ? 8 : 16;  // elements per 16-byte chunk
+  __shared__ int part[2][kRThreads / 64];
   int mn = INT_MAX, mx = INT_MIN;
   const int t = threadIdx.x;
-  const int chunks = (im.w + kPer - 1) / kPer;
-  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
-    const uint8_t* row = im.base + (size_t)y * im.pitch;
-    for (int c = t; c < chunks; c += kGThreads) {
-      const uint4 q = *(const uint4*)(row + 16 * c);
-      const int n = min(kPer, im.w - kPer * c);
-      const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+  stream_image<kPer, kRThreads, 4>(im, [&](const uint4& q, int n) {
+    const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
-        if (k < n) {
-          mn = min(mn, v);
-          mx = max(mx, v);
-        }
+    for (int k = 0; k < kPer; ++k) {
+      const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
+      if (k < n) {
+        mn = min(mn, v);
+        mx = max(mx, v);
       }
     }
-  }
+  });
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     mn = min(mn, __shfl_xor(mn, off));
     mx = max(mx, __shfl_xor(mx, off));
   }
   if ((t & 63) == 0) {
-    atomicMin(&out[0], mn);
-    atomicMax(&out[1], mx);
+    part[0][t >> 6] = mn;
+    part[1][t >> 6] = mx;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kRThreads / 64; ++w) {
+      mn = min(mn, part[0][w]);
+      mx = max(mx, part[1][w]);
+    }
+    // the result only moves one way: a group that cannot improve it skips
+    // the atomic (a stale read only costs an unneeded atomic)
+    if (mn < __atomic_load_n(&out[0], __ATOMIC_RELAXED)) atomicMin(&out[0], mn);
+    if (mx > __atomic_load_n(&out[1], __ATOMIC_RELAXED)) atomicMax(&out[1], mx);
   }
 }
 
@@ -106,8 +142,9 @@ hipError_t launch_min_max(const GlobalImg& im, int32_t* min_max, hipStream_t s) 
                      (uint32_t)INT_MIN);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
-  if (im.bpp == 2) hipLaunchKernelGGL(k_min_max<true>, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, min_max);
-  else hipLaunchKernelGGL(k_min_max<false>, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, min_max);
+  const dim3 grid(global_grid(im, 4, kRGroups));
+  if (im.bpp == 2) hipLaunchKernelGGL(k_min_max<true>, grid, dim3(kRThreads), 0, s, im, min_max);
+  else hipLaunchKernelGGL(k_min_max<false>, grid, dim3(kRThreads), 0, s, im, min_max);
   return hipGetLastError();
 }
 
@@ -115,33 +152,37 @@ hipError_t launch_min_max(const GlobalImg& im, int32_t* min_max, hipStream_t s) 
 // Exact sums S1 = sum v and S2 = sum v^2 (64-bit), then one thread forms
 // mean = S1 / N and stddev = sqrt(S2 / N - mean^2) in double precision.
 // result: u64 S1, u64 S2, f32 mean, f32 stddev.
-__global__ __launch_bounds__(kGThreads) void k_sums(GlobalImg im, unsigned long long* __restrict__ sums) {
+__global__ __launch_bounds__(kRThreads) void k_sums(GlobalImg im, unsigned long long* __restrict__ sums) {
+  __shared__ unsigned long long part[2][kRThreads / 64];
   unsigned long long s1 = 0, s2 = 0;
   const int t = threadIdx.x;
-  const int chunks = (im.w + 15) >> 4;
-  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
-    const uint8_t* row = im.base + (size_t)y * im.pitch;
-    for (int c = t; c < chunks; c += kGThreads) {
-      const uint4 q = *(const uint4*)(row + 16 * c);
-      const int n = min(16, im.w - 16 * c);
-      const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
-      uint32_t a = 0, b = 0;  // at most 16 * 255^2 < 2^21
+  stream_image<16, kRThreads, 4>(im, [&](const uint4& q, int n) {
+    const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+    uint32_t a = 0, b = 0;  // at most 16 * 255^2 < 2^21
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const uint32_t v = k < n ? (wd[k >> 2] >> (8 * (k & 3))) & 0xFF : 0u;
-        a += v;
-        b += v * v;
-      }
-      s1 += a;
-      s2 += b;
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t v = k < n ? (wd[k >> 2] >> (8 * (k & 3))) & 0xFF : 0u;
+      a += v;
+      b += v * v;
     }
-  }
+    s1 += a;
+    s2 += b;
+  });
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     s1 += __shfl_xor(s1, off);
     s2 += __shfl_xor(s2, off);
   }
   if ((t & 63) == 0) {
+    part[0][t >> 6] = s1;
+    part[1][t >> 6] = s2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kRThreads / 64; ++w) {
+      s1 += part[0][w];
+      s2 += part[1][w];
+    }
     atomicAdd(&sums[0], s1);
     atomicAdd(&sums[1], s2);
   }
@@ -160,7 +201,8 @@ hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s)
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result, 6, 0u, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
-  hipLaunchKernelGGL(k_sums, dim3(global_grid(im)), dim3(kGThreads), 0, s, im, (unsigned long long*)result);
+  hipLaunchKernelGGL(k_sums, dim3(global_grid(im, 4, kRGroups)), dim3(kRThreads), 0, s, im,
+                     (unsigned long long*)result);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mean_std_final, dim3(1), dim3(64), 0, s, (unsigned long long*)result,
