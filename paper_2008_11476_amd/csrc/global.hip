@@ -59,23 +59,27 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t a, uint32_t
 
 // ---- histogram of a U8 image ------------------------------------------------
 // Bin of value v: (v - offset) * num_bins / range for offset <= v < offset +
-// range, none otherwise; looked up from a 256-entry table in LDS.  Each wave
-// counts into its own LDS sub-histogram (fewer collisions between waves).
+// range, none otherwise.  The division is a multiply-high by m = ceil(2^32 /
+// range) (0 for range 1), exact because (v - offset) * num_bins < 2^16 and
+// range <= 2^8.  Pixels outside the interval, and the bytes past the row's
+// end in its last chunk, go to a spare counter (index 256), so that every
+// lane adds for every byte without a branch.  Each wave counts into its own
+// LDS sub-histogram (fewer collisions between waves).
 __global__ __launch_bounds__(kGThreads) void k_histogram(GlobalImg im, int num_bins, int offset, int range,
-                                                         uint32_t* __restrict__ counts) {
-  __shared__ uint32_t sub[kGThreads / 64][256];
-  __shared__ int lut[256];
+                                                         uint32_t m, uint32_t* __restrict__ counts) {
+  constexpr int kSlots = 257;
+  __shared__ uint32_t sub[kGThreads / 64][kSlots];
   const int t = threadIdx.x, wv = t >> 6;
-  for (int k = t; k < (kGThreads / 64) * 256; k += kGThreads) (&sub[0][0])[k] = 0;
-  lut[t] = (t >= offset && t < offset + range) ? (t - offset) * num_bins / range : -1;
+  for (int k = t; k < (kGThreads / 64) * kSlots; k += kGThreads) (&sub[0][0])[k] = 0;
   __syncthreads();
   uint32_t* mine = sub[wv];
   stream_image<16, kGThreads, 2>(im, [&](const uint4& q, int n) {
     const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int b = lut[(wd[k >> 2] >> (8 * (k & 3))) & 0xFF];
-      if (k < n && b >= 0) atomicAdd(&mine[b], 1u);
+      const uint32_t x = ((wd[k >> 2] >> (8 * (k & 3))) & 0xFFu) - (uint32_t)offset;
+      const uint32_t b = __umulhi(x * (uint32_t)num_bins, m);
+      atomicAdd(&mine[(k < n && x < (uint32_t)range) ? b : 256u], 1u);
     }
   });
   __syncthreads();
@@ -92,7 +96,8 @@ hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int r
   hipLaunchKernelGGL(k_fill_u32, dim3((num_bins + 255) / 256), dim3(256), 0, s, counts, num_bins, 0u, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
-  hipLaunchKernelGGL(k_histogram, dim3(global_grid(im, 2, 2048)), dim3(kGThreads), 0, s, im, num_bins, offset, range,
+  const uint32_t m = range == 1 ? 0u : (uint32_t)((((uint64_t)1 << 32) + (uint64_t)range - 1) / (uint64_t)range);
+  hipLaunchKernelGGL(k_histogram, dim3(global_grid(im, 2, 2048)), dim3(kGThreads), 0, s, im, num_bins, offset, range, m,
                      counts);
   return hipGetLastError();
 }
