@@ -28,6 +28,13 @@ def min_max(img: np.ndarray) -> tuple:
     return int(img.min()), int(img.max())
 
 
+def min_max_count(img: np.ndarray) -> tuple:
+    """Smallest and largest pixel of a U8 or S16 image and how many pixels
+    take each value (the counts of MinMaxLoc)."""
+    mn, mx = min_max(img)
+    return mn, mx, int(np.count_nonzero(img == mn)), int(np.count_nonzero(img == mx))
+
+
 def mean_std_dev(img: np.ndarray) -> tuple:
     """Mean and population standard deviation of a U8 image, from the exact
     integer sums S1 = sum v and S2 = sum v^2 over N pixels: mean = S1 / N,

@@ -36,6 +36,18 @@ def test_min_max_brute_force():
         assert G.min_max(img) == (m, M)
 
 
+def test_min_max_count_brute_force():
+    img = np.array([[3, 9, 3], [9, 1, 9]], np.uint8)
+    assert G.min_max_count(img) == (1, 9, 1, 3)
+    const = np.full((4, 4), -5, np.int16)
+    assert G.min_max_count(const) == (-5, -5, 16, 16)
+    for dt, lo, hi in ((np.uint8, 0, 4), (np.int16, -3, 3)):
+        img = RNG.integers(lo, hi, (6, 5)).astype(dt)
+        flat = [int(x) for x in img.ravel()]
+        m, M = min(flat), max(flat)
+        assert G.min_max_count(img) == (m, M, sum(1 for x in flat if x == m), sum(1 for x in flat if x == M))
+
+
 def test_mean_std_dev_matches_numpy():
     mean, std, s1, s2 = G.mean_std_dev(IMG)
     assert mean == pytest.approx(float(np.mean(IMG, dtype=np.float64)), rel=1e-15)
