@@ -308,6 +308,7 @@ def global_ops(hvx, torch, ctx, stream, rec):
     gout = torch.zeros(512, dtype=torch.int64, device="cuda")
     gops = {"histogram256": lambda: hvx.hvx_histogram(ctx, gim, 256, 0, 256, gout.data_ptr(), stream),
             "min_max": lambda: hvx.hvx_min_max(ctx, gim, gout.data_ptr(), stream),
+            "min_max_count": lambda: hvx.hvx_min_max_count(ctx, gim, gout.data_ptr(), stream),
             "mean_std_dev": lambda: hvx.hvx_mean_std_dev(ctx, gim, gout.data_ptr(), stream)}
     gd = {"image": "16384x16384 U8, uniform random", "alg_bytes": gw * gh}
     for name, fn in gops.items():

@@ -257,6 +257,9 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
  *    range (integer division); other pixels are not counted.  Needs
  *    1 <= num_bins <= range and offset + range <= 256.
  *  min_max: U8 or S16 image; dev_min_max receives {smallest, largest}.
+ *  min_max_count: U8 or S16 image; dev_result receives {smallest, largest,
+ *    number of pixels equal to the smallest, number equal to the largest}
+ *    (the counts of MinMaxLoc; a second pass over the image).
  *  mean_std_dev: U8 image; dev_result (24 bytes, 8-byte aligned) receives
  *    the exact sums uint64 S1 = sum v and S2 = sum v^2, then float mean =
  *    S1 / N and float population standard deviation sqrt(S2 / N - mean^2),
@@ -264,6 +267,7 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
 hvx_status hvx_histogram(hvx_context ctx, hvx_image in, uint32_t num_bins, uint32_t offset, uint32_t range,
                          uint32_t* dev_counts, void* stream);
 hvx_status hvx_min_max(hvx_context ctx, hvx_image in, int32_t* dev_min_max, void* stream);
+hvx_status hvx_min_max_count(hvx_context ctx, hvx_image in, int32_t* dev_result, void* stream);
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream);
 
 /* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the

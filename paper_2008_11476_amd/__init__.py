@@ -85,6 +85,7 @@ def _load():
         "hvx_histogram": [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp],
         "hvx_min_max": [_vp, _vp, _vp, _vp],
         "hvx_mean_std_dev": [_vp, _vp, _vp, _vp],
+        "hvx_min_max_count": [_vp, _vp, _vp, _vp],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -276,6 +277,10 @@ def hvx_histogram(ctx, img, num_bins, offset, rng, dev_counts, stream=None):
 
 def hvx_min_max(ctx, img, dev_min_max, stream=None):
     _check(_load().hvx_min_max(ctx, img, dev_min_max, stream), ctx)
+
+
+def hvx_min_max_count(ctx, img, dev_result, stream=None):
+    _check(_load().hvx_min_max_count(ctx, img, dev_result, stream), ctx)
 
 
 def hvx_mean_std_dev(ctx, img, dev_result, stream=None):

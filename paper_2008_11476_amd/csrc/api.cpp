@@ -578,6 +578,14 @@ hvx_status hvx_min_max(hvx_context ctx, hvx_image in, int32_t* dev_min_max, void
   return launched(ctx, launch_min_max(gi, dev_min_max, (hipStream_t)stream));
 }
 
+hvx_status hvx_min_max_count(hvx_context ctx, hvx_image in, int32_t* dev_result, void* stream) {
+  GlobalImg gi;
+  hvx_status s = global_input(ctx, in, {DF_U8, DF_S16}, &gi);
+  if (s) return s;
+  if (!dev_result) return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "null result buffer");
+  return launched(ctx, launch_min_max_count(gi, dev_result, (hipStream_t)stream));
+}
+
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream) {
   GlobalImg gi;
   hvx_status s = global_input(ctx, in, {DF_U8}, &gi);

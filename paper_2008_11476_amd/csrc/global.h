@@ -16,6 +16,8 @@ struct GlobalImg {
 hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int range, uint32_t* counts,
                             hipStream_t s);
 hipError_t launch_min_max(const GlobalImg& im, int32_t* min_max, hipStream_t s);
+// min_max plus the counts of pixels equal to each: result[0..3]
+hipError_t launch_min_max_count(const GlobalImg& im, int32_t* result, hipStream_t s);
 hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s);
 
 }  // namespace hvx

@@ -142,6 +142,55 @@ __global__ __launch_bounds__(kRThreads) void k_min_max(GlobalImg im, int32_t* __
   }
 }
 
+// Pixels equal to the smallest and to the largest value, which the min/max
+// kernel left in mm[0], mm[1] earlier in the same stream; added to mm[2],
+// mm[3] (one atomic pair per group, after a group reduction in LDS).
+template <bool S16>
+__global__ __launch_bounds__(kRThreads) void k_count_extremes(GlobalImg im, int32_t* __restrict__ mm) {
+  constexpr int kPer = S16 ? 8 : 16;
+  __shared__ int part[2][kRThreads / 64];
+  const int lo = mm[0], hi = mm[1];
+  int cl = 0, ch = 0;
+  const int t = threadIdx.x;
+  stream_image<kPer, kRThreads, 4>(im, [&](const uint4& q, int n) {
+    const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
+      cl += (k < n && v == lo) ? 1 : 0;
+      ch += (k < n && v == hi) ? 1 : 0;
+    }
+  });
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    cl += __shfl_xor(cl, off);
+    ch += __shfl_xor(ch, off);
+  }
+  if ((t & 63) == 0) {
+    part[0][t >> 6] = cl;
+    part[1][t >> 6] = ch;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kRThreads / 64; ++w) {
+      cl += part[0][w];
+      ch += part[1][w];
+    }
+    if (cl) atomicAdd(&mm[2], cl);
+    if (ch) atomicAdd(&mm[3], ch);
+  }
+}
+
+hipError_t launch_min_max_count(const GlobalImg& im, int32_t* result, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result + 2, 2, 0u, 0u);
+  hipError_t e = launch_min_max(im, result, s);
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  const dim3 grid(global_grid(im, 4, kRGroups));
+  if (im.bpp == 2) hipLaunchKernelGGL(k_count_extremes<true>, grid, dim3(kRThreads), 0, s, im, result);
+  else hipLaunchKernelGGL(k_count_extremes<false>, grid, dim3(kRThreads), 0, s, im, result);
+  return hipGetLastError();
+}
+
 hipError_t launch_min_max(const GlobalImg& im, int32_t* min_max, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)min_max, 2, (uint32_t)INT_MAX,
                      (uint32_t)INT_MIN);

@@ -111,3 +111,21 @@ def test_global_ops_reject_bad_arguments(ctx):
         hvx.hvx_mean_std_dev(ctx, im, buf.data_ptr() + 4)
     with pytest.raises(hvx.HvxError):
         hvx.hvx_min_max(ctx, im, None)
+
+
+@pytest.mark.parametrize("w,h", SIZES)
+@pytest.mark.parametrize("dtype", [np.uint8, np.int16])
+def test_min_max_count(ctx, w, h, dtype):
+    """The MinMaxLoc counts: narrow values so that both extremes repeat,
+    and a constant image where they coincide."""
+    import torch
+    log("min_max_count %dx%d %s" % (w, h, np.dtype(dtype).name))
+    rng = np.random.default_rng(w + h)
+    df = hvx.HVX_DF_U8 if dtype == np.uint8 else hvx.HVX_DF_S16
+    for img in (rng.integers(-2 if dtype == np.int16 else 7, 12, (h, w)).astype(dtype),
+                np.full((h, w), 5, dtype)):
+        im, keep = device_image(ctx, img, df, seed=9)
+        out = torch.full((4,), 77, dtype=torch.int32, device="cuda")
+        hvx.hvx_min_max_count(ctx, im, out.data_ptr())
+        torch.cuda.synchronize()
+        assert tuple(out.cpu().tolist()) == G.min_max_count(img)
