@@ -28,6 +28,24 @@ def min_max(img: np.ndarray) -> tuple:
     return int(img.min()), int(img.max())
 
 
+def equalize_hist(img: np.ndarray) -> np.ndarray:
+    """EqualizeHist (Table 2) of a U8 image: with cdf(v) the number of pixels
+    <= v, cdf_min the smallest nonzero cdf value and N the pixel count, value v
+    maps to round((cdf(v) - cdf_min) * 255 / (N - cdf_min)) (halves up); an
+    image of one value is returned unchanged."""
+    if img.dtype != np.uint8 or img.size == 0:
+        raise ValueError("non-empty U8 image")
+    cdf = np.cumsum(np.bincount(img.ravel(), minlength=256)).astype(np.int64)
+    n = img.size
+    cmin = int(cdf[cdf > 0][0])
+    if n == cmin:
+        return img.copy()
+    num = (cdf - cmin) * 255
+    lut = (2 * num + (n - cmin)) // (2 * (n - cmin))
+    lut = np.clip(lut, 0, 255).astype(np.uint8)
+    return lut[img]
+
+
 def min_max_count(img: np.ndarray) -> tuple:
     """Smallest and largest pixel of a U8 or S16 image and how many pixels
     take each value (the counts of MinMaxLoc)."""

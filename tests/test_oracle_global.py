@@ -48,6 +48,21 @@ def test_min_max_count_brute_force():
         assert G.min_max_count(img) == (m, M, sum(1 for x in flat if x == m), sum(1 for x in flat if x == M))
 
 
+def test_equalize_hist_worked_example_and_properties():
+    # four values with counts 1, 2, 3, 2 (N = 8): cdf 1, 3, 6, 8, cdf_min 1, so the levels are
+    # round(0), round(2 * 255 / 7) = round(72.86), round(5 * 255 / 7) = round(182.14), 255
+    img = np.array([[10, 20, 20, 30], [30, 30, 40, 40]], np.uint8)
+    assert G.equalize_hist(img).tolist() == [[0, 73, 73, 182], [182, 182, 255, 255]]
+    # a half rounds up: N - cdf_min = 2, values 0 / 127.5 / 255
+    assert G.equalize_hist(np.array([[5, 6, 7]], np.uint8)).tolist() == [[0, 128, 255]]
+    const = np.full((3, 3), 42, np.uint8)
+    assert np.array_equal(G.equalize_hist(const), const)
+    out = G.equalize_hist(IMG)
+    order = np.argsort(IMG.ravel(), kind="stable")
+    assert np.all(np.diff(out.ravel()[order].astype(int)) >= 0)  # monotone in the input value
+    assert out.min() == 0 and out.max() == 255
+
+
 def test_mean_std_dev_matches_numpy():
     mean, std, s1, s2 = G.mean_std_dev(IMG)
     assert mean == pytest.approx(float(np.mean(IMG, dtype=np.float64)), rel=1e-15)
