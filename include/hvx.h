@@ -260,6 +260,12 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
  *  min_max_count: U8 or S16 image; dev_result receives {smallest, largest,
  *    number of pixels equal to the smallest, number equal to the largest}
  *    (the counts of MinMaxLoc; a second pass over the image).
+ *  equalize_hist: U8 image -> U8 image `out` of the same size (may be the
+ *    input).  With cdf(v) the pixels <= v, cdf_min the smallest nonzero
+ *    cdf and N the pixel count, v maps to round((cdf(v) - cdf_min) * 255 /
+ *    (N - cdf_min)), halves up; an image of one value is copied unchanged.
+ *    dev_workspace: 1280 bytes of device memory, 4-byte aligned (the
+ *    histogram and the mapping), used until the stream reaches the call.
  *  mean_std_dev: U8 image; dev_result (24 bytes, 8-byte aligned) receives
  *    the exact sums uint64 S1 = sum v and S2 = sum v^2, then float mean =
  *    S1 / N and float population standard deviation sqrt(S2 / N - mean^2),
@@ -268,6 +274,7 @@ hvx_status hvx_histogram(hvx_context ctx, hvx_image in, uint32_t num_bins, uint3
                          uint32_t* dev_counts, void* stream);
 hvx_status hvx_min_max(hvx_context ctx, hvx_image in, int32_t* dev_min_max, void* stream);
 hvx_status hvx_min_max_count(hvx_context ctx, hvx_image in, int32_t* dev_result, void* stream);
+hvx_status hvx_equalize_hist(hvx_context ctx, hvx_image in, hvx_image out, void* dev_workspace, void* stream);
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream);
 
 /* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the

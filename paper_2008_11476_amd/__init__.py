@@ -86,6 +86,7 @@ def _load():
         "hvx_min_max": [_vp, _vp, _vp, _vp],
         "hvx_mean_std_dev": [_vp, _vp, _vp, _vp],
         "hvx_min_max_count": [_vp, _vp, _vp, _vp],
+        "hvx_equalize_hist": [_vp, _vp, _vp, _vp, _vp],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -281,6 +282,10 @@ def hvx_min_max(ctx, img, dev_min_max, stream=None):
 
 def hvx_min_max_count(ctx, img, dev_result, stream=None):
     _check(_load().hvx_min_max_count(ctx, img, dev_result, stream), ctx)
+
+
+def hvx_equalize_hist(ctx, img, out, dev_workspace, stream=None):
+    _check(_load().hvx_equalize_hist(ctx, img, out, dev_workspace, stream), ctx)
 
 
 def hvx_mean_std_dev(ctx, img, dev_result, stream=None):

@@ -586,6 +586,19 @@ hvx_status hvx_min_max_count(hvx_context ctx, hvx_image in, int32_t* dev_result,
   return launched(ctx, launch_min_max_count(gi, dev_result, (hipStream_t)stream));
 }
 
+hvx_status hvx_equalize_hist(hvx_context ctx, hvx_image in, hvx_image out, void* dev_workspace, void* stream) {
+  GlobalImg gi, go;
+  hvx_status s = global_input(ctx, in, {DF_U8}, &gi);
+  if (s) return s;
+  s = global_input(ctx, out, {DF_U8}, &go);
+  if (s) return s;
+  Context* c = as<Context>(ctx, T_CONTEXT);
+  if (go.w != gi.w || go.h != gi.h) return set_error(c, HVX_ERROR_INVALID_DIMENSION, "output size differs from input");
+  if (!dev_workspace || ((uintptr_t)dev_workspace & 3))
+    return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "workspace null or not 4-byte aligned");
+  return launched(ctx, launch_equalize_hist(gi, (uint8_t*)go.base, go.pitch, dev_workspace, (hipStream_t)stream));
+}
+
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream) {
   GlobalImg gi;
   hvx_status s = global_input(ctx, in, {DF_U8}, &gi);

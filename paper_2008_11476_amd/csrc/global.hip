@@ -102,6 +102,75 @@ hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int r
   return hipGetLastError();
 }
 
+// ---- histogram equalisation of a U8 image ----------------------------------------
+// From the 256-bin histogram: cdf(v) by an LDS scan, cdf_min the cdf at the
+// first nonzero bin, and lut[v] = round((cdf(v) - cdf_min) * 255 / (N -
+// cdf_min)) clamped to 0..255, or v itself for an image of one value.
+__global__ __launch_bounds__(256) void k_eq_lut(const uint32_t* __restrict__ hist, uint8_t* __restrict__ lut,
+                                                 long long n) {
+  __shared__ unsigned long long cdf[256];
+  __shared__ int first;
+  const int t = threadIdx.x;
+  if (t == 0) first = 256;
+  cdf[t] = hist[t];
+  __syncthreads();
+  if (hist[t] != 0) atomicMin(&first, t);
+  for (int d = 1; d < 256; d <<= 1) {  // inclusive scan
+    const unsigned long long add = t >= d ? cdf[t - d] : 0ull;
+    __syncthreads();
+    cdf[t] += add;
+    __syncthreads();
+  }
+  const long long cmin = (long long)cdf[first < 256 ? first : 0];
+  const long long den = n - cmin;
+  int v = t;
+  if (den > 0) {
+    const long long num = ((long long)cdf[t] - cmin) * 255;
+    long long r = num >= 0 ? (2 * num + den) / (2 * den) : 0;
+    v = (int)(r > 255 ? 255 : r);
+  }
+  lut[t] = (uint8_t)v;
+}
+
+// out = lut[in], 16 bytes per lane per step; rows strided over the grid.  A
+// thread reads and writes the same chunk, so in place is allowed.
+__global__ __launch_bounds__(kGThreads) void k_apply_lut(GlobalImg im, const uint8_t* __restrict__ lut,
+                                                         uint8_t* out, int64_t out_pitch) {
+  __shared__ uint8_t tab[256];
+  tab[threadIdx.x] = lut[threadIdx.x];
+  __syncthreads();
+  const int chunks = (im.w + 15) >> 4;
+  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
+    const uint8_t* row = im.base + (size_t)y * im.pitch;
+    uint8_t* orow = out + (size_t)y * out_pitch;
+    for (int c = threadIdx.x; c < chunks; c += kGThreads) {
+      const uint4 q = *(const uint4*)(row + 16 * c);
+      const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+      uint32_t o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        o[j] = (uint32_t)tab[wd[j] & 0xFF] | (uint32_t)tab[(wd[j] >> 8) & 0xFF] << 8 |
+               (uint32_t)tab[(wd[j] >> 16) & 0xFF] << 16 | (uint32_t)tab[wd[j] >> 24] << 24;
+      }
+      *(uint4*)(orow + 16 * c) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+  }
+}
+
+hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_pitch, void* workspace,
+                                hipStream_t s) {
+  uint32_t* hist = (uint32_t*)workspace;
+  uint8_t* lut = (uint8_t*)workspace + 256 * 4;
+  hipError_t e = launch_histogram(im, 256, 0, 256, hist, s);
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  hipLaunchKernelGGL(k_eq_lut, dim3(1), dim3(256), 0, s, (const uint32_t*)hist, lut, (long long)im.w * im.h);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_apply_lut, dim3(im.h < 2048 ? im.h : 2048), dim3(kGThreads), 0, s, im, (const uint8_t*)lut,
+                     out, out_pitch);
+  return hipGetLastError();
+}
+
 // ---- smallest and largest element of a U8 or S16 image ------------------------
 template <bool S16>
 __global__ __launch_bounds__(kRThreads) void k_min_max(GlobalImg im, int32_t* __restrict__ out) {

@@ -129,3 +129,29 @@ def test_min_max_count(ctx, w, h, dtype):
         hvx.hvx_min_max_count(ctx, im, out.data_ptr())
         torch.cuda.synchronize()
         assert tuple(out.cpu().tolist()) == G.min_max_count(img)
+
+
+@pytest.mark.parametrize("w,h", SIZES)
+@pytest.mark.parametrize("kind", ["edge", "uniform", "narrow", "constant"])
+def test_equalize_hist(ctx, w, h, kind):
+    import torch
+    log("equalize_hist %dx%d %s" % (w, h, kind))
+    if kind == "narrow":
+        img = (synth.uniform_u8(w, h, seed=w) // 32 + 100).astype(np.uint8)
+    elif kind == "constant":
+        img = np.full((h, w), 77, np.uint8)
+    else:
+        img = _img(w, h, seed=h + 1, kind=kind)
+    want = G.equalize_hist(img)
+    im, keep = device_image(ctx, img, hvx.HVX_DF_U8, seed=11)
+    ob, ov = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+    om = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
+    ws = torch.full((320,), -1, dtype=torch.int32, device="cuda")
+    hvx.hvx_equalize_hist(ctx, im, om, ws.data_ptr())
+    hvx.hvx_equalize_hist(ctx, im, im, ws.data_ptr())  # in place
+    torch.cuda.synchronize()
+    assert np.array_equal(ov.cpu().numpy(), want)
+    got_in_place = keep.cpu().numpy()[:, :w]
+    assert np.array_equal(got_in_place, want)
+    with pytest.raises(hvx.HvxError):
+        hvx.hvx_equalize_hist(ctx, im, om, ws.data_ptr() + 2)
