@@ -53,6 +53,18 @@ def min_max_count(img: np.ndarray) -> tuple:
     return mn, mx, int(np.count_nonzero(img == mn)), int(np.count_nonzero(img == mx))
 
 
+def min_max_loc(img: np.ndarray) -> tuple:
+    """MinMaxLoc (Table 2): the extremes, their counts and the (x, y) of
+    every pixel equal to each (row-major order here; any order is a valid
+    answer)."""
+    mn, mx, cmin, cmax = min_max_count(img)
+    ys, xs = np.nonzero(img == mn)
+    lmin = [(int(x), int(y)) for y, x in zip(ys, xs)]
+    ys, xs = np.nonzero(img == mx)
+    lmax = [(int(x), int(y)) for y, x in zip(ys, xs)]
+    return mn, mx, cmin, cmax, lmin, lmax
+
+
 def mean_std_dev(img: np.ndarray) -> tuple:
     """Mean and population standard deviation of a U8 image, from the exact
     integer sums S1 = sum v and S2 = sum v^2 over N pixels: mean = S1 / N,

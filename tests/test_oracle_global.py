@@ -63,6 +63,16 @@ def test_equalize_hist_worked_example_and_properties():
     assert out.min() == 0 and out.max() == 255
 
 
+def test_min_max_loc_brute_force():
+    img = np.array([[3, 9, 3], [9, 1, 9]], np.uint8)
+    assert G.min_max_loc(img) == (1, 9, 1, 3, [(1, 1)], [(1, 0), (0, 1), (2, 1)])
+    img = RNG.integers(0, 3, (4, 6)).astype(np.int16)
+    mn, mx, cmin, cmax, lmin, lmax = G.min_max_loc(img)
+    assert sorted(lmin) == sorted((x, y) for y in range(4) for x in range(6) if img[y, x] == mn)
+    assert sorted(lmax) == sorted((x, y) for y in range(4) for x in range(6) if img[y, x] == mx)
+    assert len(lmin) == cmin and len(lmax) == cmax
+
+
 def test_mean_std_dev_matches_numpy():
     mean, std, s1, s2 = G.mean_std_dev(IMG)
     assert mean == pytest.approx(float(np.mean(IMG, dtype=np.float64)), rel=1e-15)
