@@ -260,6 +260,11 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
  *  min_max_count: U8 or S16 image; dev_result receives {smallest, largest,
  *    number of pixels equal to the smallest, number equal to the largest}
  *    (the counts of MinMaxLoc; a second pass over the image).
+ *  min_max_loc: as min_max_count, and the (x, y) of the pixels equal to
+ *    each extreme, two uint32 per location, into dev_min_locs / dev_max_locs
+ *    (capacity locations each; both may be NULL when capacity is 0).  When
+ *    an extreme occurs more than capacity times, capacity of its locations
+ *    are kept; which ones, and the order of any list, are unspecified.
  *  equalize_hist: U8 image -> U8 image `out` of the same size (may be the
  *    input).  With cdf(v) the pixels <= v, cdf_min the smallest nonzero
  *    cdf and N the pixel count, v maps to round((cdf(v) - cdf_min) * 255 /
@@ -274,6 +279,8 @@ hvx_status hvx_histogram(hvx_context ctx, hvx_image in, uint32_t num_bins, uint3
                          uint32_t* dev_counts, void* stream);
 hvx_status hvx_min_max(hvx_context ctx, hvx_image in, int32_t* dev_min_max, void* stream);
 hvx_status hvx_min_max_count(hvx_context ctx, hvx_image in, int32_t* dev_result, void* stream);
+hvx_status hvx_min_max_loc(hvx_context ctx, hvx_image in, int32_t* dev_result, uint32_t* dev_min_locs,
+                           uint32_t* dev_max_locs, uint32_t capacity, void* stream);
 hvx_status hvx_equalize_hist(hvx_context ctx, hvx_image in, hvx_image out, void* dev_workspace, void* stream);
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream);
 

@@ -87,6 +87,7 @@ def _load():
         "hvx_mean_std_dev": [_vp, _vp, _vp, _vp],
         "hvx_min_max_count": [_vp, _vp, _vp, _vp],
         "hvx_equalize_hist": [_vp, _vp, _vp, _vp, _vp],
+        "hvx_min_max_loc": [_vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -282,6 +283,10 @@ def hvx_min_max(ctx, img, dev_min_max, stream=None):
 
 def hvx_min_max_count(ctx, img, dev_result, stream=None):
     _check(_load().hvx_min_max_count(ctx, img, dev_result, stream), ctx)
+
+
+def hvx_min_max_loc(ctx, img, dev_result, dev_min_locs, dev_max_locs, capacity, stream=None):
+    _check(_load().hvx_min_max_loc(ctx, img, dev_result, dev_min_locs, dev_max_locs, capacity, stream), ctx)
 
 
 def hvx_equalize_hist(ctx, img, out, dev_workspace, stream=None):

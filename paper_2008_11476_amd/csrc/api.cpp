@@ -586,6 +586,16 @@ hvx_status hvx_min_max_count(hvx_context ctx, hvx_image in, int32_t* dev_result,
   return launched(ctx, launch_min_max_count(gi, dev_result, (hipStream_t)stream));
 }
 
+hvx_status hvx_min_max_loc(hvx_context ctx, hvx_image in, int32_t* dev_result, uint32_t* dev_min_locs,
+                           uint32_t* dev_max_locs, uint32_t capacity, void* stream) {
+  GlobalImg gi;
+  hvx_status s = global_input(ctx, in, {DF_U8, DF_S16}, &gi);
+  if (s) return s;
+  if (!dev_result || (capacity && (!dev_min_locs || !dev_max_locs)))
+    return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "null result or location buffer");
+  return launched(ctx, launch_min_max_loc(gi, dev_result, dev_min_locs, dev_max_locs, capacity, (hipStream_t)stream));
+}
+
 hvx_status hvx_equalize_hist(hvx_context ctx, hvx_image in, hvx_image out, void* dev_workspace, void* stream) {
   GlobalImg gi, go;
   hvx_status s = global_input(ctx, in, {DF_U8}, &gi);

@@ -18,6 +18,9 @@ hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int r
 hipError_t launch_min_max(const GlobalImg& im, int32_t* min_max, hipStream_t s);
 // min_max plus the counts of pixels equal to each: result[0..3]
 hipError_t launch_min_max_count(const GlobalImg& im, int32_t* result, hipStream_t s);
+// min_max_count plus up to `cap` (x, y) locations of each extreme
+hipError_t launch_min_max_loc(const GlobalImg& im, int32_t* result, uint32_t* lmin, uint32_t* lmax, uint32_t cap,
+                              hipStream_t s);
 // histogram equalisation into `out` (same size, U8); workspace: 1280 bytes
 hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_pitch, void* workspace,
                                 hipStream_t s);

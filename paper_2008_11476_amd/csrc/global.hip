@@ -250,6 +250,79 @@ __global__ __launch_bounds__(kRThreads) void k_count_extremes(GlobalImg im, int3
   }
 }
 
+// MinMaxLoc: the (x, y) of every pixel equal to mm[0] (into lmin) and to
+// mm[1] (into lmax), two words per location, the first `cap` of each list
+// kept, in no particular order; mm[2], mm[3] receive the full counts.  Each
+// lane marks the matches of its 16-byte chunk; a scan across the wave gives
+// each lane its offset and one atomic per wave and list reserves the slots.
+// The chunk loop steps on a wave-uniform base so every lane takes part in
+// the lane exchanges.
+template <bool S16>
+__global__ __launch_bounds__(kGThreads) void k_extreme_locs(GlobalImg im, int32_t* __restrict__ mm,
+                                                            uint32_t* __restrict__ lmin, uint32_t* __restrict__ lmax,
+                                                            uint32_t cap) {
+  constexpr int kPer = S16 ? 8 : 16;
+  const int lo = mm[0], hi = mm[1];
+  const int t = threadIdx.x, lane = t & 63;
+  const int chunks = (im.w + kPer - 1) / kPer;
+  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
+    const uint8_t* row = im.base + (size_t)y * im.pitch;
+    for (int cb = t & ~63; cb < chunks; cb += kGThreads) {
+      const int c = cb + lane;
+      uint32_t ml = 0, mh = 0;
+      if (c < chunks) {
+        const uint4 q = *(const uint4*)(row + 16 * c);
+        const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+        const int n = min(kPer, im.w - kPer * c);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+          const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
+          ml |= (k < n && v == lo) ? 1u << k : 0u;
+          mh |= (k < n && v == hi) ? 1u << k : 0u;
+        }
+      }
+#pragma unroll
+      for (int list = 0; list < 2; ++list) {
+        uint32_t m = list ? mh : ml;
+        const int cnt = __popc(m);
+        int inc = cnt;  // inclusive scan across the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int u = __shfl_up(inc, off);
+          if (lane >= off) inc += u;
+        }
+        const int total = __shfl(inc, 63);
+        if (total == 0) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&mm[2 + list], total);
+        base = __shfl(base, 0);
+        uint32_t i = (uint32_t)(base + inc - cnt);
+        uint32_t* out = list ? lmax : lmin;
+        while (m) {
+          const int k = __ffs(m) - 1;
+          m &= m - 1;
+          if (i < cap) {
+            out[2 * i] = (uint32_t)(kPer * c + k);
+            out[2 * i + 1] = (uint32_t)y;
+          }
+          ++i;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_min_max_loc(const GlobalImg& im, int32_t* result, uint32_t* lmin, uint32_t* lmax, uint32_t cap,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result + 2, 2, 0u, 0u);
+  hipError_t e = launch_min_max(im, result, s);
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  const dim3 grid(im.h < 2048 ? im.h : 2048);
+  if (im.bpp == 2) hipLaunchKernelGGL(k_extreme_locs<true>, grid, dim3(kGThreads), 0, s, im, result, lmin, lmax, cap);
+  else hipLaunchKernelGGL(k_extreme_locs<false>, grid, dim3(kGThreads), 0, s, im, result, lmin, lmax, cap);
+  return hipGetLastError();
+}
+
 hipError_t launch_min_max_count(const GlobalImg& im, int32_t* result, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result + 2, 2, 0u, 0u);
   hipError_t e = launch_min_max(im, result, s);

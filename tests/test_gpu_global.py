@@ -155,3 +155,33 @@ def test_equalize_hist(ctx, w, h, kind):
     assert np.array_equal(got_in_place, want)
     with pytest.raises(hvx.HvxError):
         hvx.hvx_equalize_hist(ctx, im, om, ws.data_ptr() + 2)
+
+
+@pytest.mark.parametrize("w,h", SIZES)
+@pytest.mark.parametrize("dtype", [np.uint8, np.int16])
+def test_min_max_loc(ctx, w, h, dtype):
+    """Locations compared as sets when they fit; when an extreme occurs more
+    often than the capacity, every kept location must hold the extreme and
+    be distinct.  Counts are always the full counts."""
+    import torch
+    log("min_max_loc %dx%d %s" % (w, h, np.dtype(dtype).name))
+    rng = np.random.default_rng(3 * w + h)
+    df = hvx.HVX_DF_U8 if dtype == np.uint8 else hvx.HVX_DF_S16
+    for img in (rng.integers(0, 200, (h, w)).astype(dtype), rng.integers(-1 if dtype == np.int16 else 4, 9,
+                                                                          (h, w)).astype(dtype)):
+        mn, mx, cmin, cmax, lmin, lmax = G.min_max_loc(img)
+        cap = min(w * h, 5000)
+        im, keep = device_image(ctx, img, df, seed=13)
+        res = torch.full((4,), 99, dtype=torch.int32, device="cuda")
+        lmn = torch.full((2 * cap,), -1, dtype=torch.int32, device="cuda")
+        lmx = torch.full((2 * cap,), -1, dtype=torch.int32, device="cuda")
+        hvx.hvx_min_max_loc(ctx, im, res.data_ptr(), lmn.data_ptr(), lmx.data_ptr(), cap)
+        torch.cuda.synchronize()
+        assert tuple(res.cpu().tolist()) == (mn, mx, cmin, cmax)
+        for got, want, val, cnt in ((lmn, lmin, mn, cmin), (lmx, lmax, mx, cmax)):
+            pts = [tuple(p) for p in got.cpu().numpy().reshape(-1, 2)[:min(cnt, cap)].tolist()]
+            if cnt <= cap:
+                assert sorted(pts) == sorted(want)
+            else:
+                assert len(set(pts)) == cap
+                assert all(0 <= x < w and 0 <= y < h and img[y, x] == val for x, y in pts)
