@@ -313,6 +313,9 @@ def _run_node(n: Node, env: dict):
     elif n.op == "custom_point":
         from . import custom
         res = [custom.evaluate(p["expr"], ins, p["out_dtype"])]
+    elif n.op == "custom_local":
+        from . import custom
+        res = [custom.evaluate_local(p["expr"], ins[0], p["out_dtype"], b, c)]
     else:
         raise ValueError("unknown op " + n.op)
     for name, val in zip(n.outputs, res):
@@ -336,6 +339,15 @@ def _radius(n: Node) -> tuple:
     if n.op == "nonmax":
         r = n.params.get("win", 3) // 2
         return r, r
+    if n.op == "custom_local":
+        import ast
+        from . import custom
+        rx = ry = 0
+        for node in ast.walk(custom.check(n.params["expr"], 1, True, local=True)):
+            if isinstance(node, ast.Subscript):
+                dx, dy = custom._offset(node)
+                rx, ry = max(rx, abs(dx)), max(ry, abs(dy))
+        return rx, ry
     r = RADIUS.get(n.op, 0)
     return r, r
 

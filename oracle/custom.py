@@ -13,6 +13,10 @@ usual precedence and parentheses, and the functions ``min(x, y)``,
 ``gt(x, y)`` (1 where x > y, else 0), ``sel(p, x, y)`` (x where p != 0, else
 y) and ``sqrt(x)`` (float kernels only).
 
+A user local kernel has one input ``a`` and may also read it at offsets
+``a[dx, dy]`` (integers, |dx|, |dy| <= 2; ``a`` alone is ``a[0, 0]``); the
+positions outside the image follow the node's border mode.
+
 Integer kernels (every input U8/S16, output U8/S16) compute in 32-bit two's
 complement: + - * and negation wrap modulo 2^32, / truncates toward zero,
 x / 0 = 0 and the one overflowing quotient (-2^31) / (-1) wraps to -2^31.
@@ -34,8 +38,27 @@ def _wrap(x):
     return ((x + 2 ** 31) % 2 ** 32) - 2 ** 31
 
 
-def check(expr: str, nin: int, is_float: bool):
-    """Raise ValueError unless ``expr`` is in the grammar for ``nin`` inputs."""
+def _offset(n):
+    """(dx, dy) of a subscript a[dx, dy] with integer literals in [-2, 2]."""
+    sl = n.slice
+    if not isinstance(sl, ast.Tuple) or len(sl.elts) != 2:
+        raise ValueError("a[dx, dy] takes two offsets")
+    out = []
+    for e in sl.elts:
+        neg = isinstance(e, ast.UnaryOp) and isinstance(e.op, ast.USub)
+        v = e.operand if neg else e
+        if not isinstance(v, ast.Constant) or isinstance(v.value, bool) or not isinstance(v.value, int):
+            raise ValueError("offsets are integer literals")
+        k = -v.value if neg else v.value
+        if not -2 <= k <= 2:
+            raise ValueError("offsets within -2..2")
+        out.append(k)
+    return tuple(out)
+
+
+def check(expr: str, nin: int, is_float: bool, local: bool = False):
+    """Raise ValueError unless ``expr`` is in the grammar for ``nin`` inputs
+    (a local kernel: one input, offsets allowed)."""
     try:
         tree = ast.parse(expr, mode="eval")
     except SyntaxError as e:
@@ -60,6 +83,10 @@ def check(expr: str, nin: int, is_float: bool):
                 raise ValueError("sqrt needs a float kernel")
             for x in n.args:
                 walk(x)
+        elif isinstance(n, ast.Subscript):
+            if not local or not isinstance(n.value, ast.Name) or n.value.id != "a":
+                raise ValueError("offsets only on input a of a local kernel")
+            _offset(n)
         elif isinstance(n, ast.Name):
             if n.id not in INPUTS[:nin]:
                 raise ValueError("unknown name %s" % n.id)
@@ -75,6 +102,54 @@ def check(expr: str, nin: int, is_float: bool):
     return tree.body
 
 
+_PAD = {"replicate": "edge", "undefined": "edge", "mirror": "reflect", "repeat": "wrap"}
+
+
+def evaluate_local(expr: str, img: np.ndarray, out_dtype, border="replicate", c=0) -> np.ndarray:
+    """A user local kernel over one image: every a[dx, dy] reads the image
+    shifted by (dx, dy), positions outside it taken by the border mode
+    (numpy's edge / reflect / wrap padding for REPLICATE / MIRROR / REPEAT,
+    the constant for CONSTANT; UNDEFINED as REPLICATE, its border pixels
+    being unspecified)."""
+    f32_out = np.dtype(out_dtype).kind == "f"
+    is_float = img.dtype.kind == "f" or f32_out
+    tree = check(expr, 1, is_float, local=True)
+    h, w = img.shape
+    pad = img
+    for axis, n in ((0, h), (1, w)):
+        widths = ((2, 2), (0, 0)) if axis == 0 else ((0, 0), (2, 2))
+        if border == "constant":
+            pad = np.pad(pad, widths, mode="constant", constant_values=c)
+        elif border == "mirror" and n == 1:  # a one-pixel axis repeats its pixel
+            pad = np.pad(pad, widths, mode="edge")
+        else:
+            pad = np.pad(pad, widths, mode=_PAD[border])
+
+    def shifted(dx, dy):
+        return pad[2 + dy:2 + dy + h, 2 + dx:2 + dx + w]
+
+    offs = {}
+
+    def walk(n):
+        if isinstance(n, ast.Subscript):
+            offs[id(n)] = _offset(n)
+        for ch in ast.iter_child_nodes(n):
+            walk(ch)
+
+    walk(tree)
+
+    class Sub(ast.NodeTransformer):
+        def visit_Subscript(self, n):
+            dx, dy = offs[id(n)]
+            return ast.copy_location(ast.Name(id="w_%d_%d" % (dx + 2, dy + 2), ctx=ast.Load()), n)
+
+    names = {}
+    for dx in range(-2, 3):
+        for dy in range(-2, 3):
+            names["w_%d_%d" % (dx + 2, dy + 2)] = shifted(dx, dy)
+    return _run(Sub().visit(tree), {"a": img, **names}, shape=img.shape, is_float=is_float, out_dtype=out_dtype)
+
+
 def evaluate(expr: str, inputs: list, out_dtype) -> np.ndarray:
     """Evaluate ``expr`` over the input images (numpy arrays of one shape:
     uint8 / int16, or a float type standing for F32).  ``out_dtype``:
@@ -84,8 +159,11 @@ def evaluate(expr: str, inputs: list, out_dtype) -> np.ndarray:
     if is_float and not f32_out:
         raise ValueError("a float kernel has an F32 output")
     tree = check(expr, len(inputs), is_float)
-    env = {INPUTS[i]: (x.astype(np.float64) if is_float else x.astype(np.int64)) for i, x in enumerate(inputs)}
-    shape = inputs[0].shape
+    return _run(tree, {INPUTS[i]: x for i, x in enumerate(inputs)}, inputs[0].shape, is_float, out_dtype)
+
+
+def _run(tree, images: dict, shape, is_float: bool, out_dtype):
+    env = {k: (x.astype(np.float64) if is_float else x.astype(np.int64)) for k, x in images.items()}
 
     def ev(n):
         if isinstance(n, ast.Constant):

@@ -74,3 +74,33 @@ def test_grammar_rejects(expr, nin, flt):
 def test_float_kernel_needs_f32_output():
     with pytest.raises(ValueError):
         custom.evaluate("a", [np.zeros((2, 2))], np.uint8)
+
+
+SOBEL_X = "a[1, -1] + 2 * a[1, 0] + a[1, 1] - a[-1, -1] - 2 * a[-1, 0] - a[-1, 1]"
+GAUSS3 = "(a[-1, -1] + 2 * a[0, -1] + a[1, -1] + 2 * a[-1, 0] + 4 * a + 2 * a[1, 0] + a[-1, 1] + 2 * a[0, 1] + a[1, 1]) / 16"
+
+
+@pytest.mark.parametrize("border,c", [("replicate", 0), ("constant", 0), ("constant", 77), ("mirror", 0),
+                                      ("repeat", 0)])
+@pytest.mark.parametrize("h,w", [(9, 13), (2, 3), (1, 5)])
+def test_local_kernel_matches_the_c_oracle_stencils(border, c, h, w):
+    """A user local kernel written as the Sobel gx or the Gaussian3x3 stencil
+    equals the C oracle's node at every border (numpy padding here, the C
+    oracle's own border fetch there)."""
+    import oracle
+    img = np.random.default_rng(h * w).integers(0, 256, (h, w), dtype=np.uint8)
+    gx, _ = oracle.sobel3x3(img, border, c)
+    assert np.array_equal(custom.evaluate_local(SOBEL_X, img, np.int16, border, c), gx)
+    assert np.array_equal(custom.evaluate_local(GAUSS3, img, np.uint8, border, c), oracle.gaussian3x3(img, border, c))
+
+
+def test_local_kernel_grammar():
+    with pytest.raises(ValueError):
+        custom.check("a[3, 0]", 1, False, local=True)
+    with pytest.raises(ValueError):
+        custom.check("a[1]", 1, False, local=True)
+    with pytest.raises(ValueError):
+        custom.check("a[1, 0]", 1, False, local=False)
+    with pytest.raises(ValueError):
+        custom.check("b[1, 0]", 2, False, local=True)
+    custom.check("a[-2, 2] - a", 1, False, local=True)
