@@ -284,6 +284,15 @@ hvx_status hvx_min_max_loc(hvx_context ctx, hvx_image in, int32_t* dev_result, u
 hvx_status hvx_equalize_hist(hvx_context ctx, hvx_image in, hvx_image out, void* dev_workspace, void* stream);
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream);
 
+/* User-defined local kernel (Section 5.1): `expr` over one input image a in
+ * the grammar of hvx_custom_point_node, where a[dx, dy] (one-digit integer
+ * offsets, |dx|, |dy| <= 2) reads the input at (x + dx, y + dy) and a alone
+ * is a[0, 0].  Positions outside the image follow the node's border mode
+ * (hvx_node_set_border).  The node is fused like the built-in local
+ * operators; its window is read at run-time offsets by the generic kernels. */
+hvx_status hvx_custom_local_node(hvx_graph g, const char* expr, hvx_image in, int out_format, hvx_image out,
+                                 hvx_node* node_out);
+
 /* Border mode of a node's inputs (default REPLICATE).  For CONSTANT the
  * value is read as the input's element type (0..255 for U8). */
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value);

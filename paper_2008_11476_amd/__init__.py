@@ -82,6 +82,7 @@ def _load():
         "hvx_nonlinear_filter_node": [_vp, ctypes.c_int, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _P(_vp)],
         "hvx_non_max_suppression_node": [_vp, _vp, ctypes.c_uint32, _vp, _P(_vp)],
         "hvx_custom_point_node": [_vp, ctypes.c_char_p, _P(_vp), ctypes.c_uint32, ctypes.c_int, _vp, _P(_vp)],
+        "hvx_custom_local_node": [_vp, ctypes.c_char_p, _vp, ctypes.c_int, _vp, _P(_vp)],
         "hvx_histogram": [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp],
         "hvx_min_max": [_vp, _vp, _vp, _vp],
         "hvx_mean_std_dev": [_vp, _vp, _vp, _vp],
@@ -295,6 +296,11 @@ def hvx_equalize_hist(ctx, img, out, dev_workspace, stream=None):
 
 def hvx_mean_std_dev(ctx, img, dev_result, stream=None):
     _check(_load().hvx_mean_std_dev(ctx, img, dev_result, stream), ctx)
+
+
+def hvx_custom_local_node(g, expr, i, out_format, o, ctx=None):
+    """User local kernel: `expr` over the window of image `i` (a[dx, dy])."""
+    return _node("hvx_custom_local_node", ctx, g, expr.encode(), i, out_format, o)
 
 
 def hvx_box5x5_f32_node(g, i, o, ctx=None):

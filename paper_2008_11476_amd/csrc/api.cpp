@@ -522,6 +522,8 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
   if (prog.max_input >= (int)num_inputs)
     return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "expression names input %c of %u", 'a' + prog.max_input,
                      num_inputs);
+  if (prog.has_offsets)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "window offsets need a user local kernel");
   Node* n = nullptr;
   hvx_status s = num_inputs == 1   ? add_node(g, NK_CUSTOM_POINT, {inputs[0]}, {out}, 1, no, &n)
                  : num_inputs == 2 ? add_node(g, NK_CUSTOM_POINT, {inputs[0], inputs[1]}, {out}, 1, no, &n)
@@ -616,6 +618,25 @@ hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, voi
   if (!dev_result || ((uintptr_t)dev_result & 7))
     return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "result buffer null or not 8-byte aligned");
   return launched(ctx, launch_mean_std_dev(gi, dev_result, (hipStream_t)stream));
+}
+
+hvx_status hvx_custom_local_node(hvx_graph g, const char* expr, hvx_image in, int out_format, hvx_image out,
+                                 hvx_node* no) {
+  Graph* gg = as<Graph>(g, T_GRAPH);
+  if (!gg) return HVX_ERROR_INVALID_REFERENCE;
+  if (out_format != HVX_DF_U8 && out_format != HVX_DF_S16 && out_format != HVX_DF_F32)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_FORMAT, "output format must be U8, S16 or F32");
+  ExprProg prog;
+  std::string why = parse_expr(expr, &prog);
+  if (!why.empty()) return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "expression: %s", why.c_str());
+  if (prog.max_input > 0)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "a user local kernel has one input, a");
+  Node* n = nullptr;
+  hvx_status s = add_node(g, NK_CUSTOM_LOCAL, {in}, {out}, 1, no, &n);
+  if (s) return s;
+  n->expr = std::move(prog);
+  n->out_df = out_format;
+  return HVX_SUCCESS;
 }
 
 hvx_status hvx_node_set_border(hvx_node node, int border, uint32_t constant_value) {

@@ -110,14 +110,15 @@ __host__ __device__ inline bool is_point_op(int kind) {
          kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS || kind == OP_EXPR;
 }
 
-// A user point kernel (Section 5.1) at one pixel: its postfix program over
-// the input elements a, b, c (int bits; F32 inputs as bit patterns, marked in
-// o.p2).  Integer kernels compute in 32-bit two's complement: + - * and
+// A user kernel (Section 5.1) at one pixel: its postfix program.  in(op,
+// arg) returns an input element (int bits; F32 inputs as bit patterns, marked
+// in o.p2): for X_IN input `arg`, for X_INW input a at a window offset.  Integer kernels compute in 32-bit two's complement: + - * and
 // negation wrap, / truncates toward zero, x / 0 = 0 and INT_MIN / -1 wraps
 // to INT_MIN; the result saturates to the output type.  Float kernels
 // (o.p1) compute in F32 and return F32 bits.  Every lane runs the same
 // program, so the stack position is uniform across the wave.
-__device__ __forceinline__ int expr_eval(const GOp& o, int out_df, int a, int b, int c) {
+template <class IN>
+__device__ __forceinline__ int expr_run(const GOp& o, int out_df, const IN& in) {
   const int n = o.p0;
   if (o.p1) {
     float st[kExprStack];
@@ -125,9 +126,10 @@ __device__ __forceinline__ int expr_eval(const GOp& o, int out_df, int a, int b,
     for (int k = 0; k < n; ++k) {
       const int op = o.code[k] & 0xFF, arg = o.code[k] >> 8;
       switch (op) {
-        case X_IN: {
-          const int v = arg == 0 ? a : (arg == 1 ? b : c);
-          st[sp++] = ((o.p2 >> arg) & 1) ? __int_as_float(v) : (float)v;
+        case X_IN:
+        case X_INW: {
+          const int v = in(op, arg);
+          st[sp++] = ((o.p2 >> (op == X_IN ? arg : 0)) & 1) ? __int_as_float(v) : (float)v;
           break;
         }
         case X_CONST: st[sp++] = __int_as_float(o.kc[arg]); break;
@@ -152,7 +154,8 @@ __device__ __forceinline__ int expr_eval(const GOp& o, int out_df, int a, int b,
   for (int k = 0; k < n; ++k) {
     const int op = o.code[k] & 0xFF, arg = o.code[k] >> 8;
     switch (op) {
-      case X_IN: st[sp++] = arg == 0 ? a : (arg == 1 ? b : c); break;
+      case X_IN:
+      case X_INW: st[sp++] = in(op, arg); break;
       case X_CONST: st[sp++] = o.kc[arg]; break;
       case X_ADD: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] + (uint32_t)st[sp]); break;
       case X_SUB: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] - (uint32_t)st[sp]); break;
@@ -175,6 +178,22 @@ __device__ __forceinline__ int expr_eval(const GOp& o, int out_df, int a, int b,
   const int r = st[0];
   return out_df == DF_U8 ? min(max(r, 0), 255) : min(max(r, -32768), 32767);
 }
+
+__device__ __forceinline__ int expr_eval(const GOp& o, int out_df, int a, int b, int c) {
+  return expr_run(o, out_df, [&](int, int arg) { return arg == 0 ? a : (arg == 1 ? b : c); });
+}
+
+// Readers whose offsets may be run-time values (the tile reader) declare
+// kAnyOffset; the one-operator local kernel's window reader takes constant
+// offsets only, so user local kernels are compiled into the tile path alone.
+template <class T, class = void>
+struct any_offset {
+  static constexpr bool value = false;
+};
+template <class T>
+struct any_offset<T, decltype((void)T::kAnyOffset)> {
+  static constexpr bool value = true;
+};
 
 // A point operator (Section 4) on one pixel: a, b, c are its input elements
 // (int bits; F32 as bit patterns; a UYVY input as its 16-bit U/V,Y pair),
@@ -330,6 +349,10 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
       const int mm = max(min(md[0], md[1]), min(max(md[0], md[1]), md[2]));
       return max(min(lo, mm), min(max(lo, mm), hi));
     }
+    case OP_EXPR_LOCAL:
+      if constexpr (any_offset<RD>::value)
+        return expr_run(o, out_df, [&](int op, int arg) { return op == X_IN ? rd(0, 0) : rd(arg % 5 - 2, arg / 5 - 2); });
+      break;
     case OP_NONLINEAR:
       // compiled only into the kernels built for it: its window and counters
       // would otherwise set the register budget of every generic kernel
@@ -399,13 +422,15 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
 }
 
 __host__ __device__ inline int local_radius(int kind) {
-  return (kind == OP_GAUSS5 || kind == OP_BOX5F || kind == OP_CONVOLVE || kind == OP_NONLINEAR || kind == OP_NONMAX)
+  return (kind == OP_GAUSS5 || kind == OP_BOX5F || kind == OP_CONVOLVE || kind == OP_NONLINEAR || kind == OP_NONMAX ||
+          kind == OP_EXPR_LOCAL)
              ? 2
              : 1;
 }
 
 // reads value `vi` of a tile as operator `o` sees it
 struct TileRd {
+  static constexpr bool kAnyOffset = true;
   const TileCtx* t;
   const GOp* o;
   int vi, x, y;

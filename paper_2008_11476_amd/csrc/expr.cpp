@@ -3,7 +3,9 @@
 //   sum     := product (('+' | '-') product)*
 //   product := unary (('*' | '/') unary)*
 //   unary   := '-' unary | primary
-//   primary := number | 'a' | 'b' | 'c' | name '(' sum (',' sum)* ')' | '(' sum ')'
+//   primary := number | 'a' | 'b' | 'c' | 'a' '[' offset ',' offset ']'
+//            | name '(' sum (',' sum)* ')' | '(' sum ')'
+//   offset  := ['-'] digit          (-2 .. 2; a local kernel's window read)
 //
 // Functions: min, max (2), abs (1), clamp (3), gt (2), sel (3), sqrt (1).
 // The program keeps at most kExprStack values on its stack and holds at most
@@ -14,6 +16,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+
+#include <algorithm>
 
 namespace hvx {
 
@@ -86,7 +90,31 @@ struct Parser {
     if (name == "a" || name == "b" || name == "c") {
       int k = name[0] - 'a';
       if (k > p->max_input) p->max_input = k;
-      return emit(X_IN, k, 0, 1);
+      ws();
+      if (s[i] != '[') return emit(X_IN, k, 0, 1);
+      if (k != 0) return fail("offsets only on input a");
+      ++i;
+      int off[2];
+      for (int j = 0; j < 2; ++j) {
+        ws();
+        bool neg = false;
+        if (s[i] == '-') {
+          neg = true;
+          ++i;
+          ws();
+        }
+        if (!isdigit((unsigned char)s[i]) || isdigit((unsigned char)s[i + 1])) return fail("offset must be one digit");
+        off[j] = (s[i] - '0') * (neg ? -1 : 1);
+        ++i;
+        if (off[j] < -2 || off[j] > 2) return fail("offset outside -2..2");
+        ws();
+        if (s[i] != (j == 0 ? ',' : ']')) return fail(j == 0 ? "',' expected in a[dx, dy]" : "']' expected");
+        ++i;
+      }
+      p->has_offsets = true;
+      p->rx = std::max(p->rx, std::abs(off[0]));
+      p->ry = std::max(p->ry, std::abs(off[1]));
+      return emit(X_INW, (off[1] + 2) * 5 + (off[0] + 2), 0, 1);
     }
     struct F {
       const char* n;

@@ -15,6 +15,8 @@ struct ExprProg {
   int max_input = -1;          // highest input index named (a = 0)
   bool needs_float = false;    // uses sqrt or a non-integer literal
   bool int_literals_ok = true; // every literal is an integer that fits 32 bits
+  bool has_offsets = false;    // reads a[dx, dy] (a local kernel)
+  int rx = 0, ry = 0;          // largest |dx|, |dy| read
 };
 
 // Parse `src`.  Returns an empty string on success, else what is wrong.

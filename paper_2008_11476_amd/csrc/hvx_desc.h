@@ -28,12 +28,14 @@ enum OpKind : int32_t {
   OP_NONLINEAR,  // median / min / max over a mask (p0 x p1, p2: 0 median, 1 min, 2 max)
   OP_NONMAX,     // NonMaxSuppression over a (2 p0 + 1)^2 window, U8 or S16
   OP_EXPR,       // user point kernel (Section 5.1): p0 steps of `code`, p1 = 1 float kernel, p2 bit k: input k F32
+  OP_EXPR_LOCAL, // user local kernel: as OP_EXPR over one input read at window offsets
 };
 
 // Steps of a user point kernel's postfix program: the low byte is the
 // operation, the high byte its argument (input index, literal index).
 enum ExprOp : int16_t {
-  X_IN = 1, X_CONST, X_ADD, X_SUB, X_MUL, X_DIV, X_NEG, X_MIN, X_MAX, X_ABS, X_CLAMP, X_GT, X_SEL, X_SQRT
+  X_IN = 1, X_CONST, X_ADD, X_SUB, X_MUL, X_DIV, X_NEG, X_MIN, X_MAX, X_ABS, X_CLAMP, X_GT, X_SEL, X_SQRT,
+  X_INW  // input a at window offset: argument (dy + 2) * 5 + (dx + 2)
 };
 constexpr int kMaxExpr = 32;       // steps
 constexpr int kMaxExprConst = 8;   // distinct literals

@@ -61,6 +61,7 @@ enum NodeKind : int32_t {
   NK_THRESHOLD,
   NK_CONVOLVE,
   NK_CUSTOM_POINT,
+  NK_CUSTOM_LOCAL,
 };
 
 struct Node : Object {

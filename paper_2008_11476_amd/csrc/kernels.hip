@@ -151,7 +151,8 @@ hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& 
     return hipGetLastError();
   }
   const int in_df = P.nops == 1 && P.ops[0].in[0] >= 0 ? P.vals[P.ops[0].in[0]].df : -1;
-  if (P.nops == 1 && (in_df == DF_U8 || in_df == DF_F32)) {
+  // a user local kernel reads its window at run-time offsets: tile path only
+  if (P.nops == 1 && (in_df == DF_U8 || in_df == DF_F32) && P.ops[0].kind != OP_EXPR_LOCAL) {
     const GOp& o = P.ops[0];
     const long long blocks = (long long)((P.w + 1023) >> 10) * P.h;
     if (blocks <= 0) return hipSuccess;

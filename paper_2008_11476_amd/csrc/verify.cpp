@@ -39,6 +39,10 @@ static int op_radius(const LOp& o, int* rx, int* ry) {
     case OP_GAUSS5:
     case OP_BOX5F: r = 2; break;
     case OP_NONMAX: r = o.policy / 2; break;  // the window size
+    case OP_EXPR_LOCAL:
+      *rx = o.expr->rx;
+      *ry = o.expr->ry;
+      return std::max(*rx, *ry);
     case OP_CONVOLVE:
     case OP_NONLINEAR:
       *rx = (int)o.conv->cols / 2;
@@ -91,6 +95,7 @@ static const char* node_name(int kind) {
     case NK_NONLINEAR: return "NonLinearFilter";
     case NK_NONMAX: return "NonMaxSuppression";
     case NK_CUSTOM_POINT: return "user point kernel";
+    case NK_CUSTOM_LOCAL: return "user local kernel";
     case NK_BOX5F: return "Box5x5F32";
     case NK_SOBEL3: return "Sobel3x3";
     case NK_MAGNITUDE: return "Magnitude";
@@ -409,7 +414,8 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
       case OP_ADD: q.p0 = o.policy; break;
       case OP_HARRIS: q.pf = o.k; break;
       case OP_NONMAX: q.p0 = o.policy / 2; break;
-      case OP_EXPR: {
+      case OP_EXPR:
+      case OP_EXPR_LOCAL: {
         const ExprProg& e = *o.expr;
         q.p0 = (int)e.code.size();
         q.p1 = P.vals[q.out].df == DF_F32 ? 1 : 0;
@@ -564,7 +570,8 @@ hvx_status verify_graph(Graph* g) {
         if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
         s = bind_output(g, p, nout[i][0], DF_U8, w, h, nn);
         break;
-      case NK_CUSTOM_POINT: {
+      case NK_CUSTOM_POINT:
+      case NK_CUSTOM_LOCAL: {
         // a float kernel (an F32 input or output) has an F32 output; an
         // integer kernel uses no sqrt and only 32-bit integer literals
         bool flt = n->out_df == DF_F32;
@@ -672,6 +679,7 @@ hvx_status verify_graph(Graph* g) {
       case NK_NONLINEAR: emit(OP_NONLINEAR, nin[i], nout[i][0]); break;
       case NK_NONMAX: emit(OP_NONMAX, nin[i], nout[i][0]); break;
       case NK_CUSTOM_POINT: emit(OP_EXPR, nin[i], nout[i][0]); break;
+      case NK_CUSTOM_LOCAL: emit(OP_EXPR_LOCAL, nin[i], nout[i][0]); break;
       case NK_BOX5F: emit(OP_BOX5F, nin[i], nout[i][0]); break;
       case NK_SOBEL3:  // two parallel local operators
         if (nout[i][0] >= 0) emit(OP_SOBEL_X, nin[i], nout[i][0]);

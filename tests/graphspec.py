@@ -84,6 +84,8 @@ def build_hvx(spec: Spec, ctx, images: dict):
             h = hvx.hvx_nonlinear_filter_node(g, fn[p["func"]], a[0], p["mask"], o[0], ctx=ctx)
         elif n.op == "custom_point":
             h = hvx.hvx_custom_point_node(g, p["expr"], a, DF_OF_DTYPE[np.dtype(p["out_dtype"])], o[0], ctx=ctx)
+        elif n.op == "custom_local":
+            h = hvx.hvx_custom_local_node(g, p["expr"], a[0], DF_OF_DTYPE[np.dtype(p["out_dtype"])], o[0], ctx=ctx)
         elif n.op == "nonmax":
             h = hvx.hvx_non_max_suppression_node(g, a[0], p.get("win", 3), o[0], ctx=ctx)
         elif n.op == "box5x5_f32":

@@ -5,6 +5,7 @@ tolerance derived from the F32 arithmetic."""
 import numpy as np
 import pytest
 
+import oracle
 import paper_2008_11476_amd as hvx
 import synth
 from tests import graphspec as gs
@@ -224,3 +225,55 @@ def test_fchain_application(ctx, w, h, border):
     compare(spec, got, env)
     unf, _ = run_spec(spec, ctx, fusion=False)
     compare(spec, unf, env)
+
+
+LOCAL_KERNELS = [
+    ("a[1, -1] + 2 * a[1, 0] + a[1, 1] - a[-1, -1] - 2 * a[-1, 0] - a[-1, 1]", np.int16),   # Sobel gx
+    ("(a[-1, -1] + 2 * a[0, -1] + a[1, -1] + 2 * a[-1, 0] + 4 * a + 2 * a[1, 0] + a[-1, 1] + 2 * a[0, 1]"
+     " + a[1, 1]) / 16", np.uint8),                                                          # Gaussian3x3
+    ("max(a[-2, -2], a[2, 2]) - min(a[0, -2], a[0, 2]) + a[-2, 1] / 3", np.int16),          # 5x5 reach
+    ("sqrt(a[1, 0] * a[-1, 0] + 1) / 2 + a[0, -1] * 0.25", np.float32),                   # float kernel
+]
+GPU_BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("undefined", 0), ("mirror", 0), ("repeat", 0)]
+
+
+@pytest.mark.parametrize("expr,out", LOCAL_KERNELS)
+@pytest.mark.parametrize("border", GPU_BORDERS)
+@pytest.mark.parametrize("w,h", [(67, 45), (3, 2)])
+def test_local_kernel(ctx, expr, out, border, w, h):
+    """User local kernels node by node (generic tile kernel) and fused behind
+    a Gaussian3x3 with a threshold after them."""
+    log("custom local %r %s %dx%d" % (expr[:30], border, w, h))
+    img = synth.edge_image(w, h, seed=w + len(expr))
+    one = gs.Spec([gs.N("custom_local", ["in"], ["out"], *border, params={"expr": expr, "out_dtype": out})],
+                  {"in": img}, {"out": out})
+    env = one.run_oracle()
+    got, _ = run_spec(one, ctx, fusion=False)
+    if out == np.float32:
+        m = oracle.valid_masks(one.oracle_graph(), one.shapes())["out"]
+        _close(got["out"][m], env["out"][m], 1 + np.abs(env["out"][m]))
+    else:
+        compare(one, got, env)
+    nodes = [gs.N("gaussian3x3", ["in"], ["g"], *border),
+             gs.N("custom_local", ["g"], ["r"], *border, params={"expr": expr, "out_dtype": out}),
+             gs.N("threshold", ["r"], ["t"], params={"thresh": 20})]
+    fused = gs.Spec(nodes, {"in": img}, {"r": out, "t": np.uint8})
+    env = fused.run_oracle()
+    got, g = run_spec(fused, ctx)
+    if border[0] != "repeat":
+        assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    if out == np.float32:
+        m = oracle.valid_masks(fused.oracle_graph(), fused.shapes())["r"]
+        _close(got["r"][m], env["r"][m], 1 + np.abs(env["r"][m]))
+    else:
+        compare(fused, got, env)
+
+
+@pytest.mark.parametrize("expr", ["a[3, 0]", "a[1]", "a[1, 0", "b[1, 0]", "a[1.5, 0]", "a[12, 0]", "b"])
+def test_local_kernel_rejects(ctx, expr):
+    g, ims, keep = _graph_with_images(ctx, [hvx.HVX_DF_U8, hvx.HVX_DF_U8])
+    with pytest.raises(hvx.HvxError):
+        hvx.hvx_custom_local_node(g, expr, ims[0], hvx.HVX_DF_U8, ims[1], ctx=ctx)
+    with pytest.raises(hvx.HvxError):  # offsets are not allowed in a point kernel
+        hvx.hvx_custom_point_node(g, "a[1, 0]", ims[:1], hvx.HVX_DF_U8, ims[1], ctx=ctx)
+    hvx.hvx_release_graph(g)
