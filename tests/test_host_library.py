@@ -297,3 +297,37 @@ def test_tune_cache_roundtrip(ctx, tmp_path):
     q = tmp_path / "out.json"
     hvx.hvx_context_save_tune_cache(ctx, str(q))
     assert '"gfx950|k1:3840x2160:3.2.0,": [32, 1, 12.5]' in q.read_text()
+
+
+EXPR_CORPUS = ["a", "a + b * c", "-a - -b", "(a + 1) * (b - 2) / 3", "min(a, b)", "max(a, min(b, c))", "abs(a)",
+               "clamp(a, 0, 9)", "gt(a, b)", "sel(a, b, c)", "a / 0", "2147483647 + a", "sqrt(a)", "a * 0.5",
+               "a +", "a b", "(a", "a)", "min(a)", "max(a, b, c)", "foo(a)", "d", "a ** 2", "a % 2", "a // 2",
+               "a > b", "", "   ", "1e3", "a[1, 0]", "a[-2, 2] + a", "a[3, 0]", "a[1]", "b[0, 0]", "a[1, 0",
+               "a[ -1 , 1 ] * 2", "a[1.0, 0]", "2147483648", "-2147483648 + a", "clamp(a, b)", "sel(a, b)"]
+
+
+@pytest.mark.parametrize("local", [False, True])
+def test_user_kernel_parser_agrees_with_the_oracle_grammar(ctx, local):
+    """The library's parser (node creation plus verification of an integer
+    kernel) accepts exactly the expressions the oracle's own parser accepts."""
+    from oracle import custom
+    for expr in EXPR_CORPUS:
+        try:
+            custom.check(expr, 1 if local else 3, False, local=local)
+            want = True
+        except ValueError:
+            want = False
+        ims = [_img(ctx, 16, 4, hvx.HVX_DF_U8, k) for k in range(3)] + [_img(ctx, 16, 4, hvx.HVX_DF_S16, 3)]
+        g = hvx.hvx_graph_create(ctx)
+        try:
+            if local:
+                hvx.hvx_custom_local_node(g, expr, ims[0], hvx.HVX_DF_S16, ims[3], ctx=ctx)
+            else:
+                hvx.hvx_custom_point_node(g, expr, ims[:3], hvx.HVX_DF_S16, ims[3], ctx=ctx)
+            got = _verify_status(g) == hvx.HVX_SUCCESS
+        except hvx.HvxError:
+            got = False
+        hvx.hvx_release_graph(g)
+        for im in ims:
+            hvx.hvx_release_image(im)
+        assert got == want, (expr, local, got, want)
