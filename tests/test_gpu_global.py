@@ -185,3 +185,38 @@ def test_min_max_loc(ctx, w, h, dtype):
             else:
                 assert len(set(pts)) == cap
                 assert all(0 <= x < w and 0 <= y < h and img[y, x] == val for x, y in pts)
+
+
+def test_global_ops_replay_from_a_hip_graph(ctx):
+    """The calls capture into a HIP graph (their result buffers are set by a
+    kernel, not a memset); each replay, after eager changes to the input,
+    matches the oracle on the input as it then is."""
+    import torch
+    w, h = 300, 70
+    img = synth.uniform_u8(w, h, seed=21)
+    im, dev = device_image(ctx, img, hvx.HVX_DF_U8, seed=1)
+    hist = torch.zeros(256, dtype=torch.int32, device="cuda")
+    mm = torch.zeros(2, dtype=torch.int32, device="cuda")
+    ms = torch.zeros(3, dtype=torch.int64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            s = torch.cuda.current_stream().cuda_stream
+            hvx.hvx_histogram(ctx, im, 256, 0, 256, hist.data_ptr(), s)
+            hvx.hvx_min_max(ctx, im, mm.data_ptr(), s)
+            hvx.hvx_mean_std_dev(ctx, im, ms.data_ptr(), s)
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        cur = (img.astype(np.int32) * (rep + 1) // 3).astype(np.uint8)
+        dev[:, :w].copy_(torch.from_numpy(cur))  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        log("graph replay %d" % rep)
+        assert np.array_equal(hist.cpu().numpy().view(np.uint32), G.histogram(cur, 256, 0, 256))
+        assert tuple(mm.cpu().tolist()) == G.min_max(cur)
+        mean, std, s1, s2 = G.mean_std_dev(cur)
+        raw = ms.cpu().numpy()
+        assert int(raw[0]) == s1 and int(raw[1]) == s2
