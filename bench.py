@@ -299,25 +299,33 @@ def extras(hvx, torch, ctx, quick=False, only_global=False):
 
 def global_ops(hvx, torch, ctx, stream, rec):
     """Global operators (Table 2) over one 16384 x 16384 U8 image: one read
-    pass of 268 MB each.  The timed call includes the kernel that initialises
+    pass of 268 MB each (EqualizeHist also writes 268 MB; MinMaxLoc keeps at
+    most 1024 locations of each extreme).  The timed call includes the kernel that initialises
     the result (and, for mean/stddev, the final kernel)."""
     gw = gh = 16384
     gb, gv = hvx.alloc_image(gh, gw, hvx.HVX_DF_U8)
     gv.copy_(torch.randint(0, 256, (gh, gw), dtype=torch.uint8, device="cuda"))
     gim = hvx.image_from_tensor(ctx, gv, hvx.HVX_DF_U8)
     gout = torch.zeros(512, dtype=torch.int64, device="cuda")
+    gloc = torch.zeros(4096, dtype=torch.int32, device="cuda")  # two lists of 1024 (x, y) pairs
+    gob, gov = hvx.alloc_image(gh, gw, hvx.HVX_DF_U8)
+    gom = hvx.image_from_tensor(ctx, gov, hvx.HVX_DF_U8)
     gops = {"histogram256": lambda: hvx.hvx_histogram(ctx, gim, 256, 0, 256, gout.data_ptr(), stream),
             "min_max": lambda: hvx.hvx_min_max(ctx, gim, gout.data_ptr(), stream),
             "min_max_count": lambda: hvx.hvx_min_max_count(ctx, gim, gout.data_ptr(), stream),
+            "min_max_loc_cap1024": lambda: hvx.hvx_min_max_loc(ctx, gim, gout.data_ptr(), gloc.data_ptr(),
+                                                               gloc.data_ptr() + 8192, 1024, stream),
+            "equalize_hist": lambda: hvx.hvx_equalize_hist(ctx, gim, gom, gout.data_ptr() + 1024, stream),
             "mean_std_dev": lambda: hvx.hvx_mean_std_dev(ctx, gim, gout.data_ptr(), stream)}
     gd = {"image": "16384x16384 U8, uniform random", "alg_bytes": gw * gh}
     for name, fn in gops.items():
         ms, _ = time_region(torch, fn, 20, 3)
-        gbs = gw * gh / (ms / 1e3) / 1e9
+        gbs = gw * gh * (2 if name == "equalize_hist" else 1) / (ms / 1e3) / 1e9  # equalize also writes
         gd[name] = {"ms": round(ms, 4), "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     rec("global_ops_16k", gd)
     hvx.hvx_release_image(gim)
-    del gb, gv, gout
+    hvx.hvx_release_image(gom)
+    del gb, gv, gout, gloc, gob, gov
     torch.cuda.empty_cache()
 
 

@@ -262,7 +262,9 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
  *    (the counts of MinMaxLoc; a second pass over the image).
  *  min_max_loc: as min_max_count, and the (x, y) of the pixels equal to
  *    each extreme, two uint32 per location, into dev_min_locs / dev_max_locs
- *    (capacity locations each; both may be NULL when capacity is 0).  When
+ *    (capacity locations each; both may be NULL when capacity is 0).
+ *    dev_result holds 6 int32: the 4 results, then 2 words the call uses as
+ *    slot counters.  When
  *    an extreme occurs more than capacity times, capacity of its locations
  *    are kept; which ones, and the order of any list, are unspecified.
  *  equalize_hist: U8 image -> U8 image `out` of the same size (may be the

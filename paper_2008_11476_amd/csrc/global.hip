@@ -250,11 +250,14 @@ __global__ __launch_bounds__(kRThreads) void k_count_extremes(GlobalImg im, int3
   }
 }
 
-// MinMaxLoc: the (x, y) of every pixel equal to mm[0] (into lmin) and to
-// mm[1] (into lmax), two words per location, the first `cap` of each list
-// kept, in no particular order; mm[2], mm[3] receive the full counts.  Each
-// lane marks the matches of its 16-byte chunk; a scan across the wave gives
-// each lane its offset and one atomic per wave and list reserves the slots.
+// MinMaxLoc: the (x, y) of pixels equal to mm[0] (into lmin) and to mm[1]
+// (into lmax), two words per location, at most `cap` of each list, in no
+// particular order; mm[4], mm[5] count the reserved slots (the exact counts
+// come from k_count_extremes).  Each lane marks the matches of its 16-byte
+// chunk; a scan across the wave gives each lane its offset and one atomic per
+// wave and list reserves the slots.  Once a list is full (read without an
+// atomic: a stale value only costs one more atomic) the wave skips it, so an
+// extreme that occurs millions of times does not serialise on its counter.
 // The chunk loop steps on a wave-uniform base so every lane takes part in
 // the lane exchanges.
 template <bool S16>
@@ -292,9 +295,9 @@ __global__ __launch_bounds__(kGThreads) void k_extreme_locs(GlobalImg im, int32_
           if (lane >= off) inc += u;
         }
         const int total = __shfl(inc, 63);
-        if (total == 0) continue;
+        if (total == 0 || (uint32_t)__atomic_load_n(&mm[4 + list], __ATOMIC_RELAXED) >= cap) continue;
         int base = 0;
-        if (lane == 0) base = atomicAdd(&mm[2 + list], total);
+        if (lane == 0) base = atomicAdd(&mm[4 + list], total);
         base = __shfl(base, 0);
         uint32_t i = (uint32_t)(base + inc - cnt);
         uint32_t* out = list ? lmax : lmin;
@@ -314,9 +317,9 @@ __global__ __launch_bounds__(kGThreads) void k_extreme_locs(GlobalImg im, int32_
 
 hipError_t launch_min_max_loc(const GlobalImg& im, int32_t* result, uint32_t* lmin, uint32_t* lmax, uint32_t cap,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result + 2, 2, 0u, 0u);
-  hipError_t e = launch_min_max(im, result, s);
-  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result + 4, 2, 0u, 0u);
+  hipError_t e = launch_min_max_count(im, result, s);
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0 || cap == 0) return e;
   const dim3 grid(im.h < 2048 ? im.h : 2048);
   if (im.bpp == 2) hipLaunchKernelGGL(k_extreme_locs<true>, grid, dim3(kGThreads), 0, s, im, result, lmin, lmax, cap);
   else hipLaunchKernelGGL(k_extreme_locs<false>, grid, dim3(kGThreads), 0, s, im, result, lmin, lmax, cap);
