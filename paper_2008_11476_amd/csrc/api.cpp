@@ -545,6 +545,9 @@ static hvx_status global_input(hvx_context ctx, hvx_image in, std::initializer_l
   bool ok = false;
   for (int d : dfs) ok |= im->df == d;
   if (!ok) return set_error(c, HVX_ERROR_INVALID_FORMAT, "unsupported image format");
+  // counts and histogram bins are 32-bit: a pixel count must fit in 31 bits
+  if ((uint64_t)im->w * im->h >= ((uint64_t)1 << 31))
+    return set_error(c, HVX_ERROR_INVALID_DIMENSION, "global operators take images of fewer than 2^31 pixels");
   hvx_status s = ensure_device(c);
   if (s) return s;
   gi->base = (const uint8_t*)im->ptr;

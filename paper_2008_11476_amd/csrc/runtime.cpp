@@ -649,19 +649,28 @@ hvx_status hvx_process_batch(hvx_context ctx, const hvx_graph* graphs, uint32_t 
 // ---- autotuning -----------------------------------------------------------------
 
 static hvx_status read_outputs(Graph* g, hipStream_t st, std::vector<std::vector<uint8_t>>* out) {
-  // copies ordered after the work on `st` and complete before returning
+  // Copies ordered after the work on `st` and complete before returning.
+  // The destination of the device-to-host copy is memory allocated pinned
+  // (hipHostMalloc), then copied into the vector on the host: an
+  // asynchronous copy into pageable memory makes the runtime pin or stage
+  // the caller's pages on the fly, and where pinning memory that already
+  // exists is refused, that copy can complete without writing the
+  // destination (the comparison then sees the vector's zeros).
   out->clear();
   const Plan& p = *g->plan;
   for (size_t v = 0; v < p.vals.size(); ++v) {
     const Value& val = p.vals[v];
     if (val.is_virtual || val.producer < 0 || !p.ops[val.producer].live) continue;
-    size_t row = (size_t)val.w * df_bytes(val.df);
-    std::vector<uint8_t> buf(row * val.h);
-    if (hipMemcpy2DAsync(buf.data(), row, val.img->ptr, val.img->pitch, row, val.h, hipMemcpyDeviceToHost, st) !=
-            hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return set_error(g->ctx, HVX_ERROR_DEVICE, "autotune readback failed");
-    out->push_back(std::move(buf));
+    const size_t row = (size_t)val.w * df_bytes(val.df);
+    const size_t bytes = row * val.h;
+    void* stage = nullptr;
+    if (hipHostMalloc(&stage, bytes, 0) != hipSuccess)
+      return set_error(g->ctx, HVX_ERROR_NO_MEMORY, "autotune readback: cannot allocate %zu pinned bytes", bytes);
+    hipError_t e = hipMemcpy2DAsync(stage, row, val.img->ptr, val.img->pitch, row, val.h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) out->emplace_back((const uint8_t*)stage, (const uint8_t*)stage + bytes);
+    (void)hipHostFree(stage);
+    if (e != hipSuccess) return set_error(g->ctx, HVX_ERROR_DEVICE, "autotune readback: %s", hipGetErrorString(e));
   }
   return HVX_SUCCESS;
 }

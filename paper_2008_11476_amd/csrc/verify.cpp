@@ -700,37 +700,30 @@ hvx_status verify_graph(Graph* g) {
     for (int k = 0; k < p.ops[o].nin; ++k) p.vals[p.ops[o].in[k]].consumers.push_back((int)o);
   }
 
-  // ---- 4: dead-computation elimination (Algorithm 1) ----
-  // Non-virtual data vertices with no producer are inputs, those with no
-  // consumer are results, the others are both.  From every result, walk the
-  // transposed graph and mark what is reached as alive; the walk does not go
-  // past another input vertex.  Operators not reached are dead.
+  // ---- 4: dead-computation elimination (Section 5.2.2, Algorithm 1) ----
+  // Only non-virtual images are visible after a process call, so an operator
+  // is needed exactly when it writes a non-virtual image or writes a virtual
+  // one that a needed operator reads.  Liveness is therefore one backward
+  // reachability over operators: seed a worklist with every operator whose
+  // output is non-virtual, and from each operator taken off the list mark the
+  // producers of its virtual inputs.  (A non-virtual image that is also read
+  // is a seed itself, so the walk never needs to pass through one.)
   if (g->opt_dce) {
     for (auto& o : p.ops) o.live = false;
-    std::vector<char> d_in(p.vals.size(), 0), d_out(p.vals.size(), 0);
-    for (size_t v = 0; v < p.vals.size(); ++v) {
-      if (p.vals[v].is_virtual) continue;
-      bool has_in = p.vals[v].producer >= 0, has_out = !p.vals[v].consumers.empty();
-      if (!has_in) d_in[v] = 1;
-      else if (!has_out) d_out[v] = 1;
-      else d_in[v] = d_out[v] = 1;
-    }
-    std::vector<char> seen(p.vals.size(), 0);
-    for (size_t s = 0; s < p.vals.size(); ++s) {
-      if (!d_out[s]) continue;
-      std::vector<int> stack{(int)s};
-      std::vector<char> visited(p.vals.size(), 0);
-      while (!stack.empty()) {
-        int v = stack.back();
-        stack.pop_back();
-        if (visited[v]) continue;
-        visited[v] = 1;
-        seen[v] = 1;
-        if (v != (int)s && d_in[v]) continue;  // stop at other input vertices
-        int pr = p.vals[v].producer;
-        if (pr < 0) continue;
-        p.ops[pr].live = true;
-        for (int k = 0; k < p.ops[pr].nin; ++k) stack.push_back(p.ops[pr].in[k]);
+    std::vector<int> work;
+    for (size_t o = 0; o < p.ops.size(); ++o)
+      if (!p.vals[p.ops[o].out].is_virtual) {
+        p.ops[o].live = true;
+        work.push_back((int)o);
+      }
+    while (!work.empty()) {
+      const LOp& o = p.ops[work.back()];
+      work.pop_back();
+      for (int k = 0; k < o.nin; ++k) {
+        const Value& in = p.vals[o.in[k]];
+        if (!in.is_virtual || in.producer < 0 || p.ops[in.producer].live) continue;
+        p.ops[in.producer].live = true;
+        work.push_back(in.producer);
       }
     }
   }

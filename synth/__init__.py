@@ -97,6 +97,20 @@ def uyvy_image(w: int, h: int, seed: int = 0) -> np.ndarray:
     return out
 
 
+def frame_recipe(i: int, n_bases: int = 4):
+    """Frame i of a multi-frame workload: (seed of its base image, byte it is
+    XORed with).  Frames cycle over ``n_bases`` seeded ``edge_image`` bases,
+    and each cycle XORs a different byte into every pixel, so all frames are
+    distinct buffers with the statistics of the bases."""
+    return i % n_bases, (i // n_bases) * 37 % 256
+
+
+def recipe_frame(w: int, h: int, i: int, n_bases: int = 4) -> np.ndarray:
+    """Host copy of frame i of ``frame_recipe`` (the base image XOR its byte)."""
+    seed, x = frame_recipe(i, n_bases)
+    return edge_image(w, h, seed=seed) ^ np.uint8(x)
+
+
 def uniform_u8(w: int, h: int, seed: int = 0) -> np.ndarray:
     return np.random.default_rng(seed).integers(0, 256, size=(h, w), dtype=np.uint8)
 

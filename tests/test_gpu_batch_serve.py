@@ -284,6 +284,56 @@ def test_server_results_alone_equals_mix(ctx, mode):
     hvx.hvx_release_server(s)
 
 
+@pytest.mark.parametrize("mode", [hvx.HVX_SERVER_CONTINUOUS, hvx.HVX_SERVER_PLAIN])
+def test_server_configured_sizes(ctx, mode):
+    """The serving workload's own sizes, 640x480 to 3840x2160, for the three
+    served graphs, under a budget that binds (a 4K UYVY request holds 24.9 MB,
+    the budget 40 MiB): every result against the oracle, then every request
+    served again alone, byte-equal to its result in the mix."""
+    import torch
+    sizes = list(synth.SERVE_SIZES)
+    templ, keep = _templates(ctx, sizes)
+    budget = 40 << 20
+    reqs = {}
+    tag = 0
+    for (w, h) in sizes:
+        for kind in synth.SERVE_TYPES:
+            for rep in range(2):
+                f, spec = _host_frames(kind, w, h, seed=200 + tag)
+                src = torch.from_numpy(np.ascontiguousarray(f)).pin_memory()
+                reqs[tag] = (kind, w, h, spec, src)
+                tag += 1
+    order = list(np.random.default_rng(11).permutation(len(reqs)))
+
+    def serve(tags, drain_each):
+        s = hvx.hvx_server_create(ctx, mode, budget, 8, 2)
+        dst = {}
+        for t in tags:
+            kind, w, h, spec, src = reqs[t]
+            dst[t] = torch.full((h, w), 7, dtype=torch.uint8).pin_memory()
+            hvx.hvx_server_submit(s, templ[(kind, w, h)], src.data_ptr(), src.stride(0), dst[t].data_ptr(),
+                                  dst[t].stride(0), t, ctx=ctx)
+            if drain_each:
+                hvx.hvx_server_drain(s, ctx=ctx)
+        hvx.hvx_server_drain(s, ctx=ctx)
+        done = hvx.hvx_server_poll(s, 1000, ctx=ctx)
+        assert sorted(t for t, _, _ in done) == sorted(tags)
+        assert all(st == 0 for _, st, _ in done)
+        assert hvx.hvx_server_stats(s, 2) <= budget
+        hvx.hvx_release_server(s)
+        return dst
+
+    log("serving %d requests at the configured sizes, mode %d" % (len(order), mode))
+    mix = serve(order, False)
+    for t in sorted(reqs):
+        kind, w, h, spec, src = reqs[t]
+        log("served %d %s %dx%d vs oracle" % (t, kind, w, h))
+        compare(spec, {"out": mix[t].numpy()}, spec.run_oracle(), corner=(kind == "harris"))
+    alone = serve(sorted(reqs), True)
+    for t in sorted(reqs):
+        assert torch.equal(alone[t], mix[t]), t
+
+
 def test_server_limits(ctx):
     with pytest.raises(hvx.HvxError) as e:
         hvx.hvx_server_create(ctx, hvx.HVX_SERVER_CONTINUOUS, 0, 4, 2)

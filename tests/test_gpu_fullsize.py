@@ -100,6 +100,97 @@ def test_edge_4k_batch64_bench_launch(ctx):
         hvx.hvx_release_graph(g)
 
 
+def _recipe_batch(ctx, w, h, n, phase=True, border=None):
+    """The benchmark's frames on the device: frame i is seeded base
+    synth.frame_recipe(i) XORed with its byte, outputs poisoned.  Returns
+    (graphs, {output name: (view, width)} per frame, keep-alive list)."""
+    import torch
+    nb = min(n, 4)
+    bases = [torch.from_numpy(synth.edge_image(w, h, seed=s)).cuda() for s in range(nb)]
+    graphs, outs, keep = [], [], []
+    for i in range(n):
+        base, x = synth.frame_recipe(i, nb)
+        ib, iv = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+        iv.copy_(bases[base] ^ x)
+        o = {}
+        imgs = {"in": hvx.image_from_tensor(ctx, iv, hvx.HVX_DF_U8)}
+        for name in (("out", "ph") if phase else ("out",)):
+            ob, ov = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+            ob.fill_(0x5A)
+            imgs[name] = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
+            o[name] = (ov, w)
+            keep.append(ob)
+        spec = gs.edge_spec(np.zeros((1, 1), np.uint8), phase=phase,
+                            **({} if border is None else {"b0": border, "b1": border}))
+        g, _, _ = gs.build_hvx(spec, ctx, imgs)
+        hvx.hvx_graph_verify(g, ctx=ctx)
+        graphs.append(g)
+        outs.append(o)
+        keep.append(ib)
+    torch.cuda.synchronize()
+    return graphs, outs, keep
+
+
+def test_edge_phase_4k_batch64_headline(ctx):
+    """The benchmarked workload itself: 64 distinct 3840x2160 frames built as
+    the benchmark builds them, edge map + Phase, REPLICATE, in one direct
+    batch launch of 45 rows per work item (the shape the tuner picks on
+    MI355X), then in the shape the tuner picks here, in both launch modes.
+    Sampled frames element by element against the oracle (edge map exact,
+    Phase within one level circularly); every frame byte-equal across the
+    launch shapes."""
+    import torch
+    w, h, n = 3840, 2160, 64
+    graphs, outs, keep = _recipe_batch(ctx, w, h, n)
+    side = torch.cuda.Stream()
+    stream = side.cuda_stream
+    b = hvx.hvx_batch_create(ctx, graphs)
+    hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_ROWS, 45, ctx=ctx)
+    hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, 0, ctx=ctx)
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_OPS) == n * 4 * 48  # 4 strips x 48 bands per frame
+    log("headline: 64 x 4K edge+phase, rows 45, direct")
+    hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+    torch.cuda.synchronize()
+    first = [{k: v.clone() for k, (v, _) in o.items()} for o in outs]
+    for i in (0, 1, 2, 3, 4, 31, 62, 63):
+        log("headline frame %d vs oracle" % i)
+        spec = gs.edge_spec(synth.recipe_frame(w, h, i, 4), phase=True)
+        got = {k: v.cpu().numpy() for k, v in first[i].items()}
+        compare(spec, got, spec.run_oracle(), phase_names=("ph",))
+    hvx.hvx_batch_autotune(b, stream, 1, ctx=ctx)
+    log("tuned: rows %d" % hvx.hvx_batch_query(b, hvx.HVX_QUERY_ROWS_PER_ITEM))
+    for persistent in (0, 1):
+        hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, persistent, ctx=ctx)
+        for o in outs:
+            for v, _ in o.values():
+                v.fill_(0xA5)
+        torch.cuda.synchronize()
+        log("headline tuned shape, persistent=%d" % persistent)
+        hvx.hvx_batch_schedule(b, stream, ctx=ctx)
+        torch.cuda.synchronize()
+        for i, (a, o) in enumerate(zip(first, outs)):
+            for k, (v, _) in o.items():
+                assert torch.equal(a[k], v), (i, k, persistent)
+    hvx.hvx_release_batch(b)
+    for g in graphs:
+        hvx.hvx_release_graph(g)
+
+
+@pytest.mark.parametrize("w,h", [(3840, 2160), (7680, 4320)])
+@pytest.mark.parametrize("border", [("replicate", 0), ("constant", 0)])
+def test_edge_phase_unfused_fullsize(ctx, w, h, border):
+    """Node by node (fusion off: six kernels, every intermediate in device
+    memory) at 4K and 8K, REPLICATE and CONSTANT(0), against the oracle."""
+    img = synth.edge_image(w, h, seed=w + (border[0] == "constant"))
+    spec = gs.edge_spec(img, phase=True, b0=border, b1=border)
+    log("unfused edge+phase %dx%d %s" % (w, h, border[0]))
+    got, g = run_spec(spec, ctx, fusion=False)
+    assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 6
+    compare(spec, got, spec.run_oracle(), phase_names=("ph",))
+    hvx.hvx_release_graph(g)
+
+
 def test_edge_phase_8k_batch16(ctx):
     """16 frames of 7680x4320 with the Phase output; CONSTANT(0) Sobel border
     on half of them."""

@@ -290,6 +290,28 @@ def test_no_device_errors_cleanly(ctx):
     assert hvx.lib().hvx_graph_process(g) == hvx.HVX_ERROR_DEVICE
 
 
+def test_global_ops_reject_2_31_pixels(ctx):
+    """The global operators count in 32 bits: an image of 2^31 pixels or more
+    (which the image constructors accept) is refused before any device work,
+    so a constant 65536x65536 image can never wrap a bin or a count."""
+    import torch
+    big = _img(ctx, 65536, 32768, hvx.HVX_DF_U8, 0)      # exactly 2^31 pixels
+    big16 = _img(ctx, 65536, 65536, hvx.HVX_DF_S16, 1)
+    L = hvx.lib()
+    buf = ctypes.c_void_p(FAKE)
+    assert L.hvx_histogram(ctx, big, 256, 0, 256, buf, None) == hvx.HVX_ERROR_INVALID_DIMENSION
+    assert L.hvx_min_max(ctx, big16, buf, None) == hvx.HVX_ERROR_INVALID_DIMENSION
+    assert L.hvx_min_max_count(ctx, big, buf, None) == hvx.HVX_ERROR_INVALID_DIMENSION
+    assert L.hvx_min_max_loc(ctx, big16, buf, buf, buf, 16, None) == hvx.HVX_ERROR_INVALID_DIMENSION
+    assert L.hvx_equalize_hist(ctx, big, big, buf, None) == hvx.HVX_ERROR_INVALID_DIMENSION
+    assert L.hvx_mean_std_dev(ctx, big, buf, None) == hvx.HVX_ERROR_INVALID_DIMENSION
+    assert "2^31" in hvx.hvx_last_error(ctx)
+    if not torch.cuda.is_available():
+        # one pixel fewer passes the size check and only then needs the device
+        ok = _img(ctx, 65535, 32768, hvx.HVX_DF_U8, 2)
+        assert L.hvx_min_max(ctx, ok, buf, None) == hvx.HVX_ERROR_DEVICE
+
+
 def test_tune_cache_roundtrip(ctx, tmp_path):
     p = tmp_path / "tune.json"
     p.write_text('{\n  "gfx950|k1:3840x2160:3.2.0,": [32, 1, 12.5]\n}\n')
