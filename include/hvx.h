@@ -286,6 +286,21 @@ hvx_status hvx_min_max_loc(hvx_context ctx, hvx_image in, int32_t* dev_result, u
 hvx_status hvx_equalize_hist(hvx_context ctx, hvx_image in, hvx_image out, void* dev_workspace, void* stream);
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream);
 
+/* EqualizeHist for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * hvx_equalize_hist with the same arguments, arithmetic and errors, minus
+ * the workspace.  The 1280 bytes of histogram and mapping come from a fixed
+ * device array inside the library, one per GPU, held until the process
+ * ends; the call allocates nothing (no hipMalloc, no allocating library
+ * routine).  Limit: images of fewer than 2^31 pixels (INVALID_DIMENSION
+ * otherwise), as for every global operator.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (on different streams, or
+ * from different threads) race and give undefined results; calls ordered on
+ * one stream are safe, since each call clears what it counts in a kernel of
+ * its own stream.  DEVICE if the array's address cannot be resolved or a
+ * launch fails. */
+hvx_status hvx_equalize_hist_noalloc(hvx_context ctx, hvx_image in, hvx_image out, void* stream);
+
 /* User-defined local kernel (Section 5.1): `expr` over one input image a in
  * the grammar of hvx_custom_point_node, where a[dx, dy] (one-digit integer
  * offsets, |dx|, |dy| <= 2) reads the input at (x + dx, y + dy) and a alone

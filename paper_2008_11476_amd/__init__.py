@@ -88,6 +88,7 @@ def _load():
         "hvx_mean_std_dev": [_vp, _vp, _vp, _vp],
         "hvx_min_max_count": [_vp, _vp, _vp, _vp],
         "hvx_equalize_hist": [_vp, _vp, _vp, _vp, _vp],
+        "hvx_equalize_hist_noalloc": [_vp, _vp, _vp, _vp],
         "hvx_min_max_loc": [_vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -292,6 +293,10 @@ def hvx_min_max_loc(ctx, img, dev_result, dev_min_locs, dev_max_locs, capacity, 
 
 def hvx_equalize_hist(ctx, img, out, dev_workspace, stream=None):
     _check(_load().hvx_equalize_hist(ctx, img, out, dev_workspace, stream), ctx)
+
+
+def hvx_equalize_hist_noalloc(ctx, img, out, stream=None):
+    _check(_load().hvx_equalize_hist_noalloc(ctx, img, out, stream), ctx)
 
 
 def hvx_mean_std_dev(ctx, img, dev_result, stream=None):

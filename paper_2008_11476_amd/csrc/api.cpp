@@ -614,6 +614,22 @@ hvx_status hvx_equalize_hist(hvx_context ctx, hvx_image in, hvx_image out, void*
   return launched(ctx, launch_equalize_hist(gi, (uint8_t*)go.base, go.pitch, dev_workspace, (hipStream_t)stream));
 }
 
+hvx_status hvx_equalize_hist_noalloc(hvx_context ctx, hvx_image in, hvx_image out, void* stream) {
+  GlobalImg gi, go;
+  hvx_status s = global_input(ctx, in, {DF_U8}, &gi);
+  if (s) return s;
+  s = global_input(ctx, out, {DF_U8}, &go);
+  if (s) return s;
+  Context* c = as<Context>(ctx, T_CONTEXT);
+  if (go.w != gi.w || go.h != gi.h) return set_error(c, HVX_ERROR_INVALID_DIMENSION, "output size differs from input");
+  // global_input made the context's device current
+  void* ws = nullptr;
+  const hipError_t e = equalize_scratch(c->device, &ws);
+  if (e != hipSuccess)
+    return set_error(c, HVX_ERROR_DEVICE, "device address of the fixed workspace: %s", hipGetErrorString(e));
+  return launched(ctx, launch_equalize_hist(gi, (uint8_t*)go.base, go.pitch, ws, (hipStream_t)stream));
+}
+
 hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, void* stream) {
   GlobalImg gi;
   hvx_status s = global_input(ctx, in, {DF_U8}, &gi);

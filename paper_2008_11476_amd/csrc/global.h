@@ -26,4 +26,11 @@ hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_p
                                 hipStream_t s);
 hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s);
 
+// Bytes of the fixed device array that replaces the EqualizeHist workspace
+// (256 uint32 counts, then the 256-byte mapping).
+constexpr size_t kEqualizeScratchBytes = 1280;
+// Device address of that array on `device`, which must be the current
+// device; resolved on the first call per device, then cached.
+hipError_t equalize_scratch(int device, void** ptr);
+
 }  // namespace hvx

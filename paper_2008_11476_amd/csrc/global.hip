@@ -11,6 +11,8 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "global.h"
 
 namespace hvx {
@@ -159,6 +161,7 @@ __global__ __launch_bounds__(kGThreads) void k_apply_lut(GlobalImg im, const uin
 
 hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_pitch, void* workspace,
                                 hipStream_t s) {
+  static_assert(256 * 4 + 256 <= kEqualizeScratchBytes, "the fixed workspace holds the counts and the mapping");
   uint32_t* hist = (uint32_t*)workspace;
   uint8_t* lut = (uint8_t*)workspace + 256 * 4;
   hipError_t e = launch_histogram(im, 256, 0, 256, hist, s);
@@ -169,6 +172,36 @@ hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_p
   hipLaunchKernelGGL(k_apply_lut, dim3(im.h < 2048 ? im.h : 2048), dim3(kGThreads), 0, s, im, (const uint8_t*)lut,
                      out, out_pitch);
   return hipGetLastError();
+}
+
+// ---- EqualizeHist without a caller workspace ------------------------------------
+// For callers that cannot allocate: the histogram and the mapping live in a
+// fixed device array, `scratch`, one copy per GPU, held until the process
+// ends.  In host code the array's name is only a host-side stand-in, so it
+// is never passed to a kernel: its device address is resolved once per
+// device (with that device current) and kept.  Every call on a GPU shares
+// that GPU's copy; the histogram part is cleared by a kernel at the start
+// of each call, and calls that overlap on one GPU race.
+static __device__ __align__(256) uint8_t scratch[kEqualizeScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t equalize_scratch(int device, void** ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> l(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 // ---- smallest and largest element of a U8 or S16 image ------------------------
