@@ -308,7 +308,7 @@ def global_ops(hvx, torch, ctx, stream, rec):
     gb, gv = hvx.alloc_image(gh, gw, hvx.HVX_DF_U8)
     gv.copy_(torch.randint(0, 256, (gh, gw), dtype=torch.uint8, device="cuda"))
     gim = hvx.image_from_tensor(ctx, gv, hvx.HVX_DF_U8)
-    gout = torch.zeros(512, dtype=torch.int64, device="cuda")
+    gout = torch.zeros(1024, dtype=torch.int64, device="cuda")  # results (MinMaxLoc: 4128 bytes), then a workspace
     gloc = torch.zeros(4096, dtype=torch.int32, device="cuda")  # two lists of 1024 (x, y) pairs
     gob, gov = hvx.alloc_image(gh, gw, hvx.HVX_DF_U8)
     gom = hvx.image_from_tensor(ctx, gov, hvx.HVX_DF_U8)
@@ -317,7 +317,7 @@ def global_ops(hvx, torch, ctx, stream, rec):
             "min_max_count": lambda: hvx.hvx_min_max_count(ctx, gim, gout.data_ptr(), stream),
             "min_max_loc_cap1024": lambda: hvx.hvx_min_max_loc(ctx, gim, gout.data_ptr(), gloc.data_ptr(),
                                                                gloc.data_ptr() + 8192, 1024, stream),
-            "equalize_hist": lambda: hvx.hvx_equalize_hist(ctx, gim, gom, gout.data_ptr() + 1024, stream),
+            "equalize_hist": lambda: hvx.hvx_equalize_hist(ctx, gim, gom, gout.data_ptr() + 4160, stream),
             "mean_std_dev": lambda: hvx.hvx_mean_std_dev(ctx, gim, gout.data_ptr(), stream)}
     gd = {"image": "16384x16384 U8, uniform random", "alg_bytes": gw * gh}
     for name, fn in gops.items():

@@ -48,6 +48,7 @@ typedef struct hvx_node_s* hvx_node;
 typedef struct hvx_conv_s* hvx_convolution;
 typedef struct hvx_batch_s* hvx_batch;
 typedef struct hvx_server_s* hvx_server;
+typedef struct hvx_buffer_s* hvx_buffer;
 
 typedef int32_t hvx_status;
 #define HVX_SUCCESS 0
@@ -97,10 +98,12 @@ typedef int32_t hvx_status;
 #define HVX_QUERY_NUM_NODES 1      /* function nodes added */
 #define HVX_QUERY_NUM_OPS 2        /* point/local operators after lowering */
 #define HVX_QUERY_NUM_LIVE_OPS 3   /* operators left after dead-computation elimination */
-#define HVX_QUERY_NUM_KERNELS 4    /* kernel launches per process call */
+#define HVX_QUERY_NUM_KERNELS 4    /* fused kernels per process call (not counting the one-group steps that
+                                      start and finish a global operator's result) */
 #define HVX_QUERY_ALG_BYTES 5      /* bytes a process call must move: inputs read once, outputs written once */
 #define HVX_QUERY_HBM_BYTES 6      /* bytes the plan moves, materialised intermediates included (no halos) */
-#define HVX_QUERY_KERNEL_KIND 7    /* kind of the first kernel: 0 generic, 1 edge, 2 corner, 3 gauss5 */
+#define HVX_QUERY_KERNEL_KIND 7    /* kind of the first kernel: 0 generic, 1 edge, 2 corner, 3 gauss5,
+                                      4 one global operator */
 #define HVX_QUERY_SCRATCH_BYTES 8  /* device bytes of materialised intermediates */
 #define HVX_QUERY_OP_LIVE_MASK 9   /* bit i set: lowered operator i is live (first 63 operators) */
 #define HVX_QUERY_ROWS_PER_ITEM 10 /* rows per work item of the first kernel */
@@ -147,6 +150,16 @@ hvx_status hvx_image_create_virtual(hvx_graph graph, uint32_t w, uint32_t h, int
  * (1..2^15).  Copied. */
 hvx_status hvx_convolution_create(hvx_context ctx, uint32_t cols, uint32_t rows, const int16_t* coeffs,
                                   uint32_t scale, hvx_convolution* out);
+
+/* Wrap caller-owned device memory of `bytes` bytes (8-byte aligned) that a
+ * global operator node writes its result into: a global operator reads every
+ * pixel of an image and produces a few values rather than an image (Table 2).
+ * BORROWED like hvx_image_from_ptr.  A buffer is a non-virtual data object
+ * of the graph: the node writing it is never dead code.  Verification checks
+ * that it is large enough (INVALID_DIMENSION).  INVALID_PARAMETERS for a
+ * NULL or misaligned pointer, INVALID_DIMENSION for 0 or more than 2^31
+ * bytes. */
+hvx_status hvx_buffer_from_ptr(hvx_context ctx, void* dev_ptr, size_t bytes, hvx_buffer* out);
 
 /* ---- graph and nodes ---------------------------------------------------- */
 
@@ -257,14 +270,18 @@ hvx_status hvx_custom_point_node(hvx_graph g, const char* expr, const hvx_image*
  *    range (integer division); other pixels are not counted.  Needs
  *    1 <= num_bins <= range and offset + range <= 256.
  *  min_max: U8 or S16 image; dev_min_max receives {smallest, largest}.
- *  min_max_count: U8 or S16 image; dev_result receives {smallest, largest,
- *    number of pixels equal to the smallest, number equal to the largest}
- *    (the counts of MinMaxLoc; a second pass over the image).
+ *  min_max_count: U8 or S16 image; dev_result (4128 bytes, 8-byte aligned)
+ *    receives {smallest, largest, number of pixels equal to the smallest,
+ *    number equal to the largest} (the counts of MinMaxLoc) in its first 4
+ *    int32, all from one pass over the image; the call uses the rest while
+ *    counting.
  *  min_max_loc: as min_max_count, and the (x, y) of the pixels equal to
  *    each extreme, two uint32 per location, into dev_min_locs / dev_max_locs
- *    (capacity locations each; both may be NULL when capacity is 0).
- *    dev_result holds 6 int32: the 4 results, then 2 words the call uses as
- *    slot counters.  When
+ *    (capacity locations each; both may be NULL when capacity is 0), from a
+ *    second pass that stops once both lists are full.  dev_result (4128
+ *    bytes, 8-byte aligned): the 4 results, then 2 int32 the call uses as
+ *    slot counters (reservations; min(counter, capacity) locations are
+ *    stored), then words used while counting.  When
  *    an extreme occurs more than capacity times, capacity of its locations
  *    are kept; which ones, and the order of any list, are unspecified.
  *  equalize_hist: U8 image -> U8 image `out` of the same size (may be the
@@ -300,6 +317,37 @@ hvx_status hvx_mean_std_dev(hvx_context ctx, hvx_image in, void* dev_result, voi
  * its own stream.  DEVICE if the array's address cannot be resolved or a
  * launch fails. */
 hvx_status hvx_equalize_hist_noalloc(hvx_context ctx, hvx_image in, hvx_image out, void* stream);
+
+/* Global operator nodes (Table 2), the graph form of the immediate-mode
+ * calls above: verified, ordered and dead-code eliminated with the rest of
+ * the graph.  A point or local producer of the node's input is fused into the
+ * reduction (one kernel computes the producer over its tiles and reduces its
+ * values without writing them to memory).  Anything that reads a global
+ * operator's result runs in a later kernel, since the result is complete
+ * only once every pixel has been counted.  Results, byte layouts:
+ *  histogram_node: U8 image; `counts` num_bins uint32 (bins as in
+ *    hvx_histogram; INVALID_PARAMETERS for bad bins/offset/range).
+ *  min_max_node: U8 or S16 image; `result` 2 int32 {smallest, largest}.
+ *  min_max_loc_node: U8 or S16 image; `result` 4128 bytes: 8 int32
+ *    {smallest, largest, pixels equal to the smallest, pixels equal to the
+ *    largest, locations stored in each of the two lists (at most capacity; 0
+ *    without locations), 2 reserved}, then 4096 bytes used while counting;
+ *    `locations` (NULL exactly when capacity is 0) 4 * capacity uint32: up
+ *    to capacity (x, y) pairs of pixels equal to the smallest value, then
+ *    capacity pairs for the largest; which ones are kept when an extreme
+ *    occurs more often, and their order, are unspecified.  The locations take
+ *    a second pass over the image (materialised if it is virtual).
+ *  mean_std_dev_node: U8 image; `result` 24 bytes as in hvx_mean_std_dev.
+ *  equalize_hist_node: U8 image -> U8 image of the same size (a point
+ *    operator applying the mapping of hvx_equalize_hist; the histogram and
+ *    mapping live in the graph's device memory). */
+hvx_status hvx_histogram_node(hvx_graph g, hvx_image in, uint32_t num_bins, uint32_t offset, uint32_t range,
+                              hvx_buffer counts, hvx_node* node_out);
+hvx_status hvx_min_max_node(hvx_graph g, hvx_image in, hvx_buffer result, hvx_node* node_out);
+hvx_status hvx_min_max_loc_node(hvx_graph g, hvx_image in, hvx_buffer result, hvx_buffer locations,
+                                uint32_t capacity, hvx_node* node_out);
+hvx_status hvx_mean_std_dev_node(hvx_graph g, hvx_image in, hvx_buffer result, hvx_node* node_out);
+hvx_status hvx_equalize_hist_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* node_out);
 
 /* User-defined local kernel (Section 5.1): `expr` over one input image a in
  * the grammar of hvx_custom_point_node, where a[dx, dy] (one-digit integer
@@ -427,6 +475,7 @@ hvx_status hvx_release_node(hvx_node* node);
 hvx_status hvx_release_convolution(hvx_convolution* conv);
 hvx_status hvx_release_batch(hvx_batch* b);
 hvx_status hvx_release_server(hvx_server* s);
+hvx_status hvx_release_buffer(hvx_buffer* b);
 
 #ifdef __cplusplus
 }

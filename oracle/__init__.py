@@ -11,6 +11,11 @@ its own inputs.  Dead-computation elimination, transfer reduction and fusion
 (Sections 5.2.1, 5.2.2, 6.3) are optimisations that must reach exactly this
 result, so the plain execution is the reference for all of them.
 
+Global operators (Table 2: histogram, min/max, MinMaxLoc, mean and
+standard deviation, EqualizeHist) are nodes like the others: they run in
+the same order over the materialised image they read, with the arithmetic
+of ``globalops.py``, and their results are kept under their output names.
+
 The per-node arithmetic lives in ``hvx_oracle.c`` (plain C, compiled with gcc
 on first use).  Real-valued nodes (the corner graph) run in double precision:
 their images are ``float64`` arrays here.
@@ -33,6 +38,9 @@ BORDERS = {"undefined": 0, "constant": 1, "replicate": 2, "mirror": 3, "repeat":
 # Window radius of each local operator (point operators have radius 0).
 RADIUS = {"gaussian3x3": 1, "gaussian5x5": 2, "box3x3": 1, "sobel3x3": 1, "box5x5_f32": 2, "dilate3x3": 1,
           "erode3x3": 1, "median3x3": 1}
+
+# Nodes whose results are a few values rather than an image (Table 2).
+GLOBAL_OPS = ("histogram", "min_max", "min_max_loc", "mean_std_dev")
 
 _lib = None
 
@@ -316,6 +324,22 @@ def _run_node(n: Node, env: dict):
     elif n.op == "custom_local":
         from . import custom
         res = [custom.evaluate_local(p["expr"], ins[0], p["out_dtype"], b, c)]
+    elif n.op == "histogram":
+        from . import globalops
+        res = [globalops.histogram(ins[0], p["bins"], p.get("offset", 0), p.get("range", 256))]
+    elif n.op == "min_max":
+        from . import globalops
+        res = [globalops.min_max(ins[0])]
+    elif n.op == "min_max_loc":
+        from . import globalops
+        mn, mx, cmin, cmax, lmin, lmax = globalops.min_max_loc(ins[0])
+        res = [(mn, mx, cmin, cmax), (lmin, lmax)]
+    elif n.op == "mean_std_dev":
+        from . import globalops
+        res = [globalops.mean_std_dev(ins[0])]
+    elif n.op == "equalize_hist":
+        from . import globalops
+        res = [globalops.equalize_hist(ins[0])]
     else:
         raise ValueError("unknown op " + n.op)
     for name, val in zip(n.outputs, res):
@@ -359,6 +383,8 @@ def valid_masks(graph: Graph, shapes: dict) -> dict:
     ``shapes`` gives (H, W) of the graph inputs (UYVY given in pixels)."""
     env = {k: np.ones(s, bool) for k, s in shapes.items()}
     for n in _topo(graph.nodes):
+        if n.op in GLOBAL_OPS:  # results are values, not images
+            continue
         ins = [env[name] for name in n.inputs]
         rx, ry = _radius(n)
         h, w = ins[0].shape

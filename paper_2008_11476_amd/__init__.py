@@ -90,6 +90,12 @@ def _load():
         "hvx_equalize_hist": [_vp, _vp, _vp, _vp, _vp],
         "hvx_equalize_hist_noalloc": [_vp, _vp, _vp, _vp],
         "hvx_min_max_loc": [_vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp],
+        "hvx_buffer_from_ptr": [_vp, _vp, ctypes.c_size_t, _P(_vp)],
+        "hvx_histogram_node": [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _vp, _P(_vp)],
+        "hvx_min_max_node": [_vp, _vp, _vp, _P(_vp)],
+        "hvx_min_max_loc_node": [_vp, _vp, _vp, _vp, ctypes.c_uint32, _P(_vp)],
+        "hvx_mean_std_dev_node": [_vp, _vp, _vp, _P(_vp)],
+        "hvx_equalize_hist_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_box5x5_f32_node": [_vp, _vp, _vp, _P(_vp)],
         "hvx_sobel3x3_node": [_vp, _vp, _vp, _vp, _P(_vp)],
         "hvx_magnitude_node": [_vp, _vp, _vp, _vp, _P(_vp)],
@@ -129,6 +135,7 @@ def _load():
         "hvx_release_convolution": [_P(_vp)],
         "hvx_release_batch": [_P(_vp)],
         "hvx_release_server": [_P(_vp)],
+        "hvx_release_buffer": [_P(_vp)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -301,6 +308,32 @@ def hvx_equalize_hist_noalloc(ctx, img, out, stream=None):
 
 def hvx_mean_std_dev(ctx, img, dev_result, stream=None):
     _check(_load().hvx_mean_std_dev(ctx, img, dev_result, stream), ctx)
+
+
+def hvx_buffer_from_ptr(ctx, ptr, nbytes):
+    """Wrap `nbytes` of caller-owned device memory (8-byte aligned) as the
+    result buffer of a global operator node."""
+    return _out(_load().hvx_buffer_from_ptr, ctx, ctx, ptr, nbytes)
+
+
+def hvx_histogram_node(g, i, num_bins, offset, rng, counts, ctx=None):
+    return _node("hvx_histogram_node", ctx, g, i, num_bins, offset, rng, counts)
+
+
+def hvx_min_max_node(g, i, result, ctx=None):
+    return _node("hvx_min_max_node", ctx, g, i, result)
+
+
+def hvx_min_max_loc_node(g, i, result, locations, capacity, ctx=None):
+    return _node("hvx_min_max_loc_node", ctx, g, i, result, locations, capacity)
+
+
+def hvx_mean_std_dev_node(g, i, result, ctx=None):
+    return _node("hvx_mean_std_dev_node", ctx, g, i, result)
+
+
+def hvx_equalize_hist_node(g, i, o, ctx=None):
+    return _node("hvx_equalize_hist_node", ctx, g, i, o)
 
 
 def hvx_custom_local_node(g, expr, i, out_format, o, ctx=None):
@@ -481,6 +514,10 @@ def hvx_release_batch(h):
 
 def hvx_release_server(h):
     _release("hvx_release_server", h)
+
+
+def hvx_release_buffer(h):
+    _release("hvx_release_buffer", h)
 
 
 # ---- torch marshalling helpers ----------------------------------------------------------

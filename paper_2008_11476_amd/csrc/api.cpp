@@ -149,7 +149,7 @@ hvx_status hvx_context_release(hvx_context* pctx) {
   for (Object* o : kids)
     if (o->type == T_GRAPH) destroy_graph((Graph*)o);
   for (Object* o : kids) {
-    if (o->type == T_IMAGE) destroy_image((Image*)o);
+    if (o->type == T_IMAGE || o->type == T_BUFFER) destroy_image((Image*)o);
     else if (o->type == T_CONV || o->type == T_NODE) {
       registry_remove(o);
       delete o;
@@ -323,6 +323,32 @@ hvx_status hvx_convolution_create(hvx_context ctx, uint32_t cols, uint32_t rows,
   return HVX_SUCCESS;
 }
 
+hvx_status hvx_buffer_from_ptr(hvx_context ctx, void* dev_ptr, size_t bytes, hvx_buffer* out) {
+  Context* c = as<Context>(ctx, T_CONTEXT);
+  if (!c) return HVX_ERROR_INVALID_REFERENCE;
+  if (!out) return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "null output handle");
+  *out = nullptr;
+  if (!dev_ptr || ((uintptr_t)dev_ptr & 7))
+    return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "buffer pointer null or not 8-byte aligned");
+  if (bytes == 0 || bytes > ((size_t)1 << 31))
+    return set_error(c, HVX_ERROR_INVALID_DIMENSION, "buffer size %zu out of range", bytes);
+  Image* b = new Image();
+  b->type = T_BUFFER;
+  b->ctx = c;
+  b->w = (uint32_t)bytes;
+  b->h = 1;
+  b->df = DF_BUF;
+  b->ptr = dev_ptr;
+  b->pitch = bytes;
+  registry_add(b);
+  {
+    std::lock_guard<std::recursive_mutex> l(c->mu);
+    c->children.push_back(b);
+  }
+  *out = (hvx_buffer)b;
+  return HVX_SUCCESS;
+}
+
 // ---- graph and nodes -------------------------------------------------------
 
 hvx_status hvx_graph_create(hvx_context ctx, hvx_graph* out) {
@@ -457,6 +483,77 @@ hvx_status hvx_threshold_node(hvx_graph g, hvx_image in, double value, uint8_t t
   }
   return s;
 }
+// Global operator nodes: one image in, result buffers out (a NULL buffer
+// only where the call allows it).
+static hvx_status add_global_node(hvx_graph graph, int kind, hvx_image in, std::initializer_list<hvx_buffer> outs,
+                                  int min_outs, hvx_node* node_out, Node** made) {
+  Graph* g = as<Graph>(graph, T_GRAPH);
+  if (!g) return HVX_ERROR_INVALID_REFERENCE;
+  if (node_out) *node_out = nullptr;
+  if (!registry_check(in, T_IMAGE)) return set_error(g->ctx, HVX_ERROR_INVALID_REFERENCE, "invalid input image");
+  if (((Image*)in)->ctx != g->ctx)
+    return set_error(g->ctx, HVX_ERROR_INVALID_GRAPH, "input image belongs to another context");
+  int present = 0;
+  for (hvx_buffer b : outs) {
+    if (!b) continue;
+    if (!registry_check(b, T_BUFFER)) return set_error(g->ctx, HVX_ERROR_INVALID_REFERENCE, "invalid result buffer");
+    if (((Image*)b)->ctx != g->ctx)
+      return set_error(g->ctx, HVX_ERROR_INVALID_GRAPH, "result buffer belongs to another context");
+    ++present;
+  }
+  if (present < min_outs) return set_error(g->ctx, HVX_ERROR_INVALID_PARAMETERS, "missing result buffer");
+  Node* n = new Node();
+  n->type = T_NODE;
+  n->ctx = g->ctx;
+  n->g = g;
+  n->kind = kind;
+  n->in.push_back((Image*)in);
+  for (hvx_buffer b : outs) n->out.push_back((Image*)b);
+  registry_add(n);
+  g->nodes.push_back(n);
+  invalidate(g);
+  if (node_out) *node_out = (hvx_node)n;
+  if (made) *made = n;
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_histogram_node(hvx_graph g, hvx_image in, uint32_t num_bins, uint32_t offset, uint32_t range,
+                              hvx_buffer counts, hvx_node* no) {
+  Graph* gg = as<Graph>(g, T_GRAPH);
+  if (!gg) return HVX_ERROR_INVALID_REFERENCE;
+  if (num_bins < 1 || num_bins > 256 || range < num_bins || offset + (uint64_t)range > 256)
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "need 1 <= num_bins <= range and offset + range <= 256");
+  Node* n = nullptr;
+  hvx_status s = add_global_node(g, NK_HISTOGRAM, in, {counts}, 1, no, &n);
+  if (!s) {
+    n->gp[0] = num_bins;
+    n->gp[1] = offset;
+    n->gp[2] = range;
+  }
+  return s;
+}
+hvx_status hvx_min_max_node(hvx_graph g, hvx_image in, hvx_buffer result, hvx_node* no) {
+  return add_global_node(g, NK_MINMAX, in, {result}, 1, no, nullptr);
+}
+hvx_status hvx_min_max_loc_node(hvx_graph g, hvx_image in, hvx_buffer result, hvx_buffer locations,
+                                uint32_t capacity, hvx_node* no) {
+  Graph* gg = as<Graph>(g, T_GRAPH);
+  if (!gg) return HVX_ERROR_INVALID_REFERENCE;
+  if ((capacity == 0) != (locations == nullptr))
+    return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "locations and a capacity go together");
+  if (capacity > (1u << 24)) return set_error(gg->ctx, HVX_ERROR_INVALID_PARAMETERS, "capacity above 2^24");
+  Node* n = nullptr;
+  hvx_status s = add_global_node(g, NK_MINMAXLOC, in, {result, locations}, 1, no, &n);
+  if (!s) n->gp[0] = capacity;
+  return s;
+}
+hvx_status hvx_mean_std_dev_node(hvx_graph g, hvx_image in, hvx_buffer result, hvx_node* no) {
+  return add_global_node(g, NK_MEANSTD, in, {result}, 1, no, nullptr);
+}
+hvx_status hvx_equalize_hist_node(hvx_graph g, hvx_image in, hvx_image out, hvx_node* no) {
+  return add_node(g, NK_EQHIST, {in}, {out}, 1, no, nullptr);
+}
+
 hvx_status hvx_convolve_node(hvx_graph g, hvx_image in, hvx_convolution conv, hvx_image out, hvx_node* no) {
   Graph* gg = as<Graph>(g, T_GRAPH);
   if (!gg) return HVX_ERROR_INVALID_REFERENCE;
@@ -587,7 +684,8 @@ hvx_status hvx_min_max_count(hvx_context ctx, hvx_image in, int32_t* dev_result,
   GlobalImg gi;
   hvx_status s = global_input(ctx, in, {DF_U8, DF_S16}, &gi);
   if (s) return s;
-  if (!dev_result) return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "null result buffer");
+  if (!dev_result || ((uintptr_t)dev_result & 7))
+    return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "result buffer null or not 8-byte aligned");
   return launched(ctx, launch_min_max_count(gi, dev_result, (hipStream_t)stream));
 }
 
@@ -596,8 +694,9 @@ hvx_status hvx_min_max_loc(hvx_context ctx, hvx_image in, int32_t* dev_result, u
   GlobalImg gi;
   hvx_status s = global_input(ctx, in, {DF_U8, DF_S16}, &gi);
   if (s) return s;
-  if (!dev_result || (capacity && (!dev_min_locs || !dev_max_locs)))
-    return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS, "null result or location buffer");
+  if (!dev_result || ((uintptr_t)dev_result & 7) || (capacity && (!dev_min_locs || !dev_max_locs)))
+    return set_error(as<Context>(ctx, T_CONTEXT), HVX_ERROR_INVALID_PARAMETERS,
+                     "null result or location buffer, or a result not 8-byte aligned");
   return launched(ctx, launch_min_max_loc(gi, dev_result, dev_min_locs, dev_max_locs, capacity, (hipStream_t)stream));
 }
 
@@ -748,7 +847,7 @@ hvx_status hvx_graph_query(hvx_graph graph, int attr, int64_t* out) {
       break;
     }
     case HVX_QUERY_ROWS_PER_ITEM:
-      *out = (p.groups.empty() || p.groups[0].kind == FK_GENERIC) ? 0 : rows_for(g, p.groups[0]);
+      *out = (p.groups.empty() || !is_strip_kind(p.groups[0].kind)) ? 0 : rows_for(g, p.groups[0]);
       break;
     default: return set_error(g->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown query %d", attr);
   }
@@ -835,6 +934,28 @@ hvx_status hvx_release_convolution(hvx_convolution* pc) {
     delete cv;
   }
   *pc = nullptr;
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_release_buffer(hvx_buffer* pb) {
+  if (!pb) return HVX_ERROR_INVALID_PARAMETERS;
+  Image* b = as<Image>(*pb, T_BUFFER);
+  if (!b) return HVX_ERROR_INVALID_REFERENCE;
+  Context* c = b->ctx;
+  bool used = false;
+  {
+    std::lock_guard<std::recursive_mutex> l(c->mu);
+    for (Object* o : c->children)
+      if (o->type == T_GRAPH)
+        for (Node* n : ((Graph*)o)->nodes)
+          for (Image* x : n->out) used |= x == b;
+  }
+  registry_remove(b);
+  if (!used) {
+    remove_child(c, b);
+    delete b;
+  }
+  *pb = nullptr;
   return HVX_SUCCESS;
 }
 

@@ -365,6 +365,9 @@ struct EdgeStream {
   __device__ __forceinline__ void unpk(u32x4 r, int y, u32 p[8]) const {
     unpack16(r, p);
     if (!repl0 && (y < 0 || y >= H)) {
+      // a rare, wave-uniform case: the empty asm keeps it a branch (the
+      // compiler would otherwise select all eight registers on every row)
+      asm volatile("");
 #pragma unroll
       for (int k = 0; k < 8; ++k) p[k] = cin;
     }
@@ -624,6 +627,7 @@ struct G5Stream {
       unpack16(r[0], p);
     }
     if (!repl && (y < 0 || y >= H)) {
+      asm volatile("");  // keep the rare case a branch (see EdgeStream::unpk)
 #pragma unroll
       for (int k = 0; k < 8; ++k) p[k] = cin;
     }

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include "dev_phase.hpp"
+#include "dev_reduce.hpp"
 
 #include "hvx_desc.h"
 
@@ -45,6 +46,7 @@ __device__ __forceinline__ void gstore(int df, void* base, int64_t pitch, int x,
 
 struct TileCtx {
   const GProg* P;
+  const IOTable* io;
   const int32_t* lds;
   int tx0, ty0;
 };
@@ -107,7 +109,13 @@ __device__ __forceinline__ int sat_s16(int v) { return min(max(v, -32768), 32767
 
 __host__ __device__ inline bool is_point_op(int kind) {
   return kind == OP_CHANNEL_Y || kind == OP_MAGNITUDE || kind == OP_PHASE || kind == OP_THRESHOLD ||
-         kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS || kind == OP_EXPR;
+         kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS || kind == OP_EXPR || kind == OP_LUT;
+}
+
+// The EqualizeHist mapping table of an OP_LUT operator: the 256 bytes after
+// the counts in its second input, a buffer in device memory.
+__device__ __forceinline__ const uint8_t* lut_table(const GProg& P, const IOTable& io, const GOp& o) {
+  return (const uint8_t*)io.ptr[P.vals[o.in[1]].io] + 256 * 4;
 }
 
 // A user kernel (Section 5.1) at one pixel: its postfix program.  in(op,
@@ -442,6 +450,7 @@ struct TileRd {
 template <bool NL>
 __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, int y) {
   const GProg& P = *t.P;
+  if (o.kind == OP_LUT) return lut_table(P, *t.io, o)[rd(t, o, o.in[0], x, y) & 0xFF];
   if (is_point_op(o.kind)) {
     const int a = rd(t, o, o.in[0], x, y);
     const int b = o.in[1] >= 0 ? rd(t, o, o.in[1], x, y) : 0;
@@ -452,11 +461,147 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
   return local_eval<NL>(o, P.vals[o.out].df, TileRd{&t, &o, vi, x, y});
 }
 
-// One tile of a generic program.  `lds` holds P.lds_words words.
-template <int NT, bool NL>
-__device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_t* lds) {
+// ---- global operators reduced over the tiles of a fused kernel --------------
+// A work-group visits many tiles; for each global operator of the program
+// (slot r, in program order) every thread keeps running partial results over
+// the pixels it evaluates, the histogram counts go to an LDS histogram of the
+// group, and the group merges everything into the operator's result once, at
+// the end.  Only the tile's own pixels count (never the halo), so each pixel
+// of the image is counted once.
+struct RedState {
+  int mn[kMaxRed], mx[kMaxRed];
+  uint32_t cmn[kMaxRed], cmx[kMaxRed];
+  unsigned long long s1[kMaxRed], s2[kMaxRed];
+  uint32_t* hist;  // kHistWords words of LDS
+};
+
+template <int NT>
+__device__ __forceinline__ void red_begin(RedState& r, uint32_t* hist) {
+#pragma unroll
+  for (int k = 0; k < kMaxRed; ++k) {
+    r.mn[k] = 2147483647;
+    r.mx[k] = -2147483647 - 1;
+    r.cmn[k] = r.cmx[k] = 0;
+    r.s1[k] = r.s2[k] = 0;
+  }
+  r.hist = hist;
+  for (int b = threadIdx.x; b < kHistWords; b += NT) hist[b] = 0;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void red_add(RedState& r, int k, const GOp& o, int v) {
+  switch (o.kind) {
+    case OP_HISTOGRAM:
+    case OP_EQHIST: {
+      const uint32_t x = (uint32_t)(v - o.p1);
+      atomicAdd(&r.hist[x < (uint32_t)o.p2 ? x * (uint32_t)o.p0 / (uint32_t)o.p2 : 256u], 1u);
+      break;
+    }
+    case OP_MMCOUNT:
+      r.cmn[k] = v < r.mn[k] ? 1u : r.cmn[k] + (v == r.mn[k] ? 1u : 0u);
+      r.cmx[k] = v > r.mx[k] ? 1u : r.cmx[k] + (v == r.mx[k] ? 1u : 0u);
+      r.mn[k] = min(r.mn[k], v);
+      r.mx[k] = max(r.mx[k], v);
+      break;
+    case OP_MINMAX:
+      r.mn[k] = min(r.mn[k], v);
+      r.mx[k] = max(r.mx[k], v);
+      break;
+    case OP_SUMS:
+      r.s1[k] += (unsigned)v;
+      r.s2[k] += (unsigned)(v * v);
+      break;
+  }
+}
+
+// The group's partial results merged into the operators' results: waves
+// reduce by lane exchange, the group through LDS, and one thread applies
+// one atomic (or compare-and-swap loop) per result word.
+template <int NT>
+__device__ void red_end(const GProg& P, const IOTable& io, RedState& r) {
+  __shared__ unsigned long long part[4][NT / 64];
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  __syncthreads();  // the LDS histogram is complete
+  int k = 0;
+  for (int oi = 0; oi < P.nops; ++oi) {
+    const GOp& o = P.ops[oi];
+    if (!is_reduce_op(o.kind)) continue;
+    void* out = io.ptr[P.vals[o.out].io];
+    if (o.kind == OP_HISTOGRAM || o.kind == OP_EQHIST) {
+      for (int b = t; b < o.p0; b += NT)
+        if (r.hist[b]) atomicAdd((uint32_t*)out + b, r.hist[b]);
+    } else {
+      int mn = r.mn[k], mx = r.mx[k];
+      uint32_t cmn = r.cmn[k], cmx = r.cmx[k];
+      unsigned long long s1 = r.s1[k], s2 = r.s2[k];
+      if (o.kind == OP_SUMS) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          s1 += __shfl_xor(s1, off);
+          s2 += __shfl_xor(s2, off);
+        }
+      } else if (o.kind == OP_MINMAX) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          mn = min(mn, __shfl_xor(mn, off));
+          mx = max(mx, __shfl_xor(mx, off));
+        }
+      } else {
+        wave_merge_extremes(mn, cmn, mx, cmx);
+      }
+      if (lane == 0) {
+        if (o.kind == OP_SUMS) {
+          part[0][wv] = s1;
+          part[1][wv] = s2;
+        } else {
+          // a wave that saw no pixel holds the identities INT_MAX / INT_MIN,
+          // which are no pixel values: it contributes the neutral keys
+          part[0][wv] = o.kind == OP_MINMAX ? (unsigned long long)(unsigned)mn : (cmn ? mm_key(mn, cmn) : kMinKeyInit);
+          part[1][wv] = o.kind == OP_MINMAX ? (unsigned long long)(unsigned)mx : (cmx ? mm_key(mx, cmx) : kMaxKeyInit);
+        }
+      }
+      __syncthreads();
+      if (t == 0) {
+        if (o.kind == OP_SUMS) {
+          for (int w = 1; w < NT / 64; ++w) {
+            s1 += part[0][w];
+            s2 += part[1][w];
+          }
+          atomicAdd((unsigned long long*)out, s1);
+          atomicAdd((unsigned long long*)out + 1, s2);
+        } else if (o.kind == OP_MINMAX) {
+          for (int w = 1; w < NT / 64; ++w) {
+            mn = min(mn, (int)(unsigned)part[0][w]);
+            mx = max(mx, (int)(unsigned)part[1][w]);
+          }
+          int32_t* mm = (int32_t*)out;
+          if (mn < __atomic_load_n(&mm[0], __ATOMIC_RELAXED)) atomicMin(&mm[0], mn);
+          if (mx > __atomic_load_n(&mm[1], __ATOMIC_RELAXED)) atomicMax(&mm[1], mx);
+        } else {
+          unsigned long long kmin = kMinKeyInit, kmax = kMaxKeyInit;
+          for (int w = 0; w < NT / 64; ++w) {
+            kmin = mm_merge(kmin, part[0][w], true);
+            kmax = mm_merge(kmax, part[1][w], false);
+          }
+          unsigned long long* keys = (unsigned long long*)((uint8_t*)out + kMMKeyOffset);
+          const int sub = blockIdx.x % kMMSubKeys;
+          merge_key(&keys[sub], kmin, true);
+          merge_key(&keys[kMMSubKeys + sub], kmax, false);
+        }
+      }
+      __syncthreads();
+    }
+    ++k;
+  }
+}
+
+// One tile of a generic program.  `lds` holds P.lds_words words.  RED: the
+// program holds global operators, reduced into `red`.
+template <int NT, bool NL, bool RED>
+__device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_t* lds, RedState* red) {
   TileCtx t;
   t.P = &P;
+  t.io = &io;
   t.lds = lds;
   t.tx0 = (tile % P.tiles_x) * P.tw;
   t.ty0 = (tile / P.tiles_x) * P.th;
@@ -484,8 +629,23 @@ __device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_
         lds[v.lds + (yy - y0) * rw + (xx - x0)] = gload(v.df, base, pitch, xx, yy);
   }
   __syncthreads();
+  int slot = 0;
   for (int oi = 0; oi < P.nops; ++oi) {
     const GOp& o = P.ops[oi];
+    if constexpr (RED) {
+      if (is_reduce_op(o.kind)) {
+        // the tile's own pixels of the input, read from its LDS tile
+        const int x1 = min(t.tx0 + P.tw, W), y1 = min(t.ty0 + P.th, H);
+        for (int yy = t.ty0 + (int)(threadIdx.x >> 6); yy < y1; yy += NT / 64)
+          for (int xx = t.tx0 + (int)(threadIdx.x & 63); xx < x1; xx += 64)
+            red_add(*red, slot, o, rd(t, o, o.in[0], xx, yy));
+        ++slot;
+        // the LDS the input occupies may be reused by the next operator's
+        // output or the next tile's loads: every thread must be done reading
+        __syncthreads();
+        continue;
+      }
+    }
     const GVal& ov = P.vals[o.out];
     const int e = ov.lds >= 0 ? ov.ext : 0;
     const int rw = P.tw + 2 * e;
@@ -589,13 +749,20 @@ __device__ __forceinline__ void point_image(const GProg& P, const IOTable& io) {
   for (int i = 0; i < 3; ++i) {
     if (o.in[i] < 0) continue;
     const GVal& v = P.vals[o.in[i]];
+    if (v.df == DF_BUF) continue;  // a table (OP_LUT), read below
     load4(v.df, (const uint8_t*)io.ptr[v.io] + (size_t)y * io.pitch[v.io], x, W, a[i]);
   }
   const GVal& ov = P.vals[o.out];
   const bool in_f32 = P.vals[o.in[0]].df == DF_F32;
   int r[4];
+  if (o.kind == OP_LUT) {
+    const uint8_t* tab = lut_table(P, io, o);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r[k] = point_eval(o, ov.df, in_f32, a[0][k], a[1][k], a[2][k]);
+    for (int k = 0; k < 4; ++k) r[k] = tab[a[0][k] & 0xFF];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = point_eval(o, ov.df, in_f32, a[0][k], a[1][k], a[2][k]);
+  }
   store4(ov.df, (uint8_t*)io.ptr[ov.io] + (size_t)y * io.pitch[ov.io], x, W, r);
 }
 

@@ -25,6 +25,19 @@ hipError_t launch_min_max_loc(const GlobalImg& im, int32_t* result, uint32_t* lm
 hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_pitch, void* workspace,
                                 hipStream_t s);
 hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s);
+// the location pass of min_max_loc alone, after a min_max_count into `result`
+hipError_t launch_extreme_locs(const GlobalImg& im, int32_t* result, uint32_t* lmin, uint32_t* lmax, uint32_t cap,
+                               hipStream_t s);
+// result[4..5] := min(result[4..5], cap): the locations each list holds
+hipError_t launch_clamp_slots(int32_t* result, uint32_t cap, hipStream_t s);
+// histogram and EqualizeHist mapping into `workspace` (counts, then the table)
+hipError_t launch_equalize_mapping(const GlobalImg& im, void* workspace, hipStream_t s);
+// starting value and final step of a global operator (OP_*) that fused
+// kernels reduce into `result`
+hipError_t launch_reduce_init(int kind, void* result, int num_bins, hipStream_t s);
+hipError_t launch_reduce_finish(int kind, void* result, long long npix, hipStream_t s);
+// n uint32 words of device memory set to zero
+hipError_t launch_zero_words(void* p, int n, hipStream_t s);
 
 // Bytes of the fixed device array that replaces the EqualizeHist workspace
 // (256 uint32 counts, then the 256-byte mapping).

@@ -13,7 +13,9 @@
 
 #include <mutex>
 
+#include "dev_reduce.hpp"
 #include "global.h"
+#include "hvx_desc.h"
 
 namespace hvx {
 
@@ -26,6 +28,7 @@ constexpr int kGThreads = 256;
 // whole 1024-thread group in LDS first and launch one group per CU.
 constexpr int kRThreads = 1024;
 constexpr int kRGroups = 256;
+static_assert(kRGroups <= kMMSubKeys, "one counting key per group");
 
 static int global_grid(const GlobalImg& im, int rows_in_flight, int cap) {
   const int g = (im.h + rows_in_flight - 1) / rows_in_flight;
@@ -159,18 +162,22 @@ __global__ __launch_bounds__(kGThreads) void k_apply_lut(GlobalImg im, const uin
   }
 }
 
-hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_pitch, void* workspace,
-                                hipStream_t s) {
-  static_assert(256 * 4 + 256 <= kEqualizeScratchBytes, "the fixed workspace holds the counts and the mapping");
+hipError_t launch_equalize_mapping(const GlobalImg& im, void* workspace, hipStream_t s) {
+  static_assert(kEqHistBytes <= (int)kEqualizeScratchBytes, "the fixed workspace holds the counts and the mapping");
   uint32_t* hist = (uint32_t*)workspace;
   uint8_t* lut = (uint8_t*)workspace + 256 * 4;
   hipError_t e = launch_histogram(im, 256, 0, 256, hist, s);
   if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
   hipLaunchKernelGGL(k_eq_lut, dim3(1), dim3(256), 0, s, (const uint32_t*)hist, lut, (long long)im.w * im.h);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_apply_lut, dim3(im.h < 2048 ? im.h : 2048), dim3(kGThreads), 0, s, im, (const uint8_t*)lut,
-                     out, out_pitch);
+  return hipGetLastError();
+}
+
+hipError_t launch_equalize_hist(const GlobalImg& im, uint8_t* out, int64_t out_pitch, void* workspace,
+                                hipStream_t s) {
+  const uint8_t* lut = (const uint8_t*)workspace + 256 * 4;
+  hipError_t e = launch_equalize_mapping(im, workspace, s);
+  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
+  hipLaunchKernelGGL(k_apply_lut, dim3(im.h < 2048 ? im.h : 2048), dim3(kGThreads), 0, s, im, lut, out, out_pitch);
   return hipGetLastError();
 }
 
@@ -244,128 +251,255 @@ __global__ __launch_bounds__(kRThreads) void k_min_max(GlobalImg im, int32_t* __
   }
 }
 
-// Pixels equal to the smallest and to the largest value, which the min/max
-// kernel left in mm[0], mm[1] earlier in the same stream; added to mm[2],
-// mm[3] (one atomic pair per group, after a group reduction in LDS).
+// Number of elements of the 32-bit word w equal to the element value whose
+// copies fill `splat` (SWAR: an element of x = w ^ splat is zero exactly
+// where w matches; adding 0x7F.. to its low bits sets its top bit unless the
+// element is zero, and no carry crosses an element), added to acc.
 template <bool S16>
-__global__ __launch_bounds__(kRThreads) void k_count_extremes(GlobalImg im, int32_t* __restrict__ mm) {
+__device__ __forceinline__ uint32_t count_eq(uint32_t w, uint32_t splat, uint32_t acc) {
+  const uint32_t lo = S16 ? 0x7FFF7FFFu : 0x7F7F7F7Fu, hi = S16 ? 0x80008000u : 0x80808080u;
+  const uint32_t x = w ^ splat;
+  const uint32_t y = ((x & lo) + lo) | x;
+  return acc + (uint32_t)__popc(~y & hi);
+}
+
+// One pass for the smallest and the largest value and how many pixels take
+// each.  Every lane keeps a running (value, count) pair per extreme: for each
+// 16-byte chunk it takes the chunk's extremes, restarts a count when the
+// value improves, and adds the chunk's matches counted word-wise.  The pairs
+// are merged across the wave and the group, then into the group's own
+// 64-bit key of each extreme (at most kMMSubKeys groups run, so no two share
+// a key and the compare-and-swap never retries; see kMMSubKeys).
+template <bool S16>
+__global__ __launch_bounds__(kRThreads) void k_min_max_count(GlobalImg im, unsigned long long* __restrict__ keys) {
   constexpr int kPer = S16 ? 8 : 16;
-  __shared__ int part[2][kRThreads / 64];
-  const int lo = mm[0], hi = mm[1];
-  int cl = 0, ch = 0;
+  __shared__ int part[4][kRThreads / 64];
+  int mn = S16 ? 32767 : 255, mx = S16 ? -32768 : 0;
+  uint32_t cmn = 0, cmx = 0;
   const int t = threadIdx.x;
   stream_image<kPer, kRThreads, 4>(im, [&](const uint4& q, int n) {
     const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+    if (n == kPer) {
+      int a = S16 ? 32767 : 255, b = S16 ? -32768 : 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
-      cl += (k < n && v == lo) ? 1 : 0;
-      ch += (k < n && v == hi) ? 1 : 0;
+      for (int k = 0; k < kPer; ++k) {
+        const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
+        a = min(a, v);
+        b = max(b, v);
+      }
+      cmn = a < mn ? 0u : cmn;
+      cmx = b > mx ? 0u : cmx;
+      mn = min(mn, a);
+      mx = max(mx, b);
+      const uint32_t sl = S16 ? ((uint32_t)mn & 0xFFFFu) * 0x10001u : (uint32_t)mn * 0x01010101u;
+      const uint32_t sh = S16 ? ((uint32_t)mx & 0xFFFFu) * 0x10001u : (uint32_t)mx * 0x01010101u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cmn = count_eq<S16>(wd[j], sl, cmn);
+        cmx = count_eq<S16>(wd[j], sh, cmx);
+      }
+    } else {  // the last chunk of a row: element by element
+      for (int k = 0; k < n; ++k) {
+        const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
+        cmn = v < mn ? 1u : cmn + (v == mn ? 1u : 0u);
+        cmx = v > mx ? 1u : cmx + (v == mx ? 1u : 0u);
+        mn = min(mn, v);
+        mx = max(mx, v);
+      }
     }
   });
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    cl += __shfl_xor(cl, off);
-    ch += __shfl_xor(ch, off);
-  }
+  wave_merge_extremes(mn, cmn, mx, cmx);
   if ((t & 63) == 0) {
-    part[0][t >> 6] = cl;
-    part[1][t >> 6] = ch;
+    part[0][t >> 6] = mn;
+    part[1][t >> 6] = (int)cmn;
+    part[2][t >> 6] = mx;
+    part[3][t >> 6] = (int)cmx;
   }
   __syncthreads();
   if (t == 0) {
-    for (int w = 1; w < kRThreads / 64; ++w) {
-      cl += part[0][w];
-      ch += part[1][w];
+    unsigned long long kmin = kMinKeyInit, kmax = kMaxKeyInit;
+    for (int w = 0; w < kRThreads / 64; ++w) {
+      kmin = mm_merge(kmin, mm_key(part[0][w], (uint32_t)part[1][w]), true);
+      kmax = mm_merge(kmax, mm_key(part[2][w], (uint32_t)part[3][w]), false);
     }
-    if (cl) atomicAdd(&mm[2], cl);
-    if (ch) atomicAdd(&mm[3], ch);
+    const int sub = blockIdx.x % kMMSubKeys;
+    merge_key(&keys[sub], kmin, true);
+    merge_key(&keys[kMMSubKeys + sub], kmax, false);
   }
+}
+
+// The sub-keys merged into {min, max, count of min, count of max} at the
+// front of the result.
+// (One wave: each lane merges every 64th key, then the lanes merge by
+// exchange.)
+__global__ __launch_bounds__(64) void k_unpack_keys(int32_t* __restrict__ mm) {
+  const unsigned long long* k = (const unsigned long long*)((uint8_t*)mm + kMMKeyOffset);
+  const int lane = threadIdx.x;
+  unsigned long long kmin = kMinKeyInit, kmax = kMaxKeyInit;
+  for (int i = lane; i < kMMSubKeys; i += 64) {
+    kmin = mm_merge(kmin, k[i], true);
+    kmax = mm_merge(kmax, k[kMMSubKeys + i], false);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    kmin = mm_merge(kmin, __shfl_xor(kmin, off), true);
+    kmax = mm_merge(kmax, __shfl_xor(kmax, off), false);
+  }
+  if (lane == 0) {
+    mm[0] = mm_value(kmin);
+    mm[1] = mm_value(kmax);
+    mm[2] = (int32_t)(uint32_t)kmin;
+    mm[3] = (int32_t)(uint32_t)kmax;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_init_keys(int32_t* __restrict__ mm) {
+  unsigned long long* k = (unsigned long long*)((uint8_t*)mm + kMMKeyOffset);
+  for (int i = threadIdx.x; i < 2 * kMMSubKeys; i += blockDim.x) k[i] = i < kMMSubKeys ? kMinKeyInit : kMaxKeyInit;
+}
+
+hipError_t launch_min_max_count(const GlobalImg& im, int32_t* result, hipStream_t s) {
+  unsigned long long* keys = (unsigned long long*)((uint8_t*)result + kMMKeyOffset);
+  hipLaunchKernelGGL(k_init_keys, dim3(1), dim3(256), 0, s, result);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (im.w > 0 && im.h > 0) {
+    const dim3 grid(global_grid(im, 4, kRGroups));
+    if (im.bpp == 2) hipLaunchKernelGGL(k_min_max_count<true>, grid, dim3(kRThreads), 0, s, im, keys);
+    else hipLaunchKernelGGL(k_min_max_count<false>, grid, dim3(kRThreads), 0, s, im, keys);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_unpack_keys, dim3(1), dim3(64), 0, s, result);
+  return hipGetLastError();
 }
 
 // MinMaxLoc: the (x, y) of pixels equal to mm[0] (into lmin) and to mm[1]
 // (into lmax), two words per location, at most `cap` of each list, in no
 // particular order; mm[4], mm[5] count the reserved slots (the exact counts
-// come from k_count_extremes).  Each lane marks the matches of its 16-byte
-// chunk; a scan across the wave gives each lane its offset and one atomic per
-// wave and list reserves the slots.  Once a list is full (read without an
-// atomic: a stale value only costs one more atomic) the wave skips it, so an
-// extreme that occurs millions of times does not serialise on its counter.
-// The chunk loop steps on a wave-uniform base so every lane takes part in
-// the lane exchanges.
+// come from k_min_max_count).  One 1024-thread group per CU streams K rows a
+// grid apart per step, one 16-byte chunk per lane and row.  Each lane marks
+// its matches, the counts are scanned across the wave and summed over the
+// group in LDS, and one thread reserves the group's slots of each list with
+// a single atomic; then every lane writes its entries.  Once both lists are
+// full the groups stop (thread 0 reads the counters and the decision goes
+// through LDS, so the whole group leaves together).
 template <bool S16>
-__global__ __launch_bounds__(kGThreads) void k_extreme_locs(GlobalImg im, int32_t* __restrict__ mm,
+__global__ __launch_bounds__(kRThreads) void k_extreme_locs(GlobalImg im, int32_t* __restrict__ mm,
                                                             uint32_t* __restrict__ lmin, uint32_t* __restrict__ lmax,
                                                             uint32_t cap) {
-  constexpr int kPer = S16 ? 8 : 16;
+  constexpr int kPer = S16 ? 8 : 16, K = 4, NW = kRThreads / 64;
+  __shared__ uint32_t wtot[2][NW];  // wave totals, then their exclusive prefix
+  __shared__ uint32_t gbase[2];     // the group's first slot of each list (cap: none)
+  __shared__ int stop;
   const int lo = mm[0], hi = mm[1];
-  const int t = threadIdx.x, lane = t & 63;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int chunks = (im.w + kPer - 1) / kPer;
-  for (int y = blockIdx.x; y < im.h; y += gridDim.x) {
-    const uint8_t* row = im.base + (size_t)y * im.pitch;
-    for (int cb = t & ~63; cb < chunks; cb += kGThreads) {
-      const int c = cb + lane;
-      uint32_t ml = 0, mh = 0;
-      if (c < chunks) {
-        const uint4 q = *(const uint4*)(row + 16 * c);
-        const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
-        const int n = min(kPer, im.w - kPer * c);
+  const int G = gridDim.x;
+  for (int y = blockIdx.x; y < im.h; y += K * G) {
+    if (t == 0)
+      stop = (uint32_t)__atomic_load_n(&mm[4], __ATOMIC_RELAXED) >= cap &&
+             (uint32_t)__atomic_load_n(&mm[5], __ATOMIC_RELAXED) >= cap;
+    __syncthreads();
+    if (stop) return;
+    for (int cb = 0; cb < chunks; cb += kRThreads) {
+      const int c = cb + t;
+      uint32_t m[2][K];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-          const int v = S16 ? (int)(int16_t)(wd[k >> 1] >> (16 * (k & 1))) : (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xFF);
-          ml |= (k < n && v == lo) ? 1u << k : 0u;
-          mh |= (k < n && v == hi) ? 1u << k : 0u;
+      for (int k = 0; k < K; ++k) {
+        m[0][k] = m[1][k] = 0;
+        const int yy = y + k * G;
+        if (c < chunks && yy < im.h) {
+          const uint4 q = *(const uint4*)(im.base + (size_t)yy * im.pitch + 16 * c);
+          const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
+          const int n = min(kPer, im.w - kPer * c);
+#pragma unroll
+          for (int e = 0; e < kPer; ++e) {
+            const int v = S16 ? (int)(int16_t)(wd[e >> 1] >> (16 * (e & 1))) : (int)((wd[e >> 2] >> (8 * (e & 3))) & 0xFF);
+            m[0][k] |= (e < n && v == lo) ? 1u << e : 0u;
+            m[1][k] |= (e < n && v == hi) ? 1u << e : 0u;
+          }
         }
       }
+      uint32_t cnt[2], inc[2];
 #pragma unroll
-      for (int list = 0; list < 2; ++list) {
-        uint32_t m = list ? mh : ml;
-        const int cnt = __popc(m);
-        int inc = cnt;  // inclusive scan across the wave
+      for (int l = 0; l < 2; ++l) {
+        cnt[l] = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) cnt[l] += (uint32_t)__popc(m[l][k]);
+        inc[l] = cnt[l];  // inclusive scan across the wave
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-          const int u = __shfl_up(inc, off);
-          if (lane >= off) inc += u;
+          const uint32_t u = (uint32_t)__shfl_up((int)inc[l], off);
+          if (lane >= off) inc[l] += u;
         }
-        const int total = __shfl(inc, 63);
-        if (total == 0 || (uint32_t)__atomic_load_n(&mm[4 + list], __ATOMIC_RELAXED) >= cap) continue;
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&mm[4 + list], total);
-        base = __shfl(base, 0);
-        uint32_t i = (uint32_t)(base + inc - cnt);
-        uint32_t* out = list ? lmax : lmin;
-        while (m) {
-          const int k = __ffs(m) - 1;
-          m &= m - 1;
-          if (i < cap) {
-            out[2 * i] = (uint32_t)(kPer * c + k);
-            out[2 * i + 1] = (uint32_t)y;
+        if (lane == 63) wtot[l][wv] = inc[l];
+      }
+      __syncthreads();
+      if (t < 2) {  // exclusive prefix over the waves, one reservation per list
+        uint32_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t x = wtot[t][w];
+          wtot[t][w] = run;
+          run += x;
+        }
+        uint32_t base = cap;
+        if (run && (uint32_t)__atomic_load_n(&mm[4 + t], __ATOMIC_RELAXED) < cap)
+          base = (uint32_t)atomicAdd(&mm[4 + t], (int)run);
+        gbase[t] = base;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        uint32_t i = gbase[l] + wtot[l][wv] + inc[l] - cnt[l];
+        if (gbase[l] >= cap || i >= cap) continue;
+        uint32_t* out = l ? lmax : lmin;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          uint32_t mk = m[l][k];
+          while (mk && i < cap) {
+            const int e = __ffs(mk) - 1;
+            mk &= mk - 1;
+            out[2 * i] = (uint32_t)(kPer * c + e);
+            out[2 * i + 1] = (uint32_t)(y + k * G);
+            ++i;
           }
-          ++i;
         }
       }
+      __syncthreads();  // wtot and gbase are rewritten by the next step
     }
   }
 }
 
-hipError_t launch_min_max_loc(const GlobalImg& im, int32_t* result, uint32_t* lmin, uint32_t* lmax, uint32_t cap,
-                              hipStream_t s) {
+hipError_t launch_extreme_locs(const GlobalImg& im, int32_t* result, uint32_t* lmin, uint32_t* lmax, uint32_t cap,
+                               hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result + 4, 2, 0u, 0u);
-  hipError_t e = launch_min_max_count(im, result, s);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess || im.w <= 0 || im.h <= 0 || cap == 0) return e;
-  const dim3 grid(im.h < 2048 ? im.h : 2048);
-  if (im.bpp == 2) hipLaunchKernelGGL(k_extreme_locs<true>, grid, dim3(kGThreads), 0, s, im, result, lmin, lmax, cap);
-  else hipLaunchKernelGGL(k_extreme_locs<false>, grid, dim3(kGThreads), 0, s, im, result, lmin, lmax, cap);
+  const dim3 grid(global_grid(im, 4, kRGroups));
+  if (im.bpp == 2) hipLaunchKernelGGL(k_extreme_locs<true>, grid, dim3(kRThreads), 0, s, im, result, lmin, lmax, cap);
+  else hipLaunchKernelGGL(k_extreme_locs<false>, grid, dim3(kRThreads), 0, s, im, result, lmin, lmax, cap);
   return hipGetLastError();
 }
 
-hipError_t launch_min_max_count(const GlobalImg& im, int32_t* result, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result + 2, 2, 0u, 0u);
-  hipError_t e = launch_min_max(im, result, s);
-  if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
-  const dim3 grid(global_grid(im, 4, kRGroups));
-  if (im.bpp == 2) hipLaunchKernelGGL(k_count_extremes<true>, grid, dim3(kRThreads), 0, s, im, result);
-  else hipLaunchKernelGGL(k_count_extremes<false>, grid, dim3(kRThreads), 0, s, im, result);
+hipError_t launch_min_max_loc(const GlobalImg& im, int32_t* result, uint32_t* lmin, uint32_t* lmax, uint32_t cap,
+                              hipStream_t s) {
+  hipError_t e = launch_min_max_count(im, result, s);
+  if (e != hipSuccess) return e;
+  return launch_extreme_locs(im, result, lmin, lmax, cap, s);
+}
+
+// Slot counters of the location lists clamped to the capacity: the number of
+// locations each list holds.
+__global__ void k_clamp_slots(int32_t* __restrict__ mm, uint32_t cap) {
+  if (threadIdx.x < 2) {
+    const uint32_t v = (uint32_t)mm[4 + threadIdx.x];
+    mm[4 + threadIdx.x] = (int32_t)(v < cap ? v : cap);
+  }
+}
+
+hipError_t launch_clamp_slots(int32_t* result, uint32_t cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_clamp_slots, dim3(1), dim3(64), 0, s, result, cap);
   return hipGetLastError();
 }
 
@@ -439,6 +573,50 @@ hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s)
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mean_std_final, dim3(1), dim3(64), 0, s, (unsigned long long*)result,
                      (double)im.w * (double)im.h);
+  return hipGetLastError();
+}
+
+// ---- first and last steps of global operators reduced inside fused kernels ----
+// The fused kernels merge their partial results into the operator's result
+// buffer; these kernels set its starting value before and form the final
+// values after, in the same stream.
+
+hipError_t launch_reduce_init(int kind, void* result, int num_bins, hipStream_t s) {
+  switch (kind) {
+    case OP_HISTOGRAM:
+    case OP_EQHIST: {
+      const int n = kind == OP_EQHIST ? 256 : num_bins;
+      hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, (uint32_t*)result, n, 0u, 0u);
+      break;
+    }
+    case OP_MINMAX:
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result, 2, (uint32_t)INT_MAX,
+                         (uint32_t)INT_MIN);
+      break;
+    case OP_MMCOUNT: hipLaunchKernelGGL(k_init_keys, dim3(1), dim3(256), 0, s, (int32_t*)result); break;
+    case OP_SUMS: hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)result, 6, 0u, 0u); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_words(void* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, (uint32_t*)p, n, 0u, 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_finish(int kind, void* result, long long npix, hipStream_t s) {
+  switch (kind) {
+    case OP_EQHIST:
+      hipLaunchKernelGGL(k_eq_lut, dim3(1), dim3(256), 0, s, (const uint32_t*)result, (uint8_t*)result + 256 * 4,
+                         npix);
+      break;
+    case OP_MMCOUNT: hipLaunchKernelGGL(k_unpack_keys, dim3(1), dim3(64), 0, s, (int32_t*)result); break;
+    case OP_SUMS:
+      hipLaunchKernelGGL(k_mean_std_final, dim3(1), dim3(64), 0, s, (unsigned long long*)result, (double)npix);
+      break;
+    default: return hipSuccess;
+  }
   return hipGetLastError();
 }
 

@@ -29,7 +29,57 @@ enum OpKind : int32_t {
   OP_NONMAX,     // NonMaxSuppression over a (2 p0 + 1)^2 window, U8 or S16
   OP_EXPR,       // user point kernel (Section 5.1): p0 steps of `code`, p1 = 1 float kernel, p2 bit k: input k F32
   OP_EXPR_LOCAL, // user local kernel: as OP_EXPR over one input read at window offsets
+  // Global operators (Table 2): each reads every pixel of its input and
+  // writes a few values (a buffer, not an image).
+  OP_HISTOGRAM,  // U8 -> p0 bins over [p1, p1 + p2), uint32 counts
+  OP_MINMAX,     // U8/S16 -> int32 {smallest, largest}
+  OP_MMCOUNT,    // U8/S16 -> the extremes and how many pixels equal each (MinMaxLoc counts)
+  OP_MMLOCS,     // image, MMCOUNT result -> (x, y) of up to p0 pixels equal to each extreme
+  OP_SUMS,       // U8 -> exact sums of v and v^2, mean and standard deviation
+  OP_EQHIST,     // U8 -> 256-bin histogram, then the EqualizeHist mapping (a 256-byte table)
+  OP_LUT,        // point operator: U8 image, EQHIST table -> U8 (the table applied)
 };
+
+// A global operator (its output is a buffer; nothing reads it in the same
+// kernel, since it is complete only once every pixel has been seen).
+__host__ __device__ inline bool is_global_op(int kind) { return kind >= OP_HISTOGRAM && kind <= OP_EQHIST; }
+// The global operators a fused kernel can compute as a reduction over its
+// tiles (the location lists need the final extremes, so they run apart).
+__host__ __device__ inline bool is_reduce_op(int kind) { return is_global_op(kind) && kind != OP_MMLOCS; }
+
+// Bytes of each global operator's result.  EQHIST: the counts, then the
+// mapping table.  MMCOUNT: int32 {min, max, count of min, count of max},
+// two int32 slot counters of the location lists, two reserved words, then
+// the 64-bit (value, count) keys the counting merges into: kMMSubKeys for
+// the minimum, kMMSubKeys for the maximum.  Work-group g merges into key
+// g mod kMMSubKeys: a compare-and-swap that loses to another group retries
+// after a full round trip to the cache, so a key shared by many groups
+// serialises them (the streaming kernel has at most kMMSubKeys groups, one
+// key each).  The last step merges the keys into the first four words.
+constexpr int kEqHistBytes = 256 * 4 + 256;
+constexpr int kMinMaxBytes = 8;
+constexpr int kMMSubKeys = 256;
+constexpr int kMMKeyOffset = 32;  // bytes
+constexpr int kMMCountBytes = kMMKeyOffset + 2 * kMMSubKeys * 8;
+constexpr int kSumsBytes = 24;
+
+// (value, count) keys of the one-pass count of the extremes: the value in
+// the high word, biased by 32768 so that every U8 or S16 value is ordered as
+// an unsigned number, the count in the low word.  Merging two keys keeps the
+// better value and adds the counts when the values are equal; a key with a
+// zero count is neutral, so the minimum starts at (65535, 0) and the maximum
+// at (0, 0).
+__host__ __device__ inline unsigned long long mm_key(int v, unsigned c) {
+  return ((unsigned long long)(unsigned)(v + 32768) << 32) | c;
+}
+constexpr unsigned long long kMinKeyInit = 0xFFFFull << 32;
+constexpr unsigned long long kMaxKeyInit = 0;
+__host__ __device__ inline unsigned long long mm_merge(unsigned long long a, unsigned long long b, bool want_min) {
+  const unsigned va = (unsigned)(a >> 32), vb = (unsigned)(b >> 32);
+  if (va == vb) return a + (unsigned)b;
+  return (want_min ? vb < va : vb > va) ? b : a;
+}
+__host__ __device__ inline int mm_value(unsigned long long k) { return (int)(unsigned)(k >> 32) - 32768; }
 
 // Steps of a user point kernel's postfix program: the low byte is the
 // operation, the high byte its argument (input index, literal index).
@@ -42,7 +92,8 @@ constexpr int kMaxExprConst = 8;   // distinct literals
 constexpr int kExprStack = 8;      // values on the evaluation stack
 
 // Element formats (same numbering as the public HVX_DF_* constants).
-enum Df : int32_t { DF_VIRT = 0, DF_U8 = 1, DF_S16 = 2, DF_S32 = 3, DF_F32 = 4, DF_UYVY = 5 };
+enum Df : int32_t { DF_VIRT = 0, DF_U8 = 1, DF_S16 = 2, DF_S32 = 3, DF_F32 = 4, DF_UYVY = 5,
+                   DF_BUF = 16 /* library-internal: a global operator's result, w bytes */ };
 enum Border : int32_t { B_UNDEFINED = 0, B_CONSTANT = 1, B_REPLICATE = 2, B_MIRROR = 3, B_REPEAT = 4 };
 
 inline int df_bytes(int df) {
@@ -52,6 +103,7 @@ inline int df_bytes(int df) {
     case DF_UYVY: return 2;
     case DF_S32: return 4;
     case DF_F32: return 4;
+    case DF_BUF: return 1;
     default: return 0;
   }
 }
@@ -61,6 +113,8 @@ constexpr int kMaxGVals = 16;
 constexpr int kMaxGOps = 12;
 constexpr int kMaxIO = 8;
 constexpr int kMaxMask = 25;
+constexpr int kMaxRed = 2;
+constexpr int kHistWords = 257;  // 256 bins and a spare counter for pixels outside the range
 
 struct GVal {
   int32_t df;     // element format
@@ -90,7 +144,8 @@ struct GOp {
 struct GProg {
   int32_t nvals, nops;
   int32_t tw, th;     // output tile of one work-group
-  int32_t lds_words;  // LDS words used by one tile
+  int32_t lds_words;  // LDS words used by one tile (a histogram, if any, follows: kHistWords)
+  int32_t nred;       // global operators reduced over the tiles (at most kMaxRed, one histogram)
   int32_t w, h;
   int32_t tiles_x, tiles_y;
   GVal vals[kMaxGVals];
@@ -160,7 +215,11 @@ struct Gauss5Desc {
   int32_t b0, c0;
 };
 
-enum FastKind : int32_t { FK_GENERIC = 0, FK_EDGE = 1, FK_CORNER = 2, FK_GAUSS5 = 3 };
+// FK_GLOBAL: one global operator over an image in memory (the streaming
+// reduction kernels of the immediate-mode calls).
+enum FastKind : int32_t { FK_GENERIC = 0, FK_EDGE = 1, FK_CORNER = 2, FK_GAUSS5 = 3, FK_GLOBAL = 4 };
+// the register-streaming strip kernels (work items of strips x bands; batchable)
+inline bool is_strip_kind(int k) { return k == FK_EDGE || k == FK_CORNER || k == FK_GAUSS5; }
 
 // One image of a batch: the kind selects which fused body processes its items.
 struct BatchImage {

@@ -14,7 +14,7 @@
 
 namespace hvx {
 
-enum ObjType : uint32_t { T_CONTEXT = 0x5a01, T_GRAPH, T_IMAGE, T_NODE, T_CONV, T_BATCH, T_SERVER };
+enum ObjType : uint32_t { T_CONTEXT = 0x5a01, T_GRAPH, T_IMAGE, T_NODE, T_CONV, T_BATCH, T_SERVER, T_BUFFER };
 
 struct Context;
 struct Graph;
@@ -25,6 +25,8 @@ struct Object {
   virtual ~Object() {}
 };
 
+// An image, or (type T_BUFFER) a caller's device buffer receiving a global
+// operator's result: df DF_BUF, w = its size in bytes, h = 1.
 struct Image : Object {
   uint32_t w = 0, h = 0;
   int df = DF_VIRT;
@@ -62,6 +64,11 @@ enum NodeKind : int32_t {
   NK_CONVOLVE,
   NK_CUSTOM_POINT,
   NK_CUSTOM_LOCAL,
+  NK_HISTOGRAM,  // global operators (Table 2)
+  NK_MINMAX,
+  NK_MINMAXLOC,
+  NK_MEANSTD,
+  NK_EQHIST,
 };
 
 struct Node : Object {
@@ -80,6 +87,7 @@ struct Node : Object {
   Conv own_mask;  // NonLinearFilter: the node's own copy of its mask (conv points here)
   ExprProg expr;  // user point kernel
   int out_df = 0; // user point kernel: declared output format
+  uint32_t gp[3] = {0, 0, 0};  // histogram: bins, offset, range; MinMaxLoc: location capacity
 };
 
 // ---- lowered graph and plan -------------------------------------------------
@@ -109,6 +117,7 @@ struct LOp {
   float k = 0.04f;
   const Conv* conv = nullptr;
   const ExprProg* expr = nullptr;
+  uint32_t gp[3] = {0, 0, 0};  // global operators: as Node::gp
   int rx = 0, ry = 0;
   bool live = true;
 };
@@ -119,6 +128,7 @@ struct Group {
   std::vector<int> outputs;  // values written to global memory
   std::vector<int> gvals;    // generic program value index -> plan value id
   int kind = FK_GENERIC;
+  int phase = 0;             // global operators whose results this group waits for (launch order)
   int footprint = 0;  // max total stencil radius along any path
   GProg prog{};       // generic program (kind == FK_GENERIC)
   int rows = 0;       // rows per work item (fast kinds); 0 = tuned or default

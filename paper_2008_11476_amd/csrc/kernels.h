@@ -6,8 +6,9 @@
 
 namespace hvx {
 
-// P: host copy (launch shape); dev_prog: the same program in device memory
-hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& io, hipStream_t s);
+// P: host copy (launch shape); dev_prog: the same program in device memory;
+// num_cus sizes the grid of programs that reduce global operators
+hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& io, int num_cus, hipStream_t s);
 hipError_t launch_edge(const EdgeDesc& d, bool xcd, hipStream_t s);
 hipError_t launch_corner(const CornerDesc& d, bool xcd, hipStream_t s);
 hipError_t launch_gauss5(const Gauss5Desc& d, bool xcd, hipStream_t s);

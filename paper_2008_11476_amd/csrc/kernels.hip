@@ -1,6 +1,8 @@
 // Kernel entry points and their host-side launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dev_fast.hpp"
 #include "dev_generic.hpp"
 #include "kernels.h"
@@ -21,10 +23,24 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
 // kernel argument would turn into a private (scratch) copy.
 // NL: the program holds a NonLinearFilter (its evaluation is compiled only
 // into these variants, which carry its registers)
-template <bool NL>
+// RED: the program reduces global operators; the groups then loop over the
+// tiles (fewer groups than tiles, so each merges its partial results once)
+// and the LDS after the tiles holds the group's histogram.
+template <bool NL, bool RED>
 __global__ __launch_bounds__(256) void k_generic(const GProg* __restrict__ P, const IOTable io) {
   extern __shared__ int32_t lds[];
-  generic_tile<256, NL>(*P, io, blockIdx.x, lds);
+  if constexpr (!RED) {
+    generic_tile<256, NL, false>(*P, io, blockIdx.x, lds, nullptr);
+  } else {
+    RedState rs;
+    red_begin<256>(rs, (uint32_t*)(lds + P->lds_words));
+    const int ntiles = P->tiles_x * P->tiles_y;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+      generic_tile<256, NL, true>(*P, io, tile, lds, &rs);
+      __syncthreads();  // the tile's LDS is free for the next tile's loads
+    }
+    red_end<256>(*P, io, rs);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_point(const GProg* __restrict__ P, const IOTable io) {
@@ -143,7 +159,7 @@ __global__ __launch_bounds__(64) void k_batch_direct(const BatchImage* __restric
 
 // ---- host launchers ---------------------------------------------------------
 
-hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& io, hipStream_t s) {
+hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& io, int num_cus, hipStream_t s) {
   if (P.nops == 1 && is_point_op(P.ops[0].kind)) {
     const long long blocks = (long long)((P.w + 1023) >> 10) * P.h;
     if (blocks <= 0) return hipSuccess;
@@ -173,8 +189,16 @@ hipError_t launch_generic(const GProg& P, const GProg* dev_prog, const IOTable& 
   if (tiles <= 0) return hipSuccess;
   bool nl = false;
   for (int i = 0; i < P.nops; ++i) nl |= P.ops[i].kind == OP_NONLINEAR;
-  if (nl) hipLaunchKernelGGL((k_generic<true>), dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
-  else hipLaunchKernelGGL((k_generic<false>), dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
+  if (P.nred > 0) {
+    // four groups per CU at most, each merging its results once
+    const dim3 g((unsigned)std::min(tiles, 4 * num_cus));
+    const size_t lds = (size_t)(P.lds_words + kHistWords) * 4;
+    if (nl) hipLaunchKernelGGL((k_generic<true, true>), g, dim3(256), lds, s, dev_prog, io);
+    else hipLaunchKernelGGL((k_generic<false, true>), g, dim3(256), lds, s, dev_prog, io);
+    return hipGetLastError();
+  }
+  if (nl) hipLaunchKernelGGL((k_generic<true, false>), dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
+  else hipLaunchKernelGGL((k_generic<false, false>), dim3(tiles), dim3(256), (size_t)P.lds_words * 4, s, dev_prog, io);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <fstream>
 #include <sstream>
 
+#include "global.h"
 #include "hvx_internal.h"
 #include "kernels.h"
 
@@ -209,6 +210,39 @@ void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_ov
   }
 }
 
+// One global operator over an image in memory (group kind FK_GLOBAL), with
+// the streaming kernels of the immediate-mode calls.
+static hipError_t launch_global_group(Graph* g, const Group& gr, hipStream_t s) {
+  const Plan& p = *g->plan;
+  const LOp& o = p.ops[gr.ops[0]];
+  void* ptr;
+  int64_t pitch;
+  value_ptr(g, o.in[0], &ptr, &pitch);
+  const Value& iv = p.vals[o.in[0]];
+  GlobalImg im{(const uint8_t*)ptr, pitch, (int32_t)iv.w, (int32_t)iv.h, df_bytes(iv.df)};
+  void* out;
+  int64_t unused;
+  value_ptr(g, o.out, &out, &unused);
+  switch (o.kind) {
+    case OP_HISTOGRAM: return launch_histogram(im, (int)o.gp[0], (int)o.gp[1], (int)o.gp[2], (uint32_t*)out, s);
+    case OP_MINMAX: return launch_min_max(im, (int32_t*)out, s);
+    case OP_MMCOUNT: {
+      hipError_t e = launch_min_max_count(im, (int32_t*)out, s);
+      return e != hipSuccess ? e : launch_zero_words((int32_t*)out + 4, 2, s);  // no locations stored (yet)
+    }
+    case OP_SUMS: return launch_mean_std_dev(im, out, s);
+    case OP_EQHIST: return launch_equalize_mapping(im, out, s);
+    case OP_MMLOCS: {
+      void* mm;
+      value_ptr(g, o.in[1], &mm, &unused);
+      const uint32_t cap = o.gp[0];
+      hipError_t e = launch_extreme_locs(im, (int32_t*)mm, (uint32_t*)out, (uint32_t*)out + 2 * cap, cap, s);
+      return e != hipSuccess ? e : launch_clamp_slots((int32_t*)mm, cap, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
   hipError_t e = hipSuccess;
   const int gi = (int)(&gr - g->plan->groups.data());
@@ -221,7 +255,21 @@ static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
       value_ptr(g, gr.gvals[i], &io.ptr[v.io], &io.pitch[v.io]);
       if (!io.ptr[v.io]) return set_error(g->ctx, HVX_ERROR_DEVICE, "unbound image in plan");
     }
-    e = launch_generic(gr.prog, g->dev_progs + gi, io, s);
+    // global operators reduced by the kernel: starting values before it,
+    // final values after it, in the same stream
+    const GProg& P = gr.prog;
+    for (int i = 0; i < P.nops && e == hipSuccess; ++i)
+      if (is_reduce_op(P.ops[i].kind))
+        e = launch_reduce_init(P.ops[i].kind, io.ptr[P.vals[P.ops[i].out].io], P.ops[i].p0, s);
+    if (e == hipSuccess) e = launch_generic(P, g->dev_progs + gi, io, g->ctx->num_cus, s);
+    for (int i = 0; i < P.nops && e == hipSuccess; ++i)
+      if (is_reduce_op(P.ops[i].kind)) {
+        void* out = io.ptr[P.vals[P.ops[i].out].io];
+        e = launch_reduce_finish(P.ops[i].kind, out, (long long)P.w * P.h, s);
+        if (e == hipSuccess && P.ops[i].kind == OP_MMCOUNT) e = launch_zero_words((int32_t*)out + 4, 2, s);
+      }
+  } else if (gr.kind == FK_GLOBAL) {
+    e = launch_global_group(g, gr, s);
   } else {
     BatchImage bi;
     fill_fast_desc(g, gr, &bi);
@@ -321,7 +369,7 @@ static hvx_status batch_build(Batch* b) {
     if (s) return s;
     b->alg_bytes += g->plan->alg_bytes;
     const auto& gs = g->plan->groups;
-    if (gs.size() == 1 && gs[0].kind != FK_GENERIC) {
+    if (gs.size() == 1 && is_strip_kind(gs[0].kind)) {
       BatchImage bi;
       fill_fast_desc(g, gs[0], &bi, b->rows_override);
       b->imgs.push_back(bi);
@@ -686,7 +734,7 @@ hvx_status hvx_graph_autotune(hvx_graph hg, void* stream, int iters) {
   hvx_status s = prepare_graph(g);
   if (s) return s;
   Plan& p = *g->plan;
-  if (p.groups.size() != 1 || p.groups[0].kind == FK_GENERIC) return HVX_SUCCESS;  // nothing to tune
+  if (p.groups.size() != 1 || !is_strip_kind(p.groups[0].kind)) return HVX_SUCCESS;  // nothing to tune
   Group& gr = p.groups[0];
   const int saved_rows = gr.rows, saved_xcd = gr.xcd;
   hipStream_t st = (hipStream_t)stream;

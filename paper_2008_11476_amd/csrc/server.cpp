@@ -135,7 +135,7 @@ struct Server : Object {
 };
 
 static bool batchable(const Graph* g) {
-  return g->plan && g->plan->groups.size() == 1 && g->plan->groups[0].kind != FK_GENERIC;
+  return g->plan && g->plan->groups.size() == 1 && is_strip_kind(g->plan->groups[0].kind);
 }
 
 static void finish(Server* sv, Request* r, int32_t status, double t) {

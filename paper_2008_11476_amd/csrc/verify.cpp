@@ -105,6 +105,11 @@ static const char* node_name(int kind) {
     case NK_HARRIS: return "HarrisResponse";
     case NK_THRESHOLD: return "Threshold";
     case NK_CONVOLVE: return "Convolve";
+    case NK_HISTOGRAM: return "Histogram";
+    case NK_MINMAX: return "MinMax";
+    case NK_MINMAXLOC: return "MinMaxLoc";
+    case NK_MEANSTD: return "MeanStdDev";
+    case NK_EQHIST: return "EqualizeHist";
     default: return "?";
   }
 }
@@ -124,6 +129,15 @@ static hvx_status bind_output(Graph* g, Plan& p, int v, int df, uint32_t w, uint
   }
   if (val.df != df) return err(g, HVX_ERROR_INVALID_FORMAT, "%s: output image has the wrong format", nn);
   if (val.w != w || val.h != h) return err(g, HVX_ERROR_INVALID_DIMENSION, "%s: output size differs from input", nn);
+  return HVX_SUCCESS;
+}
+
+// A global operator's result buffer: must be one and hold `need` bytes.
+static hvx_status bind_buffer(Graph* g, Plan& p, int v, int64_t need, const char* nn) {
+  const Value& val = p.vals[v];
+  if (val.df != DF_BUF) return err(g, HVX_ERROR_INVALID_FORMAT, "%s writes its result to a buffer", nn);
+  if ((int64_t)val.w < need)
+    return err(g, HVX_ERROR_INVALID_DIMENSION, "%s: result buffer too small (needs %d bytes)", nn, (int)need);
   return HVX_SUCCESS;
 }
 
@@ -294,6 +308,22 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
     return false;
   }
   std::set<int> outset(gr.outputs.begin(), gr.outputs.end());
+  // global operators reduced over the tiles: at most kMaxRed, one of them a
+  // histogram (its counters take LDS next to the tiles)
+  int nred = 0, nhist = 0;
+  for (int o : gr.ops) {
+    const int k = p.ops[o].kind;
+    if (k == OP_MMLOCS) {
+      *why = "the location pass runs alone";
+      return false;
+    }
+    nred += is_reduce_op(k) ? 1 : 0;
+    nhist += (k == OP_HISTOGRAM || k == OP_EQHIST) ? 1 : 0;
+  }
+  if (nred > kMaxRed || nhist > 1) {
+    *why = "too many global operators for one kernel";
+    return false;
+  }
   // halo extents, consumers first
   std::vector<int> ext(vals.size(), 0);
   std::vector<int> read_in_group(vals.size(), 0);
@@ -318,7 +348,7 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
     for (int k = 0; k < o.nin; ++k) last[loc[o.in[k]]] = std::max(last[loc[o.in[k]]], (int)i);
   }
   // choose the tile: shrink until the live set fits the LDS budget
-  const int budget_words = 48 * 1024 / 4;
+  const int budget_words = 48 * 1024 / 4 - (nhist ? kHistWords : 0);
   static const int shapes[][2] = {{64, 16}, {64, 8}, {32, 8}, {32, 4}, {16, 4}};
   for (auto& sh : shapes) {
     int tw = sh[0], th = sh[1];
@@ -330,7 +360,7 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return def[a] < def[b]; });
     std::vector<std::array<int, 3>> blocks;  // offset, size, last use
     for (int li : order) {
-      if (!read_in_group[li]) continue;
+      if (!read_in_group[li] || p.vals[vals[li]].df == DF_BUF) continue;  // buffers stay in memory
       int e = ext[li];
       int sz = (tw + 2 * e) * (th + 2 * e);
       size[li] = sz;
@@ -362,6 +392,7 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
   }
   P.nvals = (int)vals.size();
   P.nops = (int)gr.ops.size();
+  P.nred = nred;
   gr.gvals = vals;
   P.w = (int)gr.w;
   P.h = (int)gr.h;
@@ -413,6 +444,16 @@ static bool build_generic(Graph* g, Plan& p, Group& gr, std::string* why) {
       }
       case OP_ADD: q.p0 = o.policy; break;
       case OP_HARRIS: q.pf = o.k; break;
+      case OP_HISTOGRAM:
+        q.p0 = (int)o.gp[0];
+        q.p1 = (int)o.gp[1];
+        q.p2 = (int)o.gp[2];
+        break;
+      case OP_EQHIST:
+        q.p0 = 256;
+        q.p1 = 0;
+        q.p2 = 256;
+        break;
       case OP_NONMAX: q.p0 = o.policy / 2; break;
       case OP_EXPR:
       case OP_EXPR_LOCAL: {
@@ -641,6 +682,25 @@ hvx_status verify_graph(Graph* g) {
         s = bind_output(g, p, nout[i][0], df, w, h, nn);
         break;
       }
+      case NK_HISTOGRAM:
+        if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
+        s = bind_buffer(g, p, nout[i][0], 4 * (int64_t)n->gp[0], nn);
+        break;
+      case NK_MINMAX:
+      case NK_MINMAXLOC:
+        if (!need(nin[i][0], {DF_U8, DF_S16})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 or S16 input", nn);
+        s = bind_buffer(g, p, nout[i][0], n->kind == NK_MINMAX ? kMinMaxBytes : kMMCountBytes, nn);
+        if (!s && n->kind == NK_MINMAXLOC && nout[i].size() > 1 && nout[i][1] >= 0)
+          s = bind_buffer(g, p, nout[i][1], 16 * (int64_t)n->gp[0], nn);
+        break;
+      case NK_MEANSTD:
+        if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
+        s = bind_buffer(g, p, nout[i][0], kSumsBytes, nn);
+        break;
+      case NK_EQHIST:
+        if (!need(nin[i][0], {DF_U8})) return err(g, HVX_ERROR_INVALID_FORMAT, "%s needs a U8 input", nn);
+        s = bind_output(g, p, nout[i][0], DF_U8, w, h, nn);
+        break;
       default: return err(g, HVX_ERROR_NOT_SUPPORTED, "unknown node kind");
     }
     if (s) return s;
@@ -665,6 +725,7 @@ hvx_status verify_graph(Graph* g) {
       o.k = n->k;
       o.conv = n->conv;
       o.expr = &n->expr;
+      for (int k = 0; k < 3; ++k) o.gp[k] = n->gp[k];
       op_radius(o, &o.rx, &o.ry);
       p.ops.push_back(o);
     };
@@ -692,6 +753,27 @@ hvx_status verify_graph(Graph* g) {
       case NK_HARRIS: emit(OP_HARRIS, nin[i], nout[i][0]); break;
       case NK_THRESHOLD: emit(OP_THRESHOLD, nin[i], nout[i][0]); break;
       case NK_CONVOLVE: emit(OP_CONVOLVE, nin[i], nout[i][0]); break;
+      case NK_HISTOGRAM: emit(OP_HISTOGRAM, nin[i], nout[i][0]); break;
+      case NK_MINMAX: emit(OP_MINMAX, nin[i], nout[i][0]); break;
+      case NK_MEANSTD: emit(OP_SUMS, nin[i], nout[i][0]); break;
+      case NK_MINMAXLOC:  // the counts in one pass, the locations in a second one
+        emit(OP_MMCOUNT, nin[i], nout[i][0]);
+        if (nout[i].size() > 1 && nout[i][1] >= 0) emit(OP_MMLOCS, {nin[i][0], nout[i][0]}, nout[i][1]);
+        break;
+      case NK_EQHIST: {
+        // histogram and mapping into a buffer of the graph's own, then the
+        // mapping applied as a point operator
+        Value t;
+        t.df = DF_BUF;
+        t.w = kEqHistBytes;
+        t.h = 1;
+        t.is_virtual = true;
+        p.vals.push_back(t);
+        const int tv = (int)p.vals.size() - 1;
+        emit(OP_EQHIST, nin[i], tv);
+        emit(OP_LUT, {nin[i][0], tv}, nout[i][0]);
+        break;
+      }
     }
   }
   p.num_ops = (int)p.ops.size();
@@ -744,18 +826,34 @@ hvx_status verify_graph(Graph* g) {
   if (p.num_live == 0) return err(g, HVX_ERROR_INVALID_GRAPH, "no operator reaches a non-virtual image");
 
   // ---- 5: grouping ----
-  // Fusion on: one group per weakly connected component of live operators.
-  // Fusion off: one group per operator ("node by node").
+  // A global operator's result is complete only once every pixel has been
+  // seen, so whatever reads it runs in a later kernel.  The phase of an
+  // operator counts the global operators on its longest path from the graph
+  // inputs; producer and consumer fuse only within one phase.  (The live
+  // operators are in a topological order: nodes in dependency order, each
+  // node's operators in their own.)
+  std::vector<int> phase(p.ops.size(), 0);
+  for (int o : p.topo)
+    for (int k = 0; k < p.ops[o].nin; ++k) {
+      const int pr = p.vals[p.ops[o].in[k]].producer;
+      if (pr >= 0 && p.ops[pr].live) phase[o] = std::max(phase[o], phase[pr] + (is_global_op(p.ops[pr].kind) ? 1 : 0));
+    }
+  // Fusion on: one group per weakly connected component of live operators
+  // of one phase (the location pass of MinMaxLoc alone).  Fusion off: one
+  // group per operator ("node by node").
   std::vector<int> comp(p.ops.size(), -1);
   if (g->opt_fusion) {
     std::vector<int> parent(p.ops.size());
     for (size_t i = 0; i < parent.size(); ++i) parent[i] = (int)i;
     std::function<int(int)> find = [&](int x) { return parent[x] == x ? x : parent[x] = find(parent[x]); };
-    for (int o : p.topo)
+    for (int o : p.topo) {
+      if (p.ops[o].kind == OP_MMLOCS) continue;
       for (int k = 0; k < p.ops[o].nin; ++k) {
         int pr = p.vals[p.ops[o].in[k]].producer;
-        if (pr >= 0 && p.ops[pr].live) parent[find(o)] = find(pr);
+        if (pr >= 0 && p.ops[pr].live && phase[pr] == phase[o] && !is_global_op(p.ops[pr].kind))
+          parent[find(o)] = find(pr);
       }
+    }
     for (int o : p.topo) comp[o] = find(o);
   } else {
     for (int o : p.topo) comp[o] = o;
@@ -765,6 +863,7 @@ hvx_status verify_graph(Graph* g) {
     if (!gid.count(comp[o])) {
       gid[comp[o]] = (int)p.groups.size();
       p.groups.emplace_back();
+      p.groups.back().phase = phase[o];
     }
     p.groups[gid[comp[o]]].ops.push_back(o);
   }
@@ -786,8 +885,12 @@ hvx_status verify_graph(Graph* g) {
       if (!p.vals[v].is_virtual || outside) gr.outputs.push_back(v);
       if (p.vals[v].is_virtual && outside) p.vals[v].materialize = true;
     }
-    gr.w = p.vals[p.ops[gr.ops[0]].out].w;
-    gr.h = p.vals[p.ops[gr.ops[0]].out].h;
+    // the image size the group runs over (a global operator's output is a
+    // buffer: its input gives the size)
+    const LOp& o0 = p.ops[gr.ops[0]];
+    const Value& sz = p.vals[p.vals[o0.out].df == DF_BUF ? o0.in[0] : o0.out];
+    gr.w = sz.w;
+    gr.h = sz.h;
   };
   for (auto& gr : p.groups) finish_group(gr);
   // a component too big for one generic kernel is split into single operators
@@ -803,6 +906,7 @@ hvx_status verify_graph(Graph* g) {
         for (int o : gr.ops) {
           Group s;
           s.ops.push_back(o);
+          s.phase = gr.phase;
           final_groups.push_back(s);
         }
         continue;
@@ -810,6 +914,11 @@ hvx_status verify_graph(Graph* g) {
     }
     final_groups.push_back(gr);
   }
+  // launch order: by phase, then by first operator (a group depends only on
+  // groups of an earlier phase or, within a phase, on earlier operators)
+  std::stable_sort(final_groups.begin(), final_groups.end(), [](const Group& a, const Group& b) {
+    return a.phase != b.phase ? a.phase < b.phase : a.ops[0] < b.ops[0];
+  });
   p.groups.swap(final_groups);
   for (auto& v : p.vals) v.materialize = false;
   for (auto& gr : p.groups) finish_group(gr);
@@ -818,6 +927,13 @@ hvx_status verify_graph(Graph* g) {
   for (auto& gr : p.groups) {
     int in_v = -1, out_v = -1, aux = -1;
     gr.kind = FK_GENERIC;
+    if (gr.ops.size() == 1 && is_global_op(p.ops[gr.ops[0]].kind)) {
+      // one global operator over an image in memory: the streaming reduction kernels
+      gr.kind = FK_GLOBAL;
+      gr.v_in = p.ops[gr.ops[0]].in[0];
+      gr.v_out = p.ops[gr.ops[0]].out;
+      continue;
+    }
     if (g->opt_specialize && fast_borders(p, gr)) {
       if (match_edge(p, gr, &in_v, &out_v, &aux)) gr.kind = FK_EDGE;
       else if (match_corner(p, gr, &in_v, &out_v)) gr.kind = FK_CORNER;
@@ -848,7 +964,7 @@ hvx_status verify_graph(Graph* g) {
   for (auto& gr : p.groups) {
     for (int v : gr.inputs) p.hbm_bytes += (int64_t)p.vals[v].w * p.vals[v].h * df_bytes(p.vals[v].df);
     for (int v : gr.outputs) p.hbm_bytes += (int64_t)p.vals[v].w * p.vals[v].h * df_bytes(p.vals[v].df);
-    if (gr.kind != FK_GENERIC) {
+    if (is_strip_kind(gr.kind)) {
       gr.rows = g->opt_tile ? g->opt_tile : 0;  // 0: tuned or default at schedule time
       gr.xcd = g->opt_xcd;
     }

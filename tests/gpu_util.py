@@ -28,15 +28,18 @@ def device_image(ctx, arr, df, seed=0):
     return hvx.hvx_image_from_ptr(ctx, w, h, df, t.data_ptr(), pitch), t
 
 
-def run_spec(spec: gs.Spec, ctx, fusion=True, specialize=True, rows=0, dce=True, xcd=True, autotune=False):
-    """Execute `spec` on the GPU; returns ({output name: numpy array}, graph)."""
+def run_spec(spec: gs.Spec, ctx, fusion=True, specialize=True, rows=0, dce=True, xcd=True, autotune=False,
+             keep=None):
+    """Execute `spec` on the GPU; returns ({output name: numpy array}, graph).
+    `keep`, a dict, receives the device tensors (inputs, outputs, buffers) so
+    that the graph can be processed again."""
     import torch
-    imgs, keep, shapes = {}, [], {}
+    imgs, keep_in, shapes = {}, [], {}
     for name, arr in spec.inputs.items():
         df = hvx.HVX_DF_UYVY if name in spec.uyvy else gs.DF_OF_DTYPE[arr.dtype]
-        im, t = device_image(ctx, arr, df, seed=len(keep) + 1)
+        im, t = device_image(ctx, arr, df, seed=len(keep_in) + 1)
         imgs[name] = im
-        keep.append(t)
+        keep_in.append(t)
         h = arr.shape[0]
         w = arr.shape[1] // 2 if df == hvx.HVX_DF_UYVY else arr.shape[1]
         shapes[name] = (h, w)
@@ -49,6 +52,11 @@ def run_spec(spec: gs.Spec, ctx, fusion=True, specialize=True, rows=0, dce=True,
         im, t = device_image(ctx, garbage, df, seed=200 + i)
         imgs[name] = im
         outs[name] = (t, w, dt)
+    bufs = {}
+    for name, nbytes in spec.buffers.items():
+        t = torch.full((nbytes,), 0x5A, dtype=torch.uint8, device="cuda")  # stale contents are overwritten
+        imgs[name] = hvx.hvx_buffer_from_ptr(ctx, t.data_ptr(), nbytes)
+        bufs[name] = t
     g, _, _ = gs.build_hvx(spec, ctx, imgs)
     hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, int(fusion))
     hvx.hvx_graph_set_option(g, hvx.HVX_OPT_SPECIALIZE, int(specialize))
@@ -65,6 +73,10 @@ def run_spec(spec: gs.Spec, ctx, fusion=True, specialize=True, rows=0, dce=True,
     for name, (t, ww, dt) in outs.items():
         a = t.cpu().numpy()
         res[name] = a.view(dt)[:, :ww] if a.dtype != dt else a[:, :ww]
+    for name, t in bufs.items():
+        res[name] = t.cpu().numpy()  # raw bytes
+    if keep is not None:
+        keep.update({"inputs": keep_in, "outputs": outs, "buffers": bufs})
     return res, g
 
 

@@ -32,6 +32,7 @@ class Spec:
     inputs: dict    # name -> numpy array (UYVY: (H, 2W) uint8 with params["uyvy"])
     outputs: dict   # name -> numpy dtype of a non-virtual output
     uyvy: tuple = ()  # input names holding UYVY frames
+    buffers: dict = field(default_factory=dict)  # name -> bytes of a global operator's result buffer
 
     def oracle_graph(self):
         g = oracle.Graph()
@@ -109,6 +110,17 @@ def build_hvx(spec: Spec, ctx, images: dict):
         elif n.op == "convolve":
             conv = hvx.hvx_convolution_create(ctx, p["coeffs"], p["scale"])
             h = hvx.hvx_convolve_node(g, a[0], conv, o[0], ctx=ctx)
+        elif n.op == "histogram":
+            h = hvx.hvx_histogram_node(g, a[0], p["bins"], p.get("offset", 0), p.get("range", 256), o[0], ctx=ctx)
+        elif n.op == "min_max":
+            h = hvx.hvx_min_max_node(g, a[0], o[0], ctx=ctx)
+        elif n.op == "min_max_loc":
+            h = hvx.hvx_min_max_loc_node(g, a[0], o[0], o[1] if len(o) > 1 else None, p.get("capacity", 0),
+                                         ctx=ctx)
+        elif n.op == "mean_std_dev":
+            h = hvx.hvx_mean_std_dev_node(g, a[0], o[0], ctx=ctx)
+        elif n.op == "equalize_hist":
+            h = hvx.hvx_equalize_hist_node(g, a[0], o[0], ctx=ctx)
         else:
             raise ValueError(n.op)
         if n.border != "replicate" or n.c:

@@ -125,10 +125,10 @@ def test_min_max_count(ctx, w, h, dtype):
     for img in (rng.integers(-2 if dtype == np.int16 else 7, 12, (h, w)).astype(dtype),
                 np.full((h, w), 5, dtype)):
         im, keep = device_image(ctx, img, df, seed=9)
-        out = torch.full((4,), 77, dtype=torch.int32, device="cuda")
+        out = torch.full((1032,), 77, dtype=torch.int32, device="cuda")  # 4128 bytes
         hvx.hvx_min_max_count(ctx, im, out.data_ptr())
         torch.cuda.synchronize()
-        assert tuple(out.cpu().tolist()) == G.min_max_count(img)
+        assert tuple(out.cpu().tolist()[:4]) == G.min_max_count(img)
 
 
 @pytest.mark.parametrize("w,h", SIZES)
@@ -172,7 +172,7 @@ def test_min_max_loc(ctx, w, h, dtype):
         mn, mx, cmin, cmax, lmin, lmax = G.min_max_loc(img)
         cap = min(w * h, 5000)
         im, keep = device_image(ctx, img, df, seed=13)
-        res = torch.full((6,), 99, dtype=torch.int32, device="cuda")
+        res = torch.full((1032,), 99, dtype=torch.int32, device="cuda")  # 4128 bytes
         lmn = torch.full((2 * cap,), -1, dtype=torch.int32, device="cuda")
         lmx = torch.full((2 * cap,), -1, dtype=torch.int32, device="cuda")
         hvx.hvx_min_max_loc(ctx, im, res.data_ptr(), lmn.data_ptr(), lmx.data_ptr(), cap)
