@@ -39,7 +39,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "dev_fast.hpp", "dev_generic.hpp", "dev_phase.hpp", "hvx_desc.h"):
+    for f in ("kernels.hip", "dev_fast.hpp", "dev_phase.hpp", "hvx_desc.h"):
         with open(os.path.join(ROOT, "paper_2008_11476_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -177,98 +177,142 @@ def edge_batch(hvx, torch, ctx, w, h, nframes, steps, warmup, phase=False, borde
                 rows=per_mode["rows_per_item"], mode=mode, per_mode=per_mode)
 
 
-def extras(hvx, torch, ctx, quick=False, only_global=False):
-    import synth
-    res = {}
+def kind_counters(name, kernel, rows, ms):
+    """frac and VALU issue fraction of one profiled batch launch, from the
+    committed counter summary profiles/<name>_counters.json (written from
+    rocprofv3 runs of `bench.py --only <name>`), used only while its hash
+    matches the kernel sources and it holds the launch's rows per item."""
+    f = os.path.join(ROOT, "profiles", name + "_counters.json")
+    if not os.path.exists(f):
+        return {}
+    c = json.load(open(f))
+    if c.get("kernel_hash") != kernel_source_hash() or c.get("kernel") != kernel:
+        return {}
+    e = c.get("shapes", {}).get(str(rows))
+    if not e:
+        return {}
+    out = {}
+    if e.get("valu_insts_per_launch"):
+        out["valu_issue_frac"] = round(e["valu_insts_per_launch"] / (VALU_SIMDS * (ms * 1e-3) * CLOCK_HZ / 4), 4)
+    if e.get("bytes_per_launch"):
+        out["traffic_bytes"] = e["bytes_per_launch"]
+    return out
+
+
+def batch_kernel(per_mode, kinds):
+    """Name of the batch kernel a measurement ran (direct or persistent)."""
+    direct = per_mode.get("direct", 1e9) <= per_mode.get("persistent", 1e9)
+    return "hvx::k_batch%s<%d>" % ("_direct" if direct else "", kinds)
+
+
+def ex_edge_4k_batch64(hvx, torch, ctx, rec, rows=None):
+    # the graph without its Phase branch (2 B/px), 64 4K frames
+    r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 20, 3, rows=rows, modes=("direct",) if rows else
+                   ("persistent", "direct"))
+    d = {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1), "hbm_frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
+         "ms": round(r["ms"], 4), "rows": r["rows"], "batch_mode_ms": r["per_mode"]}
+    d.update(kind_counters("edge_4k_batch64", batch_kernel(r["per_mode"], 1), r["rows"], r["ms"]))
+    rec("edge_4k_batch64", d)
+
+
+def ex_edge_phase_4k_latency(hvx, torch, ctx, rec):
     stream = torch.cuda.current_stream().cuda_stream
-
-    def rec(name, d):
-        res[name] = d
-        log(name, json.dumps(d))
-
-    if only_global:
-        global_ops(hvx, torch, ctx, stream, rec)
-        return res
-
-    # the same graph without the Phase branch (2 B/px), 64 4K frames
-    r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 20, 3)
-    rec("edge_4k_batch64", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
-                            "hbm_frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "ms": round(r["ms"], 4),
-                            "rows": r["rows"], "batch_mode_ms": r["per_mode"]})
     # single 4K frame, one launch per frame (latency view)
     inp, out = make_frames(hvx, torch, 3840, 2160, 1, n_out=2)
     g = edge_graph(hvx, ctx, inp[0][1], out[0], phase=True)
     hvx.hvx_graph_autotune(g, stream, 5, ctx=ctx)
     ms, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(g, stream, ctx=ctx), 50, 5)
     rec("edge_phase_4k_single_frame", {"us_per_frame": round(ms * 1e3, 2), "mpix_s": round(8.2944 / (ms / 1e3), 1),
-                                 "rows_per_item": hvx.hvx_graph_query(g, hvx.HVX_QUERY_ROWS_PER_ITEM)})
+                                       "rows_per_item": hvx.hvx_graph_query(g, hvx.HVX_QUERY_ROWS_PER_ITEM)})
     # node by node (fusion off): six kernels, intermediates in HBM
     gu = edge_graph(hvx, ctx, inp[0][1], out[0], phase=True, fusion=False)
     ms_u, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(gu, stream, ctx=ctx), 20, 3)
     hbm_u = hvx.hvx_graph_query(gu, hvx.HVX_QUERY_HBM_BYTES)
     rec("edge_phase_4k_unfused", {"us_per_frame": round(ms_u * 1e3, 2), "mpix_s": round(8.2944 / (ms_u / 1e3), 1),
-                            "kernels": hvx.hvx_graph_query(gu, hvx.HVX_QUERY_NUM_KERNELS),
-                            "hbm_bytes_per_frame": hbm_u, "gbs": round(hbm_u / (ms_u / 1e3) / 1e9, 1),
-                            "fused_speedup_single_frame": round(ms_u / ms, 2)})
+                                  "kernels": hvx.hvx_graph_query(gu, hvx.HVX_QUERY_NUM_KERNELS),
+                                  "hbm_bytes_per_frame": hbm_u, "gbs": round(hbm_u / (ms_u / 1e3) / 1e9, 1),
+                                  "fused_speedup_single_frame": round(ms_u / ms, 2)})
     for x in (g, gu):
         hvx.hvx_release_graph(x)
     del inp, out
-    # 8K frames, CONSTANT(0) borders
+
+
+def ex_edge_8k(hvx, torch, ctx, rec):
     r = edge_batch(hvx, torch, ctx, 7680, 4320, 16, 10, 2, phase=True)
     rec("edge_phase_8k_batch16", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
                                   "ms": round(r["ms"], 3), "rows": r["rows"], "batch_mode_ms": r["per_mode"]})
     r = edge_batch(hvx, torch, ctx, 7680, 4320, 16, 10, 2)
     rec("edge_8k_batch16", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
                             "ms": round(r["ms"], 3), "rows": r["rows"], "batch_mode_ms": r["per_mode"]})
+
+
+def ex_edge_constant(hvx, torch, ctx, rec):
     r = edge_batch(hvx, torch, ctx, 3840, 2160, 64, 10, 2, phase=True, border=(hvx.HVX_BORDER_CONSTANT, 0))
     rec("edge_phase_4k_constant0_batch64", {"mpix_s": round(r["mpix_s"], 1), "alg_gbs": round(r["gbs"], 1),
-                                      "ms": round(r["ms"], 3)})
-    # Gaussian5x5 on 64 4K frames: U8 input (2 B/px) and UYVY input (3 B/px)
-    for uyvy in (False, True):
-        W4, H4, n = 3840, 2160, 64
-        ins, outs = [], []
-        for i in range(n):
-            if uyvy:
-                ib, iv = hvx.alloc_image(H4, W4, hvx.HVX_DF_UYVY)
-                if i < 4:
-                    iv.copy_(torch.from_numpy(synth.uyvy_image(W4, H4, seed=i)))
-                else:
-                    iv.copy_(ins[i % 4][1] ^ ((i // 4) * 37 % 256))
+                                            "ms": round(r["ms"], 3)})
+
+
+def ex_gauss5(hvx, torch, ctx, rec, uyvy=False, rows=None):
+    """Gaussian5x5 on 64 4K frames: U8 input (2 B/px) or UYVY input (3 B/px)."""
+    import synth
+    W4, H4, n = 3840, 2160, 64
+    ins, outs = [], []
+    for i in range(n):
+        if uyvy:
+            ib, iv = hvx.alloc_image(H4, W4, hvx.HVX_DF_UYVY)
+            if i < 4:
+                iv.copy_(torch.from_numpy(synth.uyvy_image(W4, H4, seed=i)))
             else:
-                ib, iv = hvx.alloc_image(H4, W4, hvx.HVX_DF_U8)
-                if i < 4:
-                    iv.copy_(torch.from_numpy(synth.edge_image(W4, H4, seed=i)))
-                else:
-                    iv.copy_(ins[i % 4][1] ^ ((i // 4) * 37 % 256))
-            ins.append((ib, iv))
-            outs.append([hvx.alloc_image(H4, W4, hvx.HVX_DF_U8)])
-        graphs = [gauss5_graph(hvx, ctx, ins[i][1], outs[i], uyvy=uyvy, w=W4) for i in range(n)]
-        ms, _, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, 10, 2)
-        rec("uyvy_gauss5_4k_batch64" if uyvy else "gauss5_4k_batch64",
-            {"mpix_s": round(n * W4 * H4 / 1e6 / (ms / 1e3), 1), "alg_gbs": round(alg / (ms / 1e3) / 1e9, 1),
-             "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms, 4),
-             "batch_mode_ms": per_mode})
-        for x in graphs:
-            hvx.hvx_release_graph(x)
-        del ins, outs
-        torch.cuda.empty_cache()
-    # corner graph at 1080p: single frame and 32-frame batch
+                iv.copy_(ins[i % 4][1] ^ ((i // 4) * 37 % 256))
+        else:
+            ib, iv = hvx.alloc_image(H4, W4, hvx.HVX_DF_U8)
+            if i < 4:
+                iv.copy_(torch.from_numpy(synth.edge_image(W4, H4, seed=i)))
+            else:
+                iv.copy_(ins[i % 4][1] ^ ((i // 4) * 37 % 256))
+        ins.append((ib, iv))
+        outs.append([hvx.alloc_image(H4, W4, hvx.HVX_DF_U8)])
+    graphs = [gauss5_graph(hvx, ctx, ins[i][1], outs[i], uyvy=uyvy, w=W4) for i in range(n)]
+    ms, _, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, 10, 2, rows=rows,
+                                           modes=("direct",) if rows else ("persistent", "direct"))
+    name = "uyvy_gauss5_4k_batch64" if uyvy else "gauss5_4k_batch64"
+    d = {"mpix_s": round(n * W4 * H4 / 1e6 / (ms / 1e3), 1), "alg_gbs": round(alg / (ms / 1e3) / 1e9, 1),
+         "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms, 4), "batch_mode_ms": per_mode}
+    d.update(kind_counters(name, batch_kernel(per_mode, 16 if uyvy else 4), per_mode["rows_per_item"], ms))
+    rec(name, d)
+    for x in graphs:
+        hvx.hvx_release_graph(x)
+    del ins, outs
+    torch.cuda.empty_cache()
+
+
+def ex_corner(hvx, torch, ctx, rec, rows=None):
+    """Corner graph at 1080p: single frame and a 32-frame batch (2 B/px)."""
+    stream = torch.cuda.current_stream().cuda_stream
     inp, out = make_frames(hvx, torch, 1920, 1080, 32)
     graphs = [corner_graph(hvx, ctx, inp[i][1], out[i]) for i in range(32)]
     hvx.hvx_graph_autotune(graphs[0], stream, 5, ctx=ctx)
     for x in graphs:
         hvx.hvx_graph_verify(x, ctx=ctx)
     ms1, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(graphs[0], stream, ctx=ctx), 50, 5)
-    ms, _, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, 10, 2)
+    ms, _, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, 10, 2, rows=rows,
+                                           modes=("direct",) if rows else ("persistent", "direct"))
     mp = 32 * 1920 * 1080 / 1e6
-    rec("corner_1080p", {"us_single_frame": round(ms1 * 1e3, 2), "batch32_mpix_s": round(mp / (ms / 1e3), 1),
-                         "batch32_alg_gbs": round(alg / (ms / 1e3) / 1e9, 1), "batch_mode_ms": per_mode,
-                         "kernel_kind": hvx.hvx_graph_query(graphs[0], hvx.HVX_QUERY_KERNEL_KIND)})
+    d = {"us_single_frame": round(ms1 * 1e3, 2), "batch32_mpix_s": round(mp / (ms / 1e3), 1),
+         "batch32_alg_gbs": round(alg / (ms / 1e3) / 1e9, 1),
+         "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "batch32_ms": round(ms, 4),
+         "batch_mode_ms": per_mode, "kernel_kind": hvx.hvx_graph_query(graphs[0], hvx.HVX_QUERY_KERNEL_KIND)}
+    d.update(kind_counters("corner_1080p", batch_kernel(per_mode, 2), per_mode["rows_per_item"], ms))
+    rec("corner_1080p", d)
     for x in graphs:
         hvx.hvx_release_graph(x)
     del inp, out
     torch.cuda.empty_cache()
-    # mixed batch: 256 images of random sizes and kinds in one launch
+
+
+def ex_mixed(hvx, torch, ctx, rec, rows=None):
+    """256 images of random sizes and kinds in one launch."""
+    import synth
     shapes = synth.batch_shapes(256, seed=0)
     keep, graphs = [], []
     total_px = 0
@@ -285,17 +329,51 @@ def extras(hvx, torch, ctx, quick=False, only_global=False):
             graphs.append(gauss5_graph(hvx, ctx, iv, [ob]))
         total_px += w * h
     torch.cuda.synchronize()
-    ms, ms_host, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, 10, 2)
-    rec("mixed_batch256", {"mpix": round(total_px / 1e6, 1), "ms": round(ms, 3), "batch_mode_ms": per_mode,
-                           "mpix_s": round(total_px / 1e6 / (ms / 1e3), 1),
-                           "alg_gbs": round(alg / (ms / 1e3) / 1e9, 1)})
+    ms, ms_host, alg, mode, per_mode = batch_run(hvx, torch, ctx, graphs, 10, 2, rows=rows,
+                                                 modes=("direct",) if rows else ("persistent", "direct"))
+    d = {"mpix": round(total_px / 1e6, 1), "ms": round(ms, 3), "batch_mode_ms": per_mode,
+         "mpix_s": round(total_px / 1e6 / (ms / 1e3), 1), "alg_gbs": round(alg / (ms / 1e3) / 1e9, 1),
+         "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    d.update(kind_counters("mixed_batch256", batch_kernel(per_mode, 7), per_mode["rows_per_item"], ms))
+    rec("mixed_batch256", d)
     for x in graphs:
         hvx.hvx_release_graph(x)
     del keep
     torch.cuda.empty_cache()
-    global_ops(hvx, torch, ctx, stream, rec)
-    res["serving"] = serving(hvx, torch, ctx)
-    log("serving", json.dumps(res["serving"]))
+
+
+# named context measurements (`--only NAME` runs one of them without the headline)
+EXTRAS = {
+    "edge_4k_batch64": ex_edge_4k_batch64,
+    "edge_phase_4k_latency": ex_edge_phase_4k_latency,
+    "edge_8k": ex_edge_8k,
+    "edge_constant": ex_edge_constant,
+    "gauss5_4k_batch64": lambda hvx, torch, ctx, rec, rows=None: ex_gauss5(hvx, torch, ctx, rec, rows=rows),
+    "uyvy_gauss5_4k_batch64": lambda hvx, torch, ctx, rec, rows=None: ex_gauss5(hvx, torch, ctx, rec, uyvy=True,
+                                                                                 rows=rows),
+    "corner_1080p": ex_corner,
+    "mixed_batch256": ex_mixed,
+    "global_ops_16k": lambda hvx, torch, ctx, rec: global_ops(hvx, torch, ctx, torch.cuda.current_stream().cuda_stream,
+                                                              rec),
+    "global_graph_4k": lambda hvx, torch, ctx, rec: global_graph(hvx, torch, ctx, rec),
+    "serving": lambda hvx, torch, ctx, rec: rec("serving", serving(hvx, torch, ctx)),
+}
+
+
+def extras(hvx, torch, ctx, only=None, rows=None):
+    res = {}
+
+    def rec(name, d):
+        res[name] = d
+        log(name, json.dumps(d))
+
+    for name, fn in EXTRAS.items():
+        if only and name not in only:
+            continue
+        if rows is not None:
+            fn(hvx, torch, ctx, rec, rows=rows)
+        else:
+            fn(hvx, torch, ctx, rec)
     return res
 
 
@@ -329,6 +407,48 @@ def global_ops(hvx, torch, ctx, stream, rec):
     hvx.hvx_release_image(gom)
     del gb, gv, gout, gloc, gob, gov
     torch.cuda.empty_cache()
+
+
+def global_graph(hvx, torch, ctx, rec):
+    """Global operators as graph nodes on one 3840x2160 frame: Gaussian3x3 ->
+    Histogram and Gaussian5x5 -> MinMaxLoc counts, the producer fused into the
+    reduction (one kernel, 1 B/px read) against the same graphs node by node
+    (the Gaussian written to memory and read back: 3 B/px)."""
+    import synth
+    stream = torch.cuda.current_stream().cuda_stream
+    w, h = 3840, 2160
+    ib, iv = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+    iv.copy_(torch.from_numpy(synth.edge_image(w, h, seed=0)))
+    img = hvx.image_from_tensor(ctx, iv, hvx.HVX_DF_U8)
+    buf = torch.zeros(8192, dtype=torch.uint8, device="cuda")
+    res = hvx.hvx_buffer_from_ptr(ctx, buf.data_ptr(), 8192)
+    d = {"image": "3840x2160 U8"}
+    for name, make in (("gauss3_histogram", lambda g, v: hvx.hvx_histogram_node(g, v, 256, 0, 256, res)),
+                       ("gauss5_min_max_loc_counts", lambda g, v: hvx.hvx_min_max_loc_node(g, v, res, None, 0))):
+        row = {}
+        for fusion in (1, 0):
+            g = hvx.hvx_graph_create(ctx)
+            v = hvx.hvx_image_create_virtual(g)
+            if name.startswith("gauss3"):
+                hvx.hvx_gaussian3x3_node(g, img, v)
+            else:
+                hvx.hvx_gaussian5x5_node(g, img, v)
+            make(g, v)
+            hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, fusion)
+            hvx.hvx_graph_verify(g, ctx=ctx)
+            ms, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(g, stream, ctx=ctx), 20, 3)
+            hbm = hvx.hvx_graph_query(g, hvx.HVX_QUERY_HBM_BYTES)
+            row["fused" if fusion else "node_by_node"] = {
+                "us": round(ms * 1e3, 2), "mpix_s": round(w * h / 1e6 / (ms / 1e3), 1),
+                "kernels": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS), "hbm_bytes": hbm,
+                "gbs": round(hbm / (ms / 1e3) / 1e9, 1)}
+            hvx.hvx_release_graph(g)
+        row["fused_speedup"] = round(row["node_by_node"]["us"] / row["fused"]["us"], 2)
+        d[name] = row
+    rec("global_graph_4k", d)
+    hvx.hvx_release_image(img)
+    hvx.hvx_release_buffer(res)
+    del ib, iv, buf
 
 
 def serving(hvx, torch, ctx, n_req=240, budget=512 << 20):
@@ -523,8 +643,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--global-ops-only", action="store_true",
-                    help="of the extra measurements, run only the global operators")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated names of extra measurements (%s) to run alone, without the headline "
+                         "(profiling runs)" % ", ".join(EXTRAS))
+    ap.add_argument("--extra-rows", type=int, default=None,
+                    help="with --only: pin the batches to this many rows per work item, direct launch (no tuning)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rows", type=int, default=None,
                     help="pin the headline batch to this many rows per work item (default: tune)")
@@ -552,8 +675,16 @@ def main():
 
 def run(args, torch, hvx, ctx):
     W, H = 3840, 2160
-    copy_ref = copy_calibration(torch)
+    copy_ref = copy_calibration(torch)  # also the known-size copy that calibrates the traffic counters
     log("plain device copy:", copy_ref)
+    if args.only:
+        names = args.only.split(",")
+        bad = [n for n in names if n not in EXTRAS]
+        if bad:
+            print("unknown measurement(s): %s" % ", ".join(bad), file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(extras(hvx, torch, ctx, only=names, rows=args.extra_rows)), flush=True)
+        return
     log("edge+phase graph: %d x %dx%d frames per step, %d steps" % (args.frames, W, H, args.steps))
     modes = ("persistent", "direct") if args.mode == "auto" else (args.mode,)
     r = edge_batch(hvx, torch, ctx, W, H, args.frames, args.steps, args.warmup, phase=True, rows=args.rows,
@@ -614,7 +745,7 @@ def run(args, torch, hvx, ctx):
         r["mpix_s"], r["gbs"], 100 * r["gbs"] / HBM_PEAK_GBS, ms, r["ms_host"]))
     if not args.no_extras:
         try:
-            out["extras"] = extras(hvx, torch, ctx, only_global=args.global_ops_only)
+            out["extras"] = extras(hvx, torch, ctx)
         except Exception as e:  # context numbers must never cost the headline
             import traceback
             traceback.print_exc()

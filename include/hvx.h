@@ -440,13 +440,38 @@ hvx_status hvx_batch_autotune(hvx_batch b, void* hip_stream, int iters);
  * most max_slots requests on the device, using n_streams streams (>= 1). */
 hvx_status hvx_server_create(hvx_context ctx, int mode, size_t hbm_budget_bytes, uint32_t max_slots,
                              uint32_t n_streams, hvx_server* out);
-/* Queue a request: run verified `templ` (one non-virtual input, one
- * non-virtual output, both U8 or UYVY) on host frame `in` (row pitch
- * in_pitch) and write its output to host memory `out` (row pitch
- * out_pitch).  Host buffers must stay valid until the request is reported
- * done.  `tag` is returned by hvx_server_poll. */
+/* Queue a request: run verified `templ` (one non-virtual input image, one
+ * non-virtual output image) on host frame `in` (row pitch in_pitch) and
+ * write its output to host memory `out` (row pitch out_pitch).  Host buffers
+ * must stay valid until the request is reported done.  `tag` is returned by
+ * hvx_server_poll.  Templates with more images, or frames in device memory:
+ * hvx_server_submit_bound. */
 hvx_status hvx_server_submit(hvx_server s, hvx_graph templ, const void* in, size_t in_pitch, void* out,
                              size_t out_pitch, uint64_t tag);
+/* One image of a request: the template image it stands for and the
+ * request's pixels for it (host or device memory, row pitch in bytes). */
+typedef struct hvx_binding {
+  hvx_image image;
+  void* ptr;
+  size_t pitch;
+} hvx_binding;
+#define HVX_MEMORY_HOST 0   /* copied into device buffers from the HBM budget, outputs copied back */
+#define HVX_MEMORY_DEVICE 1 /* already in device memory: the request runs on it in place */
+/* Queue a request of any verified template: every non-virtual image the
+ * template reads or writes is bound once in `bindings` (n entries), all in
+ * the `memory` given.  Device memory needs a 16-byte aligned base and a pitch
+ * that is a multiple of 64; it is read and written in place, so frames that
+ * stay resident in HBM cost no copies.  Host memory is copied in (inputs)
+ * and out (outputs) as in hvx_server_submit.  A template whose plan is one
+ * strip kernel (edge with or without Phase, corner, Gaussian5x5, UYVY luma
+ * Gaussian5x5) joins the batch launch of a step; any other template runs its
+ * own plan, its intermediate images in a block taken from the HBM budget.
+ * Buffers stay valid until the request is reported done.  INVALID_PARAMETERS
+ * for an unbound, twice-bound or misaligned image; NOT_SUPPORTED for a
+ * template with global operator results; NO_MEMORY when the request alone
+ * exceeds the budget. */
+hvx_status hvx_server_submit_bound(hvx_server s, hvx_graph templ, const hvx_binding* bindings, uint32_t n,
+                                   int memory, uint64_t tag);
 /* Collect up to `max` finished requests: tags, statuses, latencies (s, from
  * submit to completion).  Non-blocking; *n = number returned. */
 hvx_status hvx_server_poll(hvx_server s, uint64_t* tags, int32_t* statuses, double* latency_s, uint32_t max,

@@ -41,6 +41,15 @@ HVX_BATCH_PERSISTENT, HVX_BATCH_USE_GRAPH, HVX_BATCH_ROWS = 1, 2, 3
 BYTES_PER_PIXEL = {HVX_DF_U8: 1, HVX_DF_S16: 2, HVX_DF_S32: 4, HVX_DF_F32: 4, HVX_DF_UYVY: 2}
 
 
+HVX_MEMORY_HOST, HVX_MEMORY_DEVICE = 0, 1
+
+
+class hvx_binding(ctypes.Structure):
+    """One image of a served request (include/hvx.h): the template image it
+    stands for, the request's pixels and their row pitch."""
+    _fields_ = [("image", ctypes.c_void_p), ("ptr", ctypes.c_void_p), ("pitch", ctypes.c_size_t)]
+
+
 class HvxError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (status_name(status) if _lib else status, message))
@@ -124,6 +133,7 @@ def _load():
         "hvx_batch_autotune": [_vp, _vp, ctypes.c_int],
         "hvx_server_create": [_vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, _P(_vp)],
         "hvx_server_submit": [_vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, ctypes.c_uint64],
+        "hvx_server_submit_bound": [_vp, _vp, _P(hvx_binding), ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64],
         "hvx_server_poll": [_vp, _P(ctypes.c_uint64), _P(ctypes.c_int32), _P(ctypes.c_double), ctypes.c_uint32,
                             _P(ctypes.c_uint32)],
         "hvx_server_drain": [_vp],
@@ -462,6 +472,14 @@ def hvx_server_create(ctx, mode, budget_bytes, max_slots, n_streams):
 
 def hvx_server_submit(s, templ, in_ptr, in_pitch, out_ptr, out_pitch, tag, ctx=None):
     _check(_load().hvx_server_submit(s, templ, in_ptr, in_pitch, out_ptr, out_pitch, tag), ctx)
+
+
+def hvx_server_submit_bound(s, templ, bindings, memory, tag, ctx=None):
+    """Queue a request; `bindings` lists (template image, pointer, pitch) for
+    every non-virtual image of the template, in `memory` (HVX_MEMORY_HOST or
+    HVX_MEMORY_DEVICE)."""
+    arr = (hvx_binding * max(1, len(bindings)))(*[hvx_binding(i, p, pt) for (i, p, pt) in bindings])
+    _check(_load().hvx_server_submit_bound(s, templ, arr, len(bindings), memory, tag), ctx)
 
 
 def hvx_server_poll(s, max_n=256, ctx=None):

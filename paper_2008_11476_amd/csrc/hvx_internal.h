@@ -153,8 +153,13 @@ struct Graph : Object {
   bool verified = false;
   int opt_fusion = 1, opt_dce = 1, opt_tile = 0, opt_specialize = 1, opt_xcd = 1;
   std::unique_ptr<Plan> plan;
-  // device state
-  std::vector<void*> scratch;  // one buffer per materialised value (index = value id), or null
+  // device state: the materialised values live in one block of scratch_total
+  // bytes, value v at scratch_off[v] with row pitch scratch_pitch[v] (0: not
+  // materialised); a served request runs the plan on a block of its own
+  char* scratch_base = nullptr;
+  size_t scratch_total = 0;
+  bool prepared = false;
+  std::vector<size_t> scratch_off;
   std::vector<size_t> scratch_pitch;
   GProg* dev_progs = nullptr;  // device copies of the groups' generic programs (index = group)
   void* last_stream = nullptr;
@@ -189,12 +194,23 @@ hvx_status verify_graph(Graph* g);
 std::string graph_signature(const Graph* g);
 
 // ---- runtime (runtime.cpp) --------------------------------------------------
+// Device memory of one execution of a plan in place of the graph's own: the
+// non-virtual values listed in `ptr` (index = value id; null = the image's
+// own pointer) and a scratch block for the materialised values (null = the
+// graph's).  Used by the server to run a template on a request's buffers.
+struct Bind {
+  std::vector<void*> ptr;
+  std::vector<int64_t> pitch;
+  char* scratch = nullptr;
+};
 hvx_status ensure_device(Context* ctx);
+hvx_status prepare_graph(Graph* g);
 hvx_status schedule_graph(Graph* g, void* stream);
+hvx_status schedule_bound(Graph* g, void* stream, const Bind* b);
 void free_graph_device(Graph* g);
 int default_rows(const Group& gr, int num_cus);
 int rows_for(const Graph* g, const Group& gr);  // rows per work item in effect (option, tuned, default)
-void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_override = 0);
+void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_override = 0, const Bind* b = nullptr);
 int64_t fast_items(const Group& gr);
 
 }  // namespace hvx

@@ -40,19 +40,22 @@ hvx_status ensure_device(Context* ctx) {
 
 void free_graph_device(Graph* g) {
   if (g->scheduled && g->last_stream != (void*)-1) (void)hipStreamSynchronize((hipStream_t)g->last_stream);
-  for (void* p : g->scratch)
-    if (p) (void)hipFree(p);
+  if (g->scratch_base) (void)hipFree(g->scratch_base);
   if (g->dev_progs) (void)hipFree(g->dev_progs);
   g->dev_progs = nullptr;
-  g->scratch.clear();
+  g->scratch_base = nullptr;
+  g->scratch_total = 0;
+  g->scratch_off.clear();
   g->scratch_pitch.clear();
+  g->prepared = false;
   g->scheduled = false;
 }
 
+// Device copies of the generic programs and one scratch block holding every
+// materialised value (rows pitched to 64 bytes, each value 256-byte aligned).
 static hvx_status ensure_scratch(Graph* g) {
   Plan& p = *g->plan;
-  if (g->scratch.size() == p.vals.size()) return HVX_SUCCESS;
-  // generic programs, one device copy per group
+  if (g->prepared) return HVX_SUCCESS;
   std::vector<GProg> progs(p.groups.size());
   for (size_t i = 0; i < p.groups.size(); ++i) progs[i] = p.groups[i].prog;
   if (hipMalloc((void**)&g->dev_progs, progs.size() * sizeof(GProg)) != hipSuccess ||
@@ -61,31 +64,46 @@ static hvx_status ensure_scratch(Graph* g) {
     g->dev_progs = nullptr;
     return set_error(g->ctx, HVX_ERROR_NO_MEMORY, "cannot upload kernel programs");
   }
-  g->scratch.assign(p.vals.size(), nullptr);
+  g->scratch_off.assign(p.vals.size(), 0);
   g->scratch_pitch.assign(p.vals.size(), 0);
+  size_t total = 0;
   for (size_t v = 0; v < p.vals.size(); ++v) {
     if (!p.vals[v].materialize) continue;
-    size_t pitch = ((size_t)p.vals[v].w * df_bytes(p.vals[v].df) + 63) / 64 * 64;
-    void* ptr = nullptr;
-    if (hipMalloc(&ptr, pitch * p.vals[v].h) != hipSuccess) {
-      free_graph_device(g);
-      return set_error(g->ctx, HVX_ERROR_NO_MEMORY, "cannot allocate %zu bytes for an intermediate image",
-                       pitch * p.vals[v].h);
-    }
-    g->scratch[v] = ptr;
+    const size_t pitch = ((size_t)p.vals[v].w * df_bytes(p.vals[v].df) + 63) / 64 * 64;
+    g->scratch_off[v] = total;
     g->scratch_pitch[v] = pitch;
+    total += (pitch * p.vals[v].h + 255) & ~(size_t)255;
   }
+  if (total && hipMalloc((void**)&g->scratch_base, total) != hipSuccess) {
+    g->scratch_base = nullptr;
+    free_graph_device(g);
+    return set_error(g->ctx, HVX_ERROR_NO_MEMORY, "cannot allocate %zu bytes for intermediate images", total);
+  }
+  g->scratch_total = total;
+  g->prepared = true;
   return HVX_SUCCESS;
 }
 
-static void value_ptr(const Graph* g, int v, void** ptr, int64_t* pitch) {
+// Device address and pitch of value v: a non-virtual image's own memory (or
+// the request's, under a binding), a materialised intermediate in the
+// scratch block (the graph's, or the binding's).
+static void value_ptr(const Graph* g, int v, void** ptr, int64_t* pitch, const Bind* b = nullptr) {
   const Value& val = g->plan->vals[v];
   if (!val.is_virtual) {
-    *ptr = val.img->ptr;
-    *pitch = (int64_t)val.img->pitch;
+    if (b && v < (int)b->ptr.size() && b->ptr[v]) {
+      *ptr = b->ptr[v];
+      *pitch = b->pitch[v];
+    } else {
+      *ptr = val.img->ptr;
+      *pitch = (int64_t)val.img->pitch;
+    }
+  } else if (v < (int)g->scratch_pitch.size() && g->scratch_pitch[v]) {
+    char* base = b && b->scratch ? b->scratch : g->scratch_base;
+    *ptr = base + g->scratch_off[v];
+    *pitch = (int64_t)g->scratch_pitch[v];
   } else {
-    *ptr = v < (int)g->scratch.size() ? g->scratch[v] : nullptr;
-    *pitch = v < (int)g->scratch_pitch.size() ? (int64_t)g->scratch_pitch[v] : 0;
+    *ptr = nullptr;
+    *pitch = 0;
   }
 }
 
@@ -137,7 +155,7 @@ static StripGrid strip_grid(const Group& gr, int rows) {
 
 int64_t fast_items(const Group& gr) { return (int64_t)gr.prog.tiles_x; }
 
-void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_override) {
+void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_override, const Bind* b) {
   const Plan& p = *g->plan;
   memset(bi, 0, sizeof *bi);
   bi->kind = gr.kind;
@@ -147,14 +165,14 @@ void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_ov
   if (gr.kind == FK_EDGE) {
     EdgeDesc& d = bi->d.e;
     d.g = strip_grid(gr, rows);
-    value_ptr(g, gr.v_in, &ptr, &pitch);
+    value_ptr(g, gr.v_in, &ptr, &pitch, b);
     d.in = (const uint8_t*)ptr;
     d.in_pitch = pitch;
-    value_ptr(g, gr.v_out, &ptr, &pitch);
+    value_ptr(g, gr.v_out, &ptr, &pitch, b);
     d.out = (uint8_t*)ptr;
     d.out_pitch = pitch;
     if (gr.v_aux >= 0) {
-      value_ptr(g, gr.v_aux, &ptr, &pitch);
+      value_ptr(g, gr.v_aux, &ptr, &pitch, b);
       d.phase = (uint8_t*)ptr;
       d.phase_pitch = pitch;
     }
@@ -172,10 +190,10 @@ void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_ov
   } else if (gr.kind == FK_CORNER) {
     CornerDesc& d = bi->d.c;
     d.g = strip_grid(gr, rows);
-    value_ptr(g, gr.v_in, &ptr, &pitch);
+    value_ptr(g, gr.v_in, &ptr, &pitch, b);
     d.in = (const uint8_t*)ptr;
     d.in_pitch = pitch;
-    value_ptr(g, gr.v_out, &ptr, &pitch);
+    value_ptr(g, gr.v_out, &ptr, &pitch, b);
     d.out = (uint8_t*)ptr;
     d.out_pitch = pitch;
     const LOp* sx = find_op(p, gr, OP_SOBEL_X);
@@ -196,11 +214,11 @@ void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_ov
   } else if (gr.kind == FK_GAUSS5) {
     Gauss5Desc& d = bi->d.g5;
     d.g = strip_grid(gr, rows);
-    value_ptr(g, gr.v_in, &ptr, &pitch);
+    value_ptr(g, gr.v_in, &ptr, &pitch, b);
     d.in = (const uint8_t*)ptr;
     d.in_pitch = pitch;
     d.uyvy = p.vals[gr.v_in].df == DF_UYVY;
-    value_ptr(g, gr.v_out, &ptr, &pitch);
+    value_ptr(g, gr.v_out, &ptr, &pitch, b);
     d.out = (uint8_t*)ptr;
     d.out_pitch = pitch;
     const LOp* g5 = find_op(p, gr, OP_GAUSS5);
@@ -212,17 +230,17 @@ void fill_fast_desc(const Graph* g, const Group& gr, BatchImage* bi, int rows_ov
 
 // One global operator over an image in memory (group kind FK_GLOBAL), with
 // the streaming kernels of the immediate-mode calls.
-static hipError_t launch_global_group(Graph* g, const Group& gr, hipStream_t s) {
+static hipError_t launch_global_group(Graph* g, const Group& gr, hipStream_t s, const Bind* b) {
   const Plan& p = *g->plan;
   const LOp& o = p.ops[gr.ops[0]];
   void* ptr;
   int64_t pitch;
-  value_ptr(g, o.in[0], &ptr, &pitch);
+  value_ptr(g, o.in[0], &ptr, &pitch, b);
   const Value& iv = p.vals[o.in[0]];
   GlobalImg im{(const uint8_t*)ptr, pitch, (int32_t)iv.w, (int32_t)iv.h, df_bytes(iv.df)};
   void* out;
   int64_t unused;
-  value_ptr(g, o.out, &out, &unused);
+  value_ptr(g, o.out, &out, &unused, b);
   switch (o.kind) {
     case OP_HISTOGRAM: return launch_histogram(im, (int)o.gp[0], (int)o.gp[1], (int)o.gp[2], (uint32_t*)out, s);
     case OP_MINMAX: return launch_min_max(im, (int32_t*)out, s);
@@ -234,7 +252,7 @@ static hipError_t launch_global_group(Graph* g, const Group& gr, hipStream_t s) 
     case OP_EQHIST: return launch_equalize_mapping(im, out, s);
     case OP_MMLOCS: {
       void* mm;
-      value_ptr(g, o.in[1], &mm, &unused);
+      value_ptr(g, o.in[1], &mm, &unused, b);
       const uint32_t cap = o.gp[0];
       hipError_t e = launch_extreme_locs(im, (int32_t*)mm, (uint32_t*)out, (uint32_t*)out + 2 * cap, cap, s);
       return e != hipSuccess ? e : launch_clamp_slots((int32_t*)mm, cap, s);
@@ -243,7 +261,7 @@ static hipError_t launch_global_group(Graph* g, const Group& gr, hipStream_t s) 
   return hipErrorInvalidValue;
 }
 
-static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
+static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s, const Bind* b) {
   hipError_t e = hipSuccess;
   const int gi = (int)(&gr - g->plan->groups.data());
   if (gr.kind == FK_GENERIC) {
@@ -252,7 +270,7 @@ static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
     for (int i = 0; i < gr.prog.nvals; ++i) {
       const GVal& v = gr.prog.vals[i];
       if (v.io < 0) continue;
-      value_ptr(g, gr.gvals[i], &io.ptr[v.io], &io.pitch[v.io]);
+      value_ptr(g, gr.gvals[i], &io.ptr[v.io], &io.pitch[v.io], b);
       if (!io.ptr[v.io]) return set_error(g->ctx, HVX_ERROR_DEVICE, "unbound image in plan");
     }
     // global operators reduced by the kernel: starting values before it,
@@ -269,10 +287,10 @@ static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s) {
         if (e == hipSuccess && P.ops[i].kind == OP_MMCOUNT) e = launch_zero_words((int32_t*)out + 4, 2, s);
       }
   } else if (gr.kind == FK_GLOBAL) {
-    e = launch_global_group(g, gr, s);
+    e = launch_global_group(g, gr, s, b);
   } else {
     BatchImage bi;
-    fill_fast_desc(g, gr, &bi);
+    fill_fast_desc(g, gr, &bi, 0, b);
     const bool xcd = xcd_for(g, gr) != 0;
     if (gr.kind == FK_EDGE) e = launch_edge(bi.d.e, xcd, s);
     else if (gr.kind == FK_CORNER) e = launch_corner(bi.d.c, xcd, s);
@@ -289,18 +307,20 @@ hvx_status prepare_graph(Graph* g) {
   return ensure_scratch(g);
 }
 
-hvx_status schedule_graph(Graph* g, void* stream) {
+hvx_status schedule_bound(Graph* g, void* stream, const Bind* b) {
   hvx_status s = prepare_graph(g);
   if (s) return s;
   hipStream_t st = (hipStream_t)stream;
   for (const Group& gr : g->plan->groups) {
-    s = launch_group(g, gr, st);
+    s = launch_group(g, gr, st, b);
     if (s) return s;
   }
   g->last_stream = stream;
   g->scheduled = true;
   return HVX_SUCCESS;
 }
+
+hvx_status schedule_graph(Graph* g, void* stream) { return schedule_bound(g, stream, nullptr); }
 
 // ---- batches --------------------------------------------------------------------
 
@@ -428,7 +448,7 @@ static hvx_status batch_enqueue(Batch* b, hipStream_t s) {
   for (Graph* g : b->separate) {
     hvx_status st = HVX_SUCCESS;
     for (const Group& gr : g->plan->groups) {
-      st = launch_group(g, gr, s);
+      st = launch_group(g, gr, s, nullptr);
       if (st) return st;
     }
   }

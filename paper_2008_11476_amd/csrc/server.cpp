@@ -1,15 +1,24 @@
 // Request loop over verified graph templates.
 //
+// A request runs a template on images of its own: host frames (copied into
+// device buffers the server takes from its HBM budget, and back), or frames
+// already in device memory (run in place).  A template whose plan is one
+// strip kernel (edge, with or without Phase; corner; Gaussian5x5) joins the
+// batch launch of a step; any other template runs its own plan on the
+// request's images, its intermediates in a scratch block taken from the
+// budget.
+//
 // CONTINUOUS mode: a worker thread admits queued requests in arrival order
-// while their device buffers fit in the HBM budget and a slot is free, packs
+// while their device memory fits in the HBM budget and a slot is free, packs
 // every admitted request into one device step (host-to-device copies, one
-// batch launch over all their work items, device-to-host copies)
-// on a stream with no step in flight, and retires steps as their completion
-// events fire.  With n_streams >= 2, requests that arrive while a step runs
-// start in a new step that overlaps it on the device.
+// batch launch over all their work items plus the plans of the other
+// templates, device-to-host copies) on a stream with no step in flight, and
+// retires steps as their completion events fire.  With n_streams >= 2,
+// requests that arrive while a step runs start in a new step that overlaps
+// it on the device.
 //
 // PLAIN mode: one request at a time, each with its own copies, its own
-// kernel launch and a wait, the way a program calling process per frame
+// kernel launches and a wait, the way a program calling process per frame
 // would run them.
 #include <hip/hip_runtime.h>
 #include <string.h>
@@ -81,20 +90,27 @@ struct Arena {
   }
 };
 
+// One non-virtual image of a request's template, bound to the request's memory.
+struct Binding {
+  int v = -1;                // plan value of the template image
+  bool input = false;        // a graph input (copied in for host requests)
+  const void* host = nullptr;  // host requests: the caller's pixels
+  size_t host_pitch = 0;
+  void* dev = nullptr;       // device memory the request runs on
+  size_t dev_pitch = 0;
+  size_t row = 0, h = 0;     // bytes per row, rows
+  size_t bytes = 0;          // arena bytes (host requests)
+};
+
 struct Request {
   uint64_t tag;
   Graph* templ;
-  const void* in;
-  size_t in_pitch;
-  void* out;
-  size_t out_pitch;
   double t_submit;
-  Value* vin;
-  Value* vout;
-  size_t in_row, out_row, in_bytes, out_bytes;  // device layout
-  size_t d_in_pitch, d_out_pitch;
-  void* d_in = nullptr;
-  void* d_out = nullptr;
+  bool device = false;  // frames already in device memory: no copies, nothing from the arena
+  std::vector<Binding> io;
+  char* scratch = nullptr;  // intermediates of a non-batched template
+  size_t scratch_bytes = 0;
+  Bind bind;
   bool fail = false;
 };
 
@@ -138,37 +154,53 @@ static bool batchable(const Graph* g) {
   return g->plan && g->plan->groups.size() == 1 && is_strip_kind(g->plan->groups[0].kind);
 }
 
+static void release_memory(Server* sv, Request* r) {
+  if (!r->device)
+    for (Binding& b : r->io)
+      if (b.dev) {
+        sv->arena.release(b.dev, b.bytes);
+        b.dev = nullptr;
+      }
+  if (r->scratch) sv->arena.release(r->scratch, r->scratch_bytes);
+  r->scratch = nullptr;
+}
+
+// Device memory of a request from the arena (host buffers, the scratch
+// block); false, with nothing kept, when it does not fit now.
+static bool take_memory(Server* sv, Request* r) {
+  bool ok = true;
+  if (!r->device)
+    for (Binding& b : r->io) {
+      b.dev = sv->arena.alloc(b.bytes);
+      if (!b.dev) {
+        ok = false;
+        break;
+      }
+    }
+  if (ok && r->scratch_bytes) {
+    r->scratch = (char*)sv->arena.alloc(r->scratch_bytes);
+    ok = r->scratch != nullptr;
+  }
+  if (!ok) {
+    release_memory(sv, r);
+    return false;
+  }
+  r->bind.ptr.assign(r->templ->plan->vals.size(), nullptr);
+  r->bind.pitch.assign(r->templ->plan->vals.size(), 0);
+  for (const Binding& b : r->io) {
+    r->bind.ptr[b.v] = b.dev;
+    r->bind.pitch[b.v] = (int64_t)b.dev_pitch;
+  }
+  r->bind.scratch = r->scratch;
+  return true;
+}
+
 static void finish(Server* sv, Request* r, int32_t status, double t) {
-  if (r->d_in) sv->arena.release(r->d_in, r->in_bytes);
-  if (r->d_out) sv->arena.release(r->d_out, r->out_bytes);
+  release_memory(sv, r);
   sv->done.push_back({r->tag, status, t - r->t_submit});
   --sv->in_flight;
   ++sv->completed;
   delete r;
-}
-
-// Build the request's work description from its template with the request's
-// device buffers bound in place of the template's images.
-static void request_desc(Request* r, BatchImage* bi) {
-  const Group& gr = r->templ->plan->groups[0];
-  fill_fast_desc(r->templ, gr, bi);
-  if (bi->kind == FK_EDGE) {
-    bi->d.e.in = (const uint8_t*)r->d_in;
-    bi->d.e.in_pitch = (int64_t)r->d_in_pitch;
-    bi->d.e.out = (uint8_t*)r->d_out;
-    bi->d.e.out_pitch = (int64_t)r->d_out_pitch;
-    bi->d.e.phase = nullptr;
-  } else if (bi->kind == FK_CORNER) {
-    bi->d.c.in = (const uint8_t*)r->d_in;
-    bi->d.c.in_pitch = (int64_t)r->d_in_pitch;
-    bi->d.c.out = (uint8_t*)r->d_out;
-    bi->d.c.out_pitch = (int64_t)r->d_out_pitch;
-  } else if (bi->kind == FK_GAUSS5) {
-    bi->d.g5.in = (const uint8_t*)r->d_in;
-    bi->d.g5.in_pitch = (int64_t)r->d_in_pitch;
-    bi->d.g5.out = (uint8_t*)r->d_out;
-    bi->d.g5.out_pitch = (int64_t)r->d_out_pitch;
-  }
 }
 
 static bool grow(StreamSlot& sl, size_t nimg, size_t nitems) {
@@ -195,30 +227,24 @@ static bool launch_step(Server* sv, StreamSlot& sl, std::vector<Request*>& reqs)
   std::vector<Request*> live;
   for (Request* r : reqs)
     if (!r->fail) live.push_back(r);
+  for (Request* r : live)
+    if (!r->device)
+      for (const Binding& b : r->io)
+        if (b.input && hipMemcpy2DAsync(b.dev, b.dev_pitch, b.host, b.host_pitch, b.row, b.h, hipMemcpyHostToDevice,
+                                        s) != hipSuccess)
+          return false;
+  std::vector<BatchImage> imgs;
   for (Request* r : live) {
-    if (hipMemcpy2DAsync(r->d_in, r->d_in_pitch, r->in, r->in_pitch, r->in_row, r->vin->h, hipMemcpyHostToDevice,
-                         s) != hipSuccess)
+    if (batchable(r->templ) && sv->mode == HVX_SERVER_CONTINUOUS) {
+      imgs.emplace_back();
+      fill_fast_desc(r->templ, r->templ->plan->groups[0], &imgs.back(), 0, &r->bind);
+    } else if (schedule_bound(r->templ, s, &r->bind) != HVX_SUCCESS) {
       return false;
+    }
   }
-  if (sv->mode == HVX_SERVER_PLAIN) {
-    for (Request* r : live) {
-      if (batchable(r->templ)) {
-        BatchImage bi;
-        request_desc(r, &bi);
-        const bool xcd = r->templ->plan->groups[0].xcd != 0;
-        hipError_t e = bi.kind == FK_EDGE     ? launch_edge(bi.d.e, xcd, s)
-                       : bi.kind == FK_CORNER ? launch_corner(bi.d.c, xcd, s)
-                                              : launch_gauss5(bi.d.g5, xcd, s);
-        if (e != hipSuccess) return false;
-      }
-    }
-  } else if (!live.empty()) {
+  if (!imgs.empty()) {
     size_t nitems = 0;
-    std::vector<BatchImage> imgs(live.size());
-    for (size_t i = 0; i < live.size(); ++i) {
-      request_desc(live[i], &imgs[i]);
-      nitems += imgs[i].nitems;
-    }
+    for (const BatchImage& bi : imgs) nitems += bi.nitems;
     if (!grow(sl, imgs.size(), nitems)) return false;
     size_t first = 0;
     for (size_t i = 0; i < imgs.size(); ++i) {
@@ -238,11 +264,12 @@ static bool launch_step(Server* sv, StreamSlot& sl, std::vector<Request*>& reqs)
     if (launch_batch(sl.d_imgs, sl.d_items, (int)nitems, nullptr, 1, false, kinds, s) != hipSuccess)
       return false;
   }
-  for (Request* r : live) {
-    if (hipMemcpy2DAsync(r->out, r->out_pitch, r->d_out, r->d_out_pitch, r->out_row, r->vout->h,
-                         hipMemcpyDeviceToHost, s) != hipSuccess)
-      return false;
-  }
+  for (Request* r : live)
+    if (!r->device)
+      for (const Binding& b : r->io)
+        if (!b.input && hipMemcpy2DAsync((void*)b.host, b.host_pitch, b.dev, b.dev_pitch, b.row, b.h,
+                                         hipMemcpyDeviceToHost, s) != hipSuccess)
+          return false;
   if (hipEventRecord(sl.done, s) != hipSuccess) return false;
   sl.reqs = reqs;
   sl.busy = true;
@@ -285,14 +312,7 @@ static void worker_main(Server* sv) {
         if (plain) break;
         continue;
       }
-      void* a = sv->arena.alloc(r->in_bytes);
-      void* b = a ? sv->arena.alloc(r->out_bytes) : nullptr;
-      if (!a || !b) {
-        if (a) sv->arena.release(a, r->in_bytes);
-        break;  // head of line waits for memory
-      }
-      r->d_in = a;
-      r->d_out = b;
+      if (!take_memory(sv, r)) break;  // head of line waits for memory
       sv->queue.pop_front();
       ++sv->in_flight;
       sv->peak_in_flight = std::max(sv->peak_in_flight, sv->in_flight);
@@ -341,6 +361,90 @@ void destroy_server_object(Object* o) {
   sv->arena.destroy();
   registry_remove(sv);
   delete sv;
+}
+
+// Checks a request against its template and queues it.  `bind` gives, for
+// each non-virtual image of the template, the request's memory (host or
+// device) and its pitch.
+static hvx_status submit_request(Server* sv, Graph* g, const std::vector<std::pair<Image*, std::pair<void*, size_t>>>& bind,
+                                 bool device, uint64_t tag) {
+  if (!g->verified) {
+    hvx_status s = verify_graph(g);
+    if (s) return s;
+  }
+  hvx_status st = prepare_graph(g);
+  if (st) return st;
+  const Plan& p = *g->plan;
+  auto* r = new Request();
+  r->tag = tag;
+  r->templ = g;
+  r->device = device;
+  std::vector<int> seen(p.vals.size(), 0);
+  for (size_t v = 0; v < p.vals.size(); ++v) {
+    const Value& val = p.vals[v];
+    if (val.is_virtual || !val.live) continue;
+    if (val.df == DF_BUF) {
+      delete r;
+      return set_error(sv->ctx, HVX_ERROR_NOT_SUPPORTED, "templates with global operator results are not served");
+    }
+    Binding b;
+    b.v = (int)v;
+    b.input = val.producer < 0;
+    b.row = (size_t)val.w * df_bytes(val.df);
+    b.h = val.h;
+    bool found = false;
+    for (const auto& x : bind)
+      if (x.first == val.img) {
+        if (found) {
+          delete r;
+          return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "an image is bound twice");
+        }
+        found = true;
+        if (!x.second.first || x.second.second < b.row) {
+          delete r;
+          return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "null buffer or pitch smaller than a row");
+        }
+        if (device) {
+          if (x.second.second % 64 || ((uintptr_t)x.second.first & 15)) {
+            delete r;
+            return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS,
+                             "device buffers need a 16-byte aligned base and a pitch that is a multiple of 64");
+          }
+          b.dev = x.second.first;
+          b.dev_pitch = x.second.second;
+        } else {
+          b.host = x.second.first;
+          b.host_pitch = x.second.second;
+          b.dev_pitch = (b.row + 63) / 64 * 64;
+          b.bytes = b.dev_pitch * b.h;
+        }
+      }
+    if (!found) {
+      delete r;
+      return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "an image of the template is not bound");
+    }
+    r->io.push_back(b);
+  }
+  size_t need = 0;
+  for (const Binding& b : r->io) need += (b.bytes + 255) & ~(size_t)255;
+  if (!batchable(g)) r->scratch_bytes = g->scratch_total;
+  need += (r->scratch_bytes + 255) & ~(size_t)255;
+  if (need > sv->budget) {
+    delete r;
+    return set_error(sv->ctx, HVX_ERROR_NO_MEMORY, "request needs more than the whole HBM budget");
+  }
+  // the server's device pointers are set at admission
+  if (!device)
+    for (Binding& b : r->io) b.dev = nullptr;
+  {
+    std::lock_guard<std::mutex> l(sv->mu);
+    r->fail = sv->fail_tags.count(tag) > 0;
+    r->t_submit = now_s();
+    sv->queue.push_back(r);
+    ++sv->submitted;
+  }
+  sv->cv.notify_all();
+  return HVX_SUCCESS;
 }
 
 }  // namespace hvx
@@ -402,44 +506,41 @@ hvx_status hvx_server_submit(hvx_server hs, hvx_graph templ, const void* in, siz
     hvx_status s = verify_graph(g);
     if (s) return s;
   }
-  if (!batchable(g))
-    return set_error(sv->ctx, HVX_ERROR_NOT_SUPPORTED, "template must be a single fused kernel of a served kind");
-  if (g->plan->groups[0].inputs.size() != 1 || g->plan->groups[0].outputs.size() != 1)
-    return set_error(sv->ctx, HVX_ERROR_NOT_SUPPORTED, "template must have one input and one output image");
   if (!in || !out) return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "null host buffer");
-  const Group& gr = g->plan->groups[0];
-  Request* r = new Request();
-  r->tag = tag;
-  r->templ = g;
-  r->in = in;
-  r->in_pitch = in_pitch;
-  r->out = out;
-  r->out_pitch = out_pitch;
-  r->vin = &g->plan->vals[gr.v_in];
-  r->vout = &g->plan->vals[gr.v_out];
-  r->in_row = (size_t)r->vin->w * df_bytes(r->vin->df);
-  r->out_row = (size_t)r->vout->w * df_bytes(r->vout->df);
-  if (in_pitch < r->in_row || out_pitch < r->out_row) {
-    delete r;
-    return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "host pitch smaller than a row");
+  // the template's one input and one output image
+  Image *iim = nullptr, *oim = nullptr;
+  int nin = 0, nout = 0;
+  for (const Value& val : g->plan->vals) {
+    if (val.is_virtual || !val.live) continue;
+    if (val.producer < 0) {
+      iim = val.img;
+      ++nin;
+    } else {
+      oim = val.img;
+      ++nout;
+    }
   }
-  r->d_in_pitch = (r->in_row + 63) / 64 * 64;
-  r->d_out_pitch = (r->out_row + 63) / 64 * 64;
-  r->in_bytes = r->d_in_pitch * r->vin->h;
-  r->out_bytes = r->d_out_pitch * r->vout->h;
-  if (r->in_bytes + r->out_bytes + 512 > sv->budget) {
-    delete r;
-    return set_error(sv->ctx, HVX_ERROR_NO_MEMORY, "request needs more than the whole HBM budget");
+  if (nin != 1 || nout != 1)
+    return set_error(sv->ctx, HVX_ERROR_NOT_SUPPORTED,
+                     "this call serves templates with one input and one output image (see hvx_server_submit_bound)");
+  return submit_request(sv, g, {{iim, {(void*)in, in_pitch}}, {oim, {out, out_pitch}}}, false, tag);
+}
+
+hvx_status hvx_server_submit_bound(hvx_server hs, hvx_graph templ, const hvx_binding* bindings, uint32_t n,
+                                   int memory, uint64_t tag) {
+  if (!registry_check(hs, T_SERVER)) return HVX_ERROR_INVALID_REFERENCE;
+  Server* sv = (Server*)hs;
+  if (!registry_check(templ, T_GRAPH)) return set_error(sv->ctx, HVX_ERROR_INVALID_REFERENCE, "invalid template");
+  if (memory != HVX_MEMORY_HOST && memory != HVX_MEMORY_DEVICE)
+    return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown memory kind %d", memory);
+  if (n && !bindings) return set_error(sv->ctx, HVX_ERROR_INVALID_PARAMETERS, "null bindings");
+  std::vector<std::pair<Image*, std::pair<void*, size_t>>> bind;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!registry_check(bindings[i].image, T_IMAGE))
+      return set_error(sv->ctx, HVX_ERROR_INVALID_REFERENCE, "binding %u: invalid image", i);
+    bind.push_back({(Image*)bindings[i].image, {bindings[i].ptr, bindings[i].pitch}});
   }
-  {
-    std::lock_guard<std::mutex> l(sv->mu);
-    r->fail = sv->fail_tags.count(tag) > 0;
-    r->t_submit = now_s();
-    sv->queue.push_back(r);
-    ++sv->submitted;
-  }
-  sv->cv.notify_all();
-  return HVX_SUCCESS;
+  return submit_request(sv, (Graph*)templ, bind, memory == HVX_MEMORY_DEVICE, tag);
 }
 
 hvx_status hvx_server_poll(hvx_server hs, uint64_t* tags, int32_t* statuses, double* latency, uint32_t max,

@@ -351,20 +351,119 @@ def test_server_limits(ctx):
 
 
 def test_server_rejects_unservable_templates(ctx):
-    """Only single-kernel templates with one input and one output image are
-    served: an edge graph with its Phase output, or a graph that needs the
-    generic kernels, is refused at submission."""
+    """The one-image call refuses a template with two outputs (the edge
+    graph with its Phase output: hvx_server_submit_bound serves it), and no
+    call serves a template whose results are global-operator buffers."""
     import torch
     w, h = 256, 64
     img = synth.edge_image(w, h, seed=2)
     s = hvx.hvx_server_create(ctx, hvx.HVX_SERVER_CONTINUOUS, 64 << 20, 4, 2)
     src = torch.zeros((h, w), dtype=torch.uint8).pin_memory()
     dst = torch.zeros((h, w), dtype=torch.uint8).pin_memory()
-    for spec in (gs.edge_spec(img, phase=True),
-                 gs.Spec([gs.N("box3x3", ["in"], ["out"])], {"in": img}, {"out": np.uint8})):
-        g, outs, keep, imgs = _build(ctx, spec)
-        with pytest.raises(hvx.HvxError) as e:
-            hvx.hvx_server_submit(s, g, src.data_ptr(), w, dst.data_ptr(), w, 7, ctx=ctx)
-        assert e.value.status == hvx.HVX_ERROR_NOT_SUPPORTED
-        hvx.hvx_release_graph(g)
+    g, outs, keep, imgs = _build(ctx, gs.edge_spec(img, phase=True))
+    with pytest.raises(hvx.HvxError) as e:
+        hvx.hvx_server_submit(s, g, src.data_ptr(), w, dst.data_ptr(), w, 7, ctx=ctx)
+    assert e.value.status == hvx.HVX_ERROR_NOT_SUPPORTED
+    # an image left unbound, or bound twice
+    with pytest.raises(hvx.HvxError) as e:
+        hvx.hvx_server_submit_bound(s, g, [(imgs["in"], src.data_ptr(), w)], hvx.HVX_MEMORY_HOST, 8, ctx=ctx)
+    assert e.value.status == hvx.HVX_ERROR_INVALID_PARAMETERS
+    with pytest.raises(hvx.HvxError) as e:
+        hvx.hvx_server_submit_bound(s, g, [(imgs["in"], src.data_ptr(), w)] * 2 + [
+            (imgs["out"], dst.data_ptr(), w), (imgs["ph"], dst.data_ptr(), w)], hvx.HVX_MEMORY_HOST, 9, ctx=ctx)
+    assert e.value.status == hvx.HVX_ERROR_INVALID_PARAMETERS
+    hvx.hvx_release_graph(g)
+    buf = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    spec = gs.Spec([gs.N("gaussian3x3", ["in"], ["out"]), gs.N("histogram", ["out"], ["hist"], params={"bins": 16})],
+                   {"in": img}, {"out": np.uint8}, buffers={"hist": 1024})
+    im, t = device_image(ctx, img, hvx.HVX_DF_U8)
+    om, t2 = device_image(ctx, np.zeros((h, w), np.uint8), hvx.HVX_DF_U8)
+    gh, _, _ = gs.build_hvx(spec, ctx, {"in": im, "out": om, "hist": hvx.hvx_buffer_from_ptr(ctx, buf.data_ptr(), 1024)})
+    with pytest.raises(hvx.HvxError) as e:
+        hvx.hvx_server_submit(s, gh, src.data_ptr(), w, dst.data_ptr(), w, 10, ctx=ctx)
+    assert e.value.status == hvx.HVX_ERROR_NOT_SUPPORTED
+    hvx.hvx_release_graph(gh)
     hvx.hvx_release_server(s)
+
+
+def _bound_specs(w, h, seed):
+    """Templates served through bindings: a two-output strip kernel, a fused
+    generic kernel, and two plans of two kernels each (EqualizeHist before
+    and after a Gaussian; the second keeps the Gaussian in a scratch block of
+    the request's own)."""
+    img = synth.edge_image(w, h, seed=seed)
+    return {
+        "edge_phase": gs.edge_spec(img, phase=True),
+        "generic": gs.Spec([gs.N("box3x3", ["in"], ["b"]), gs.N("add", ["in", "b"], ["out"], params={"policy": "wrap"})],
+                           {"in": img}, {"out": np.uint8}),
+        "eqhist_gauss": gs.Spec([gs.N("equalize_hist", ["in"], ["e"]), gs.N("gaussian3x3", ["e"], ["out"])],
+                                {"in": img}, {"out": np.uint8}),
+        "gauss_eqhist": gs.Spec([gs.N("gaussian3x3", ["in"], ["g"]), gs.N("equalize_hist", ["g"], ["out"])],
+                                {"in": img}, {"out": np.uint8}),
+    }
+
+
+@pytest.mark.parametrize("mode", [hvx.HVX_SERVER_CONTINUOUS, hvx.HVX_SERVER_PLAIN])
+def test_server_bound_requests_device_and_host(ctx, mode):
+    """Requests bound to device-resident frames (run in place) and to host
+    frames (copied), over templates with two outputs, generic kernels and
+    plans with intermediates in per-request scratch, interleaved under a
+    budget that binds: every output equals the oracle's for its own input."""
+    import torch
+    sizes = [(64, 48), (640, 480)]
+    templ = {}
+    for (w, h) in sizes:
+        for kind, spec in _bound_specs(w, h, seed=1).items():
+            g, outs, keep, imgs = _build(ctx, spec)
+            templ[(kind, w, h)] = (g, imgs, keep, outs)
+    budget = 4 << 20
+    s = hvx.hvx_server_create(ctx, mode, budget, 6, 2)
+    reqs = {}
+    rng = np.random.default_rng(11)
+    for tag in range(32):
+        kind = ("edge_phase", "generic", "eqhist_gauss", "gauss_eqhist")[tag % 4]
+        w, h = sizes[int(rng.integers(0, len(sizes)))]
+        device = bool(rng.integers(0, 2))
+        spec = _bound_specs(w, h, seed=200 + tag)[kind]
+        g, imgs, _, _ = templ[(kind, w, h)]
+        bind, held = [], {}
+        for name, arr in spec.inputs.items():
+            if device:
+                buf, view = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+                view.copy_(torch.from_numpy(arr))
+                held[name] = view
+                bind.append((imgs[name], view.data_ptr(), view.stride(0)))
+            else:
+                t = torch.from_numpy(np.ascontiguousarray(arr)).pin_memory()
+                held[name] = t
+                bind.append((imgs[name], t.data_ptr(), t.stride(0)))
+        for name in spec.outputs:
+            if device:
+                buf, view = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+                view.fill_(7)
+                held[name] = view
+                bind.append((imgs[name], view.data_ptr(), view.stride(0)))
+            else:
+                t = torch.full((h, w), 7, dtype=torch.uint8).pin_memory()
+                held[name] = t
+                bind.append((imgs[name], t.data_ptr(), t.stride(0)))
+        torch.cuda.synchronize()
+        reqs[tag] = (kind, spec, held)
+        log("submit %d %s %dx%d %s" % (tag, kind, w, h, "device" if device else "host"))
+        hvx.hvx_server_submit_bound(s, g, bind, hvx.HVX_MEMORY_DEVICE if device else hvx.HVX_MEMORY_HOST, tag, ctx=ctx)
+        if tag % 6 == 0:
+            time.sleep(0.002)
+    hvx.hvx_server_drain(s, ctx=ctx)
+    done = hvx.hvx_server_poll(s, 1000, ctx=ctx)
+    assert sorted(t for t, _, _ in done) == list(range(32))
+    assert hvx.hvx_server_stats(s, 2) <= budget
+    assert hvx.hvx_server_stats(s, 5) == 0
+    for tag, st, lat in done:
+        kind, spec, held = reqs[tag]
+        assert st == 0 and lat > 0, (tag, st)
+        env = spec.run_oracle()
+        got = {name: held[name].cpu().numpy() for name in spec.outputs}
+        compare(spec, got, env, phase_names=("ph",))
+    hvx.hvx_release_server(s)
+    for (g, imgs, keep, outs) in templ.values():
+        hvx.hvx_release_graph(g)
