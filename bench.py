@@ -64,10 +64,13 @@ def make_frames(hvx, torch, w, h, n, n_out=1, seed0=0):
     return inp, out
 
 
-def edge_graph(hvx, ctx, inp_view, outs, phase=False, fusion=True, border=None):
+def edge_graph(hvx, ctx, inp_view, outs, phase=False, fusion=True, border=None, handles=None):
     g = hvx.hvx_graph_create(ctx)
-    a = hvx.image_from_tensor(ctx, inp_view, hvx.HVX_DF_U8)
-    o = hvx.image_from_tensor(ctx, outs[0][1], hvx.HVX_DF_U8)
+    if handles:  # (input image, output image) handles made by the caller
+        a, o = handles
+    else:
+        a = hvx.image_from_tensor(ctx, inp_view, hvx.HVX_DF_U8)
+        o = hvx.image_from_tensor(ctx, outs[0][1], hvx.HVX_DF_U8)
     v = [hvx.hvx_image_create_virtual(g) for _ in range(4)]
     nodes = [hvx.hvx_gaussian3x3_node(g, a, v[0]), hvx.hvx_sobel3x3_node(g, v[0], v[1], v[2])]
     hvx.hvx_magnitude_node(g, v[1], v[2], v[3])
@@ -82,10 +85,13 @@ def edge_graph(hvx, ctx, inp_view, outs, phase=False, fusion=True, border=None):
     return g
 
 
-def corner_graph(hvx, ctx, inp_view, outs):
+def corner_graph(hvx, ctx, inp_view, outs, handles=None):
     g = hvx.hvx_graph_create(ctx)
-    a = hvx.image_from_tensor(ctx, inp_view, hvx.HVX_DF_U8)
-    o = hvx.image_from_tensor(ctx, outs[0][1], hvx.HVX_DF_U8)
+    if handles:
+        a, o = handles
+    else:
+        a = hvx.image_from_tensor(ctx, inp_view, hvx.HVX_DF_U8)
+        o = hvx.image_from_tensor(ctx, outs[0][1], hvx.HVX_DF_U8)
     v = [hvx.hvx_image_create_virtual(g) for _ in range(9)]
     hvx.hvx_sobel3x3_node(g, a, v[0], v[1])
     hvx.hvx_multiply_f32_node(g, v[0], v[0], v[2])
@@ -100,16 +106,19 @@ def corner_graph(hvx, ctx, inp_view, outs):
     return g
 
 
-def gauss5_graph(hvx, ctx, inp_view, outs, uyvy=False, w=None):
+def gauss5_graph(hvx, ctx, inp_view, outs, uyvy=False, w=None, handles=None):
     g = hvx.hvx_graph_create(ctx)
-    o = hvx.image_from_tensor(ctx, outs[0][1], hvx.HVX_DF_U8)
+    if handles:
+        a, o = handles
+    else:
+        o = hvx.image_from_tensor(ctx, outs[0][1], hvx.HVX_DF_U8)
+        a = hvx.image_from_tensor(ctx, inp_view, hvx.HVX_DF_UYVY if uyvy else hvx.HVX_DF_U8, w=w)
     if uyvy:
-        a = hvx.image_from_tensor(ctx, inp_view, hvx.HVX_DF_UYVY, w=w)
         y = hvx.hvx_image_create_virtual(g)
         hvx.hvx_channel_extract_node(g, a, hvx.HVX_CHANNEL_Y, y)
         hvx.hvx_gaussian5x5_node(g, y, o)
     else:
-        hvx.hvx_gaussian5x5_node(g, hvx.image_from_tensor(ctx, inp_view, hvx.HVX_DF_U8), o)
+        hvx.hvx_gaussian5x5_node(g, a, o)
     hvx.hvx_graph_verify(g, ctx=ctx)
     return g
 
@@ -342,6 +351,10 @@ def ex_mixed(hvx, torch, ctx, rec, rows=None):
     torch.cuda.empty_cache()
 
 
+def res_set(rec, name, d):
+    rec(name, d)
+
+
 # named context measurements (`--only NAME` runs one of them without the headline)
 EXTRAS = {
     "edge_4k_batch64": ex_edge_4k_batch64,
@@ -356,7 +369,7 @@ EXTRAS = {
     "global_ops_16k": lambda hvx, torch, ctx, rec: global_ops(hvx, torch, ctx, torch.cuda.current_stream().cuda_stream,
                                                               rec),
     "global_graph_4k": lambda hvx, torch, ctx, rec: global_graph(hvx, torch, ctx, rec),
-    "serving": lambda hvx, torch, ctx, rec: rec("serving", serving(hvx, torch, ctx)),
+    "serving": lambda hvx, torch, ctx, rec: res_set(rec, "serving", serving(hvx, torch, ctx)),
 }
 
 
@@ -453,47 +466,69 @@ def global_graph(hvx, torch, ctx, rec):
 
 def serving(hvx, torch, ctx, n_req=240, budget=512 << 20):
     """Poisson request stream over {edge, corner, UYVY->Y+Gaussian5x5} x
-    {640x480, 1280x720, 1920x1080, 3840x2160}; host frames in pinned memory;
-    the server copies each request in, runs it, copies it out."""
+    {640x480, 1280x720, 1920x1080, 3840x2160}, served two ways: frames
+    resident in HBM (requests bound to device buffers and run in place) and
+    host frames in pinned memory (copied in and out by the server).  For
+    each: the plain loop's and the continuous loop's burst capacity, then
+    arrival rates set from the plain capacity (0.5, 0.8, 0.95 and 1.2 of it),
+    served continuously and plainly."""
     import synth
-    templ, host_in = {}, {}
+    templ, host_in, dev_in, dev_out, timg = {}, {}, {}, {}, {}
     keep = []
     for kind in synth.SERVE_TYPES:
         for (w, h) in synth.SERVE_SIZES:
+            df = hvx.HVX_DF_UYVY if kind == "uyvy_gauss5" else hvx.HVX_DF_U8
+            ib, iv = hvx.alloc_image(h, w, df)
+            ob, ov = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+            ih = hvx.image_from_tensor(ctx, iv, df, w=w)
+            oh = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
             if kind == "uyvy_gauss5":
-                ib, iv = hvx.alloc_image(h, w, hvx.HVX_DF_UYVY)
-                ob = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
-                g = gauss5_graph(hvx, ctx, iv, [ob], uyvy=True, w=w)
+                g = gauss5_graph(hvx, ctx, None, None, uyvy=True, w=w, handles=(ih, oh))
                 frame = synth.uyvy_image(w, h, seed=w)
             else:
-                ib, iv = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
-                ob = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
-                g = edge_graph(hvx, ctx, iv, [ob]) if kind == "sobel_edge" else corner_graph(hvx, ctx, iv, [ob])
+                g = (edge_graph if kind == "sobel_edge" else corner_graph)(hvx, ctx, None, None, handles=(ih, oh))
                 frame = synth.edge_image(w, h, seed=w)
             keep += [ib, ob]
-            templ[(kind, w, h)] = g
-            t = torch.from_numpy(frame).pin_memory()
-            host_in[(kind, w, h)] = t
+            key = (kind, w, h)
+            templ[key] = g
+            timg[key] = (ih, oh)
+            host_in[key] = torch.from_numpy(frame).pin_memory()
+            # resident frames: 4 inputs and 8 outputs per template in HBM
+            dev_in[key] = []
+            for j in range(4):
+                db, dv = hvx.alloc_image(h, w, df)
+                dv.copy_(torch.from_numpy(frame) ^ j)
+                keep.append(db)
+                dev_in[key].append(dv)
+            dev_out[key] = []
+            for j in range(8):
+                db, dv = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+                keep.append(db)
+                dev_out[key].append(dv)
     outs = {}
-    for (kind, w, h) in templ:
-        outs[(kind, w, h)] = [torch.empty((h, w), dtype=torch.uint8).pin_memory() for _ in range(8)]
+    for key in templ:
+        outs[key] = [torch.empty((key[2], key[1]), dtype=torch.uint8).pin_memory() for _ in range(8)]
+    torch.cuda.synchronize()
 
-    def run(mode, trace, n_streams=2):
+    def run(mode, trace, device, n_streams=2):
         s = hvx.hvx_server_create(ctx, mode, budget, 16, n_streams)
         t0 = time.perf_counter()
         lat = []
         px = 0
-        i = 0
-        for (ta, kind, w, h, seed) in trace:
+        for i, (ta, kind, w, h, seed) in enumerate(trace):
             while time.perf_counter() - t0 < ta:
                 for (tag, st, l) in hvx.hvx_server_poll(s):
                     lat.append(l)
             key = (kind, w, h)
-            src = host_in[key]
-            dst = outs[key][i % 8]
-            hvx.hvx_server_submit(s, templ[key], src.data_ptr(), src.stride(0), dst.data_ptr(), dst.stride(0), i)
+            if device:
+                src, dst = dev_in[key][i % 4], dev_out[key][i % 8]
+                hvx.hvx_server_submit_bound(s, templ[key], [
+                    (timg[key][0], src.data_ptr(), src.stride(0) * src.element_size()),
+                    (timg[key][1], dst.data_ptr(), dst.stride(0))], hvx.HVX_MEMORY_DEVICE, i)
+            else:
+                src, dst = host_in[key], outs[key][i % 8]
+                hvx.hvx_server_submit(s, templ[key], src.data_ptr(), src.stride(0), dst.data_ptr(), dst.stride(0), i)
             px += w * h
-            i += 1
         hvx.hvx_server_drain(s)
         t1 = time.perf_counter()
         for (tag, st, l) in hvx.hvx_server_poll(s, 4096):
@@ -506,21 +541,28 @@ def serving(hvx, torch, ctx, n_req=240, budget=512 << 20):
                 "mean_ms": round(float(lat.mean()), 3), "mpix_s": round(px / 1e6 / (t1 - t0), 1),
                 "requests": len(lat), "device_steps": steps, "peak_device_bytes": peak}
 
-    # plain capacity: back-to-back requests, one at a time
-    burst = [(0.0, k, w, h, s) for (_, k, w, h, s) in synth.serving_trace(1.0, n_req, seed=1)]
-    cap = run(hvx.HVX_SERVER_PLAIN, burst)
-    res = {"plain_burst": cap, "budget_bytes": budget, "max_slots": 16, "streams": 2}
-    # arrival rates are set relative to the plain loop's measured throughput
-    plain_px_s = cap["mpix_s"] * 1e6
+    res = {"budget_bytes": budget, "max_slots": 16, "streams": 2, "requests_per_run": n_req}
+    burst = [(0.0, k, w, h, sd) for (_, k, w, h, sd) in synth.serving_trace(1.0, n_req, seed=1)]
     mean_px = np.mean([w * h for (_, _, w, h, _) in burst])
-    rate_cap = plain_px_s / mean_px
-    for frac in (0.5, 0.8, 0.95):
-        trace = synth.serving_trace(frac * rate_cap, n_req, seed=2)
-        res["rate_%.2f" % frac] = {"rate_rps": round(frac * rate_cap, 1),
-                                   "continuous": run(hvx.HVX_SERVER_CONTINUOUS, trace),
-                                   "plain": run(hvx.HVX_SERVER_PLAIN, trace)}
+    for device in (True, False):
+        name = "device_resident" if device else "host_copy"
+        # burst capacity: every request queued at once
+        cap = run(hvx.HVX_SERVER_PLAIN, burst, device)
+        ccap = run(hvx.HVX_SERVER_CONTINUOUS, burst, device)
+        d = {"plain_burst": cap, "continuous_burst": ccap}
+        rate_cap = cap["mpix_s"] * 1e6 / mean_px  # plain capacity in requests per second
+        for frac in (0.5, 0.8, 0.95, 1.2):
+            trace = synth.serving_trace(frac * rate_cap, n_req, seed=2)
+            d["rate_%.2f" % frac] = {"rate_rps": round(frac * rate_cap, 1),
+                                     "continuous": run(hvx.HVX_SERVER_CONTINUOUS, trace, device),
+                                     "plain": run(hvx.HVX_SERVER_PLAIN, trace, device)}
+        res[name] = d
+        log("serving", name, json.dumps(d))
     for g in templ.values():
         hvx.hvx_release_graph(g)
+    for (ih, oh) in timg.values():
+        hvx.hvx_release_image(ih)
+        hvx.hvx_release_image(oh)
     return res
 
 
