@@ -369,6 +369,7 @@ EXTRAS = {
     "global_ops_16k": lambda hvx, torch, ctx, rec: global_ops(hvx, torch, ctx, torch.cuda.current_stream().cuda_stream,
                                                               rec),
     "global_graph_4k": lambda hvx, torch, ctx, rec: global_graph(hvx, torch, ctx, rec),
+    "user_kernels_4k": lambda hvx, torch, ctx, rec: user_kernels(hvx, torch, ctx, rec),
     "serving": lambda hvx, torch, ctx, rec: res_set(rec, "serving", serving(hvx, torch, ctx)),
 }
 
@@ -462,6 +463,77 @@ def global_graph(hvx, torch, ctx, rec):
     hvx.hvx_release_image(img)
     hvx.hvx_release_buffer(res)
     del ib, iv, buf
+
+
+def user_kernels(hvx, torch, ctx, rec):
+    """The paper's applications built on user kernels (Section 6.1) on one
+    3840x2160 frame, U8 in and U8 out (2 B/px), fused (one tile-interpreter
+    kernel) and node by node: Unsharp (Gaussian3x3 and three user point
+    kernels), Tomasi (the corner graph with a user min-eigenvalue response),
+    FChain (three Convolve nodes)."""
+    import synth
+    stream = torch.cuda.current_stream().cuda_stream
+    w, h = 3840, 2160
+    ib, iv = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+    ob, ov = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+    iv.copy_(torch.from_numpy(synth.corner_image(w, h, seed=0)))
+    a = hvx.image_from_tensor(ctx, iv, hvx.HVX_DF_U8)
+    o = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
+    S16, F32, U8 = hvx.HVX_DF_S16, hvx.HVX_DF_F32, hvx.HVX_DF_U8
+
+    def unsharp(g):
+        v = [hvx.hvx_image_create_virtual(g) for _ in range(3)]
+        hvx.hvx_gaussian3x3_node(g, a, v[0])
+        hvx.hvx_custom_point_node(g, "a - b", [a, v[0]], S16, v[1])
+        hvx.hvx_custom_point_node(g, "a * 3 / 2", [v[1]], S16, v[2])
+        hvx.hvx_custom_point_node(g, "a + b", [a, v[2]], U8, o)
+
+    def tomasi(g):
+        v = [hvx.hvx_image_create_virtual(g) for _ in range(9)]
+        hvx.hvx_sobel3x3_node(g, a, v[0], v[1])
+        hvx.hvx_multiply_f32_node(g, v[0], v[0], v[2])
+        hvx.hvx_multiply_f32_node(g, v[1], v[1], v[3])
+        hvx.hvx_multiply_f32_node(g, v[0], v[1], v[4])
+        for k in range(3):
+            hvx.hvx_box5x5_f32_node(g, v[2 + k], v[5 + k])
+        hvx.hvx_custom_point_node(g, "(a + b) / 2 - sqrt((a - b) * (a - b) / 4 + c * c)", [v[5], v[6], v[7]], F32,
+                                  v[8])
+        hvx.hvx_threshold_node(g, v[8], 2e5, 255, 0, o)
+
+    masks = [(np.outer([1, 4, 6, 4, 1], [1, 4, 6, 4, 1]), 256), (np.array([[0, -1, 0], [-1, 5, -1], [0, -1, 0]]), 1),
+             (np.ones((5, 5), int), 32)]
+    convs = [hvx.hvx_convolution_create(ctx, m, sc) for (m, sc) in masks]
+
+    def fchain(g):
+        v = [hvx.hvx_image_create_virtual(g, 0, 0, U8) for _ in range(2)]
+        hvx.hvx_convolve_node(g, a, convs[0], v[0])
+        hvx.hvx_convolve_node(g, v[0], convs[1], v[1])
+        hvx.hvx_convolve_node(g, v[1], convs[2], o)
+
+    d = {"image": "3840x2160 U8 (corner workload)", "alg_bytes_per_frame": 2 * w * h}
+    for name, build in (("unsharp", unsharp), ("tomasi", tomasi), ("fchain", fchain)):
+        row = {}
+        for fusion in (1, 0):
+            g = hvx.hvx_graph_create(ctx)
+            build(g)
+            hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, fusion)
+            hvx.hvx_graph_verify(g, ctx=ctx)
+            ms, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(g, stream, ctx=ctx), 20, 3)
+            row["fused" if fusion else "node_by_node"] = {
+                "us": round(ms * 1e3, 2), "mpix_s": round(w * h / 1e6 / (ms / 1e3), 1),
+                "kernels": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS),
+                "alg_gbs": round(2 * w * h / (ms / 1e3) / 1e9, 1),
+                "hbm_frac": round(2 * w * h / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "plan_hbm_bytes": hvx.hvx_graph_query(g, hvx.HVX_QUERY_HBM_BYTES)}
+            hvx.hvx_release_graph(g)
+        row["fused_speedup"] = round(row["node_by_node"]["us"] / row["fused"]["us"], 2)
+        d[name] = row
+    rec("user_kernels_4k", d)
+    for c in convs:
+        hvx.hvx_release_convolution(c)
+    hvx.hvx_release_image(a)
+    hvx.hvx_release_image(o)
+    del ib, iv, ob, ov
 
 
 def serving(hvx, torch, ctx, n_req=240, budget=512 << 20):

@@ -120,70 +120,82 @@ __device__ __forceinline__ const uint8_t* lut_table(const GProg& P, const IOTabl
 
 // A user kernel (Section 5.1) at one pixel: its postfix program.  in(op,
 // arg) returns an input element (int bits; F32 inputs as bit patterns, marked
-// in o.p2): for X_IN input `arg`, for X_INW input a at a window offset.  Integer kernels compute in 32-bit two's complement: + - * and
-// negation wrap, / truncates toward zero, x / 0 = 0 and INT_MIN / -1 wraps
-// to INT_MIN; the result saturates to the output type.  Float kernels
-// (o.p1) compute in F32 and return F32 bits.  Every lane runs the same
-// program, so the stack position is uniform across the wave.
+// in o.p2): for X_IN input `arg`, for X_INW input a at a window offset.
+// Integer kernels compute in 32-bit two's complement: + - * and negation
+// wrap, / truncates toward zero, x / 0 = 0 and INT_MIN / -1 wraps to INT_MIN;
+// the result saturates to the output type.  Float kernels (o.p1) compute in
+// F32 and return F32 bits.
+//
+// Every lane runs the same program, so the stack position is the same in
+// the whole wave.  The stack lives in LDS, one column per thread (entry k of
+// thread t at [k][t]: the lanes of a wave touch consecutive words, no bank
+// conflicts): a per-lane array indexed by the run-time position would be
+// placed in scratch memory.  The kernels that run user kernels use
+// kExprThreads-thread groups.
+constexpr int kExprThreads = 256;
+// one stack per work-group, shared by every place a kernel runs user kernels
+__shared__ int32_t g_expr_stack[kExprStack][kExprThreads];
+
 template <class IN>
 __device__ __forceinline__ int expr_run(const GOp& o, int out_df, const IN& in) {
+  int32_t* st = &g_expr_stack[0][threadIdx.x];
+  auto at = [&](int k) -> int32_t& { return st[k * kExprThreads]; };
   const int n = o.p0;
+  int sp = 0;
   if (o.p1) {
-    float st[kExprStack];
-    int sp = 0;
+    auto f = [&](int k) { return __int_as_float(at(k)); };
+    auto setf = [&](int k, float v) { at(k) = __float_as_int(v); };
     for (int k = 0; k < n; ++k) {
       const int op = o.code[k] & 0xFF, arg = o.code[k] >> 8;
       switch (op) {
         case X_IN:
         case X_INW: {
           const int v = in(op, arg);
-          st[sp++] = ((o.p2 >> (op == X_IN ? arg : 0)) & 1) ? __int_as_float(v) : (float)v;
+          setf(sp++, ((o.p2 >> (op == X_IN ? arg : 0)) & 1) ? __int_as_float(v) : (float)v);
           break;
         }
-        case X_CONST: st[sp++] = __int_as_float(o.kc[arg]); break;
-        case X_ADD: --sp; st[sp - 1] = st[sp - 1] + st[sp]; break;
-        case X_SUB: --sp; st[sp - 1] = st[sp - 1] - st[sp]; break;
-        case X_MUL: --sp; st[sp - 1] = st[sp - 1] * st[sp]; break;
-        case X_DIV: --sp; st[sp - 1] = st[sp - 1] / st[sp]; break;
-        case X_NEG: st[sp - 1] = -st[sp - 1]; break;
-        case X_MIN: --sp; st[sp - 1] = fminf(st[sp - 1], st[sp]); break;
-        case X_MAX: --sp; st[sp - 1] = fmaxf(st[sp - 1], st[sp]); break;
-        case X_ABS: st[sp - 1] = fabsf(st[sp - 1]); break;
-        case X_CLAMP: sp -= 2; st[sp - 1] = fminf(fmaxf(st[sp - 1], st[sp]), st[sp + 1]); break;
-        case X_GT: --sp; st[sp - 1] = st[sp - 1] > st[sp] ? 1.f : 0.f; break;
-        case X_SEL: sp -= 2; st[sp - 1] = st[sp - 1] != 0.f ? st[sp] : st[sp + 1]; break;
-        case X_SQRT: st[sp - 1] = __builtin_sqrtf(st[sp - 1]); break;
+        case X_CONST: at(sp++) = o.kc[arg]; break;
+        case X_ADD: --sp; setf(sp - 1, f(sp - 1) + f(sp)); break;
+        case X_SUB: --sp; setf(sp - 1, f(sp - 1) - f(sp)); break;
+        case X_MUL: --sp; setf(sp - 1, f(sp - 1) * f(sp)); break;
+        case X_DIV: --sp; setf(sp - 1, f(sp - 1) / f(sp)); break;
+        case X_NEG: setf(sp - 1, -f(sp - 1)); break;
+        case X_MIN: --sp; setf(sp - 1, fminf(f(sp - 1), f(sp))); break;
+        case X_MAX: --sp; setf(sp - 1, fmaxf(f(sp - 1), f(sp))); break;
+        case X_ABS: setf(sp - 1, fabsf(f(sp - 1))); break;
+        case X_CLAMP: sp -= 2; setf(sp - 1, fminf(fmaxf(f(sp - 1), f(sp)), f(sp + 1))); break;
+        case X_GT: --sp; setf(sp - 1, f(sp - 1) > f(sp) ? 1.f : 0.f); break;
+        case X_SEL: sp -= 2; setf(sp - 1, f(sp - 1) != 0.f ? f(sp) : f(sp + 1)); break;
+        case X_SQRT: setf(sp - 1, __builtin_sqrtf(f(sp - 1))); break;
       }
     }
-    return __float_as_int(st[0]);
+    return at(0);
   }
-  int st[kExprStack];
-  int sp = 0;
   for (int k = 0; k < n; ++k) {
     const int op = o.code[k] & 0xFF, arg = o.code[k] >> 8;
     switch (op) {
       case X_IN:
-      case X_INW: st[sp++] = in(op, arg); break;
-      case X_CONST: st[sp++] = o.kc[arg]; break;
-      case X_ADD: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] + (uint32_t)st[sp]); break;
-      case X_SUB: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] - (uint32_t)st[sp]); break;
-      case X_MUL: --sp; st[sp - 1] = (int)((uint32_t)st[sp - 1] * (uint32_t)st[sp]); break;
+      case X_INW: at(sp++) = in(op, arg); break;
+      case X_CONST: at(sp++) = o.kc[arg]; break;
+      case X_ADD: --sp; at(sp - 1) = (int)((uint32_t)at(sp - 1) + (uint32_t)at(sp)); break;
+      case X_SUB: --sp; at(sp - 1) = (int)((uint32_t)at(sp - 1) - (uint32_t)at(sp)); break;
+      case X_MUL: --sp; at(sp - 1) = (int)((uint32_t)at(sp - 1) * (uint32_t)at(sp)); break;
       case X_DIV: {
         --sp;
-        const int x = st[sp - 1], y = st[sp];
-        st[sp - 1] = y == 0 ? 0 : (y == -1 ? (int)(0u - (uint32_t)x) : x / y);
+        const int x = at(sp - 1), y = at(sp);
+        at(sp - 1) = y == 0 ? 0 : (y == -1 ? (int)(0u - (uint32_t)x) : x / y);
         break;
       }
-      case X_NEG: st[sp - 1] = (int)(0u - (uint32_t)st[sp - 1]); break;
-      case X_MIN: --sp; st[sp - 1] = min(st[sp - 1], st[sp]); break;
-      case X_MAX: --sp; st[sp - 1] = max(st[sp - 1], st[sp]); break;
-      case X_ABS: st[sp - 1] = st[sp - 1] < 0 ? (int)(0u - (uint32_t)st[sp - 1]) : st[sp - 1]; break;
-      case X_CLAMP: sp -= 2; st[sp - 1] = min(max(st[sp - 1], st[sp]), st[sp + 1]); break;
-      case X_GT: --sp; st[sp - 1] = st[sp - 1] > st[sp] ? 1 : 0; break;
-      case X_SEL: sp -= 2; st[sp - 1] = st[sp - 1] != 0 ? st[sp] : st[sp + 1]; break;
+      case X_NEG: at(sp - 1) = (int)(0u - (uint32_t)at(sp - 1)); break;
+      case X_MIN: --sp; at(sp - 1) = min(at(sp - 1), at(sp)); break;
+      case X_MAX: --sp; at(sp - 1) = max(at(sp - 1), at(sp)); break;
+      case X_ABS: at(sp - 1) = at(sp - 1) < 0 ? (int)(0u - (uint32_t)at(sp - 1)) : at(sp - 1); break;
+      case X_CLAMP: sp -= 2; at(sp - 1) = min(max(at(sp - 1), at(sp)), at(sp + 1)); break;
+      case X_GT: --sp; at(sp - 1) = at(sp - 1) > at(sp) ? 1 : 0; break;
+      case X_SEL: sp -= 2; at(sp - 1) = at(sp - 1) != 0 ? at(sp) : at(sp + 1); break;
     }
   }
-  const int r = st[0];
+  const int r = at(0);
   return out_df == DF_U8 ? min(max(r, 0), 255) : min(max(r, -32768), 32767);
 }
 
@@ -468,22 +480,32 @@ __device__ __forceinline__ int eval_op(const TileCtx& t, const GOp& o, int x, in
 // group, and the group merges everything into the operator's result once, at
 // the end.  Only the tile's own pixels count (never the halo), so each pixel
 // of the image is counted once.
-struct RedState {
-  int mn[kMaxRed], mx[kMaxRed];
-  uint32_t cmn[kMaxRed], cmx[kMaxRed];
-  unsigned long long s1[kMaxRed], s2[kMaxRed];
-  uint32_t* hist;  // kHistWords words of LDS
+// One global operator's running partial results in a thread.
+struct RedSlot {
+  int mn, mx;
+  uint32_t cmn, cmx;
+  unsigned long long s1, s2;
 };
+
+// kMaxRed slots as separate members, chosen by uniform branches: an array
+// indexed by the run-time slot number would be placed in scratch memory.
+struct RedState {
+  RedSlot a, b;
+  uint32_t* hist;  // kHistWords words of LDS
+  template <class F>
+  __device__ __forceinline__ void with(int k, F&& f) {
+    if (k == 0) f(a);
+    else f(b);
+  }
+};
+static_assert(kMaxRed == 2, "RedState holds two slots");
 
 template <int NT>
 __device__ __forceinline__ void red_begin(RedState& r, uint32_t* hist) {
-#pragma unroll
-  for (int k = 0; k < kMaxRed; ++k) {
-    r.mn[k] = 2147483647;
-    r.mx[k] = -2147483647 - 1;
-    r.cmn[k] = r.cmx[k] = 0;
-    r.s1[k] = r.s2[k] = 0;
-  }
+  r.a.mn = r.b.mn = 2147483647;
+  r.a.mx = r.b.mx = -2147483647 - 1;
+  r.a.cmn = r.a.cmx = r.b.cmn = r.b.cmx = 0;
+  r.a.s1 = r.a.s2 = r.b.s1 = r.b.s2 = 0;
   r.hist = hist;
   for (int b = threadIdx.x; b < kHistWords; b += NT) hist[b] = 0;
   __syncthreads();
@@ -498,18 +520,24 @@ __device__ __forceinline__ void red_add(RedState& r, int k, const GOp& o, int v)
       break;
     }
     case OP_MMCOUNT:
-      r.cmn[k] = v < r.mn[k] ? 1u : r.cmn[k] + (v == r.mn[k] ? 1u : 0u);
-      r.cmx[k] = v > r.mx[k] ? 1u : r.cmx[k] + (v == r.mx[k] ? 1u : 0u);
-      r.mn[k] = min(r.mn[k], v);
-      r.mx[k] = max(r.mx[k], v);
+      r.with(k, [&](RedSlot& q) {
+        q.cmn = v < q.mn ? 1u : q.cmn + (v == q.mn ? 1u : 0u);
+        q.cmx = v > q.mx ? 1u : q.cmx + (v == q.mx ? 1u : 0u);
+        q.mn = min(q.mn, v);
+        q.mx = max(q.mx, v);
+      });
       break;
     case OP_MINMAX:
-      r.mn[k] = min(r.mn[k], v);
-      r.mx[k] = max(r.mx[k], v);
+      r.with(k, [&](RedSlot& q) {
+        q.mn = min(q.mn, v);
+        q.mx = max(q.mx, v);
+      });
       break;
     case OP_SUMS:
-      r.s1[k] += (unsigned)v;
-      r.s2[k] += (unsigned)(v * v);
+      r.with(k, [&](RedSlot& q) {
+        q.s1 += (unsigned)v;
+        q.s2 += (unsigned)(v * v);
+      });
       break;
   }
 }
@@ -518,7 +546,7 @@ __device__ __forceinline__ void red_add(RedState& r, int k, const GOp& o, int v)
 // reduce by lane exchange, the group through LDS, and one thread applies
 // one atomic (or compare-and-swap loop) per result word.
 template <int NT>
-__device__ void red_end(const GProg& P, const IOTable& io, RedState& r) {
+__device__ __forceinline__ void red_end(const GProg& P, const IOTable& io, RedState& r) {
   __shared__ unsigned long long part[4][NT / 64];
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   __syncthreads();  // the LDS histogram is complete
@@ -531,9 +559,11 @@ __device__ void red_end(const GProg& P, const IOTable& io, RedState& r) {
       for (int b = t; b < o.p0; b += NT)
         if (r.hist[b]) atomicAdd((uint32_t*)out + b, r.hist[b]);
     } else {
-      int mn = r.mn[k], mx = r.mx[k];
-      uint32_t cmn = r.cmn[k], cmx = r.cmx[k];
-      unsigned long long s1 = r.s1[k], s2 = r.s2[k];
+      RedSlot q;
+      r.with(k, [&](RedSlot& x) { q = x; });
+      int mn = q.mn, mx = q.mx;
+      uint32_t cmn = q.cmn, cmx = q.cmx;
+      unsigned long long s1 = q.s1, s2 = q.s2;
       if (o.kind == OP_SUMS) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -597,8 +627,10 @@ __device__ void red_end(const GProg& P, const IOTable& io, RedState& r) {
 
 // One tile of a generic program.  `lds` holds P.lds_words words.  RED: the
 // program holds global operators, reduced into `red`.
+// (Inlined into its kernels: as a called function it would receive the I/O
+// table through a copy in scratch memory.)
 template <int NT, bool NL, bool RED>
-__device__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_t* lds, RedState* red) {
+__device__ __forceinline__ void generic_tile(const GProg& P, const IOTable& io, int tile, int32_t* lds, RedState* red) {
   TileCtx t;
   t.P = &P;
   t.io = &io;

@@ -26,6 +26,8 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
 // RED: the program reduces global operators; the groups then loop over the
 // tiles (fewer groups than tiles, so each merges its partial results once)
 // and the LDS after the tiles holds the group's histogram.
+static_assert(kExprThreads == 256, "user kernels run in 256-thread groups");
+
 template <bool NL, bool RED>
 __global__ __launch_bounds__(256) void k_generic(const GProg* __restrict__ P, const IOTable io) {
   extern __shared__ int32_t lds[];
