@@ -423,11 +423,16 @@ def global_ops(hvx, torch, ctx, stream, rec):
     torch.cuda.empty_cache()
 
 
+# plans compared by the graph measurements: (label, HVX_OPT_FUSION, HVX_OPT_CODEGEN)
+PLANS = (("fused", 1, 1), ("fused_interpreted", 1, 0), ("node_by_node", 0, 1))
+
+
 def global_graph(hvx, torch, ctx, rec):
     """Global operators as graph nodes on one 3840x2160 frame: Gaussian3x3 ->
     Histogram and Gaussian5x5 -> MinMaxLoc counts, the producer fused into the
-    reduction (one kernel, 1 B/px read) against the same graphs node by node
-    (the Gaussian written to memory and read back: 3 B/px)."""
+    reduction (one generated kernel, 1 B/px read; and the same group run by
+    the tile interpreter) against the same graphs node by node (the Gaussian
+    written to memory and read back: 3 B/px)."""
     import synth
     stream = torch.cuda.current_stream().cuda_stream
     w, h = 3840, 2160
@@ -440,7 +445,7 @@ def global_graph(hvx, torch, ctx, rec):
     for name, make in (("gauss3_histogram", lambda g, v: hvx.hvx_histogram_node(g, v, 256, 0, 256, res)),
                        ("gauss5_min_max_loc_counts", lambda g, v: hvx.hvx_min_max_loc_node(g, v, res, None, 0))):
         row = {}
-        for fusion in (1, 0):
+        for label, fusion, codegen in PLANS:
             g = hvx.hvx_graph_create(ctx)
             v = hvx.hvx_image_create_virtual(g)
             if name.startswith("gauss3"):
@@ -449,12 +454,14 @@ def global_graph(hvx, torch, ctx, rec):
                 hvx.hvx_gaussian5x5_node(g, img, v)
             make(g, v)
             hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, fusion)
+            hvx.hvx_graph_set_option(g, hvx.HVX_OPT_CODEGEN, codegen)
             hvx.hvx_graph_verify(g, ctx=ctx)
             ms, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(g, stream, ctx=ctx), 20, 3)
             hbm = hvx.hvx_graph_query(g, hvx.HVX_QUERY_HBM_BYTES)
-            row["fused" if fusion else "node_by_node"] = {
+            row[label] = {
                 "us": round(ms * 1e3, 2), "mpix_s": round(w * h / 1e6 / (ms / 1e3), 1),
-                "kernels": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS), "hbm_bytes": hbm,
+                "kernels": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS),
+                "generated": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_GENERATED), "hbm_bytes": hbm,
                 "gbs": round(hbm / (ms / 1e3) / 1e9, 1)}
             hvx.hvx_release_graph(g)
         row["fused_speedup"] = round(row["node_by_node"]["us"] / row["fused"]["us"], 2)
@@ -467,8 +474,9 @@ def global_graph(hvx, torch, ctx, rec):
 
 def user_kernels(hvx, torch, ctx, rec):
     """The paper's applications built on user kernels (Section 6.1) on one
-    3840x2160 frame, U8 in and U8 out (2 B/px), fused (one tile-interpreter
-    kernel) and node by node: Unsharp (Gaussian3x3 and three user point
+    3840x2160 frame, U8 in and U8 out (2 B/px), fused (one generated kernel;
+    and the same group run by the tile interpreter) and node by node (user
+    kernels generated one by one): Unsharp (Gaussian3x3 and three user point
     kernels), Tomasi (the corner graph with a user min-eigenvalue response),
     FChain (three Convolve nodes)."""
     import synth
@@ -513,15 +521,17 @@ def user_kernels(hvx, torch, ctx, rec):
     d = {"image": "3840x2160 U8 (corner workload)", "alg_bytes_per_frame": 2 * w * h}
     for name, build in (("unsharp", unsharp), ("tomasi", tomasi), ("fchain", fchain)):
         row = {}
-        for fusion in (1, 0):
+        for label, fusion, codegen in PLANS:
             g = hvx.hvx_graph_create(ctx)
             build(g)
             hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, fusion)
+            hvx.hvx_graph_set_option(g, hvx.HVX_OPT_CODEGEN, codegen)
             hvx.hvx_graph_verify(g, ctx=ctx)
             ms, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(g, stream, ctx=ctx), 20, 3)
-            row["fused" if fusion else "node_by_node"] = {
+            row[label] = {
                 "us": round(ms * 1e3, 2), "mpix_s": round(w * h / 1e6 / (ms / 1e3), 1),
                 "kernels": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS),
+                "generated": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_GENERATED),
                 "alg_gbs": round(2 * w * h / (ms / 1e3) / 1e9, 1),
                 "hbm_frac": round(2 * w * h / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                 "plan_hbm_bytes": hvx.hvx_graph_query(g, hvx.HVX_QUERY_HBM_BYTES)}

@@ -93,6 +93,8 @@ typedef int32_t hvx_status;
 #define HVX_OPT_TILE 3       /* 0 (default): tuned/default tiles; else rows per work item (fast kernels) */
 #define HVX_OPT_SPECIALIZE 4 /* 1 (default): use hand-fused kernels for recognised subgraphs; 0: generic */
 #define HVX_OPT_XCD_REMAP 5  /* 1 (default): map work items to XCDs in contiguous chunks */
+#define HVX_OPT_CODEGEN 6    /* 1 (default): a kernel generated and compiled (hipRTC) per fused group that
+                                has no hand-fused kernel (Section 6); 0: the tile interpreter runs it */
 
 /* Graph queries (hvx_graph_query); valid after verification. */
 #define HVX_QUERY_NUM_NODES 1      /* function nodes added */
@@ -107,6 +109,7 @@ typedef int32_t hvx_status;
 #define HVX_QUERY_SCRATCH_BYTES 8  /* device bytes of materialised intermediates */
 #define HVX_QUERY_OP_LIVE_MASK 9   /* bit i set: lowered operator i is live (first 63 operators) */
 #define HVX_QUERY_ROWS_PER_ITEM 10 /* rows per work item of the first kernel */
+#define HVX_QUERY_NUM_GENERATED 11 /* kernels of the plan generated for their group (HVX_OPT_CODEGEN) */
 
 /* ---- context ------------------------------------------------------------ */
 

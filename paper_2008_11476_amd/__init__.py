@@ -31,10 +31,10 @@ HVX_DF_VIRT, HVX_DF_U8, HVX_DF_S16, HVX_DF_S32, HVX_DF_F32, HVX_DF_UYVY = range(
 HVX_BORDER_UNDEFINED, HVX_BORDER_CONSTANT, HVX_BORDER_REPLICATE, HVX_BORDER_MIRROR, HVX_BORDER_REPEAT = range(5)
 HVX_POLICY_SATURATE, HVX_POLICY_WRAP = 0, 1
 HVX_CHANNEL_Y = 0
-HVX_OPT_FUSION, HVX_OPT_DCE, HVX_OPT_TILE, HVX_OPT_SPECIALIZE, HVX_OPT_XCD_REMAP = 1, 2, 3, 4, 5
+HVX_OPT_FUSION, HVX_OPT_DCE, HVX_OPT_TILE, HVX_OPT_SPECIALIZE, HVX_OPT_XCD_REMAP, HVX_OPT_CODEGEN = 1, 2, 3, 4, 5, 6
 (HVX_QUERY_NUM_NODES, HVX_QUERY_NUM_OPS, HVX_QUERY_NUM_LIVE_OPS, HVX_QUERY_NUM_KERNELS, HVX_QUERY_ALG_BYTES,
  HVX_QUERY_HBM_BYTES, HVX_QUERY_KERNEL_KIND, HVX_QUERY_SCRATCH_BYTES, HVX_QUERY_OP_LIVE_MASK,
- HVX_QUERY_ROWS_PER_ITEM) = range(1, 11)
+ HVX_QUERY_ROWS_PER_ITEM, HVX_QUERY_NUM_GENERATED) = range(1, 12)
 HVX_SERVER_CONTINUOUS, HVX_SERVER_PLAIN = 0, 1
 HVX_BATCH_PERSISTENT, HVX_BATCH_USE_GRAPH, HVX_BATCH_ROWS = 1, 2, 3
 

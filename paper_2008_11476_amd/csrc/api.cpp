@@ -781,6 +781,7 @@ hvx_status hvx_graph_set_option(hvx_graph graph, int option, int64_t value) {
       break;
     case HVX_OPT_SPECIALIZE: g->opt_specialize = value != 0; break;
     case HVX_OPT_XCD_REMAP: g->opt_xcd = value != 0; break;
+    case HVX_OPT_CODEGEN: g->opt_codegen = value != 0; break;
     default: return set_error(g->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown option %d", option);
   }
   invalidate(g);
@@ -849,6 +850,7 @@ hvx_status hvx_graph_query(hvx_graph graph, int attr, int64_t* out) {
     case HVX_QUERY_ROWS_PER_ITEM:
       *out = (p.groups.empty() || !is_strip_kind(p.groups[0].kind)) ? 0 : rows_for(g, p.groups[0]);
       break;
+    case HVX_QUERY_NUM_GENERATED: *out = p.num_generated; break;
     default: return set_error(g->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown query %d", attr);
   }
   return HVX_SUCCESS;

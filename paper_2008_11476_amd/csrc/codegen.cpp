@@ -1,0 +1,676 @@
+// Kernels generated for fused groups: source emission, hipRTC compilation,
+// a process-wide cache of code objects and their launch.
+//
+// A generated tile kernel evaluates the group's operators in stages.  A
+// stage is a run of operators that need no barrier between them: each
+// thread sweeps the positions of the stage's extent and, at each position,
+// evaluates every operator of the stage whose own extent holds it, keeping
+// the results in registers.  A value crosses into LDS only when a local
+// operator of a later stage reads it at window offsets (or a later stage
+// reads it at all); a local operator that reads a value of the current
+// stage starts a new stage.  Group inputs that local operators read are
+// loaded into LDS with their halo; inputs read only by point operators are
+// read from global memory at the pixel itself.  Every window offset, tile
+// pitch and LDS offset is a literal, so a read is one LDS access with a
+// constant offset.  Tiles whose halo lies inside the image take a body
+// without border tests; the others apply each operator's border rule.
+#include "codegen.h"
+
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#ifndef HVX_ARCH
+#define HVX_ARCH "gfx950"
+#endif
+
+namespace hvx {
+
+// the device headers the generated source includes, embedded at build time
+extern const int kRtcHeaderCount;
+extern const char* const kRtcHeaderNames[];
+extern const char* const kRtcHeaderTexts[];
+
+namespace {
+
+constexpr int kGenThreads = 256;
+constexpr int kGenLdsBytes = 48 * 1024;
+constexpr int kMaxDevices = 64;
+
+bool is_local(int kind) { return !is_point_op(kind) && !is_global_op(kind); }
+
+struct Text {
+  std::string s;
+  void operator()(const char* fmt, ...) __attribute__((format(printf, 2, 3))) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    int n = vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (n >= (int)sizeof buf) {
+      std::vector<char> big(n + 1);
+      va_start(ap, fmt);
+      vsnprintf(big.data(), big.size(), fmt, ap);
+      va_end(ap);
+      s += big.data();
+    } else {
+      s += buf;
+    }
+    s += '\n';
+  }
+};
+
+std::string fmt(const char* f, ...) __attribute__((format(printf, 1, 2)));
+std::string fmt(const char* f, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, f);
+  vsnprintf(buf, sizeof buf, f, ap);
+  va_end(ap);
+  return buf;
+}
+
+std::string float_lit(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return fmt("__builtin_bit_cast(float, 0x%08xu)", u);
+}
+
+// The operator as a constant the device helpers fold over.
+void emit_gop(Text& t, int k, const GOp& o) {
+  std::string m, c, kc;
+  for (int i = 0; i < kMaxMask; ++i) m += fmt("%s%d", i ? ", " : "", o.mask[i]);
+  for (int i = 0; i < kMaxExpr; ++i) c += fmt("%s%d", i ? ", " : "", o.code[i]);
+  for (int i = 0; i < kMaxExprConst; ++i) kc += fmt("%s%d", i ? ", " : "", o.kc[i]);
+  t("__device__ constexpr GOp gop%d = {%d, %d, {%d, %d, %d}, %d, %d, %s, %d, %d, %d, %d, %d, %d, %s, {%s}, {%s}, {%s}};",
+    k, o.kind, o.out, o.in[0], o.in[1], o.in[2], o.border, o.cint, float_lit(o.cf).c_str(), o.rx, o.ry, o.p0, o.p1,
+    o.p2, o.p3, float_lit(o.pf).c_str(), m.c_str(), c.c_str(), kc.c_str());
+}
+
+// A user kernel's postfix program as one expression (Section 5.1).  The
+// arithmetic follows the interpreter's rules: 32-bit wrapping integer
+// arithmetic with the result saturated to the output format, or F32 with
+// every operation rounded (no contraction).
+bool emit_expr(Text& t, int k, const GOp& o, bool local, int out_df, std::string* why) {
+  const bool fl = o.p1 != 0;
+  std::vector<std::string> st;
+  auto pop = [&](std::string* s) {
+    if (st.empty()) return false;
+    *s = st.back();
+    st.pop_back();
+    return true;
+  };
+  if (o.p0 < 1 || o.p0 > kMaxExpr) {
+    *why = "malformed user kernel";
+    return false;
+  }
+  for (int i = 0; i < o.p0; ++i) {
+    const int op = o.code[i] & 0xFF, arg = o.code[i] >> 8;
+    std::string a, b, c;
+    bool ok = true;
+    switch (op) {
+      case X_IN:
+      case X_INW: {
+        std::string v = local ? (op == X_IN ? std::string("rd(0, 0)") : fmt("rd(%d, %d)", arg % 5 - 2, arg / 5 - 2))
+                              : fmt("a%d", arg);
+        if (fl) v = ((o.p2 >> (op == X_IN ? arg : 0)) & 1) ? "__int_as_float(" + v + ")" : "(float)(" + v + ")";
+        st.push_back(v);
+        break;
+      }
+      case X_CONST:
+        if (arg < 0 || arg >= kMaxExprConst) ok = false;
+        else st.push_back(fl ? fmt("__int_as_float((int)0x%08xu)", (uint32_t)o.kc[arg]) : fmt("(int)0x%08xu", (uint32_t)o.kc[arg]));
+        break;
+      case X_ADD:
+      case X_SUB:
+      case X_MUL:
+      case X_DIV:
+      case X_MIN:
+      case X_MAX:
+      case X_GT: {
+        ok = pop(&b) && pop(&a);
+        if (!ok) break;
+        static const char* iname[] = {"gx_add", "gx_sub", "gx_mul", "gx_div"};
+        std::string r;
+        if (op == X_MIN) r = (fl ? "fminf(" : "min(") + a + ", " + b + ")";
+        else if (op == X_MAX) r = (fl ? "fmaxf(" : "max(") + a + ", " + b + ")";
+        else if (op == X_GT) r = "((" + a + ") > (" + b + ")" + (fl ? " ? 1.f : 0.f)" : " ? 1 : 0)");
+        else if (fl) r = "(" + a + (op == X_ADD ? " + " : op == X_SUB ? " - " : op == X_MUL ? " * " : " / ") + b + ")";
+        else r = std::string(iname[op - X_ADD]) + "(" + a + ", " + b + ")";
+        st.push_back(r);
+        break;
+      }
+      case X_NEG:
+      case X_ABS:
+      case X_SQRT:
+        ok = pop(&a);
+        if (!ok) break;
+        if (op == X_NEG) st.push_back(fl ? "(-(" + a + "))" : "gx_neg(" + a + ")");
+        else if (op == X_ABS) st.push_back(fl ? "fabsf(" + a + ")" : "gx_abs(" + a + ")");
+        else if (fl) st.push_back("__builtin_sqrtf(" + a + ")");
+        else ok = false;
+        break;
+      case X_CLAMP:
+        ok = pop(&c) && pop(&b) && pop(&a);
+        if (ok) st.push_back(fl ? "fminf(fmaxf(" + a + ", " + b + "), " + c + ")" : "min(max(" + a + ", " + b + "), " + c + ")");
+        break;
+      case X_SEL:
+        ok = pop(&c) && pop(&b) && pop(&a);
+        if (ok) st.push_back("((" + a + ") != " + (fl ? "0.f" : "0") + " ? (" + b + ") : (" + c + "))");
+        break;
+      default: ok = false;
+    }
+    if (!ok) {
+      *why = "malformed user kernel";
+      return false;
+    }
+  }
+  if (st.size() != 1) {
+    *why = "malformed user kernel";
+    return false;
+  }
+  if (local) t("template <class RD> __device__ __forceinline__ int gx_expr%d(const RD& rd) {", k);
+  else t("__device__ __forceinline__ int gx_expr%d(int a0, int a1, int a2) {", k);
+  t("#pragma clang fp contract(off)");
+  if (fl) {
+    t("  const float r = %s;", st[0].c_str());
+    t("  return __float_as_int(r);");
+  } else {
+    t("  const int r = %s;", st[0].c_str());
+    t(out_df == DF_U8 ? "  return min(max(r, 0), 255);" : "  return min(max(r, -32768), 32767);");
+  }
+  t("}");
+  return true;
+}
+
+void emit_prelude(Text& t, const GProg& P, std::string* why, bool* ok) {
+  t("namespace __hip_internal {}");
+  t("using namespace __hip_internal;");
+  t("#include \"dev_generic.hpp\"");
+  t("namespace hvx {");
+  t("__device__ __forceinline__ int gx_add(int a, int b) { return (int)((uint32_t)a + (uint32_t)b); }");
+  t("__device__ __forceinline__ int gx_sub(int a, int b) { return (int)((uint32_t)a - (uint32_t)b); }");
+  t("__device__ __forceinline__ int gx_mul(int a, int b) { return (int)((uint32_t)a * (uint32_t)b); }");
+  t("__device__ __forceinline__ int gx_neg(int a) { return (int)(0u - (uint32_t)a); }");
+  t("__device__ __forceinline__ int gx_abs(int a) { return a < 0 ? gx_neg(a) : a; }");
+  t("__device__ __forceinline__ int gx_div(int x, int y) { return y == 0 ? 0 : (y == -1 ? gx_neg(x) : x / y); }");
+  // a value's LDS tile read under an operator's border rule (edge tiles)
+  t("template <int BORDER>");
+  t("__device__ __forceinline__ int gx_rd(const int32_t* L, int rw, int e, int tx0, int ty0, int W, int H, int x, int y,");
+  t("                                    int cval) {");
+  t("  if (BORDER != B_REPEAT && (x < 0 || y < 0 || x >= W || y >= H)) {");
+  t("    if (BORDER == B_CONSTANT) return cval;");
+  t("    if (BORDER == B_MIRROR) {");
+  t("      x = mirror_pos(x, W);");
+  t("      y = mirror_pos(y, H);");
+  t("    }");
+  t("    x = min(max(x, 0), W - 1);");
+  t("    y = min(max(y, 0), H - 1);");
+  t("  }");
+  t("  return L[(y - (ty0 - e)) * rw + (x - (tx0 - e))];");
+  t("}");
+  for (int k = 0; k < P.nops; ++k) {
+    emit_gop(t, k, P.ops[k]);
+    const GOp& o = P.ops[k];
+    if (o.kind == OP_EXPR || o.kind == OP_EXPR_LOCAL)
+      if (!emit_expr(t, k, o, o.kind == OP_EXPR_LOCAL, P.vals[o.out].df, why)) *ok = false;
+  }
+  t("}  // namespace hvx");
+  t("using namespace hvx;");
+}
+
+// ---- the point form ----------------------------------------------------------
+
+bool emit_points(const GProg& P, GenSource* out, std::string* why) {
+  Text t;
+  bool ok = true;
+  emit_prelude(t, P, why, &ok);
+  if (!ok) return false;
+  t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io) {",
+    kGenThreads);
+  t("  const int W = P->w, H = P->h;");
+  t("  const int bx = (W + 1023) >> 10;");
+  t("  const int y = blockIdx.x / bx;");
+  t("  const int x = ((blockIdx.x - y * bx) * %d + (int)threadIdx.x) * 4;", kGenThreads);
+  t("  if (y >= H || x >= W) return;");
+  std::vector<int> read(P.nvals, 0);
+  for (int k = 0; k < P.nops; ++k)
+    for (int i = 0; i < 3; ++i)
+      if (P.ops[k].in[i] >= 0) read[P.ops[k].in[i]] = 1;
+  for (int v = 0; v < P.nvals; ++v) {
+    const GVal& gv = P.vals[v];
+    if (!gv.input || !read[v] || gv.df == DF_BUF) continue;
+    t("  int v%d[4];", v);
+    t("  load4(%d, (const uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);", gv.df, gv.io, gv.io, v);
+  }
+  for (int k = 0; k < P.nops; ++k) {
+    const GOp& o = P.ops[k];
+    const GVal& ov = P.vals[o.out];
+    t("  int v%d[4];", o.out);
+    t("#pragma unroll");
+    t("  for (int q = 0; q < 4; ++q) {");
+    auto in = [&](int i) { return o.in[i] >= 0 && P.vals[o.in[i]].df != DF_BUF ? fmt("v%d[q]", o.in[i]) : std::string("0"); };
+    if (o.kind == OP_LUT)
+      t("    v%d[q] = ((const uint8_t*)io.ptr[%d])[%d + (v%d[q] & 0xFF)];", o.out, P.vals[o.in[1]].io, 256 * 4, o.in[0]);
+    else if (o.kind == OP_EXPR)
+      t("    v%d[q] = gx_expr%d(%s, %s, %s);", o.out, k, in(0).c_str(), in(1).c_str(), in(2).c_str());
+    else
+      t("    v%d[q] = point_eval(gop%d, %d, %s, %s, %s, %s);", o.out, k, ov.df,
+        P.vals[o.in[0]].df == DF_F32 ? "true" : "false", in(0).c_str(), in(1).c_str(), in(2).c_str());
+    t("  }");
+    if (ov.store) t("  store4(%d, (uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);", ov.df, ov.io, ov.io, o.out);
+  }
+  t("}");
+  out->text = t.s;
+  out->form = GEN_POINTS;
+  out->tw = out->th = 0;
+  out->red = false;
+  out->lds_words = 0;
+  return true;
+}
+
+// ---- the tile form -----------------------------------------------------------
+
+enum Src { S_REG = 1, S_LDS, S_GLB };
+
+struct Layout {
+  int nstages = 0;
+  std::vector<int> op_stage, stage_ext;
+  std::vector<int> def_stage, last_lds, needs_lds, producer, lds_off;
+  std::vector<std::array<int, 3>> src;
+  int lds_words = 0;
+};
+
+void plan_stages(const GProg& P, Layout& L) {
+  const int nv = P.nvals, no = P.nops;
+  L.op_stage.assign(no, 0);
+  L.def_stage.assign(nv, -1);
+  L.producer.assign(nv, -1);
+  L.needs_lds.assign(nv, 0);
+  L.last_lds.assign(nv, -2);
+  L.src.assign(no, {0, 0, 0});
+  int cur = 0;
+  for (int k = 0; k < no; ++k) {
+    const GOp& o = P.ops[k];
+    bool reads_cur = false;
+    if (is_local(o.kind))
+      for (int i = 0; i < 3; ++i)
+        if (o.in[i] >= 0 && L.producer[o.in[i]] >= 0 && L.def_stage[o.in[i]] == cur) reads_cur = true;
+    if (reads_cur) ++cur;
+    L.op_stage[k] = cur;
+    L.producer[o.out] = k;
+    L.def_stage[o.out] = cur;
+  }
+  L.nstages = cur + 1;
+  // reads: local operators read LDS; point operators and reductions read
+  // registers within a stage, LDS across stages, group inputs where they are
+  for (int k = 0; k < no; ++k) {
+    const GOp& o = P.ops[k];
+    for (int i = 0; i < 3; ++i) {
+      const int v = o.in[i];
+      if (v < 0 || P.vals[v].df == DF_BUF) continue;
+      if (is_local(o.kind)) {
+        L.src[k][i] = S_LDS;
+        L.needs_lds[v] = 1;
+      } else if (L.producer[v] >= 0) {
+        L.src[k][i] = L.def_stage[v] == L.op_stage[k] ? S_REG : S_LDS;
+        if (L.src[k][i] == S_LDS) L.needs_lds[v] = 1;
+      }
+    }
+  }
+  for (int k = 0; k < no; ++k) {
+    const GOp& o = P.ops[k];
+    for (int i = 0; i < 3; ++i) {
+      const int v = o.in[i];
+      if (v < 0 || P.vals[v].df == DF_BUF) continue;
+      if (L.producer[v] < 0 && !is_local(o.kind)) L.src[k][i] = L.needs_lds[v] ? S_LDS : S_GLB;
+      if (L.src[k][i] == S_LDS) L.last_lds[v] = std::max(L.last_lds[v], L.op_stage[k]);
+    }
+  }
+  L.stage_ext.assign(L.nstages, 0);
+  for (int k = 0; k < no; ++k) {
+    const GOp& o = P.ops[k];
+    const int e = is_global_op(o.kind) ? 0 : P.vals[o.out].ext;
+    L.stage_ext[L.op_stage[k]] = std::max(L.stage_ext[L.op_stage[k]], e);
+  }
+}
+
+// First-fit LDS blocks; two values share words only if one is last read in
+// a stage before the other is written.
+int place_lds(const GProg& P, Layout& L, int tw, int th) {
+  const int nv = P.nvals;
+  L.lds_off.assign(nv, -1);
+  std::vector<int> order;
+  for (int v = 0; v < nv; ++v)
+    if (L.needs_lds[v]) order.push_back(v);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return L.def_stage[a] < L.def_stage[b]; });
+  std::vector<std::array<int, 4>> blocks;  // offset, size, first stage, last stage
+  int top = 0;
+  for (int v : order) {
+    const int e = P.vals[v].ext;
+    const int sz = (tw + 2 * e) * (th + 2 * e);
+    const int d = L.def_stage[v], l = std::max(L.last_lds[v], d);
+    std::vector<std::array<int, 2>> busy;
+    for (auto& b : blocks)
+      if (!(b[3] < d || l < b[2])) busy.push_back({b[0], b[1]});
+    std::sort(busy.begin(), busy.end());
+    int pos = 0;
+    for (auto& b : busy) {
+      if (pos + sz <= b[0]) break;
+      pos = std::max(pos, b[0] + b[1]);
+    }
+    L.lds_off[v] = pos;
+    top = std::max(top, pos + sz);
+    blocks.push_back({pos, sz, d, l});
+  }
+  L.lds_words = top;
+  return top;
+}
+
+bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::string* why) {
+  Layout L;
+  plan_stages(P, L);
+  int nred = 0, nhist = 0;
+  for (int k = 0; k < P.nops; ++k) {
+    nred += is_reduce_op(P.ops[k].kind) ? 1 : 0;
+    nhist += (P.ops[k].kind == OP_HISTOGRAM || P.ops[k].kind == OP_EQHIST) ? 1 : 0;
+  }
+  const bool red = nred > 0;
+  const int hist_words = red ? kHistWords : 0;
+  static const int shapes[][2] = {{128, 16}, {64, 16}, {64, 8}, {32, 8}, {32, 4}, {16, 4}};
+  int TW = 0, TH = 0;
+  if (tw_req > 0) {
+    if (place_lds(P, L, tw_req, th_req) + hist_words <= kGenLdsBytes / 4) {
+      TW = tw_req;
+      TH = th_req;
+    }
+  } else {
+    for (auto& s : shapes)
+      if (place_lds(P, L, s[0], s[1]) + hist_words <= kGenLdsBytes / 4) {
+        TW = s[0];
+        TH = s[1];
+        break;
+      }
+  }
+  if (!TW) {
+    *why = "values kept on chip exceed the LDS budget";
+    return false;
+  }
+  int emax = 0;
+  for (int v = 0; v < P.nvals; ++v) emax = std::max(emax, P.vals[v].ext);
+  const int LW = std::max(1, L.lds_words + hist_words);
+
+  Text t;
+  bool ok = true;
+  emit_prelude(t, P, why, &ok);
+  if (!ok) return false;
+  (void)nhist;
+  // one tile: IN = its halo lies inside the image
+  t("template <bool IN>");
+  t("__device__ __forceinline__ void gen_tile(const IOTable& io, int W, int H, int tx0, int ty0, int32_t* L%s) {",
+    red ? ", RedState& rs" : "");
+  // load stage
+  bool loads = false;
+  for (int v = 0; v < P.nvals; ++v) {
+    const GVal& gv = P.vals[v];
+    if (!gv.input || !L.needs_lds[v]) continue;
+    loads = true;
+    const int e = gv.ext, rw = TW + 2 * e, rh = TH + 2 * e;
+    t("  {  // load value %d with a halo of %d", v, e);
+    t("    const uint8_t* base = (const uint8_t*)io.ptr[%d];", gv.io);
+    t("    const int64_t pitch = io.pitch[%d];", gv.io);
+    t("    for (int i = (int)threadIdx.x; i < %d; i += %d) {", rw * rh, kGenThreads);
+    t("      const int ly = i / %d, lx = i - ly * %d;", rw, rw);
+    t("      const int x = tx0 - %d + lx, y = ty0 - %d + ly;", e, e);
+    if (gv.wrap) {
+      t("      if (IN) L[%d + i] = gload(%d, base, pitch, x, y);", L.lds_off[v], gv.df);
+      t("      else L[%d + i] = gload(%d, base, pitch, repeat_pos(x, W), repeat_pos(y, H));", L.lds_off[v], gv.df);
+    } else {
+      t("      if (IN || (x >= 0 && y >= 0 && x < W && y < H)) L[%d + i] = gload(%d, base, pitch, x, y);", L.lds_off[v],
+        gv.df);
+    }
+    t("    }");
+    t("  }");
+  }
+  if (loads) t("  __syncthreads();");
+  int slot = 0;
+  for (int s = 0; s < L.nstages; ++s) {
+    const int ES = L.stage_ext[s], RW = TW + 2 * ES, RH = TH + 2 * ES;
+    bool need_own = false;
+    for (int k = 0; k < P.nops; ++k)
+      if (L.op_stage[k] == s && (is_reduce_op(P.ops[k].kind) || P.vals[P.ops[k].out].store)) need_own = true;
+    t("  // stage %d: extent %d", s, ES);
+    t("  for (int i = (int)threadIdx.x; i < %d; i += %d) {", RW * RH, kGenThreads);
+    t("    const int ly = i / %d, lx = i - ly * %d;", RW, RW);
+    t("    const int x = tx0 - %d + lx, y = ty0 - %d + ly;", ES, ES);
+    t("    if (!IN && (x < 0 || y < 0 || x >= W || y >= H)) continue;");
+    if (need_own) {
+      if (ES > 0) t("    const bool own = lx >= %d && lx < %d && ly >= %d && ly < %d;", ES, ES + TW, ES, ES + TH);
+      else t("    const bool own = true;");
+    }
+    for (int k = 0; k < P.nops; ++k) {
+      if (L.op_stage[k] != s) continue;
+      const GOp& o = P.ops[k];
+      // a point read at the position itself
+      auto at = [&](int i) -> std::string {
+        const int v = o.in[i];
+        if (v < 0 || P.vals[v].df == DF_BUF) return "0";
+        switch (L.src[k][i]) {
+          case S_REG: return fmt("v%d", v);
+          case S_GLB: return fmt("gload(%d, io.ptr[%d], io.pitch[%d], x, y)", P.vals[v].df, P.vals[v].io, P.vals[v].io);
+          default: {
+            const int e = P.vals[v].ext, rw = TW + 2 * e;
+            return fmt("L[%d + (ly + %d) * %d + (lx + %d)]", L.lds_off[v], e - ES, rw, e - ES);
+          }
+        }
+      };
+      if (is_reduce_op(o.kind)) {
+        t("    if (own) red_add(rs, %d, gop%d, %s);", slot++, k, at(0).c_str());
+        continue;
+      }
+      const GVal& ov = P.vals[o.out];
+      const int EK = ov.ext;
+      t("    int v%d = 0;", o.out);
+      if (EK < ES) t("    if (lx >= %d && lx < %d && ly >= %d && ly < %d) {", ES - EK, ES + EK + TW, ES - EK, ES + EK + TH);
+      else t("    {");
+      if (is_local(o.kind)) {
+        const int v = o.in[0];
+        const int e = P.vals[v].ext, rw = TW + 2 * e;
+        // the border constant as the input's element bits
+        uint32_t cval = (uint32_t)o.cint;
+        if (P.vals[v].df == DF_F32) memcpy(&cval, &o.cf, 4);
+        t("      const int b = %d + (ly + %d) * %d + (lx + %d);", L.lds_off[v], e - ES, rw, e - ES);
+        t("      auto rd = [&](int dx, int dy) -> int {");
+        t("        if constexpr (IN) return L[b + dy * %d + dx];", rw);
+        t("        else return gx_rd<%d>(L + %d, %d, %d, tx0, ty0, W, H, x + dx, y + dy, (int)0x%08xu);", o.border,
+          L.lds_off[v], rw, e, cval);
+        t("      };");
+        if (o.kind == OP_EXPR_LOCAL) t("      v%d = gx_expr%d(rd);", o.out, k);
+        else t("      v%d = local_eval<%s>(gop%d, %d, rd);", o.out, o.kind == OP_NONLINEAR ? "true" : "false", k, ov.df);
+      } else if (o.kind == OP_LUT) {
+        t("      v%d = ((const uint8_t*)io.ptr[%d])[%d + (%s & 0xFF)];", o.out, P.vals[o.in[1]].io, 256 * 4, at(0).c_str());
+      } else if (o.kind == OP_EXPR) {
+        t("      v%d = gx_expr%d(%s, %s, %s);", o.out, k, at(0).c_str(), at(1).c_str(), at(2).c_str());
+      } else {
+        t("      v%d = point_eval(gop%d, %d, %s, %s, %s, %s);", o.out, k, ov.df,
+          P.vals[o.in[0]].df == DF_F32 ? "true" : "false", at(0).c_str(), at(1).c_str(), at(2).c_str());
+      }
+      if (L.needs_lds[o.out]) {
+        const int e = ov.ext, rw = TW + 2 * e;
+        t("      L[%d + (ly + %d) * %d + (lx + %d)] = v%d;", L.lds_off[o.out], e - ES, rw, e - ES, o.out);
+      }
+      if (ov.store) t("      if (own) gstore(%d, io.ptr[%d], io.pitch[%d], x, y, v%d);", ov.df, ov.io, ov.io, o.out);
+      t("    }");
+    }
+    t("  }");
+    if (s + 1 < L.nstages) t("  __syncthreads();");
+  }
+  t("}");
+  t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io) {",
+    kGenThreads);
+  t("  __shared__ int32_t L[%d];", LW);
+  t("  const int W = P->w, H = P->h;");
+  t("  const int tiles_x = (W + %d) / %d;", TW - 1, TW);
+  t("  const int ntiles = tiles_x * ((H + %d) / %d);", TH - 1, TH);
+  if (red) {
+    t("  RedState rs;");
+    t("  red_begin<%d>(rs, (uint32_t*)(L + %d));", kGenThreads, L.lds_words);
+  }
+  t("  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {");
+  t("    const int tx0 = (tile %% tiles_x) * %d, ty0 = (tile / tiles_x) * %d;", TW, TH);
+  t("    const bool in = tx0 >= %d && ty0 >= %d && tx0 + %d <= W && ty0 + %d <= H;", emax, emax, TW + emax, TH + emax);
+  t("    if (in) gen_tile<true>(io, W, H, tx0, ty0, L%s);", red ? ", rs" : "");
+  t("    else gen_tile<false>(io, W, H, tx0, ty0, L%s);", red ? ", rs" : "");
+  t("    __syncthreads();  // the tile's LDS is free for the next tile");
+  t("  }");
+  if (red) t("  red_end<%d>(*P, io, rs);", kGenThreads);
+  t("}");
+  out->text = t.s;
+  out->form = GEN_TILES;
+  out->tw = TW;
+  out->th = TH;
+  out->red = red;
+  out->lds_words = LW;
+  return true;
+}
+
+}  // namespace
+
+// ---- cache, compilation, launch --------------------------------------------------
+
+struct GenKernel {
+  int form = 0, tw = 0, th = 0;
+  bool red = false;
+  std::vector<char> code;
+  std::mutex mu;
+  hipModule_t mod[kMaxDevices] = {};
+  hipFunction_t fn[kMaxDevices] = {};
+};
+
+namespace {
+std::mutex g_cache_mu;
+// never freed: code objects stay loaded until the process ends
+std::map<std::string, GenKernel*>* g_cache = new std::map<std::string, GenKernel*>();
+}  // namespace
+
+bool gen_wanted(const GProg& P) {
+  if (P.nops != 1) return true;
+  const GOp& o = P.ops[0];
+  if (is_global_op(o.kind)) return true;
+  if (is_point_op(o.kind)) return o.kind == OP_EXPR;
+  const int in_df = P.vals[o.in[0]].df;
+  return o.kind == OP_EXPR_LOCAL || (in_df != DF_U8 && in_df != DF_F32);
+}
+
+bool gen_source(const GProg& P, int tw, int th, GenSource* out, std::string* why) {
+  bool any_local = false, any_red = false;
+  for (int k = 0; k < P.nops; ++k) {
+    const int kind = P.ops[k].kind;
+    if (kind == OP_MMLOCS) {
+      *why = "the location pass runs alone";
+      return false;
+    }
+    any_local |= is_local(kind);
+    any_red |= is_reduce_op(kind);
+  }
+  if (!any_local && !any_red) return emit_points(P, out, why);
+  return emit_tiles(P, tw, th, out, why);
+}
+
+const GenKernel* gen_compile(const GenSource& src, std::string* why) {
+  std::lock_guard<std::mutex> l(g_cache_mu);
+  auto it = g_cache->find(src.text);
+  if (it != g_cache->end()) return it->second;
+  if (const char* dir = getenv("HVX_GEN_DUMP")) {  // the sources, for reading
+    const std::string path = std::string(dir) + "/hvx_gen_" + std::to_string(g_cache->size()) + ".hip";
+    if (FILE* f = fopen(path.c_str(), "w")) {
+      fputs(src.text.c_str(), f);
+      fclose(f);
+    }
+  }
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.text.c_str(), "hvx_gen.hip", kRtcHeaderCount,
+                          const_cast<const char**>(kRtcHeaderTexts),
+                          const_cast<const char**>(kRtcHeaderNames)) != HIPRTC_SUCCESS) {
+    *why = "hiprtcCreateProgram failed";
+    return nullptr;
+  }
+  const char* opts[] = {"--offload-arch=" HVX_ARCH, "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops", "-w"};
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    *why = std::string("hipRTC: ") + hiprtcGetErrorString(r) + "\n" + log.substr(0, 4000);
+    hiprtcDestroyProgram(&prog);
+    return nullptr;
+  }
+  size_t n = 0;
+  hiprtcGetCodeSize(prog, &n);
+  GenKernel* k = new GenKernel();
+  k->code.resize(n);
+  hiprtcGetCode(prog, k->code.data());
+  hiprtcDestroyProgram(&prog);
+  k->form = src.form;
+  k->tw = src.tw;
+  k->th = src.th;
+  k->red = src.red;
+  (*g_cache)[src.text] = k;
+  return k;
+}
+
+hipError_t gen_load(const GenKernel* kc, int device) {
+  GenKernel* k = const_cast<GenKernel*>(kc);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> l(k->mu);
+  if (k->fn[device]) return hipSuccess;
+  hipModule_t m = nullptr;
+  hipError_t e = hipModuleLoadData(&m, k->code.data());
+  if (e != hipSuccess) return e;
+  hipFunction_t f = nullptr;
+  e = hipModuleGetFunction(&f, m, "hvx_gen");
+  if (e != hipSuccess) {
+    (void)hipModuleUnload(m);
+    return e;
+  }
+  k->mod[device] = m;
+  k->fn[device] = f;
+  return hipSuccess;
+}
+
+hipError_t gen_launch(const GenKernel* k, int device, const GProg& P, const GProg* dev_prog, const IOTable& io,
+                      int num_cus, hipStream_t s) {
+  if (device < 0 || device >= kMaxDevices || !k->fn[device]) return hipErrorInvalidDeviceFunction;
+  long long grid;
+  if (k->form == GEN_POINTS) {
+    grid = (long long)((P.w + 1023) >> 10) * P.h;
+  } else {
+    const long long tiles = (long long)((P.w + k->tw - 1) / k->tw) * ((P.h + k->th - 1) / k->th);
+    grid = k->red ? std::min<long long>(tiles, 4LL * num_cus) : tiles;
+  }
+  if (grid <= 0) return hipSuccess;
+  if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const GProg* p = dev_prog;
+  IOTable t = io;
+  void* args[] = {(void*)&p, (void*)&t};
+  return hipModuleLaunchKernel(k->fn[device], (unsigned)grid, 1, 1, kGenThreads, 1, 1, 0, s, args, nullptr);
+}
+
+void gen_tile(const GenKernel* k, int* tw, int* th) {
+  *tw = k->tw;
+  *th = k->th;
+}
+
+}  // namespace hvx

@@ -15,8 +15,11 @@
 // the same intermediate (REPLICATE, UNDEFINED).  The clamped coordinate
 // always lies in the region computed for that value.
 #pragma once
+// hipRTC (kernels generated at run time) provides the HIP and integer types itself
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include "dev_phase.hpp"
 #include "dev_reduce.hpp"
@@ -106,11 +109,6 @@ __device__ __forceinline__ uint32_t isqrt_u32(uint32_t s) {
 
 __device__ __forceinline__ int sat_u8(int v) { return min(max(v, 0), 255); }
 __device__ __forceinline__ int sat_s16(int v) { return min(max(v, -32768), 32767); }
-
-__host__ __device__ inline bool is_point_op(int kind) {
-  return kind == OP_CHANNEL_Y || kind == OP_MAGNITUDE || kind == OP_PHASE || kind == OP_THRESHOLD ||
-         kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS || kind == OP_EXPR || kind == OP_LUT;
-}
 
 // The EqualizeHist mapping table of an OP_LUT operator: the 256 bytes after
 // the counts in its second input, a buffer in device memory.

@@ -34,8 +34,11 @@
 // the exact alpha, so the level is within one of round(exact level).  Inputs
 // must satisfy |g| <= 1023; larger S16 values are scaled by the caller.
 #pragma once
+// hipRTC (kernels generated at run time) provides the HIP and integer types itself
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 namespace hvx {
 

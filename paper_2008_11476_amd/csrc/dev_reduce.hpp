@@ -3,8 +3,11 @@
 // (value, count) pairs of the smallest and largest pixel across a wave and
 // into the 64-bit keys of the result (hvx_desc.h: mm_key, mm_merge).
 #pragma once
+// hipRTC (kernels generated at run time) provides the HIP and integer types itself
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include "hvx_desc.h"
 

@@ -1,7 +1,10 @@
 // Plain descriptors passed from the host runtime to the kernels by value.
 // Shared by host C++ and device code; no HIP types, no pointers to host data.
 #pragma once
+// hipRTC (kernels generated at run time) provides the HIP and integer types itself
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#endif
 
 namespace hvx {
 
@@ -43,6 +46,11 @@ enum OpKind : int32_t {
 // A global operator (its output is a buffer; nothing reads it in the same
 // kernel, since it is complete only once every pixel has been seen).
 __host__ __device__ inline bool is_global_op(int kind) { return kind >= OP_HISTOGRAM && kind <= OP_EQHIST; }
+// A point operator (Section 4): one output pixel from the same pixel of its inputs.
+__host__ __device__ inline bool is_point_op(int kind) {
+  return kind == OP_CHANNEL_Y || kind == OP_MAGNITUDE || kind == OP_PHASE || kind == OP_THRESHOLD ||
+         kind == OP_ADD || kind == OP_MULF || kind == OP_HARRIS || kind == OP_EXPR || kind == OP_LUT;
+}
 // The global operators a fused kernel can compute as a reduction over its
 // tiles (the location lists need the final extremes, so they run apart).
 __host__ __device__ inline bool is_reduce_op(int kind) { return is_global_op(kind) && kind != OP_MMLOCS; }

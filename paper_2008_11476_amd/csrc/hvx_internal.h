@@ -18,6 +18,7 @@ enum ObjType : uint32_t { T_CONTEXT = 0x5a01, T_GRAPH, T_IMAGE, T_NODE, T_CONV, 
 
 struct Context;
 struct Graph;
+struct GenKernel;  // codegen.h
 
 struct Object {
   uint32_t type;
@@ -131,6 +132,7 @@ struct Group {
   int phase = 0;             // global operators whose results this group waits for (launch order)
   int footprint = 0;  // max total stencil radius along any path
   GProg prog{};       // generic program (kind == FK_GENERIC)
+  const GenKernel* gen = nullptr;  // kernel generated for `prog` (null: the tile interpreter)
   int rows = 0;       // rows per work item (fast kinds); 0 = tuned or default
   int xcd = 1;        // XCD-contiguous work mapping
   uint32_t w = 0, h = 0;
@@ -144,6 +146,8 @@ struct Plan {
   std::vector<Group> groups;
   int num_nodes = 0, num_ops = 0, num_live = 0;
   int64_t alg_bytes = 0, hbm_bytes = 0, scratch_bytes = 0;
+  int num_generated = 0;  // groups run by generated kernels
+  std::string gen_note;   // why a group was left to the interpreter (last case)
   std::vector<int> topo;  // live op order
 };
 
@@ -151,7 +155,7 @@ struct Graph : Object {
   std::vector<Node*> nodes;
   std::vector<Image*> virt;
   bool verified = false;
-  int opt_fusion = 1, opt_dce = 1, opt_tile = 0, opt_specialize = 1, opt_xcd = 1;
+  int opt_fusion = 1, opt_dce = 1, opt_tile = 0, opt_specialize = 1, opt_xcd = 1, opt_codegen = 1;
   std::unique_ptr<Plan> plan;
   // device state: the materialised values live in one block of scratch_total
   // bytes, value v at scratch_off[v] with row pitch scratch_pitch[v] (0: not

@@ -10,6 +10,7 @@
 #include <sstream>
 
 #include "global.h"
+#include "codegen.h"
 #include "hvx_internal.h"
 #include "kernels.h"
 
@@ -56,6 +57,12 @@ void free_graph_device(Graph* g) {
 static hvx_status ensure_scratch(Graph* g) {
   Plan& p = *g->plan;
   if (g->prepared) return HVX_SUCCESS;
+  for (const Group& gr : p.groups)
+    if (gr.gen) {
+      const hipError_t e = gen_load(gr.gen, g->ctx->device);
+      if (e != hipSuccess)
+        return set_error(g->ctx, HVX_ERROR_DEVICE, "cannot load a generated kernel: %s", hipGetErrorString(e));
+    }
   std::vector<GProg> progs(p.groups.size());
   for (size_t i = 0; i < p.groups.size(); ++i) progs[i] = p.groups[i].prog;
   if (hipMalloc((void**)&g->dev_progs, progs.size() * sizeof(GProg)) != hipSuccess ||
@@ -279,7 +286,9 @@ static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s, const B
     for (int i = 0; i < P.nops && e == hipSuccess; ++i)
       if (is_reduce_op(P.ops[i].kind))
         e = launch_reduce_init(P.ops[i].kind, io.ptr[P.vals[P.ops[i].out].io], P.ops[i].p0, s);
-    if (e == hipSuccess) e = launch_generic(P, g->dev_progs + gi, io, g->ctx->num_cus, s);
+    if (e == hipSuccess)
+      e = gr.gen ? gen_launch(gr.gen, g->ctx->device, P, g->dev_progs + gi, io, g->ctx->num_cus, s)
+                 : launch_generic(P, g->dev_progs + gi, io, g->ctx->num_cus, s);
     for (int i = 0; i < P.nops && e == hipSuccess; ++i)
       if (is_reduce_op(P.ops[i].kind)) {
         void* out = io.ptr[P.vals[P.ops[i].out].io];

@@ -14,6 +14,7 @@
 //      generic tile interpreter) and its program / launch shape.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -22,6 +23,7 @@
 #include <map>
 #include <set>
 
+#include "codegen.h"
 #include "hvx_internal.h"
 
 namespace hvx {
@@ -949,6 +951,18 @@ hvx_status verify_graph(Graph* g) {
     std::string why;
     if (!build_generic(g, p, gr, &why))
       return err(g, HVX_ERROR_NOT_SUPPORTED, "cannot plan a kernel: %s", why.c_str());
+    // the group's own kernel, its operators and formats as constants
+    // (Section 6); the interpreter runs the group if it cannot be made
+    if (g->opt_codegen && gen_wanted(gr.prog)) {
+      GenSource src;
+      if (gen_source(gr.prog, 0, 0, &src, &why)) gr.gen = gen_compile(src, &why);
+      if (gr.gen) {
+        ++p.num_generated;
+      } else {
+        p.gen_note = why;
+        if (getenv("HVX_GEN_LOG")) fprintf(stderr, "hvx: group left to the interpreter: %s\n", why.c_str());
+      }
+    }
   }
 
   // byte accounting

@@ -29,7 +29,7 @@ def device_image(ctx, arr, df, seed=0):
 
 
 def run_spec(spec: gs.Spec, ctx, fusion=True, specialize=True, rows=0, dce=True, xcd=True, autotune=False,
-             keep=None):
+             keep=None, codegen=True):
     """Execute `spec` on the GPU; returns ({output name: numpy array}, graph).
     `keep`, a dict, receives the device tensors (inputs, outputs, buffers) so
     that the graph can be processed again."""
@@ -62,6 +62,7 @@ def run_spec(spec: gs.Spec, ctx, fusion=True, specialize=True, rows=0, dce=True,
     hvx.hvx_graph_set_option(g, hvx.HVX_OPT_SPECIALIZE, int(specialize))
     hvx.hvx_graph_set_option(g, hvx.HVX_OPT_DCE, int(dce))
     hvx.hvx_graph_set_option(g, hvx.HVX_OPT_XCD_REMAP, int(xcd))
+    hvx.hvx_graph_set_option(g, hvx.HVX_OPT_CODEGEN, int(codegen))
     if rows:
         hvx.hvx_graph_set_option(g, hvx.HVX_OPT_TILE, rows)
     hvx.hvx_graph_verify(g, ctx=ctx)

@@ -1,0 +1,98 @@
+"""Host-side tests of the kernels generated per fused group: verification
+writes and compiles them (hipRTC needs no device), HVX_OPT_CODEGEN switches
+them off, and the groups that the one-operator kernels run with constant
+operators are not generated.  No compute call is made."""
+import pytest
+
+import paper_2008_11476_amd as hvx
+
+FAKE = 0x7f0000000000  # 16-byte aligned, never dereferenced here
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import os
+    if not os.path.exists(hvx.LIB_PATH):
+        from paper_2008_11476_amd import build
+        build.build()
+    return hvx.lib()
+
+
+@pytest.fixture
+def ctx(lib):
+    c = hvx.hvx_context_create(0)
+    yield c
+    hvx.hvx_context_release(c)
+
+
+def _img(ctx, w, h, df=hvx.HVX_DF_U8, k=0):
+    bpp = hvx.BYTES_PER_PIXEL[df]
+    pitch = max(64, (w * bpp + 63) // 64 * 64)
+    return hvx.hvx_image_from_ptr(ctx, w, h, df, FAKE + k * (1 << 28), pitch)
+
+
+def _unsharp(ctx, w=640, h=480):
+    g = hvx.hvx_graph_create(ctx)
+    a, o = _img(ctx, w, h, k=0), _img(ctx, w, h, k=1)
+    v = [hvx.hvx_image_create_virtual(g) for _ in range(3)]
+    hvx.hvx_gaussian3x3_node(g, a, v[0])
+    hvx.hvx_custom_point_node(g, "a - b", [a, v[0]], hvx.HVX_DF_S16, v[1])
+    hvx.hvx_custom_point_node(g, "a * 3 / 2", [v[1]], hvx.HVX_DF_S16, v[2])
+    hvx.hvx_custom_point_node(g, "a + b", [a, v[2]], hvx.HVX_DF_U8, o)
+    return g
+
+
+def _q(g, attr):
+    return hvx.hvx_graph_query(g, attr)
+
+
+def test_fused_group_is_generated(ctx):
+    g = _unsharp(ctx)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 1
+    hvx.hvx_graph_set_option(g, hvx.HVX_OPT_CODEGEN, 0)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 0
+
+
+def test_node_by_node_generates_user_kernels_only(ctx):
+    """Node by node: the three user point kernels are generated; the
+    Gaussian runs in the one-operator local kernel."""
+    g = _unsharp(ctx)
+    hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, 0)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_KERNELS) == 4
+    assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 3
+
+
+def test_single_builtin_operators_not_generated(ctx):
+    g = hvx.hvx_graph_create(ctx)
+    a, b, o = _img(ctx, 100, 50, k=0), _img(ctx, 100, 50, k=1), _img(ctx, 100, 50, k=2)
+    hvx.hvx_add_node(g, a, b, hvx.HVX_POLICY_SATURATE, o)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 0
+    g2 = hvx.hvx_graph_create(ctx)
+    hvx.hvx_box3x3_node(g2, a, o)
+    hvx.hvx_graph_verify(g2)
+    assert _q(g2, hvx.HVX_QUERY_NUM_GENERATED) == 0
+
+
+def test_same_structure_other_size_and_reduction(ctx):
+    """A second image size of the same structure verifies too (the source
+    does not depend on the size); a producer fused into a histogram is
+    generated with its reduction."""
+    for w, h in ((33, 7), (1, 1), (4000, 3)):
+        g = _unsharp(ctx, w, h)
+        hvx.hvx_graph_verify(g)
+        assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 1
+    g = hvx.hvx_graph_create(ctx)
+    a = _img(ctx, 300, 200, k=0)
+    buf = hvx.hvx_buffer_from_ptr(ctx, FAKE + (1 << 40), 64 * 4)
+    v = hvx.hvx_image_create_virtual(g)
+    hvx.hvx_gaussian3x3_node(g, a, v)
+    hvx.hvx_histogram_node(g, v, 64, 0, 256, buf)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
+    assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 1
