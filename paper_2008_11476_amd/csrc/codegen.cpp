@@ -206,8 +206,8 @@ void emit_prelude(Text& t, const GProg& P, std::string* why, bool* ok) {
   t("__device__ __forceinline__ int gx_div(int x, int y) { return y == 0 ? 0 : (y == -1 ? gx_neg(x) : x / y); }");
   // a value's LDS tile read under an operator's border rule (edge tiles)
   t("template <int BORDER>");
-  t("__device__ __forceinline__ int gx_rd(const int32_t* L, int rw, int e, int tx0, int ty0, int W, int H, int x, int y,");
-  t("                                    int cval) {");
+  t("__device__ __forceinline__ int gx_rd(const int32_t* L, int rw, int ey, int ex, int tx0, int ty0, int W, int H,");
+  t("                                    int x, int y, int cval) {");
   t("  if (BORDER != B_REPEAT && (x < 0 || y < 0 || x >= W || y >= H)) {");
   t("    if (BORDER == B_CONSTANT) return cval;");
   t("    if (BORDER == B_MIRROR) {");
@@ -217,7 +217,18 @@ void emit_prelude(Text& t, const GProg& P, std::string* why, bool* ok) {
   t("    x = min(max(x, 0), W - 1);");
   t("    y = min(max(y, 0), H - 1);");
   t("  }");
-  t("  return L[(y - (ty0 - e)) * rw + (x - (tx0 - e))];");
+  t("  return L[(y - ty0 + ey) * rw + (x - tx0 + ex)];");
+  t("}");
+  // element j of a 16-byte chunk of a row in format DF (int bits)
+  t("template <int DF>");
+  t("__device__ __forceinline__ int gx_elem(const uint4& d, int j) {");
+  t("  const int bpp = DF == DF_U8 ? 1 : ((DF == DF_S16 || DF == DF_UYVY) ? 2 : 4);");
+  t("  const int k = j * bpp / 4, sh = (j * bpp % 4) * 8;");
+  t("  const uint32_t w = k == 0 ? d.x : (k == 1 ? d.y : (k == 2 ? d.z : d.w));");
+  t("  if (DF == DF_U8) return (int)((w >> sh) & 0xFFu);");
+  t("  if (DF == DF_S16) return (int)(int16_t)(uint16_t)(w >> sh);");
+  t("  if (DF == DF_UYVY) return (int)((w >> sh) & 0xFFFFu);");
+  t("  return (int)w;");
   t("}");
   for (int k = 0; k < P.nops; ++k) {
     emit_gop(t, k, P.ops[k]);
@@ -345,8 +356,23 @@ void plan_stages(const GProg& P, Layout& L) {
   }
 }
 
+// LDS geometry of a value kept on chip: rows of `rw` words, image column x
+// of the tile at column x - tx0 + co, image row y at row y - ty0 + e.  A
+// group input is loaded in whole 16-byte chunks of its rows, so its rows
+// start at a 16-byte boundary of the image row before the halo.
+int input_cols(const GVal& v) {
+  const int bpp = df_bytes(v.df);
+  return ((v.ext * bpp + 15) / 16 * 16) / bpp;
+}
+
+void value_geometry(const GProg& P, int v, int tw, int* rw, int* co) {
+  const GVal& gv = P.vals[v];
+  *co = gv.input ? input_cols(gv) : gv.ext;
+  *rw = tw + 2 * *co;
+}
+
 // First-fit LDS blocks; two values share words only if one is last read in
-// a stage before the other is written.
+// a stage before the other is written.  Blocks start at 16-byte boundaries.
 int place_lds(const GProg& P, Layout& L, int tw, int th) {
   const int nv = P.nvals;
   L.lds_off.assign(nv, -1);
@@ -357,8 +383,9 @@ int place_lds(const GProg& P, Layout& L, int tw, int th) {
   std::vector<std::array<int, 4>> blocks;  // offset, size, first stage, last stage
   int top = 0;
   for (int v : order) {
-    const int e = P.vals[v].ext;
-    const int sz = (tw + 2 * e) * (th + 2 * e);
+    int rw, co;
+    value_geometry(P, v, tw, &rw, &co);
+    const int sz = (rw * (th + 2 * P.vals[v].ext) + 3) / 4 * 4;
     const int d = L.def_stage[v], l = std::max(L.last_lds[v], d);
     std::vector<std::array<int, 2>> busy;
     for (auto& b : blocks)
@@ -377,20 +404,71 @@ int place_lds(const GProg& P, Layout& L, int tw, int th) {
   return top;
 }
 
+// Load group input v into LDS.  Interior tiles read whole 16-byte chunks
+// (every chunk holds a byte of the extent, so it lies inside the row's
+// pitch, a multiple of 64 bytes): one vector load per chunk, all of a
+// thread's loads issued before the first LDS write.  Edge tiles read
+// element by element inside the image (or the periodic copies under REPEAT).
+void emit_load(Text& t, const GProg& P, const Layout& L, int v, int TW, int TH) {
+  const GVal& gv = P.vals[v];
+  const int e = gv.ext, bpp = df_bytes(gv.df);
+  int rw, co;
+  value_geometry(P, v, TW, &rw, &co);
+  const int rows = TH + 2 * e, epc = 16 / bpp, cpr = rw / epc, nch = cpr * rows;
+  const int kc = (nch + kGenThreads - 1) / kGenThreads;
+  const int off = L.lds_off[v];
+  t("  {  // load value %d: %d rows of %d columns (%d of halo)", v, rows, rw, e);
+  t("    const uint8_t* base = (const uint8_t*)io.ptr[%d];", gv.io);
+  t("    const int64_t pitch = io.pitch[%d];", gv.io);
+  t("    if constexpr (IN) {");
+  t("      uint4 d[%d];", kc);
+  t("#pragma unroll");
+  t("      for (int k = 0; k < %d; ++k) {", kc);
+  t("        const int c = (int)threadIdx.x + k * %d;", kGenThreads);
+  t("        if (c < %d) {", nch);
+  t("          const int row = c / %d, q = c - row * %d;", cpr, cpr);
+  t("          d[k] = *(const uint4*)(base + (size_t)(ty0 - %d + row) * pitch + (size_t)(tx0 - %d) * %d + q * 16);", e,
+    co, bpp);
+  t("        }");
+  t("      }");
+  t("#pragma unroll");
+  t("      for (int k = 0; k < %d; ++k) {", kc);
+  t("        const int c = (int)threadIdx.x + k * %d;", kGenThreads);
+  t("        if (c < %d) {", nch);
+  t("          const int row = c / %d, q = c - row * %d;", cpr, cpr);
+  t("          int4* dst = (int4*)(L + %d + row * %d + q * %d);", off, rw, epc);
+  t("#pragma unroll");
+  t("          for (int j = 0; j < %d; j += 4)", epc);
+  t("            dst[j / 4] = make_int4(gx_elem<%d>(d[k], j), gx_elem<%d>(d[k], j + 1), gx_elem<%d>(d[k], j + 2),", gv.df,
+    gv.df, gv.df);
+  t("                                   gx_elem<%d>(d[k], j + 3));", gv.df);
+  t("        }");
+  t("      }");
+  t("    } else {");
+  t("      for (int i = (int)threadIdx.x; i < %d; i += %d) {", rw * rows, kGenThreads);
+  t("        const int ly = i / %d, lx = i - ly * %d;", rw, rw);
+  t("        const int x = tx0 - %d + lx, y = ty0 - %d + ly;", co, e);
+  t("        if (lx < %d || lx >= %d) continue;  // outside the extent", co - e, co + TW + e);
+  if (gv.wrap)
+    t("        L[%d + i] = gload(%d, base, pitch, repeat_pos(x, W), repeat_pos(y, H));", off, gv.df);
+  else
+    t("        if (x >= 0 && y >= 0 && x < W && y < H) L[%d + i] = gload(%d, base, pitch, x, y);", off, gv.df);
+  t("      }");
+  t("    }");
+  t("  }");
+}
+
 bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::string* why) {
   Layout L;
   plan_stages(P, L);
-  int nred = 0, nhist = 0;
-  for (int k = 0; k < P.nops; ++k) {
-    nred += is_reduce_op(P.ops[k].kind) ? 1 : 0;
-    nhist += (P.ops[k].kind == OP_HISTOGRAM || P.ops[k].kind == OP_EQHIST) ? 1 : 0;
-  }
+  int nred = 0;
+  for (int k = 0; k < P.nops; ++k) nred += is_reduce_op(P.ops[k].kind) ? 1 : 0;
   const bool red = nred > 0;
   const int hist_words = red ? kHistWords : 0;
   static const int shapes[][2] = {{128, 16}, {64, 16}, {64, 8}, {32, 8}, {32, 4}, {16, 4}};
   int TW = 0, TH = 0;
   if (tw_req > 0) {
-    if (place_lds(P, L, tw_req, th_req) + hist_words <= kGenLdsBytes / 4) {
+    if (tw_req % 16 == 0 && th_req > 0 && place_lds(P, L, tw_req, th_req) + hist_words <= kGenLdsBytes / 4) {
       TW = tw_req;
       TH = th_req;
     }
@@ -408,40 +486,22 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   }
   int emax = 0;
   for (int v = 0; v < P.nvals; ++v) emax = std::max(emax, P.vals[v].ext);
-  const int LW = std::max(1, L.lds_words + hist_words);
+  const int LW = std::max(4, L.lds_words + hist_words);
 
   Text t;
   bool ok = true;
   emit_prelude(t, P, why, &ok);
   if (!ok) return false;
-  (void)nhist;
   // one tile: IN = its halo lies inside the image
   t("template <bool IN>");
   t("__device__ __forceinline__ void gen_tile(const IOTable& io, int W, int H, int tx0, int ty0, int32_t* L%s) {",
     red ? ", RedState& rs" : "");
-  // load stage
   bool loads = false;
-  for (int v = 0; v < P.nvals; ++v) {
-    const GVal& gv = P.vals[v];
-    if (!gv.input || !L.needs_lds[v]) continue;
-    loads = true;
-    const int e = gv.ext, rw = TW + 2 * e, rh = TH + 2 * e;
-    t("  {  // load value %d with a halo of %d", v, e);
-    t("    const uint8_t* base = (const uint8_t*)io.ptr[%d];", gv.io);
-    t("    const int64_t pitch = io.pitch[%d];", gv.io);
-    t("    for (int i = (int)threadIdx.x; i < %d; i += %d) {", rw * rh, kGenThreads);
-    t("      const int ly = i / %d, lx = i - ly * %d;", rw, rw);
-    t("      const int x = tx0 - %d + lx, y = ty0 - %d + ly;", e, e);
-    if (gv.wrap) {
-      t("      if (IN) L[%d + i] = gload(%d, base, pitch, x, y);", L.lds_off[v], gv.df);
-      t("      else L[%d + i] = gload(%d, base, pitch, repeat_pos(x, W), repeat_pos(y, H));", L.lds_off[v], gv.df);
-    } else {
-      t("      if (IN || (x >= 0 && y >= 0 && x < W && y < H)) L[%d + i] = gload(%d, base, pitch, x, y);", L.lds_off[v],
-        gv.df);
+  for (int v = 0; v < P.nvals; ++v)
+    if (P.vals[v].input && L.needs_lds[v]) {
+      emit_load(t, P, L, v, TW, TH);
+      loads = true;
     }
-    t("    }");
-    t("  }");
-  }
   if (loads) t("  __syncthreads();");
   int slot = 0;
   for (int s = 0; s < L.nstages; ++s) {
@@ -458,6 +518,12 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
       if (ES > 0) t("    const bool own = lx >= %d && lx < %d && ly >= %d && ly < %d;", ES, ES + TW, ES, ES + TH);
       else t("    const bool own = true;");
     }
+    // the LDS word of value v at this position plus (dx, dy)
+    auto lds_at = [&](int v, const char* dx, const char* dy) {
+      int rw, co;
+      value_geometry(P, v, TW, &rw, &co);
+      return fmt("L[%d + (ly + %d + %s) * %d + (lx + %d + %s)]", L.lds_off[v], P.vals[v].ext - ES, dy, rw, co - ES, dx);
+    };
     for (int k = 0; k < P.nops; ++k) {
       if (L.op_stage[k] != s) continue;
       const GOp& o = P.ops[k];
@@ -468,10 +534,7 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
         switch (L.src[k][i]) {
           case S_REG: return fmt("v%d", v);
           case S_GLB: return fmt("gload(%d, io.ptr[%d], io.pitch[%d], x, y)", P.vals[v].df, P.vals[v].io, P.vals[v].io);
-          default: {
-            const int e = P.vals[v].ext, rw = TW + 2 * e;
-            return fmt("L[%d + (ly + %d) * %d + (lx + %d)]", L.lds_off[v], e - ES, rw, e - ES);
-          }
+          default: return lds_at(v, "0", "0");
         }
       };
       if (is_reduce_op(o.kind)) {
@@ -485,15 +548,15 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
       else t("    {");
       if (is_local(o.kind)) {
         const int v = o.in[0];
-        const int e = P.vals[v].ext, rw = TW + 2 * e;
+        int rw, co;
+        value_geometry(P, v, TW, &rw, &co);
         // the border constant as the input's element bits
         uint32_t cval = (uint32_t)o.cint;
         if (P.vals[v].df == DF_F32) memcpy(&cval, &o.cf, 4);
-        t("      const int b = %d + (ly + %d) * %d + (lx + %d);", L.lds_off[v], e - ES, rw, e - ES);
         t("      auto rd = [&](int dx, int dy) -> int {");
-        t("        if constexpr (IN) return L[b + dy * %d + dx];", rw);
-        t("        else return gx_rd<%d>(L + %d, %d, %d, tx0, ty0, W, H, x + dx, y + dy, (int)0x%08xu);", o.border,
-          L.lds_off[v], rw, e, cval);
+        t("        if constexpr (IN) return %s;", lds_at(v, "dx", "dy").c_str());
+        t("        else return gx_rd<%d>(L + %d, %d, %d, %d, tx0, ty0, W, H, x + dx, y + dy, (int)0x%08xu);", o.border,
+          L.lds_off[v], rw, P.vals[v].ext, co, cval);
         t("      };");
         if (o.kind == OP_EXPR_LOCAL) t("      v%d = gx_expr%d(rd);", o.out, k);
         else t("      v%d = local_eval<%s>(gop%d, %d, rd);", o.out, o.kind == OP_NONLINEAR ? "true" : "false", k, ov.df);
@@ -505,10 +568,7 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
         t("      v%d = point_eval(gop%d, %d, %s, %s, %s, %s);", o.out, k, ov.df,
           P.vals[o.in[0]].df == DF_F32 ? "true" : "false", at(0).c_str(), at(1).c_str(), at(2).c_str());
       }
-      if (L.needs_lds[o.out]) {
-        const int e = ov.ext, rw = TW + 2 * e;
-        t("      L[%d + (ly + %d) * %d + (lx + %d)] = v%d;", L.lds_off[o.out], e - ES, rw, e - ES, o.out);
-      }
+      if (L.needs_lds[o.out]) t("      %s = v%d;", lds_at(o.out, "0", "0").c_str(), o.out);
       if (ov.store) t("      if (own) gstore(%d, io.ptr[%d], io.pitch[%d], x, y, v%d);", ov.df, ov.io, ov.io, o.out);
       t("    }");
     }
@@ -518,7 +578,7 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   t("}");
   t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io) {",
     kGenThreads);
-  t("  __shared__ int32_t L[%d];", LW);
+  t("  __shared__ __attribute__((aligned(16))) int32_t L[%d];", LW);
   t("  const int W = P->w, H = P->h;");
   t("  const int tiles_x = (W + %d) / %d;", TW - 1, TW);
   t("  const int ntiles = tiles_x * ((H + %d) / %d);", TH - 1, TH);
