@@ -110,6 +110,8 @@ typedef int32_t hvx_status;
 #define HVX_QUERY_OP_LIVE_MASK 9   /* bit i set: lowered operator i is live (first 63 operators) */
 #define HVX_QUERY_ROWS_PER_ITEM 10 /* rows per work item of the first kernel */
 #define HVX_QUERY_NUM_GENERATED 11 /* kernels of the plan generated for their group (HVX_OPT_CODEGEN) */
+#define HVX_QUERY_PLAN_CUTS 12     /* values at which the plan choice in force cuts fusion */
+#define HVX_QUERY_GEN_TILE 13      /* tile of the first generated tile kernel: width << 16 | height (0: none) */
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -386,9 +388,17 @@ hvx_status hvx_graph_wait(hvx_graph g);
  * verification, INVALID_PARAMETERS for an unknown attribute. */
 hvx_status hvx_graph_query(hvx_graph g, int attr, int64_t* out);
 
-/* Time candidate launch configurations of the verified graph on the device
- * (`iters` timed runs each, outputs checked equal across candidates), keep the
- * fastest in the context's tune cache and re-plan with it. */
+/* Time candidate plans of the graph on the device and keep the fastest in
+ * the context's tune cache (`iters` timed runs each; every candidate's
+ * outputs must equal those of the plan in force before tuning, bit for bit,
+ * else the call fails).  Candidates (Section 6.3): the fused plan, each plan
+ * that cuts fusion at one value inside a fused group, the plan that cuts at
+ * all of them, then the tile of each generated kernel; for a plan of one
+ * hand-fused kernel, its rows per work item and XCD mapping.  The plan choice
+ * is recorded under the graph's operator signature, so any graph built the
+ * same way (same operators, borders, formats and sizes, same options) is
+ * verified with it; the launch shape under the graph's kernel signature.
+ * The graph is re-planned: batches built on it must be created again. */
 hvx_status hvx_graph_autotune(hvx_graph g, void* hip_stream, int iters);
 /* Tune cache as JSON text keyed by device, graph signature and size. */
 hvx_status hvx_context_save_tune_cache(hvx_context ctx, const char* path);

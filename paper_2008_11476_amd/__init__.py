@@ -34,7 +34,7 @@ HVX_CHANNEL_Y = 0
 HVX_OPT_FUSION, HVX_OPT_DCE, HVX_OPT_TILE, HVX_OPT_SPECIALIZE, HVX_OPT_XCD_REMAP, HVX_OPT_CODEGEN = 1, 2, 3, 4, 5, 6
 (HVX_QUERY_NUM_NODES, HVX_QUERY_NUM_OPS, HVX_QUERY_NUM_LIVE_OPS, HVX_QUERY_NUM_KERNELS, HVX_QUERY_ALG_BYTES,
  HVX_QUERY_HBM_BYTES, HVX_QUERY_KERNEL_KIND, HVX_QUERY_SCRATCH_BYTES, HVX_QUERY_OP_LIVE_MASK,
- HVX_QUERY_ROWS_PER_ITEM, HVX_QUERY_NUM_GENERATED) = range(1, 12)
+ HVX_QUERY_ROWS_PER_ITEM, HVX_QUERY_NUM_GENERATED, HVX_QUERY_PLAN_CUTS, HVX_QUERY_GEN_TILE) = range(1, 14)
 HVX_SERVER_CONTINUOUS, HVX_SERVER_PLAIN = 0, 1
 HVX_BATCH_PERSISTENT, HVX_BATCH_USE_GRAPH, HVX_BATCH_ROWS = 1, 2, 3
 

@@ -851,6 +851,10 @@ hvx_status hvx_graph_query(hvx_graph graph, int attr, int64_t* out) {
       *out = (p.groups.empty() || !is_strip_kind(p.groups[0].kind)) ? 0 : rows_for(g, p.groups[0]);
       break;
     case HVX_QUERY_NUM_GENERATED: *out = p.num_generated; break;
+    case HVX_QUERY_PLAN_CUTS: *out = (int64_t)p.cuts.size(); break;
+    case HVX_QUERY_GEN_TILE:
+      *out = p.tiles.empty() ? 0 : ((int64_t)p.tiles[0][1] << 16 | p.tiles[0][2]);
+      break;
     default: return set_error(g->ctx, HVX_ERROR_INVALID_PARAMETERS, "unknown query %d", attr);
   }
   return HVX_SUCCESS;

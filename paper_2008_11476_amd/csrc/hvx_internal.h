@@ -2,6 +2,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -19,6 +20,7 @@ enum ObjType : uint32_t { T_CONTEXT = 0x5a01, T_GRAPH, T_IMAGE, T_NODE, T_CONV, 
 struct Context;
 struct Graph;
 struct GenKernel;  // codegen.h
+struct TuneEntry;
 
 struct Object {
   uint32_t type;
@@ -147,6 +149,9 @@ struct Plan {
   int num_nodes = 0, num_ops = 0, num_live = 0;
   int64_t alg_bytes = 0, hbm_bytes = 0, scratch_bytes = 0;
   int num_generated = 0;  // groups run by generated kernels
+  std::string op_key;     // operator signature: the tune-cache key of plan choices
+  std::vector<int> cuts;  // values at which fusion was cut (plan choice)
+  std::vector<std::array<int, 3>> tiles;  // tiles of generated groups (plan choice)
   std::string gen_note;   // why a group was left to the interpreter (last case)
   std::vector<int> topo;  // live op order
 };
@@ -156,6 +161,9 @@ struct Graph : Object {
   std::vector<Image*> virt;
   bool verified = false;
   int opt_fusion = 1, opt_dce = 1, opt_tile = 0, opt_specialize = 1, opt_xcd = 1, opt_codegen = 1;
+  // plan choice in force for the next verification (set by the tuner while
+  // it times candidates); null: the tune cache's choice for the graph, if any
+  const TuneEntry* plan_choice = nullptr;
   std::unique_ptr<Plan> plan;
   // device state: the materialised values live in one block of scratch_total
   // bytes, value v at scratch_off[v] with row pitch scratch_pitch[v] (0: not
@@ -174,6 +182,12 @@ struct TuneEntry {
   int rows = 0;
   int xcd = 1;
   double us = 0;
+  // a plan choice (key "plan|" + the operator signature): the values at
+  // which fusion is cut and the tiles of generated groups (first operator,
+  // width, height)
+  bool has_plan = false;
+  std::vector<int> cuts;
+  std::vector<std::array<int, 3>> tiles;
 };
 
 struct Context : Object {

@@ -2,11 +2,13 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <chrono>
 #include <fstream>
+#include <set>
 #include <sstream>
 
 #include "global.h"
@@ -752,48 +754,155 @@ static hvx_status read_outputs(Graph* g, hipStream_t st, std::vector<std::vector
   return HVX_SUCCESS;
 }
 
-hvx_status hvx_graph_autotune(hvx_graph hg, void* stream, int iters) {
-  if (!registry_check(hg, T_GRAPH)) return HVX_ERROR_INVALID_REFERENCE;
-  Graph* g = (Graph*)hg;
-  if (iters < 1) iters = 1;
-  if (!g->verified) {
-    hvx_status s = verify_graph(g);
-    if (s) return s;
-  }
-  hvx_status s = prepare_graph(g);
+// Time `iters` schedules of the graph as planned now, after one checked
+// run: its outputs must equal `ref` (or become `ref` when it is empty).
+static hvx_status time_plan(Graph* g, hipStream_t st, int iters, std::vector<std::vector<uint8_t>>* ref,
+                            double* us, const char* what) {
+  hvx_status s = schedule_graph(g, st);
+  if (!s && hipStreamSynchronize(st) != hipSuccess) s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune sync failed");
+  std::vector<std::vector<uint8_t>> cur;
+  if (!s) s = read_outputs(g, st, ref->empty() ? ref : &cur);
+  if (!s && !cur.empty() && cur != *ref) s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune candidate %s changed the output", what);
   if (s) return s;
-  Plan& p = *g->plan;
-  if (p.groups.size() != 1 || !is_strip_kind(p.groups[0].kind)) return HVX_SUCCESS;  // nothing to tune
-  Group& gr = p.groups[0];
-  const int saved_rows = gr.rows, saved_xcd = gr.xcd;
-  hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  std::vector<std::vector<uint8_t>> ref, cur;
+  (void)hipEventRecord(e0, st);
+  for (int i = 0; i < iters && !s; ++i) s = schedule_graph(g, st);
+  (void)hipEventRecord(e1, st);
+  (void)hipEventSynchronize(e1);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1000.0 * ms / iters;
+  return s;
+}
+
+// Re-plan the graph under plan choice `c` (null: none) and prepare it.
+static hvx_status replan(Graph* g, const TuneEntry* c) {
+  free_graph_device(g);
+  g->plan_choice = c;
+  hvx_status s = verify_graph(g);
+  g->plan_choice = nullptr;
+  if (!s) s = prepare_graph(g);
+  return s;
+}
+
+// Plan choices (Section 6.3: whether fusing pays off depends on the
+// operators and the device): the fused plan, every plan that cuts fusion at
+// one value inside a fused group, and the plan that cuts at all of them;
+// then, for the fastest, the tile of each generated group.  Every candidate
+// must reproduce the outputs of the first one bit for bit.
+static hvx_status tune_plan(Graph* g, hipStream_t st, int iters, std::vector<std::vector<uint8_t>>* ref,
+                            TuneEntry* best) {
+  const Plan& p0 = *g->plan;
+  std::vector<int> internal;
+  for (const Group& gr : p0.groups) {
+    if (gr.ops.size() < 2) continue;
+    std::set<int> ops(gr.ops.begin(), gr.ops.end());
+    for (int o : gr.ops) {
+      const int v = p0.ops[o].out;
+      bool inside = false;
+      for (int c : p0.vals[v].consumers) inside |= ops.count(c) > 0;
+      if (inside) internal.push_back(v);
+    }
+  }
+  std::vector<TuneEntry> cands(1);
+  if (g->opt_fusion && !internal.empty()) {
+    for (int v : internal) {
+      cands.emplace_back();
+      cands.back().cuts = {v};
+    }
+    if (internal.size() > 1) {
+      cands.emplace_back();
+      cands.back().cuts = internal;
+    }
+  }
+  hvx_status s = HVX_SUCCESS;
+  best->us = 1e30;
+  for (TuneEntry& c : cands) {
+    c.has_plan = true;
+    double us = 0;
+    s = replan(g, &c);
+    if (!s) s = time_plan(g, st, iters, ref, &us, "plan");
+    if (s) return s;
+    if (us < best->us) {
+      *best = c;
+      best->us = us;
+    }
+  }
+  // tiles of the generated groups of the chosen plan, one group at a time
+  s = replan(g, best);
+  if (s) return s;
+  std::vector<int> firsts;
+  for (const auto& t : g->plan->tiles) firsts.push_back(t[0]);
+  static const int shapes[][2] = {{128, 16}, {64, 16}, {64, 32}, {128, 8}, {256, 8}, {32, 16}};
+  for (int first : firsts) {
+    for (auto& sh : shapes) {
+      TuneEntry c = *best;
+      bool found = false;
+      for (auto& t : c.tiles)
+        if (t[0] == first) {
+          t[1] = sh[0];
+          t[2] = sh[1];
+          found = true;
+        }
+      if (!found) c.tiles.push_back({first, sh[0], sh[1]});
+      double us = 0;
+      s = replan(g, &c);
+      if (s) return s;
+      bool applied = false;  // the shape fits the group's LDS budget
+      for (const auto& t : g->plan->tiles) applied |= t[0] == first && t[1] == sh[0] && t[2] == sh[1];
+      if (!applied) continue;
+      s = time_plan(g, st, iters, ref, &us, "tile");
+      if (s) return s;
+      if (us < best->us) {
+        *best = c;
+        best->us = us;
+      }
+    }
+  }
+  return HVX_SUCCESS;
+}
+
+hvx_status hvx_graph_autotune(hvx_graph hg, void* stream, int iters) {
+  if (!registry_check(hg, T_GRAPH)) return HVX_ERROR_INVALID_REFERENCE;
+  Graph* g = (Graph*)hg;
+  std::lock_guard<std::recursive_mutex> lock(g->ctx->mu);
+  if (iters < 1) iters = 1;
+  hipStream_t st = (hipStream_t)stream;
+  // the outputs of the plan in force before tuning: every candidate must reproduce them
+  std::vector<std::vector<uint8_t>> ref;
+  hvx_status s = replan(g, nullptr);
+  double us0 = 0;
+  if (!s) s = time_plan(g, st, 1, &ref, &us0, "default");
+  if (s) return s;
+  TuneEntry plan;
+  s = tune_plan(g, st, iters, &ref, &plan);
+  if (!s) {
+    g->ctx->tune["plan|" + g->plan->op_key] = plan;
+    s = replan(g, nullptr);  // the graph runs the recorded choice from here on
+  }
+  if (s) return s;
+  Plan& p = *g->plan;
+  if (p.groups.size() != 1 || !is_strip_kind(p.groups[0].kind)) return HVX_SUCCESS;  // no launch shape to tune
+  // rows per work item and the XCD mapping of a hand-fused kernel
+  Group& gr = p.groups[0];
+  const int saved_rows = gr.rows, saved_xcd = gr.xcd;
   double best_us = 1e30;
   int best_rows = 0, best_xcd = 1;
   static const int cand_rows[] = {4, 8, 16, 32, 64, 128};
   for (int rows : cand_rows) {
     if (rows > (int)gr.h * 2 && rows != 4) continue;
-    for (int xcd = 0; xcd <= 1; ++xcd) {
+    for (int xcd = 0; xcd <= 1 && !s; ++xcd) {
       gr.rows = rows;
       gr.xcd = xcd;
-      s = schedule_graph(g, st);  // warm-up, also the output check
-      if (!s && hipStreamSynchronize(st) != hipSuccess) s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune sync failed");
-      if (!s) s = read_outputs(g, st, ref.empty() ? &ref : &cur);
-      if (!s && !cur.empty() && cur != ref)
-        s = set_error(g->ctx, HVX_ERROR_DEVICE, "tune candidate rows=%d xcd=%d changed the output", rows, xcd);
-      cur.clear();
-      if (s) break;
-      (void)hipEventRecord(e0, st);
-      for (int i = 0; i < iters && !s; ++i) s = schedule_graph(g, st);
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      double us = 1000.0 * ms / iters;
-      if (us < best_us) {
+      double us = 0;
+      char what[48];
+      snprintf(what, sizeof what, "rows=%d xcd=%d", rows, xcd);
+      s = time_plan(g, st, iters, &ref, &us, what);
+      if (!s && us < best_us) {
         best_us = us;
         best_rows = rows;
         best_xcd = xcd;
@@ -801,8 +910,6 @@ hvx_status hvx_graph_autotune(hvx_graph hg, void* stream, int iters) {
     }
     if (s) break;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   gr.rows = saved_rows;
   gr.xcd = saved_xcd;
   if (s) return s;
@@ -814,7 +921,8 @@ hvx_status hvx_graph_autotune(hvx_graph hg, void* stream, int iters) {
   return HVX_SUCCESS;
 }
 
-// Tune cache file: one JSON object, {"key": [rows, xcd, microseconds], ...}.
+// Tune cache file: one JSON object, {"key": [rows, xcd, microseconds], ...}; a plan
+// choice adds its cut values and generated tiles: [..., [cuts], [[first, w, h], ...]].
 hvx_status hvx_context_save_tune_cache(hvx_context ctx, const char* path) {
   if (!registry_check(ctx, T_CONTEXT)) return HVX_ERROR_INVALID_REFERENCE;
   Context* c = (Context*)ctx;
@@ -829,8 +937,17 @@ hvx_status hvx_context_save_tune_cache(hvx_context ctx, const char* path) {
       if (ch == '"' || ch == '\\') k += '\\';
       k += ch;
     }
-    f << (first ? "" : ",") << "\n  \"" << k << "\": [" << kv.second.rows << ", " << kv.second.xcd << ", "
-      << kv.second.us << "]";
+    const TuneEntry& e = kv.second;
+    f << (first ? "" : ",") << "\n  \"" << k << "\": [" << e.rows << ", " << e.xcd << ", " << e.us;
+    if (e.has_plan) {  // plan choice: [cut values], [[first operator, tile width, tile height], ...]
+      f << ", [";
+      for (size_t i = 0; i < e.cuts.size(); ++i) f << (i ? ", " : "") << e.cuts[i];
+      f << "], [";
+      for (size_t i = 0; i < e.tiles.size(); ++i)
+        f << (i ? ", " : "") << "[" << e.tiles[i][0] << ", " << e.tiles[i][1] << ", " << e.tiles[i][2] << "]";
+      f << "]";
+    }
+    f << "]";
     first = false;
   }
   f << "\n}\n";
@@ -857,12 +974,43 @@ hvx_status hvx_context_load_tune_cache(hvx_context ctx, const char* path) {
       if (t[j] == '\\' && j + 1 < t.size()) ++j;
       key += t[j];
     }
-    size_t lb = t.find('[', j), rb = t.find(']', j);
-    if (lb == std::string::npos || rb == std::string::npos || rb < lb)
+    // the entry's list, brackets matched: [rows, xcd, us] or, for a plan
+    // choice, [rows, xcd, us, [cuts], [[first, width, height], ...]]
+    size_t lb = t.find('[', j), rb = std::string::npos;
+    int depth = 0;
+    for (size_t z = lb; lb != std::string::npos && z < t.size(); ++z) {
+      if (t[z] == '[') ++depth;
+      if (t[z] == ']' && --depth == 0) {
+        rb = z;
+        break;
+      }
+    }
+    if (lb == std::string::npos || rb == std::string::npos)
       return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "malformed tune cache %s", path);
     TuneEntry e;
     if (sscanf(t.c_str() + lb + 1, "%d , %d , %lf", &e.rows, &e.xcd, &e.us) != 3)
       return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "malformed tune entry for %s", key.c_str());
+    const size_t inner = t.find('[', lb + 1);
+    if (inner != std::string::npos && inner < rb) {
+      // numbers of the two inner lists, in order
+      std::vector<std::vector<int>> lists(1);
+      int d = 0;
+      for (size_t z = inner; z < rb; ++z) {
+        if (t[z] == '[') ++d;
+        else if (t[z] == ']') {
+          if (--d == 0) lists.emplace_back();
+        } else if (t[z] == '-' || (t[z] >= '0' && t[z] <= '9')) {
+          char* end = nullptr;
+          lists.back().push_back((int)strtol(t.c_str() + z, &end, 10));
+          z = (size_t)(end - t.c_str()) - 1;
+        }
+      }
+      if (lists.size() < 3 || lists[1].size() % 3 != 0)
+        return set_error(c, HVX_ERROR_INVALID_PARAMETERS, "malformed plan choice for %s", key.c_str());
+      e.has_plan = true;
+      e.cuts = lists[0];
+      for (size_t q = 0; q + 2 < lists[1].size(); q += 3) e.tiles.push_back({lists[1][q], lists[1][q + 1], lists[1][q + 2]});
+    }
     c->tune[key] = e;
     ++n;
     i = rb + 1;

@@ -827,6 +827,34 @@ hvx_status verify_graph(Graph* g) {
     }
   if (p.num_live == 0) return err(g, HVX_ERROR_INVALID_GRAPH, "no operator reaches a non-virtual image");
 
+  // ---- plan choice ----
+  // The operator signature keys the tuner's plan choices: it names every
+  // live operator with its border and the values it reads and writes, and
+  // every value's format, size and kind, so a choice recorded for one graph
+  // applies to any graph built the same way.
+  {
+    std::string key;
+    char buf[96];
+    snprintf(buf, sizeof buf, "f%d.s%d.c%d:", g->opt_fusion, g->opt_specialize, g->opt_codegen);
+    key += buf;
+    for (int o : p.topo) {
+      const LOp& op = p.ops[o];
+      snprintf(buf, sizeof buf, "%d.%d(%d,%d,%d>%d)", op.kind, op.border, op.in[0], op.in[1], op.in[2], op.out);
+      key += buf;
+    }
+    key += "|";
+    for (const Value& v : p.vals) {
+      snprintf(buf, sizeof buf, "%d.%ux%u%s,", v.df, v.w, v.h, v.is_virtual ? "v" : "");
+      key += buf;
+    }
+    p.op_key = key;
+  }
+  const TuneEntry* choice = g->plan_choice;
+  if (!choice) {
+    auto it = g->ctx->tune.find("plan|" + p.op_key);
+    if (it != g->ctx->tune.end() && it->second.has_plan) choice = &it->second;
+  }
+
   // ---- 5: grouping ----
   // A global operator's result is complete only once every pixel has been
   // seen, so whatever reads it runs in a later kernel.  The phase of an
@@ -843,6 +871,12 @@ hvx_status verify_graph(Graph* g) {
   // Fusion on: one group per weakly connected component of live operators
   // of one phase (the location pass of MinMaxLoc alone).  Fusion off: one
   // group per operator ("node by node").
+  // A plan choice may cut fusion at some values: their producer and
+  // consumers then fuse only through other values.
+  std::set<int> cuts;
+  if (choice)
+    for (int v : choice->cuts)
+      if (v >= 0 && v < (int)p.vals.size()) cuts.insert(v);
   std::vector<int> comp(p.ops.size(), -1);
   if (g->opt_fusion) {
     std::vector<int> parent(p.ops.size());
@@ -852,7 +886,8 @@ hvx_status verify_graph(Graph* g) {
       if (p.ops[o].kind == OP_MMLOCS) continue;
       for (int k = 0; k < p.ops[o].nin; ++k) {
         int pr = p.vals[p.ops[o].in[k]].producer;
-        if (pr >= 0 && p.ops[pr].live && phase[pr] == phase[o] && !is_global_op(p.ops[pr].kind))
+        if (pr >= 0 && p.ops[pr].live && phase[pr] == phase[o] && !is_global_op(p.ops[pr].kind) &&
+            !cuts.count(p.ops[o].in[k]))
           parent[find(o)] = find(pr);
       }
     }
@@ -916,12 +951,45 @@ hvx_status verify_graph(Graph* g) {
     }
     final_groups.push_back(gr);
   }
-  // launch order: by phase, then by first operator (a group depends only on
-  // groups of an earlier phase or, within a phase, on earlier operators)
-  std::stable_sort(final_groups.begin(), final_groups.end(), [](const Group& a, const Group& b) {
-    return a.phase != b.phase ? a.phase < b.phase : a.ops[0] < b.ops[0];
-  });
+  // launch order: every group after the groups whose values it reads (of
+  // the groups ready at each step, the one of the earliest phase, then of
+  // the earliest first operator)
+  {
+    std::vector<int> owner(p.ops.size(), -1);
+    for (size_t i = 0; i < final_groups.size(); ++i)
+      for (int o : final_groups[i].ops) owner[o] = (int)i;
+    const size_t n = final_groups.size();
+    std::vector<std::set<int>> succ(n);
+    std::vector<int> indeg(n, 0);
+    for (size_t i = 0; i < n; ++i)
+      for (int o : final_groups[i].ops)
+        for (int k = 0; k < p.ops[o].nin; ++k) {
+          const int pr = p.vals[p.ops[o].in[k]].producer;
+          if (pr < 0 || owner[pr] < 0 || owner[pr] == (int)i) continue;
+          if (succ[owner[pr]].insert((int)i).second) ++indeg[i];
+        }
+    std::vector<Group> ordered;
+    std::vector<bool> done(n, false);
+    for (size_t step = 0; step < n; ++step) {
+      int best = -1;
+      for (size_t i = 0; i < n; ++i) {
+        if (done[i] || indeg[i]) continue;
+        const Group& a = final_groups[i];
+        if (best < 0 || a.phase < final_groups[best].phase ||
+            (a.phase == final_groups[best].phase && a.ops[0] < final_groups[best].ops[0]))
+          best = (int)i;
+      }
+      if (best < 0)
+        return err(g, HVX_ERROR_INVALID_GRAPH,
+                   "the plan choice for this graph makes its kernels depend on each other in a cycle");
+      done[best] = true;
+      ordered.push_back(final_groups[best]);
+      for (int j : succ[best]) --indeg[j];
+    }
+    final_groups.swap(ordered);
+  }
   p.groups.swap(final_groups);
+  p.cuts.assign(cuts.begin(), cuts.end());
   for (auto& v : p.vals) v.materialize = false;
   for (auto& gr : p.groups) finish_group(gr);
 
@@ -955,7 +1023,17 @@ hvx_status verify_graph(Graph* g) {
     // (Section 6); the interpreter runs the group if it cannot be made
     if (g->opt_codegen && gen_wanted(gr.prog)) {
       GenSource src;
-      if (gen_source(gr.prog, 0, 0, &src, &why)) gr.gen = gen_compile(src, &why);
+      int tw = 0, th = 0;
+      if (choice)
+        for (const auto& t : choice->tiles)
+          if (t[0] == gr.ops[0]) {
+            tw = t[1];
+            th = t[2];
+          }
+      // a chosen tile that does not fit falls back to the default one
+      if (!(tw && gen_source(gr.prog, tw, th, &src, &why)) && !gen_source(gr.prog, 0, 0, &src, &why)) src.text.clear();
+      if (!src.text.empty()) gr.gen = gen_compile(src, &why);
+      if (gr.gen && src.form == GEN_TILES) p.tiles.push_back({gr.ops[0], src.tw, src.th});
       if (gr.gen) {
         ++p.num_generated;
       } else {

@@ -321,6 +321,22 @@ def test_tune_cache_roundtrip(ctx, tmp_path):
     assert '"gfx950|k1:3840x2160:3.2.0,": [32, 1, 12.5]' in q.read_text()
 
 
+def test_tune_cache_plan_choice_roundtrip(ctx, tmp_path):
+    """A plan choice (cut values and generated tiles) survives a save and a
+    load; malformed plan lists are refused."""
+    p = tmp_path / "tune.json"
+    key = "plan|f1.s1.c1:2.2(0,-1,-1>1)20.2(0,1,-1>2)|1.64x48,1.64x48v,2.64x48,"
+    p.write_text('{\n  "%s": [0, 1, 7.25, [1, 5], [[0, 64, 32], [3, 128, 8]]]\n}\n' % key)
+    hvx.hvx_context_load_tune_cache(ctx, str(p))
+    q = tmp_path / "out.json"
+    hvx.hvx_context_save_tune_cache(ctx, str(q))
+    assert '"%s": [0, 1, 7.25, [1, 5], [[0, 64, 32], [3, 128, 8]]]' % key in q.read_text()
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"plan|x": [0, 1, 2.0, [1], [[0, 64]]]}')
+    with pytest.raises(hvx.HvxError):
+        hvx.hvx_context_load_tune_cache(ctx, str(bad))
+
+
 EXPR_CORPUS = ["a", "a + b * c", "-a - -b", "(a + 1) * (b - 2) / 3", "min(a, b)", "max(a, min(b, c))", "abs(a)",
                "clamp(a, 0, 9)", "gt(a, b)", "sel(a, b, c)", "a / 0", "2147483647 + a", "sqrt(a)", "a * 0.5",
                "a +", "a b", "(a", "a)", "min(a)", "max(a, b, c)", "foo(a)", "d", "a ** 2", "a % 2", "a // 2",
