@@ -423,6 +423,26 @@ def global_ops(hvx, torch, ctx, stream, rec):
     torch.cuda.empty_cache()
 
 
+def tuned_plan(hvx, torch, ctx, build, stream, pixels, alg_bytes):
+    """The plan the autotuner picks for a graph (fused, cut at a value, or
+    cut at every value; the generated kernels' tiles), timed like the fixed
+    plans."""
+    g = hvx.hvx_graph_create(ctx)
+    build(g)
+    hvx.hvx_graph_verify(g, ctx=ctx)
+    hvx.hvx_graph_autotune(g, stream, 5, ctx=ctx)
+    ms, _ = time_region(torch, lambda: hvx.hvx_graph_schedule(g, stream, ctx=ctx), 20, 3)
+    tile = hvx.hvx_graph_query(g, hvx.HVX_QUERY_GEN_TILE)
+    r = {"us": round(ms * 1e3, 2), "mpix_s": round(pixels / 1e6 / (ms / 1e3), 1),
+         "kernels": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS),
+         "generated": hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_GENERATED),
+         "cut_values": hvx.hvx_graph_query(g, hvx.HVX_QUERY_PLAN_CUTS),
+         "tile": "%dx%d" % (tile >> 16, tile & 0xFFFF) if tile else None,
+         "alg_gbs": round(alg_bytes / (ms / 1e3) / 1e9, 1)}
+    hvx.hvx_release_graph(g)
+    return r
+
+
 # plans compared by the graph measurements: (label, HVX_OPT_FUSION, HVX_OPT_CODEGEN)
 PLANS = (("fused", 1, 1), ("fused_interpreted", 1, 0), ("node_by_node", 0, 1))
 
@@ -465,6 +485,15 @@ def global_graph(hvx, torch, ctx, rec):
                 "gbs": round(hbm / (ms / 1e3) / 1e9, 1)}
             hvx.hvx_release_graph(g)
         row["fused_speedup"] = round(row["node_by_node"]["us"] / row["fused"]["us"], 2)
+
+        def build(g, name=name, make=make):
+            v = hvx.hvx_image_create_virtual(g)
+            if name.startswith("gauss3"):
+                hvx.hvx_gaussian3x3_node(g, img, v)
+            else:
+                hvx.hvx_gaussian5x5_node(g, img, v)
+            make(g, v)
+        row["tuned"] = tuned_plan(hvx, torch, ctx, build, stream, w * h, w * h)
         d[name] = row
     rec("global_graph_4k", d)
     hvx.hvx_release_image(img)
@@ -537,6 +566,7 @@ def user_kernels(hvx, torch, ctx, rec):
                 "plan_hbm_bytes": hvx.hvx_graph_query(g, hvx.HVX_QUERY_HBM_BYTES)}
             hvx.hvx_release_graph(g)
         row["fused_speedup"] = round(row["node_by_node"]["us"] / row["fused"]["us"], 2)
+        row["tuned"] = tuned_plan(hvx, torch, ctx, build, stream, w * h, 2 * w * h)
         d[name] = row
     rec("user_kernels_4k", d)
     for c in convs:

@@ -740,7 +740,20 @@ static hvx_status read_outputs(Graph* g, hipStream_t st, std::vector<std::vector
   for (size_t v = 0; v < p.vals.size(); ++v) {
     const Value& val = p.vals[v];
     if (val.is_virtual || val.producer < 0 || !p.ops[val.producer].live) continue;
-    const size_t row = (size_t)val.w * df_bytes(val.df);
+    size_t row = (size_t)val.w * df_bytes(val.df);
+    if (val.df == DF_BUF) {
+      // a global operator's result: the words it defines (the rest of the
+      // buffer is the reduction's workspace, whose contents depend on the
+      // launch shape; location lists come in the order pixels were found)
+      const LOp& op = p.ops[val.producer];
+      switch (op.kind) {
+        case OP_HISTOGRAM: row = (size_t)op.gp[0] * 4; break;
+        case OP_MINMAX: row = kMinMaxBytes; break;
+        case OP_MMCOUNT: row = 6 * 4; break;
+        case OP_SUMS: row = kSumsBytes; break;
+        default: continue;
+      }
+    }
     const size_t bytes = row * val.h;
     void* stage = nullptr;
     if (hipHostMalloc(&stage, bytes, 0) != hipSuccess)

@@ -128,3 +128,28 @@ def test_plan_cut_inside_a_diamond_keeps_dependency_order(ctx):
     hvx.hvx_graph_autotune(g1, torch.cuda.current_stream().cuda_stream, 1, ctx=ctx)
     hvx.hvx_graph_process(g1, ctx=ctx)
     assert np.array_equal(_read(keep)["out"], base["out"])
+
+
+def test_autotune_graph_with_global_operators(ctx):
+    """Plans of a producer fused into global operators (and the plan that
+    cuts it off) agree on every result word the operators define; the
+    reductions' workspace words may differ between launch shapes."""
+    import torch
+    from tests import graphspec as gs
+    from tests.test_gpu_global_graph import _check_buffers
+    img = synth.edge_image(1280, 720, seed=2)
+    spec = gs.Spec([gs.N("gaussian5x5", ["in"], ["g"]),
+                    gs.N("histogram", ["g"], ["hist"], params={"bins": 64, "offset": 0, "range": 256}),
+                    gs.N("min_max_loc", ["g"], ["mm", "locs"], params={"capacity": 32}),
+                    gs.N("mean_std_dev", ["g"], ["ms"])],
+                   {"in": img}, {}, buffers={"hist": 8192, "mm": 4128, "locs": 2 * 32 * 8, "ms": 64})
+    env = spec.run_oracle()
+    keep = {}
+    got, g = run_spec(spec, ctx, keep=keep)
+    _check_buffers(spec, got, env)
+    log("tune plan: global operators")
+    hvx.hvx_graph_autotune(g, torch.cuda.current_stream().cuda_stream, 2, ctx=ctx)
+    hvx.hvx_graph_process(g, ctx=ctx)
+    torch.cuda.synchronize()
+    tuned = {name: t.cpu().numpy() for name, t in keep["buffers"].items()}
+    _check_buffers(spec, tuned, env)
