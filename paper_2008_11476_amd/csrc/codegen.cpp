@@ -219,6 +219,13 @@ void emit_prelude(Text& t, const GProg& P, std::string* why, bool* ok) {
   t("  }");
   t("  return L[(y - ty0 + ey) * rw + (x - tx0 + ex)];");
   t("}");
+  // four elements of a row from x on; zero outside the image (edge tiles)
+  t("__device__ __forceinline__ void gx_load4_edge(int df, const void* base, int64_t pitch, int x, int y, int W, int H,");
+  t("                                              int v[4]) {");
+  t("#pragma unroll");
+  t("  for (int q = 0; q < 4; ++q)");
+  t("    v[q] = (y >= 0 && y < H && x + q >= 0 && x + q < W) ? gload(df, base, pitch, x + q, y) : 0;");
+  t("}");
   // element j of a 16-byte chunk of a row in format DF (int bits)
   t("template <int DF>");
   t("__device__ __forceinline__ int gx_elem(const uint4& d, int j) {");
@@ -296,11 +303,21 @@ enum Src { S_REG = 1, S_LDS, S_GLB };
 
 struct Layout {
   int nstages = 0;
-  std::vector<int> op_stage, stage_ext;
+  std::vector<int> op_stage;
+  std::vector<int> stage_ev, stage_eh;  // vertical / horizontal extent of each stage's sweep
   std::vector<int> def_stage, last_lds, needs_lds, producer, lds_off;
+  std::vector<int> eh;  // horizontal extent of each value: a multiple of 4
   std::vector<std::array<int, 3>> src;
   int lds_words = 0;
+  // The border rule the local operators reading a value apply to it, as
+  // (mode, constant bits).  When every such value has one rule, edge tiles
+  // hold each value's positions outside the image resolved by that rule and
+  // run the interior code; otherwise they read through each operator's rule.
+  std::vector<int> bmode, bconst;
+  bool resolved = true;
 };
+
+int round4(int x) { return (x + 3) / 4 * 4; }
 
 void plan_stages(const GProg& P, Layout& L) {
   const int nv = P.nvals, no = P.nops;
@@ -348,26 +365,57 @@ void plan_stages(const GProg& P, Layout& L) {
       if (L.src[k][i] == S_LDS) L.last_lds[v] = std::max(L.last_lds[v], L.op_stage[k]);
     }
   }
-  L.stage_ext.assign(L.nstages, 0);
+  // Horizontal extents, consumers first: interior tiles evaluate four
+  // horizontally adjacent pixels per thread, so every operator runs over a
+  // horizontal extent that is a multiple of 4 (the extra columns are
+  // computed like any other), and its input must then hold that extent plus
+  // the operator's radius, again rounded up to a multiple of 4.
+  L.eh.assign(nv, 0);
+  for (int k = no - 1; k >= 0; --k) {
+    const GOp& o = P.ops[k];
+    const int need = (is_global_op(o.kind) ? 0 : L.eh[o.out]) + (is_local(o.kind) ? o.rx : 0);
+    for (int i = 0; i < 3; ++i)
+      if (o.in[i] >= 0) L.eh[o.in[i]] = std::max(L.eh[o.in[i]], round4(need));
+  }
+  L.bmode.assign(nv, -1);
+  L.bconst.assign(nv, 0);
   for (int k = 0; k < no; ++k) {
     const GOp& o = P.ops[k];
-    const int e = is_global_op(o.kind) ? 0 : P.vals[o.out].ext;
-    L.stage_ext[L.op_stage[k]] = std::max(L.stage_ext[L.op_stage[k]], e);
+    if (!is_local(o.kind)) continue;
+    const int v = o.in[0];
+    uint32_t c = (uint32_t)o.cint;  // the border constant as the input's element bits
+    if (P.vals[v].df == DF_F32) memcpy(&c, &o.cf, 4);
+    const int mode = o.border == B_UNDEFINED ? B_REPLICATE : o.border;
+    const int cb = mode == B_CONSTANT ? (int)c : 0;
+    if (L.bmode[v] >= 0 && (L.bmode[v] != mode || L.bconst[v] != cb)) L.resolved = false;
+    // REPEAT reads periodic copies: only a group input's load provides them
+    if (mode == B_REPEAT && L.producer[v] >= 0) L.resolved = false;
+    L.bmode[v] = mode;
+    L.bconst[v] = cb;
+  }
+  L.stage_ev.assign(L.nstages, 0);
+  L.stage_eh.assign(L.nstages, 0);
+  for (int k = 0; k < no; ++k) {
+    const GOp& o = P.ops[k];
+    if (is_global_op(o.kind)) continue;
+    L.stage_ev[L.op_stage[k]] = std::max(L.stage_ev[L.op_stage[k]], P.vals[o.out].ext);
+    L.stage_eh[L.op_stage[k]] = std::max(L.stage_eh[L.op_stage[k]], L.eh[o.out]);
   }
 }
 
 // LDS geometry of a value kept on chip: rows of `rw` words, image column x
-// of the tile at column x - tx0 + co, image row y at row y - ty0 + e.  A
-// group input is loaded in whole 16-byte chunks of its rows, so its rows
-// start at a 16-byte boundary of the image row before the halo.
-int input_cols(const GVal& v) {
+// of the tile at column x - tx0 + co, image row y at row y - ty0 + e (its
+// vertical extent).  A group input is loaded in whole 16-byte chunks of its
+// rows, so its rows start at a 16-byte boundary of the image row before the
+// halo.  Every row width and column offset is a multiple of 4 words.
+int input_cols(const GVal& v, int eh) {
   const int bpp = df_bytes(v.df);
-  return ((v.ext * bpp + 15) / 16 * 16) / bpp;
+  return ((eh * bpp + 15) / 16 * 16) / bpp;
 }
 
-void value_geometry(const GProg& P, int v, int tw, int* rw, int* co) {
+void value_geometry(const GProg& P, const Layout& L, int v, int tw, int* rw, int* co) {
   const GVal& gv = P.vals[v];
-  *co = gv.input ? input_cols(gv) : gv.ext;
+  *co = gv.input ? input_cols(gv, L.eh[v]) : L.eh[v];
   *rw = tw + 2 * *co;
 }
 
@@ -384,8 +432,8 @@ int place_lds(const GProg& P, Layout& L, int tw, int th) {
   int top = 0;
   for (int v : order) {
     int rw, co;
-    value_geometry(P, v, tw, &rw, &co);
-    const int sz = (rw * (th + 2 * P.vals[v].ext) + 3) / 4 * 4;
+    value_geometry(P, L, v, tw, &rw, &co);
+    const int sz = round4(rw * (th + 2 * P.vals[v].ext));
     const int d = L.def_stage[v], l = std::max(L.last_lds[v], d);
     std::vector<std::array<int, 2>> busy;
     for (auto& b : blocks)
@@ -411,13 +459,13 @@ int place_lds(const GProg& P, Layout& L, int tw, int th) {
 // element by element inside the image (or the periodic copies under REPEAT).
 void emit_load(Text& t, const GProg& P, const Layout& L, int v, int TW, int TH) {
   const GVal& gv = P.vals[v];
-  const int e = gv.ext, bpp = df_bytes(gv.df);
+  const int e = gv.ext, eh = L.eh[v], bpp = df_bytes(gv.df);
   int rw, co;
-  value_geometry(P, v, TW, &rw, &co);
+  value_geometry(P, L, v, TW, &rw, &co);
   const int rows = TH + 2 * e, epc = 16 / bpp, cpr = rw / epc, nch = cpr * rows;
   const int kc = (nch + kGenThreads - 1) / kGenThreads;
   const int off = L.lds_off[v];
-  t("  {  // load value %d: %d rows of %d columns (%d of halo)", v, rows, rw, e);
+  t("  {  // load value %d: %d rows of %d columns (halo %d rows, %d columns)", v, rows, rw, e, eh);
   t("    const uint8_t* base = (const uint8_t*)io.ptr[%d];", gv.io);
   t("    const int64_t pitch = io.pitch[%d];", gv.io);
   t("    if constexpr (IN) {");
@@ -447,16 +495,247 @@ void emit_load(Text& t, const GProg& P, const Layout& L, int v, int TW, int TH) 
   t("    } else {");
   t("      for (int i = (int)threadIdx.x; i < %d; i += %d) {", rw * rows, kGenThreads);
   t("        const int ly = i / %d, lx = i - ly * %d;", rw, rw);
-  t("        const int x = tx0 - %d + lx, y = ty0 - %d + ly;", co, e);
-  t("        if (lx < %d || lx >= %d) continue;  // outside the extent", co - e, co + TW + e);
-  if (gv.wrap)
+  t("        int x = tx0 - %d + lx, y = ty0 - %d + ly;", co, e);
+  t("        if (lx < %d || lx >= %d) continue;  // outside the extent", co - eh, co + TW + eh);
+  if (gv.wrap) {
     t("        L[%d + i] = gload(%d, base, pitch, repeat_pos(x, W), repeat_pos(y, H));", off, gv.df);
-  else
+  } else if (L.resolved) {
+    // positions outside the image take the border rule of the operators reading the value
+    t("        if (x < 0 || y < 0 || x >= W || y >= H) {");
+    if (L.bmode[v] == B_CONSTANT) {
+      t("          L[%d + i] = (int)0x%08xu;", off, (uint32_t)L.bconst[v]);
+      t("          continue;");
+    } else if (L.bmode[v] == B_MIRROR) {
+      t("          x = mirror_pos(x, W);");
+      t("          y = mirror_pos(y, H);");
+    }
+    t("          x = min(max(x, 0), W - 1);");
+    t("          y = min(max(y, 0), H - 1);");
+    t("        }");
+    t("        L[%d + i] = gload(%d, base, pitch, x, y);", off, gv.df);
+  } else {
     t("        if (x >= 0 && y >= 0 && x < W && y < H) L[%d + i] = gload(%d, base, pitch, x, y);", off, gv.df);
+  }
   t("      }");
   t("    }");
   t("  }");
 }
+
+// Edge tiles: the positions of value v outside the image, resolved by the
+// border rule of the operators reading it from the positions inside (which
+// lie in the value's tile: a border rule maps a position to one within the
+// value's extent of the image's edge).
+void emit_fill(Text& t, const GProg& P, const Layout& L, int v, int TW, int TH) {
+  const int e = P.vals[v].ext, eh = L.eh[v];
+  int rw, co;
+  value_geometry(P, L, v, TW, &rw, &co);
+  const int rows = TH + 2 * e, off = L.lds_off[v];
+  t("    for (int i = (int)threadIdx.x; i < %d; i += %d) {  // border of value %d", rw * rows, kGenThreads, v);
+  t("      const int ly = i / %d, lx = i - ly * %d;", rw, rw);
+  t("      int x = tx0 - %d + lx, y = ty0 - %d + ly;", co, e);
+  t("      if (lx < %d || lx >= %d || (x >= 0 && y >= 0 && x < W && y < H)) continue;", co - eh, co + TW + eh);
+  if (L.bmode[v] == B_CONSTANT) {
+    t("      L[%d + i] = (int)0x%08xu;", off, (uint32_t)L.bconst[v]);
+  } else {
+    if (L.bmode[v] == B_MIRROR) {
+      t("      x = mirror_pos(x, W);");
+      t("      y = mirror_pos(y, H);");
+    }
+    t("      x = min(max(x, 0), W - 1);");
+    t("      y = min(max(y, 0), H - 1);");
+    t("      L[%d + i] = L[%d + (y - ty0 + %d) * %d + (x - tx0 + %d)];", off, off, e, rw, co);
+  }
+  t("    }");
+}
+
+// The sweeps of one stage.  Edge tiles (1 px per thread) skip positions
+// outside the image and read windows through each operator's border rule.
+// Interior tiles take groups of four horizontally adjacent pixels per
+// thread: a local operator's window comes from LDS as 16-byte reads (three
+// per window row), LDS values move four words at a time, and outputs are
+// stored four pixels at a time.
+struct StageEmitter {
+  Text& t;
+  const GProg& P;
+  const Layout& L;
+  int TW, TH;
+  int* slot;
+
+  void geometry(int v, int* rw, int* co) const { value_geometry(P, L, v, TW, rw, co); }
+
+  // LDS index of value v at the sweep position (+ constant offsets)
+  std::string lds_index(int v, int ES_V, int ES_H, const char* dx, const char* dy) const {
+    int rw, co;
+    geometry(v, &rw, &co);
+    return fmt("%d + (ly + %d + %s) * %d + (lx + %d + %s)", L.lds_off[v], P.vals[v].ext - ES_V, dy, rw, co - ES_H, dx);
+  }
+
+  void one_pixel(int s) {
+    const int ESV = L.stage_ev[s], ESH = L.stage_eh[s];
+    const int RW = TW + 2 * ESH, RH = TH + 2 * ESV;
+    bool need_own = false;
+    for (int k = 0; k < P.nops; ++k)
+      if (L.op_stage[k] == s && (is_reduce_op(P.ops[k].kind) || P.vals[P.ops[k].out].store)) need_own = true;
+    t("    for (int i = (int)threadIdx.x; i < %d; i += %d) {", RW * RH, kGenThreads);
+    t("      const int ly = i / %d, lx = i - ly * %d;", RW, RW);
+    t("      const int x = tx0 - %d + lx, y = ty0 - %d + ly;", ESH, ESV);
+    t("      if (x < 0 || y < 0 || x >= W || y >= H) continue;");
+    if (need_own) t("      const bool own = lx >= %d && lx < %d && ly >= %d && ly < %d;", ESH, ESH + TW, ESV, ESV + TH);
+    for (int k = 0; k < P.nops; ++k) {
+      if (L.op_stage[k] != s) continue;
+      const GOp& o = P.ops[k];
+      auto at = [&](int i) -> std::string {
+        const int v = o.in[i];
+        if (v < 0 || P.vals[v].df == DF_BUF) return "0";
+        switch (L.src[k][i]) {
+          case S_REG: return fmt("v%d", v);
+          case S_GLB: return fmt("gload(%d, io.ptr[%d], io.pitch[%d], x, y)", P.vals[v].df, P.vals[v].io, P.vals[v].io);
+          default: return "L[" + lds_index(v, ESV, ESH, "0", "0") + "]";
+        }
+      };
+      if (is_reduce_op(o.kind)) {
+        t("      if (own) red_add(rs, %d, gop%d, %s);", (*slot)++, k, at(0).c_str());
+        continue;
+      }
+      const GVal& ov = P.vals[o.out];
+      const int EV = ov.ext, EH = L.eh[o.out];
+      t("      int v%d = 0;", o.out);
+      t("      if (lx >= %d && lx < %d && ly >= %d && ly < %d) {", ESH - EH, ESH + EH + TW, ESV - EV, ESV + EV + TH);
+      if (is_local(o.kind)) {
+        const int v = o.in[0];
+        int rw, co;
+        geometry(v, &rw, &co);
+        uint32_t cval = (uint32_t)o.cint;  // the border constant as the input's element bits
+        if (P.vals[v].df == DF_F32) memcpy(&cval, &o.cf, 4);
+        t("        auto rd = [&](int dx, int dy) -> int {");
+        t("          return gx_rd<%d>(L + %d, %d, %d, %d, tx0, ty0, W, H, x + dx, y + dy, (int)0x%08xu);", o.border,
+          L.lds_off[v], rw, P.vals[v].ext, co, cval);
+        t("        };");
+        if (o.kind == OP_EXPR_LOCAL) t("        v%d = gx_expr%d(rd);", o.out, k);
+        else t("        v%d = local_eval<%s>(gop%d, %d, rd);", o.out, o.kind == OP_NONLINEAR ? "true" : "false", k, ov.df);
+      } else if (o.kind == OP_LUT) {
+        t("        v%d = ((const uint8_t*)io.ptr[%d])[%d + (%s & 0xFF)];", o.out, P.vals[o.in[1]].io, 256 * 4,
+          at(0).c_str());
+      } else if (o.kind == OP_EXPR) {
+        t("        v%d = gx_expr%d(%s, %s, %s);", o.out, k, at(0).c_str(), at(1).c_str(), at(2).c_str());
+      } else {
+        t("        v%d = point_eval(gop%d, %d, %s, %s, %s, %s);", o.out, k, ov.df,
+          P.vals[o.in[0]].df == DF_F32 ? "true" : "false", at(0).c_str(), at(1).c_str(), at(2).c_str());
+      }
+      if (L.needs_lds[o.out]) t("        L[%s] = v%d;", lds_index(o.out, ESV, ESH, "0", "0").c_str(), o.out);
+      if (ov.store) t("        if (own) gstore(%d, io.ptr[%d], io.pitch[%d], x, y, v%d);", ov.df, ov.io, ov.io, o.out);
+      t("      }");
+    }
+    t("    }");
+  }
+
+  void four_pixels(int s, bool edge) {
+    const int ESV = L.stage_ev[s], ESH = L.stage_eh[s];
+    const int GR = (TW + 2 * ESH) / 4, RH = TH + 2 * ESV;
+    bool need_own = false;
+    for (int k = 0; k < P.nops; ++k)
+      if (L.op_stage[k] == s && (is_reduce_op(P.ops[k].kind) || P.vals[P.ops[k].out].store)) need_own = true;
+    t("    for (int i = (int)threadIdx.x; i < %d; i += %d) {", GR * RH, kGenThreads);
+    t("      const int ly = i / %d, lx = (i - ly * %d) * 4;", GR, GR);
+    t("      const int x = tx0 - %d + lx, y = ty0 - %d + ly;", ESH, ESV);
+    if (need_own) t("      const bool own = lx >= %d && lx < %d && ly >= %d && ly < %d;", ESH, ESH + TW, ESV, ESV + TH);
+    for (int k = 0; k < P.nops; ++k) {
+      if (L.op_stage[k] != s) continue;
+      const GOp& o = P.ops[k];
+      // four elements of input i at the position: an array name
+      auto at4 = [&](int i) -> std::string {
+        const int v = o.in[i];
+        if (v < 0 || P.vals[v].df == DF_BUF) return "gx_zero4";
+        const std::string n = fmt("a%d_%d", k, i);
+        switch (L.src[k][i]) {
+          case S_REG: return fmt("v%d", v);
+          case S_GLB:
+            t("        int %s[4];", n.c_str());
+            if (edge)
+              t("        gx_load4_edge(%d, io.ptr[%d], io.pitch[%d], x, y, W, H, %s);", P.vals[v].df, P.vals[v].io,
+                P.vals[v].io, n.c_str());
+            else
+              t("        load4(%d, (const uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, %s);", P.vals[v].df,
+                P.vals[v].io, P.vals[v].io, n.c_str());
+            return n;
+          default: {
+            t("        int %s[4];", n.c_str());
+            t("        { const int4 q = *(const int4*)(L + %s); %s[0] = q.x; %s[1] = q.y; %s[2] = q.z; %s[3] = q.w; }",
+              lds_index(v, ESV, ESH, "0", "0").c_str(), n.c_str(), n.c_str(), n.c_str(), n.c_str());
+            return n;
+          }
+        }
+      };
+      if (is_reduce_op(o.kind)) {
+        t(edge ? "      if (own && y < H) {" : "      if (own) {");
+        const std::string a = at4(0);
+        t("#pragma unroll");
+        if (edge)
+          t("        for (int q = 0; q < 4; ++q) if (x + q < W) red_add(rs, %d, gop%d, %s[q]);", (*slot)++, k, a.c_str());
+        else
+          t("        for (int q = 0; q < 4; ++q) red_add(rs, %d, gop%d, %s[q]);", (*slot)++, k, a.c_str());
+        t("      }");
+        continue;
+      }
+      const GVal& ov = P.vals[o.out];
+      const int EV = ov.ext, EH = L.eh[o.out];
+      t("      int v%d[4] = {0, 0, 0, 0};", o.out);
+      t("      if (lx >= %d && lx < %d && ly >= %d && ly < %d) {", ESH - EH, ESH + EH + TW, ESV - EV, ESV + EV + TH);
+      if (is_local(o.kind)) {
+        const int v = o.in[0], R = o.ry;
+        int rw, co;
+        geometry(v, &rw, &co);
+        // window row j: input row y - R + j, columns x - 4 .. x + 7
+        t("        int w[%d][12];", 2 * R + 1);
+        t("#pragma unroll");
+        t("        for (int j = 0; j < %d; ++j) {", 2 * R + 1);
+        const std::string dy = fmt("(j - %d)", R);
+        t("          const int4* r = (const int4*)(L + %s);", lds_index(v, ESV, ESH, "-4", dy.c_str()).c_str());
+        t("#pragma unroll");
+        t("          for (int c = 0; c < 3; ++c) {");
+        t("            const int4 q = r[c];");
+        t("            w[j][4 * c] = q.x; w[j][4 * c + 1] = q.y; w[j][4 * c + 2] = q.z; w[j][4 * c + 3] = q.w;");
+        t("          }");
+        t("        }");
+        t("        const int (*wp)[12] = w;");
+        t("#pragma unroll");
+        t("        for (int q = 0; q < 4; ++q) {");
+        if (o.kind == OP_EXPR_LOCAL) {
+          t("          v%d[q] = gx_expr%d([&](int dx, int dy) { return wp[%d + dy][4 + q + dx]; });", o.out, k, R);
+        } else {
+          t("          switch (q) {");
+          for (int q = 0; q < 4; ++q)
+            t("            case %d: v%d[%d] = local_eval<%s>(gop%d, %d, WinRd<%d, %d>{wp}); break;", q, o.out, q,
+              o.kind == OP_NONLINEAR ? "true" : "false", k, ov.df, R, q);
+          t("          }");
+        }
+        t("        }");
+      } else if (o.kind == OP_LUT) {
+        const std::string a = at4(0);
+        t("#pragma unroll");
+        t("        for (int q = 0; q < 4; ++q) v%d[q] = ((const uint8_t*)io.ptr[%d])[%d + (%s[q] & 0xFF)];", o.out,
+          P.vals[o.in[1]].io, 256 * 4, a.c_str());
+      } else {
+        const std::string a = at4(0), b = at4(1), c = at4(2);
+        t("#pragma unroll");
+        if (o.kind == OP_EXPR)
+          t("        for (int q = 0; q < 4; ++q) v%d[q] = gx_expr%d(%s[q], %s[q], %s[q]);", o.out, k, a.c_str(), b.c_str(),
+            c.c_str());
+        else
+          t("        for (int q = 0; q < 4; ++q) v%d[q] = point_eval(gop%d, %d, %s, %s[q], %s[q], %s[q]);", o.out, k,
+            ov.df, P.vals[o.in[0]].df == DF_F32 ? "true" : "false", a.c_str(), b.c_str(), c.c_str());
+      }
+      if (L.needs_lds[o.out])
+        t("        *(int4*)(L + %s) = make_int4(v%d[0], v%d[1], v%d[2], v%d[3]);",
+          lds_index(o.out, ESV, ESH, "0", "0").c_str(), o.out, o.out, o.out, o.out);
+      if (ov.store)
+        t("        if (own%s) store4(%d, (uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);",
+          edge ? " && y < H" : "", ov.df, ov.io, ov.io, o.out);
+      t("      }");
+    }
+    t("    }");
+  }
+};
 
 bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::string* why) {
   Layout L;
@@ -484,14 +763,20 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
     *why = "values kept on chip exceed the LDS budget";
     return false;
   }
-  int emax = 0;
-  for (int v = 0; v < P.nvals; ++v) emax = std::max(emax, P.vals[v].ext);
+  // a tile is interior when every position any stage sweeps, and every
+  // input column a window reads, lies inside the image
+  int ev_max = 0, eh_max = 0;
+  for (int v = 0; v < P.nvals; ++v) {
+    ev_max = std::max(ev_max, P.vals[v].ext);
+    eh_max = std::max(eh_max, L.eh[v]);
+  }
   const int LW = std::max(4, L.lds_words + hist_words);
 
   Text t;
   bool ok = true;
   emit_prelude(t, P, why, &ok);
   if (!ok) return false;
+  t("__device__ constexpr int gx_zero4[4] = {0, 0, 0, 0};");
   // one tile: IN = its halo lies inside the image
   t("template <bool IN>");
   t("__device__ __forceinline__ void gen_tile(const IOTable& io, int W, int H, int tx0, int ty0, int32_t* L%s) {",
@@ -503,74 +788,25 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
       loads = true;
     }
   if (loads) t("  __syncthreads();");
-  int slot = 0;
+  int slot_in = 0, slot_edge = 0;
   for (int s = 0; s < L.nstages; ++s) {
-    const int ES = L.stage_ext[s], RW = TW + 2 * ES, RH = TH + 2 * ES;
-    bool need_own = false;
-    for (int k = 0; k < P.nops; ++k)
-      if (L.op_stage[k] == s && (is_reduce_op(P.ops[k].kind) || P.vals[P.ops[k].out].store)) need_own = true;
-    t("  // stage %d: extent %d", s, ES);
-    t("  for (int i = (int)threadIdx.x; i < %d; i += %d) {", RW * RH, kGenThreads);
-    t("    const int ly = i / %d, lx = i - ly * %d;", RW, RW);
-    t("    const int x = tx0 - %d + lx, y = ty0 - %d + ly;", ES, ES);
-    t("    if (!IN && (x < 0 || y < 0 || x >= W || y >= H)) continue;");
-    if (need_own) {
-      if (ES > 0) t("    const bool own = lx >= %d && lx < %d && ly >= %d && ly < %d;", ES, ES + TW, ES, ES + TH);
-      else t("    const bool own = true;");
-    }
-    // the LDS word of value v at this position plus (dx, dy)
-    auto lds_at = [&](int v, const char* dx, const char* dy) {
-      int rw, co;
-      value_geometry(P, v, TW, &rw, &co);
-      return fmt("L[%d + (ly + %d + %s) * %d + (lx + %d + %s)]", L.lds_off[v], P.vals[v].ext - ES, dy, rw, co - ES, dx);
-    };
-    for (int k = 0; k < P.nops; ++k) {
-      if (L.op_stage[k] != s) continue;
-      const GOp& o = P.ops[k];
-      // a point read at the position itself
-      auto at = [&](int i) -> std::string {
-        const int v = o.in[i];
-        if (v < 0 || P.vals[v].df == DF_BUF) return "0";
-        switch (L.src[k][i]) {
-          case S_REG: return fmt("v%d", v);
-          case S_GLB: return fmt("gload(%d, io.ptr[%d], io.pitch[%d], x, y)", P.vals[v].df, P.vals[v].io, P.vals[v].io);
-          default: return lds_at(v, "0", "0");
-        }
-      };
-      if (is_reduce_op(o.kind)) {
-        t("    if (own) red_add(rs, %d, gop%d, %s);", slot++, k, at(0).c_str());
-        continue;
+    t("  // stage %d: extent %d rows, %d columns", s, L.stage_ev[s], L.stage_eh[s]);
+    t("  if constexpr (IN) {");
+    StageEmitter{t, P, L, TW, TH, &slot_in}.four_pixels(s, false);
+    t("  } else {");
+    if (L.resolved) {
+      StageEmitter{t, P, L, TW, TH, &slot_edge}.four_pixels(s, true);
+      // values of this stage that later windows read: their border
+      bool fills = false;
+      for (int k = 0; k < P.nops; ++k) {
+        const int v = P.ops[k].out;
+        if (L.op_stage[k] != s || is_global_op(P.ops[k].kind) || L.bmode[v] < 0) continue;
+        if (!fills) t("    __syncthreads();");
+        fills = true;
+        emit_fill(t, P, L, v, TW, TH);
       }
-      const GVal& ov = P.vals[o.out];
-      const int EK = ov.ext;
-      t("    int v%d = 0;", o.out);
-      if (EK < ES) t("    if (lx >= %d && lx < %d && ly >= %d && ly < %d) {", ES - EK, ES + EK + TW, ES - EK, ES + EK + TH);
-      else t("    {");
-      if (is_local(o.kind)) {
-        const int v = o.in[0];
-        int rw, co;
-        value_geometry(P, v, TW, &rw, &co);
-        // the border constant as the input's element bits
-        uint32_t cval = (uint32_t)o.cint;
-        if (P.vals[v].df == DF_F32) memcpy(&cval, &o.cf, 4);
-        t("      auto rd = [&](int dx, int dy) -> int {");
-        t("        if constexpr (IN) return %s;", lds_at(v, "dx", "dy").c_str());
-        t("        else return gx_rd<%d>(L + %d, %d, %d, %d, tx0, ty0, W, H, x + dx, y + dy, (int)0x%08xu);", o.border,
-          L.lds_off[v], rw, P.vals[v].ext, co, cval);
-        t("      };");
-        if (o.kind == OP_EXPR_LOCAL) t("      v%d = gx_expr%d(rd);", o.out, k);
-        else t("      v%d = local_eval<%s>(gop%d, %d, rd);", o.out, o.kind == OP_NONLINEAR ? "true" : "false", k, ov.df);
-      } else if (o.kind == OP_LUT) {
-        t("      v%d = ((const uint8_t*)io.ptr[%d])[%d + (%s & 0xFF)];", o.out, P.vals[o.in[1]].io, 256 * 4, at(0).c_str());
-      } else if (o.kind == OP_EXPR) {
-        t("      v%d = gx_expr%d(%s, %s, %s);", o.out, k, at(0).c_str(), at(1).c_str(), at(2).c_str());
-      } else {
-        t("      v%d = point_eval(gop%d, %d, %s, %s, %s, %s);", o.out, k, ov.df,
-          P.vals[o.in[0]].df == DF_F32 ? "true" : "false", at(0).c_str(), at(1).c_str(), at(2).c_str());
-      }
-      if (L.needs_lds[o.out]) t("      %s = v%d;", lds_at(o.out, "0", "0").c_str(), o.out);
-      if (ov.store) t("      if (own) gstore(%d, io.ptr[%d], io.pitch[%d], x, y, v%d);", ov.df, ov.io, ov.io, o.out);
-      t("    }");
+    } else {
+      StageEmitter{t, P, L, TW, TH, &slot_edge}.one_pixel(s);
     }
     t("  }");
     if (s + 1 < L.nstages) t("  __syncthreads();");
@@ -588,7 +824,8 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   }
   t("  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {");
   t("    const int tx0 = (tile %% tiles_x) * %d, ty0 = (tile / tiles_x) * %d;", TW, TH);
-  t("    const bool in = tx0 >= %d && ty0 >= %d && tx0 + %d <= W && ty0 + %d <= H;", emax, emax, TW + emax, TH + emax);
+  t("    const bool in = tx0 >= %d && ty0 >= %d && tx0 + %d <= W && ty0 + %d <= H;", eh_max, ev_max, TW + eh_max,
+    TH + ev_max);
   t("    if (in) gen_tile<true>(io, W, H, tx0, ty0, L%s);", red ? ", rs" : "");
   t("    else gen_tile<false>(io, W, H, tx0, ty0, L%s);", red ? ", rs" : "");
   t("    __syncthreads();  // the tile's LDS is free for the next tile");
@@ -611,6 +848,7 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
 struct GenKernel {
   int form = 0, tw = 0, th = 0;
   bool red = false;
+  int lds_words = 0;
   std::vector<char> code;
   std::mutex mu;
   hipModule_t mod[kMaxDevices] = {};
@@ -687,6 +925,7 @@ const GenKernel* gen_compile(const GenSource& src, std::string* why) {
   k->tw = src.tw;
   k->th = src.th;
   k->red = src.red;
+  k->lds_words = src.lds_words;
   (*g_cache)[src.text] = k;
   return k;
 }
@@ -717,6 +956,11 @@ hipError_t gen_launch(const GenKernel* k, int device, const GProg& P, const GPro
   if (k->form == GEN_POINTS) {
     grid = (long long)((P.w + 1023) >> 10) * P.h;
   } else {
+    // One work-group per tile (a persistent grid of as many groups as fit
+    // the CUs measured slower: the hardware's own dispatch of short groups
+    // overlaps one group's loads with another's arithmetic as well).  A
+    // group that reduces loops over tiles and merges its partial results
+    // once at its end: four per CU.
     const long long tiles = (long long)((P.w + k->tw - 1) / k->tw) * ((P.h + k->th - 1) / k->th);
     grid = k->red ? std::min<long long>(tiles, 4LL * num_cus) : tiles;
   }
