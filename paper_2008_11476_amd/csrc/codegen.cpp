@@ -822,7 +822,19 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
     t("  RedState rs;");
     t("  red_begin<%d>(rs, (uint32_t*)(L + %d));", kGenThreads, L.lds_words);
   }
-  t("  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {");
+  // Work-groups go to the 8 XCDs in turn (block b to XCD b mod 8), each with
+  // its own L2: give every XCD a contiguous run of tiles, so that tiles
+  // side by side, whose rows share cache lines, meet in one L2.  A group that
+  // reduces takes a contiguous run of tiles of its own.
+  t("  const int nb = (int)gridDim.x, b = (int)blockIdx.x;");
+  t("  const int per = nb / 8, rem = nb %% 8, xcd = b %% 8;");
+  t("  const int vb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;");
+  if (red) {
+    t("  const int t_end = (int)((long long)(vb + 1) * ntiles / nb);");
+    t("  for (int tile = (int)((long long)vb * ntiles / nb); tile < t_end; ++tile) {");
+  } else {
+    t("  for (int tile = vb; tile < ntiles; tile += nb) {");
+  }
   t("    const int tx0 = (tile %% tiles_x) * %d, ty0 = (tile / tiles_x) * %d;", TW, TH);
   t("    const bool in = tx0 >= %d && ty0 >= %d && tx0 + %d <= W && ty0 + %d <= H;", eh_max, ev_max, TW + eh_max,
     TH + ev_max);
