@@ -502,7 +502,9 @@ hvx_status hvx_server_inject_failure(hvx_server s, uint64_t tag);
 
 /* Each release invalidates the handle and sets *ref = NULL (explicit
  * release, Section 3.1).  A graph waits for its scheduled work first, a
- * batch for its last launch, a server drains its requests.  An image or
+ * batch for its last launch, a server drains its requests (a graph waits only
+ * for its own schedules, not for the requests a server ran on it: release the
+ * server, or drain it, before the templates it serves).  An image or
  * convolution still wired into a node of a live graph stays alive until that
  * graph (or the context) is released; a node's handle can be dropped at any
  * time, the node itself lives as long as its graph.  INVALID_PARAMETERS for a

@@ -878,8 +878,11 @@ bool gen_wanted(const GProg& P) {
   const GOp& o = P.ops[0];
   if (is_global_op(o.kind)) return true;
   if (is_point_op(o.kind)) return o.kind == OP_EXPR;
+  // the one-operator local kernel reads a Convolve or NonLinearFilter mask
+  // at run time; generated, the mask's zeros and products fold away
   const int in_df = P.vals[o.in[0]].df;
-  return o.kind == OP_EXPR_LOCAL || (in_df != DF_U8 && in_df != DF_F32);
+  return o.kind == OP_EXPR_LOCAL || o.kind == OP_CONVOLVE || o.kind == OP_NONLINEAR ||
+         (in_df != DF_U8 && in_df != DF_F32);
 }
 
 bool gen_source(const GProg& P, int tw, int th, GenSource* out, std::string* why) {

@@ -37,7 +37,8 @@ struct GenSource {
 // Whether a program is run by a generated kernel: everything except the
 // single operators that the interpreter's own one-operator kernels already
 // run with constant operators (a built-in point operator; a built-in local
-// operator on U8 or F32).
+// operator on U8 or F32 other than Convolve and NonLinearFilter, whose masks
+// that kernel reads at run time).
 bool gen_wanted(const GProg& P);
 
 // Emit the kernel of program P with an output tile of tw x th (0: the

@@ -326,8 +326,14 @@ hvx_status schedule_bound(Graph* g, void* stream, const Bind* b) {
     s = launch_group(g, gr, st, b);
     if (s) return s;
   }
-  g->last_stream = stream;
-  g->scheduled = true;
+  // The graph waits for its own schedules (hvx_graph_wait, release).  A
+  // bound run belongs to its caller (the server), which waits for its own
+  // streams and may destroy them before the graph: the graph must not keep
+  // such a stream.
+  if (!b) {
+    g->last_stream = stream;
+    g->scheduled = true;
+  }
   return HVX_SUCCESS;
 }
 

@@ -467,3 +467,34 @@ def test_server_bound_requests_device_and_host(ctx, mode):
     hvx.hvx_release_server(s)
     for (g, imgs, keep, outs) in templ.values():
         hvx.hvx_release_graph(g)
+
+
+def test_templates_outlive_their_server():
+    """Templates a server ran requests on are waited on and released, with
+    their context, after the server and its streams are gone: a run on the
+    server's stream is the server's to wait for, not the graph's."""
+    import torch
+    c = hvx.hvx_context_create(0)
+    spec = _bound_specs(64, 48, seed=3)["generic"]
+    g, outs, keep, imgs = _build(c, spec)
+    s = hvx.hvx_server_create(c, hvx.HVX_SERVER_CONTINUOUS, 1 << 22, 4, 2)
+    held, bind = {}, []
+    for name, arr in spec.inputs.items():
+        buf, view = hvx.alloc_image(48, 64, hvx.HVX_DF_U8)
+        view.copy_(torch.from_numpy(arr))
+        held[name] = view
+        bind.append((imgs[name], view.data_ptr(), view.stride(0)))
+    for name in spec.outputs:
+        buf, view = hvx.alloc_image(48, 64, hvx.HVX_DF_U8)
+        held[name] = view
+        bind.append((imgs[name], view.data_ptr(), view.stride(0)))
+    torch.cuda.synchronize()
+    log("template outlives server: submit")
+    hvx.hvx_server_submit_bound(s, g, bind, hvx.HVX_MEMORY_DEVICE, 1, ctx=c)
+    hvx.hvx_server_drain(s, ctx=c)
+    done = hvx.hvx_server_poll(s, 8, ctx=c)
+    assert [t for t, _, _ in done] == [1] and done[0][1] == 0
+    compare(spec, {n: held[n].cpu().numpy() for n in spec.outputs}, spec.run_oracle())
+    hvx.hvx_release_server(s)
+    hvx.hvx_graph_wait(g, ctx=c)
+    hvx.hvx_context_release(c)
