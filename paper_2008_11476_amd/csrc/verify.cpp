@@ -706,6 +706,11 @@ hvx_status verify_graph(Graph* g) {
       default: return err(g, HVX_ERROR_NOT_SUPPORTED, "unknown node kind");
     }
     if (s) return s;
+    // the counts of a global operator are 32-bit
+    const bool global = n->kind == NK_HISTOGRAM || n->kind == NK_MINMAX || n->kind == NK_MINMAXLOC ||
+                        n->kind == NK_MEANSTD || n->kind == NK_EQHIST;
+    if (global && (uint64_t)w * h >= ((uint64_t)1 << 31))
+      return err(g, HVX_ERROR_INVALID_DIMENSION, "%s takes images of fewer than 2^31 pixels", nn);
   }
 
   // ---- 3: lowering to point/local operators ----

@@ -224,3 +224,16 @@ def test_fusion_off_runs_node_by_node(ctx):
     hvx.hvx_graph_verify(g)
     assert _q(g, hvx.HVX_QUERY_NUM_KERNELS) == 2
     assert _q(g, hvx.HVX_QUERY_SCRATCH_BYTES) == 640 * 480
+
+
+def test_global_nodes_refuse_images_of_2_31_pixels(ctx):
+    """The counts of a global operator are 32-bit: verification refuses an
+    input of 2^31 pixels or more, and takes one pixel fewer."""
+    for h, want in ((32768, hvx.HVX_ERROR_INVALID_DIMENSION), (32767, 0)):
+        g = hvx.hvx_graph_create(ctx)
+        a = _img(ctx, 65536, h)
+        hvx.hvx_histogram_node(g, a, 16, 0, 256, _buf(ctx, 64))
+        assert _status(hvx.hvx_graph_verify, g) == want
+        if want:
+            assert "2^31" in hvx.hvx_last_error(ctx)
+        hvx.hvx_release_graph(g)
