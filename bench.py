@@ -372,6 +372,7 @@ EXTRAS = {
     "user_kernels_4k": lambda hvx, torch, ctx, rec: user_kernels(hvx, torch, ctx, rec),
     # the generated kernels alone (one fused plan per graph, default tiles): the profiled command
     "user_kernels_fused_4k": lambda hvx, torch, ctx, rec: user_kernels(hvx, torch, ctx, rec, fused_only=True),
+    "user_kernels_4k_batch32": lambda hvx, torch, ctx, rec: user_kernels_batch(hvx, torch, ctx, rec),
     "serving": lambda hvx, torch, ctx, rec: res_set(rec, "serving", serving(hvx, torch, ctx)),
 }
 
@@ -503,31 +504,22 @@ def global_graph(hvx, torch, ctx, rec):
     del ib, iv, buf
 
 
-def user_kernels(hvx, torch, ctx, rec, fused_only=False):
-    """The paper's applications built on user kernels (Section 6.1) on one
-    3840x2160 frame, U8 in and U8 out (2 B/px), fused (one generated kernel;
-    and the same group run by the tile interpreter) and node by node (user
-    kernels generated one by one): Unsharp (Gaussian3x3 and three user point
-    kernels), Tomasi (the corner graph with a user min-eigenvalue response),
-    FChain (three Convolve nodes)."""
-    import synth
-    stream = torch.cuda.current_stream().cuda_stream
-    w, h = 3840, 2160
-    ib, iv = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
-    ob, ov = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
-    iv.copy_(torch.from_numpy(synth.corner_image(w, h, seed=0)))
-    a = hvx.image_from_tensor(ctx, iv, hvx.HVX_DF_U8)
-    o = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
+def user_kernel_builders(hvx, ctx):
+    """Builders of the paper's user-kernel applications (Section 6.1), each
+    adding its nodes to a graph between an input image a and an output image
+    o (U8): Unsharp (Gaussian3x3 and three user point kernels), Tomasi (the
+    corner graph with a user min-eigenvalue response), FChain (three Convolve
+    nodes).  Returns the builders and the convolutions to release."""
     S16, F32, U8 = hvx.HVX_DF_S16, hvx.HVX_DF_F32, hvx.HVX_DF_U8
 
-    def unsharp(g):
+    def unsharp(g, a, o):
         v = [hvx.hvx_image_create_virtual(g) for _ in range(3)]
         hvx.hvx_gaussian3x3_node(g, a, v[0])
         hvx.hvx_custom_point_node(g, "a - b", [a, v[0]], S16, v[1])
         hvx.hvx_custom_point_node(g, "a * 3 / 2", [v[1]], S16, v[2])
         hvx.hvx_custom_point_node(g, "a + b", [a, v[2]], U8, o)
 
-    def tomasi(g):
+    def tomasi(g, a, o):
         v = [hvx.hvx_image_create_virtual(g) for _ in range(9)]
         hvx.hvx_sobel3x3_node(g, a, v[0], v[1])
         hvx.hvx_multiply_f32_node(g, v[0], v[0], v[2])
@@ -543,14 +535,33 @@ def user_kernels(hvx, torch, ctx, rec, fused_only=False):
              (np.ones((5, 5), int), 32)]
     convs = [hvx.hvx_convolution_create(ctx, m, sc) for (m, sc) in masks]
 
-    def fchain(g):
+    def fchain(g, a, o):
         v = [hvx.hvx_image_create_virtual(g, 0, 0, U8) for _ in range(2)]
         hvx.hvx_convolve_node(g, a, convs[0], v[0])
         hvx.hvx_convolve_node(g, v[0], convs[1], v[1])
         hvx.hvx_convolve_node(g, v[1], convs[2], o)
 
+    return (("unsharp", unsharp), ("tomasi", tomasi), ("fchain", fchain)), convs
+
+
+def user_kernels(hvx, torch, ctx, rec, fused_only=False):
+    """The user-kernel applications on one 3840x2160 frame, U8 in and U8 out
+    (2 B/px), fused (one generated kernel; and the same group run by the tile
+    interpreter) and node by node (user kernels generated one by one), and the
+    plan the tuner picks."""
+    import synth
+    stream = torch.cuda.current_stream().cuda_stream
+    w, h = 3840, 2160
+    ib, iv = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+    ob, ov = hvx.alloc_image(h, w, hvx.HVX_DF_U8)
+    iv.copy_(torch.from_numpy(synth.corner_image(w, h, seed=0)))
+    a = hvx.image_from_tensor(ctx, iv, hvx.HVX_DF_U8)
+    o = hvx.image_from_tensor(ctx, ov, hvx.HVX_DF_U8)
+    builders, convs = user_kernel_builders(hvx, ctx)
     d = {"image": "3840x2160 U8 (corner workload)", "alg_bytes_per_frame": 2 * w * h}
-    for name, build in (("unsharp", unsharp), ("tomasi", tomasi), ("fchain", fchain)):
+    for name, make in builders:
+        def build(g, make=make):
+            make(g, a, o)
         row = {}
         for label, fusion, codegen in PLANS[:1] if fused_only else PLANS:
             g = hvx.hvx_graph_create(ctx)
@@ -577,6 +588,44 @@ def user_kernels(hvx, torch, ctx, rec, fused_only=False):
     hvx.hvx_release_image(a)
     hvx.hvx_release_image(o)
     del ib, iv, ob, ov
+
+
+def user_kernels_batch(hvx, torch, ctx, rec, nframes=32):
+    """The user-kernel applications over 32 distinct 3840x2160 frames in one
+    batch: the graphs share their generated kernel, so each application is
+    one launch over every frame's tiles (throughput rather than one frame's
+    latency)."""
+    stream = torch.cuda.current_stream().cuda_stream
+    w, h = 3840, 2160
+    inp, out = make_frames(hvx, torch, w, h, nframes)
+    builders, convs = user_kernel_builders(hvx, ctx)
+    handles = [(hvx.image_from_tensor(ctx, inp[i][1], hvx.HVX_DF_U8),
+                hvx.image_from_tensor(ctx, out[i][0][1], hvx.HVX_DF_U8)) for i in range(nframes)]
+    d = {"frames": "%d x 3840x2160 U8" % nframes, "alg_bytes_per_step": 2 * w * h * nframes}
+    for name, make in builders:
+        graphs = []
+        for a, o in handles:
+            g = hvx.hvx_graph_create(ctx)
+            make(g, a, o)
+            hvx.hvx_graph_verify(g, ctx=ctx)
+            graphs.append(g)
+        b = hvx.hvx_batch_create(ctx, graphs)
+        ms, _ = time_region(torch, lambda: hvx.hvx_batch_schedule(b, stream, ctx=ctx), 10, 2)
+        alg = 2 * w * h * nframes
+        d[name] = {"ms": round(ms, 4), "mpix_s": round(nframes * w * h / 1e6 / (ms / 1e3), 1),
+                   "launches": hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS),
+                   "alg_gbs": round(alg / (ms / 1e3) / 1e9, 1), "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        hvx.hvx_release_batch(b)
+        for g in graphs:
+            hvx.hvx_release_graph(g)
+    rec("user_kernels_4k_batch32", d)
+    for c in convs:
+        hvx.hvx_release_convolution(c)
+    for a, o in handles:
+        hvx.hvx_release_image(a)
+        hvx.hvx_release_image(o)
+    del inp, out
+    torch.cuda.empty_cache()
 
 
 def serving(hvx, torch, ctx, n_req=240, budget=512 << 20):

@@ -197,6 +197,7 @@ void emit_prelude(Text& t, const GProg& P, std::string* why, bool* ok) {
   t("namespace __hip_internal {}");
   t("using namespace __hip_internal;");
   t("#include \"dev_generic.hpp\"");
+  t("#include \"gen_abi.h\"");
   t("namespace hvx {");
   t("__device__ __forceinline__ int gx_add(int a, int b) { return (int)((uint32_t)a + (uint32_t)b); }");
   t("__device__ __forceinline__ int gx_sub(int a, int b) { return (int)((uint32_t)a - (uint32_t)b); }");
@@ -218,6 +219,17 @@ void emit_prelude(Text& t, const GProg& P, std::string* why, bool* ok) {
   t("    y = min(max(y, 0), H - 1);");
   t("  }");
   t("  return L[(y - ty0 + ey) * rw + (x - tx0 + ex)];");
+  t("}");
+  // the image of a batch that work-group `blk` belongs to: the last whose
+  // first work-group is at or before it (a uniform binary search)
+  t("__device__ __forceinline__ int gx_batch_image(const GenBatchImage* imgs, int n, int blk) {");
+  t("  int lo = 0, hi = n - 1;");
+  t("  while (lo < hi) {");
+  t("    const int mid = (lo + hi + 1) >> 1;");
+  t("    if (imgs[mid].block0 <= blk) lo = mid;");
+  t("    else hi = mid - 1;");
+  t("  }");
+  t("  return lo;");
   t("}");
   // four elements of a row from x on; zero outside the image (edge tiles)
   t("__device__ __forceinline__ void gx_load4_edge(int df, const void* base, int64_t pitch, int x, int y, int W, int H,");
@@ -254,12 +266,26 @@ bool emit_points(const GProg& P, GenSource* out, std::string* why) {
   bool ok = true;
   emit_prelude(t, P, why, &ok);
   if (!ok) return false;
-  t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io) {",
+  t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io0,",
     kGenThreads);
-  t("  const int W = P->w, H = P->h;");
+  t("                                                           const GenBatchImage* __restrict__ imgs, int nimg) {");
+  // one image (the program's size), or one image of a batch of images
+  t("  IOTable io;");
+  t("  int W, H, blk = (int)blockIdx.x;");
+  t("  if (nimg == 0) {");
+  t("    io = io0;");
+  t("    W = P->w;");
+  t("    H = P->h;");
+  t("  } else {");
+  t("    const int i = gx_batch_image(imgs, nimg, blk);");
+  t("    io = imgs[i].io;");
+  t("    W = imgs[i].w;");
+  t("    H = imgs[i].h;");
+  t("    blk -= imgs[i].block0;");
+  t("  }");
   t("  const int bx = (W + 1023) >> 10;");
-  t("  const int y = blockIdx.x / bx;");
-  t("  const int x = ((blockIdx.x - y * bx) * %d + (int)threadIdx.x) * 4;", kGenThreads);
+  t("  const int y = blk / bx;");
+  t("  const int x = ((blk - y * bx) * %d + (int)threadIdx.x) * 4;", kGenThreads);
   t("  if (y >= H || x >= W) return;");
   std::vector<int> read(P.nvals, 0);
   for (int k = 0; k < P.nops; ++k)
@@ -812,12 +838,10 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
     if (s + 1 < L.nstages) t("  __syncthreads();");
   }
   t("}");
-  t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io) {",
+  t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io0,",
     kGenThreads);
+  t("                                                           const GenBatchImage* __restrict__ imgs, int nimg) {");
   t("  __shared__ __attribute__((aligned(16))) int32_t L[%d];", LW);
-  t("  const int W = P->w, H = P->h;");
-  t("  const int tiles_x = (W + %d) / %d;", TW - 1, TW);
-  t("  const int ntiles = tiles_x * ((H + %d) / %d);", TH - 1, TH);
   if (red) {
     t("  RedState rs;");
     t("  red_begin<%d>(rs, (uint32_t*)(L + %d));", kGenThreads, L.lds_words);
@@ -828,12 +852,29 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   // reduces takes a contiguous run of tiles of its own.
   t("  const int nb = (int)gridDim.x, b = (int)blockIdx.x;");
   t("  const int per = nb / 8, rem = nb %% 8, xcd = b %% 8;");
-  t("  const int vb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;");
+  t("  int vb = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;");
+  // one image (the program's size), or one tile of one image of a batch
+  t("  IOTable io;");
+  t("  int W, H, stride = nb, limit = 1 << 30;");
+  t("  if (nimg == 0) {");
+  t("    io = io0;");
+  t("    W = P->w;");
+  t("    H = P->h;");
+  t("  } else {");
+  t("    const int i = gx_batch_image(imgs, nimg, vb);");
+  t("    io = imgs[i].io;");
+  t("    W = imgs[i].w;");
+  t("    H = imgs[i].h;");
+  t("    vb -= imgs[i].block0;");
+  t("    limit = vb + 1;  // one tile per work-group");
+  t("  }");
+  t("  const int tiles_x = (W + %d) / %d;", TW - 1, TW);
+  t("  const int ntiles = min(tiles_x * ((H + %d) / %d), limit);", TH - 1, TH);
   if (red) {
     t("  const int t_end = (int)((long long)(vb + 1) * ntiles / nb);");
     t("  for (int tile = (int)((long long)vb * ntiles / nb); tile < t_end; ++tile) {");
   } else {
-    t("  for (int tile = vb; tile < ntiles; tile += nb) {");
+    t("  for (int tile = vb; tile < ntiles; tile += stride) {");
   }
   t("    const int tx0 = (tile %% tiles_x) * %d, ty0 = (tile / tiles_x) * %d;", TW, TH);
   t("    const bool in = tx0 >= %d && ty0 >= %d && tx0 + %d <= W && ty0 + %d <= H;", eh_max, ev_max, TW + eh_max,
@@ -983,8 +1024,30 @@ hipError_t gen_launch(const GenKernel* k, int device, const GProg& P, const GPro
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
   const GProg* p = dev_prog;
   IOTable t = io;
-  void* args[] = {(void*)&p, (void*)&t};
+  const GenBatchImage* none = nullptr;
+  int zero = 0;
+  void* args[] = {(void*)&p, (void*)&t, (void*)&none, (void*)&zero};
   return hipModuleLaunchKernel(k->fn[device], (unsigned)grid, 1, 1, kGenThreads, 1, 1, 0, s, args, nullptr);
+}
+
+long long gen_blocks(const GenKernel* k, int w, int h) {
+  if (k->form == GEN_POINTS) return (long long)((w + 1023) >> 10) * h;
+  return (long long)((w + k->tw - 1) / k->tw) * ((h + k->th - 1) / k->th);
+}
+
+bool gen_batchable(const GenKernel* k) { return !k->red; }
+
+hipError_t gen_launch_batch(const GenKernel* k, int device, const GenBatchImage* imgs, int n, long long blocks,
+                            hipStream_t s) {
+  if (device < 0 || device >= kMaxDevices || !k->fn[device]) return hipErrorInvalidDeviceFunction;
+  if (k->red) return hipErrorInvalidValue;
+  if (n <= 0 || blocks <= 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const GProg* p = nullptr;
+  IOTable t;
+  memset(&t, 0, sizeof t);
+  void* args[] = {(void*)&p, (void*)&t, (void*)&imgs, (void*)&n};
+  return hipModuleLaunchKernel(k->fn[device], (unsigned)blocks, 1, 1, kGenThreads, 1, 1, 0, s, args, nullptr);
 }
 
 void gen_tile(const GenKernel* k, int* tw, int* th) {

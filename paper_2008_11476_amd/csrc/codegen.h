@@ -14,6 +14,7 @@
 
 #include <string>
 
+#include "gen_abi.h"
 #include "hvx_desc.h"
 
 namespace hvx {
@@ -59,5 +60,18 @@ hipError_t gen_launch(const GenKernel* k, int device, const GProg& P, const GPro
 
 // Tile of a generated kernel (0 x 0 for the point form).
 void gen_tile(const GenKernel* k, int* tw, int* th);
+
+// Work-groups the kernel launches for one w x h image when run over a batch
+// (one per tile, or one per 1024 pixels of a row for the point form).
+long long gen_blocks(const GenKernel* k, int w, int h);
+
+// Whether one launch can run the kernel over a batch of images (a kernel
+// that reduces global operators cannot: each image has its own result).
+bool gen_batchable(const GenKernel* k);
+
+// One launch over n images: `imgs` in device memory, image i's work-groups
+// starting at imgs[i].block0, `blocks` in all.
+hipError_t gen_launch_batch(const GenKernel* k, int device, const GenBatchImage* imgs, int n, long long blocks,
+                            hipStream_t s);
 
 }  // namespace hvx

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <fstream>
+#include <map>
 #include <set>
 #include <sstream>
 
@@ -270,18 +271,25 @@ static hipError_t launch_global_group(Graph* g, const Group& gr, hipStream_t s, 
   return hipErrorInvalidValue;
 }
 
+// The device pointers and pitches a generic group's kernel reads and writes.
+static hvx_status fill_io(Graph* g, const Group& gr, IOTable* io, const Bind* b) {
+  memset(io, 0, sizeof *io);
+  for (int i = 0; i < gr.prog.nvals; ++i) {
+    const GVal& v = gr.prog.vals[i];
+    if (v.io < 0) continue;
+    value_ptr(g, gr.gvals[i], &io->ptr[v.io], &io->pitch[v.io], b);
+    if (!io->ptr[v.io]) return set_error(g->ctx, HVX_ERROR_DEVICE, "unbound image in plan");
+  }
+  return HVX_SUCCESS;
+}
+
 static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s, const Bind* b) {
   hipError_t e = hipSuccess;
   const int gi = (int)(&gr - g->plan->groups.data());
   if (gr.kind == FK_GENERIC) {
     IOTable io;
-    memset(&io, 0, sizeof io);
-    for (int i = 0; i < gr.prog.nvals; ++i) {
-      const GVal& v = gr.prog.vals[i];
-      if (v.io < 0) continue;
-      value_ptr(g, gr.gvals[i], &io.ptr[v.io], &io.pitch[v.io], b);
-      if (!io.ptr[v.io]) return set_error(g->ctx, HVX_ERROR_DEVICE, "unbound image in plan");
-    }
+    hvx_status fs = fill_io(g, gr, &io, b);
+    if (fs) return fs;
     // global operators reduced by the kernel: starting values before it,
     // final values after it, in the same stream
     const GProg& P = gr.prog;
@@ -356,6 +364,14 @@ struct Batch : Object {
   int64_t alg_bytes = 0;
   int rows_override = 0;  // rows per work item for every image (0: each graph's own)
   int kinds = 0;          // bit set of the kinds in the single batch launch
+  // graphs whose plan is one generated kernel, by kernel: one launch each
+  struct GenSet {
+    const GenKernel* k = nullptr;
+    std::vector<GenBatchImage> imgs;
+    GenBatchImage* d = nullptr;
+    long long blocks = 0;
+  };
+  std::vector<GenSet> gensets;
   void* last_stream = nullptr;
   bool scheduled = false;
 };
@@ -369,6 +385,9 @@ static void batch_free_device(Batch* b) {
   b->hg = nullptr;
   if (b->d_imgs) (void)hipFree(b->d_imgs);
   if (b->d_item_img) (void)hipFree(b->d_item_img);
+  for (auto& gs : b->gensets)
+    if (gs.d) (void)hipFree(gs.d);
+  b->gensets.clear();
   if (b->d_counter) (void)hipFree(b->d_counter);
   b->d_imgs = nullptr;
   b->d_item_img = nullptr;
@@ -414,6 +433,48 @@ static hvx_status batch_build(Batch* b) {
       b->separate.push_back(g);
     }
   }
+  // graphs whose plan is one generated kernel: those sharing a kernel run
+  // in one launch over all their tiles (a work list of image and tile)
+  {
+    std::map<const GenKernel*, std::vector<Graph*>> by_kernel;
+    for (Graph* g : b->separate) {
+      const auto& gs = g->plan->groups;
+      if (gs.size() == 1 && gs[0].kind == FK_GENERIC && gs[0].gen && gen_batchable(gs[0].gen))
+        by_kernel[gs[0].gen].push_back(g);
+    }
+    std::vector<Graph*> rest;
+    for (Graph* g : b->separate) {
+      const auto& gs = g->plan->groups;
+      const bool gen1 = gs.size() == 1 && gs[0].kind == FK_GENERIC && gs[0].gen && gen_batchable(gs[0].gen);
+      if (!gen1 || by_kernel[gs[0].gen].size() < 2) rest.push_back(g);
+    }
+    for (auto& kv : by_kernel) {
+      if (kv.second.size() < 2) continue;
+      Batch::GenSet set;
+      set.k = kv.first;
+      for (Graph* g : kv.second) {
+        const Group& gr = g->plan->groups[0];
+        GenBatchImage im;
+        memset(&im, 0, sizeof im);
+        hvx_status st = fill_io(g, gr, &im.io, nullptr);
+        if (st) return st;
+        im.w = gr.prog.w;
+        im.h = gr.prog.h;
+        im.block0 = (int32_t)set.blocks;
+        set.blocks += gen_blocks(set.k, gr.prog.w, gr.prog.h);
+        if (set.blocks > 0x7FFFFFFF) return set_error(c, HVX_ERROR_NOT_SUPPORTED, "batch launch too large");
+        set.imgs.push_back(im);
+      }
+      b->gensets.push_back(std::move(set));
+    }
+    b->separate.swap(rest);
+    for (auto& set : b->gensets) {
+      const size_t bytes = set.imgs.size() * sizeof(GenBatchImage);
+      if (hipMalloc((void**)&set.d, bytes) != hipSuccess) return set_error(c, HVX_ERROR_NO_MEMORY, "batch tables");
+      if (hipMemcpy(set.d, set.imgs.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(c, HVX_ERROR_DEVICE, "batch table upload");
+    }
+  }
   // heaviest items first, so the last items handed out are the cheapest
   std::stable_sort(b->imgs.begin(), b->imgs.end(),
                    [](const BatchImage& x, const BatchImage& y) { return kind_cost(x) > kind_cost(y); });
@@ -453,6 +514,7 @@ static hvx_status batch_build(Batch* b) {
 // the graphs it cannot hold
 static int64_t batch_launches(const Batch* b) {
   int64_t k = b->total > 0 ? 1 : 0;
+  k += (int64_t)b->gensets.size();
   for (Graph* g : b->separate) k += (int64_t)g->plan->groups.size();
   return k;
 }
@@ -461,6 +523,10 @@ static hvx_status batch_enqueue(Batch* b, hipStream_t s) {
   if (b->total > 0) {
     hipError_t e = launch_batch(b->d_imgs, b->d_item_img, b->total, b->d_counter, b->grid, b->persistent, b->kinds, s);
     if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "batch launch: %s", hipGetErrorString(e));
+  }
+  for (const auto& set : b->gensets) {
+    hipError_t e = gen_launch_batch(set.k, b->ctx->device, set.d, (int)set.imgs.size(), set.blocks, s);
+    if (e != hipSuccess) return set_error(b->ctx, HVX_ERROR_DEVICE, "generated batch launch: %s", hipGetErrorString(e));
   }
   for (Graph* g : b->separate) {
     hvx_status st = HVX_SUCCESS;

@@ -498,3 +498,57 @@ def test_templates_outlive_their_server():
     hvx.hvx_release_server(s)
     hvx.hvx_graph_wait(g, ctx=c)
     hvx.hvx_context_release(c)
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_batch_runs_generated_kernels_once_per_kernel(ctx, use_graph):
+    """Graphs whose plan is one generated kernel share a launch with the
+    other graphs of that kernel (any sizes): four Unsharp graphs, two FChain
+    graphs and two point chains run as three launches, a lone Tomasi graph as
+    its own, the edge graph in the batch launch; outputs equal each graph run
+    alone and the oracle."""
+    import torch
+    from tests.test_gpu_codegen import _fchain, _point_chain, _tomasi
+    from tests.test_gpu_custom import unsharp_spec
+    specs = [("unsharp", unsharp_spec(synth.edge_image(w, h, seed=w))) for (w, h) in
+             ((640, 480), (131, 29), (1, 1), (64, 48))]
+    specs += [("fchain", _fchain(synth.edge_image(w, h, seed=h), ("replicate", 0))) for (w, h) in ((300, 77), (17, 5))]
+    specs += [("point_chain", _point_chain(synth.uniform_u8(w, h, seed=3), synth.uniform_u8(w, h, seed=4)))
+              for (w, h) in ((1029, 3), (66, 40))]
+    specs += [("tomasi", _tomasi(synth.corner_image(129, 37, seed=1))), ("edge", gs.edge_spec(synth.edge_image(500, 60)))]
+    built = []
+    for kind, spec in specs:
+        g, outs, keep, imgs = _build(ctx, spec)
+        built.append((kind, spec, g, outs, keep))
+    alone = []
+    for kind, spec, g, outs, keep in built:
+        hvx.hvx_graph_process(g, ctx=ctx)
+        alone.append(_read(outs))
+        for t, _ in outs.values():
+            t.fill_(0x5A)
+    torch.cuda.synchronize()
+    b = hvx.hvx_batch_create(ctx, [x[2] for x in built])
+    hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_USE_GRAPH, use_graph)
+    assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) == 5
+    side = torch.cuda.Stream()
+    for rep in range(2):
+        log("generated batch use_graph=%d rep %d" % (use_graph, rep))
+        hvx.hvx_batch_schedule(b, side.cuda_stream, ctx=ctx)
+        torch.cuda.synchronize()
+        for (kind, spec, g, outs, keep), ref in zip(built, alone):
+            got = _read(outs)
+            for name in got:
+                if got[name].dtype == np.float32:
+                    assert np.array_equal(got[name].view(np.uint32), ref[name].view(np.uint32)), (kind, name, rep)
+                else:
+                    assert np.array_equal(got[name], ref[name]), (kind, name, rep)
+            for t, _ in outs.values():
+                t.fill_(rep + 1)
+        torch.cuda.synchronize()
+    for (kind, spec, g, outs, keep), ref in zip(built, alone):
+        if kind == "tomasi":
+            continue  # F32 response: its own test compares it within tolerance
+        compare(spec, ref, spec.run_oracle(), phase_names=("ph",))
+    hvx.hvx_release_batch(b)
+    for x in built:
+        hvx.hvx_release_graph(x[2])
