@@ -98,6 +98,18 @@ def _s16_local(img, border):
                    {"in": img}, {"out": np.int16})
 
 
+def _mixed_borders(img, b0, b1):
+    """One value read by local operators with different borders (the
+    generated kernel's edge tiles then read through each operator's rule)."""
+    return gs.Spec([gs.N("gaussian3x3", ["in"], ["g"], *b0),
+                    gs.N("box3x3", ["in"], ["b"], *b1),
+                    gs.N("dilate3x3", ["g"], ["d"], *b1),
+                    gs.N("median3x3", ["g"], ["m"], *b0),
+                    gs.N("add", ["d", "b"], ["s"], params={"policy": "wrap"}),
+                    gs.N("add", ["s", "m"], ["out"], params={"policy": "saturate"})],
+                   {"in": img}, {"out": np.uint8})
+
+
 BORDERS = [("replicate", 0), ("constant", 0), ("constant", 77), ("undefined", 0), ("mirror", 0)]
 SIZES = [(129, 37), (1, 1), (640, 480), (3, 2)]
 
@@ -117,6 +129,8 @@ def _cases():
             out.append(("laplace_float", (w, h, b), lambda img=img, b=b: _laplace_float(img, b)))
             out.append(("s16_local", (w, h, b), lambda img=img, b=b: _s16_local(img, b)))
             out.append(("edge_phase", (w, h, b), lambda img=img, b=b: _edge_phase(img, b, b)))
+        for b0, b1 in ((BORDERS[0], BORDERS[2]), (BORDERS[4], BORDERS[1]), (BORDERS[3], BORDERS[4])):
+            out.append(("mixed_borders", (w, h, b0, b1), lambda img=img, b0=b0, b1=b1: _mixed_borders(img, b0, b1)))
         for b in BORDERS[:3]:
             out.append(("uyvy", (w, h, b), lambda w=w, h=h, b=b: _uyvy(synth.uyvy_image(max(2, w // 2 * 2), h,
                                                                                         seed=7), b)))
