@@ -94,7 +94,9 @@ typedef int32_t hvx_status;
 #define HVX_OPT_SPECIALIZE 4 /* 1 (default): use hand-fused kernels for recognised subgraphs; 0: generic */
 #define HVX_OPT_XCD_REMAP 5  /* 1 (default): map work items to XCDs in contiguous chunks */
 #define HVX_OPT_CODEGEN 6    /* 1 (default): a kernel generated and compiled (hipRTC) per fused group that
-                                has no hand-fused kernel (Section 6); 0: the tile interpreter runs it */
+                                has no hand-fused kernel (Section 6); 0: the tile interpreter runs it.
+                                Environment: HVX_GEN_LOG set prints why a group was left to the
+                                interpreter; HVX_GEN_DUMP=<dir> writes each generated source there */
 
 /* Graph queries (hvx_graph_query); valid after verification. */
 #define HVX_QUERY_NUM_NODES 1      /* function nodes added */
