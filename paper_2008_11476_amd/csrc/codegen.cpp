@@ -268,7 +268,8 @@ bool emit_points(const GProg& P, GenSource* out, std::string* why) {
   if (!ok) return false;
   t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io0,",
     kGenThreads);
-  t("                                                           const GenBatchImage* __restrict__ imgs, int nimg) {");
+  t("                                                           const GenBatchImage* __restrict__ imgs, int nimg,");
+  t("                                                           uint32_t* __restrict__ ws) {");
   // one image (the program's size), or one image of a batch of images
   t("  IOTable io;");
   t("  int W, H, blk = (int)blockIdx.x;");
@@ -769,7 +770,7 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   int nred = 0;
   for (int k = 0; k < P.nops; ++k) nred += is_reduce_op(P.ops[k].kind) ? 1 : 0;
   const bool red = nred > 0;
-  const int hist_words = red ? kHistWords : 0;
+  const int hist_words = red ? kGenThreads / 64 * kHistWords : 0;  // a histogram per wave
   static const int shapes[][2] = {{128, 16}, {64, 16}, {64, 8}, {32, 8}, {32, 4}, {16, 4}};
   int TW = 0, TH = 0;
   if (tw_req > 0) {
@@ -840,11 +841,12 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   t("}");
   t("extern \"C\" __global__ __launch_bounds__(%d) void hvx_gen(const GProg* __restrict__ P, const IOTable io0,",
     kGenThreads);
-  t("                                                           const GenBatchImage* __restrict__ imgs, int nimg) {");
+  t("                                                           const GenBatchImage* __restrict__ imgs, int nimg,");
+  t("                                                           uint32_t* __restrict__ ws) {");
   t("  __shared__ __attribute__((aligned(16))) int32_t L[%d];", LW);
   if (red) {
     t("  RedState rs;");
-    t("  red_begin<%d>(rs, (uint32_t*)(L + %d));", kGenThreads, L.lds_words);
+    t("  red_begin<%d, %d>(rs, (uint32_t*)(L + %d));", kGenThreads, kGenThreads / 64, L.lds_words);
   }
   // Work-groups go to the 8 XCDs in turn (block b to XCD b mod 8), each with
   // its own L2: give every XCD a contiguous run of tiles, so that tiles
@@ -870,12 +872,8 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   t("  }");
   t("  const int tiles_x = (W + %d) / %d;", TW - 1, TW);
   t("  const int ntiles = min(tiles_x * ((H + %d) / %d), limit);", TH - 1, TH);
-  if (red) {
-    t("  const int t_end = (int)((long long)(vb + 1) * ntiles / nb);");
-    t("  for (int tile = (int)((long long)vb * ntiles / nb); tile < t_end; ++tile) {");
-  } else {
-    t("  for (int tile = vb; tile < ntiles; tile += stride) {");
-  }
+  t("  const int slot = vb;  // the group's tile, and its slot of partial results when it reduces");
+  t("  for (int tile = vb; tile < ntiles; tile += stride) {");
   t("    const int tx0 = (tile %% tiles_x) * %d, ty0 = (tile / tiles_x) * %d;", TW, TH);
   t("    const bool in = tx0 >= %d && ty0 >= %d && tx0 + %d <= W && ty0 + %d <= H;", eh_max, ev_max, TW + eh_max,
     TH + ev_max);
@@ -883,7 +881,7 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   t("    else gen_tile<false>(io, W, H, tx0, ty0, L%s);", red ? ", rs" : "");
   t("    __syncthreads();  // the tile's LDS is free for the next tile");
   t("  }");
-  if (red) t("  red_end<%d>(*P, io, rs);", kGenThreads);
+  if (red) t("  red_end_partial<%d>(*P, rs, ws + (size_t)slot * %d);", kGenThreads, red_slot_words(P));
   t("}");
   out->text = t.s;
   out->form = GEN_TILES;
@@ -1006,7 +1004,7 @@ hipError_t gen_load(const GenKernel* kc, int device) {
 }
 
 hipError_t gen_launch(const GenKernel* k, int device, const GProg& P, const GProg* dev_prog, const IOTable& io,
-                      int num_cus, hipStream_t s) {
+                      int num_cus, hipStream_t s, uint32_t* ws) {
   if (device < 0 || device >= kMaxDevices || !k->fn[device]) return hipErrorInvalidDeviceFunction;
   long long grid;
   if (k->form == GEN_POINTS) {
@@ -1015,18 +1013,18 @@ hipError_t gen_launch(const GenKernel* k, int device, const GProg& P, const GPro
     // One work-group per tile (a persistent grid of as many groups as fit
     // the CUs measured slower: the hardware's own dispatch of short groups
     // overlaps one group's loads with another's arithmetic as well).  A
-    // group that reduces loops over tiles and merges its partial results
-    // once at its end: four per CU.
-    const long long tiles = (long long)((P.w + k->tw - 1) / k->tw) * ((P.h + k->th - 1) / k->th);
-    grid = k->red ? std::min<long long>(tiles, 4LL * num_cus) : tiles;
+    // group that reduces writes its partial results to its slot of `ws`.
+    grid = (long long)((P.w + k->tw - 1) / k->tw) * ((P.h + k->th - 1) / k->th);
+    (void)num_cus;
   }
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (k->red && !ws) return hipErrorInvalidValue;
   const GProg* p = dev_prog;
   IOTable t = io;
   const GenBatchImage* none = nullptr;
   int zero = 0;
-  void* args[] = {(void*)&p, (void*)&t, (void*)&none, (void*)&zero};
+  void* args[] = {(void*)&p, (void*)&t, (void*)&none, (void*)&zero, (void*)&ws};
   return hipModuleLaunchKernel(k->fn[device], (unsigned)grid, 1, 1, kGenThreads, 1, 1, 0, s, args, nullptr);
 }
 
@@ -1046,7 +1044,8 @@ hipError_t gen_launch_batch(const GenKernel* k, int device, const GenBatchImage*
   const GProg* p = nullptr;
   IOTable t;
   memset(&t, 0, sizeof t);
-  void* args[] = {(void*)&p, (void*)&t, (void*)&imgs, (void*)&n};
+  uint32_t* ws = nullptr;
+  void* args[] = {(void*)&p, (void*)&t, (void*)&imgs, (void*)&n, (void*)&ws};
   return hipModuleLaunchKernel(k->fn[device], (unsigned)blocks, 1, 1, kGenThreads, 1, 1, 0, s, args, nullptr);
 }
 

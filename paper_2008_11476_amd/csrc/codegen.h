@@ -55,8 +55,10 @@ const GenKernel* gen_compile(const GenSource& src, std::string* why);
 hipError_t gen_load(const GenKernel* k, int device);
 
 // Launch on stream s (gen_load must have succeeded on the current device).
+// A kernel that reduces global operators (not gen_batchable) writes one slot
+// of red_slot_words(P) words per work-group, gen_blocks of them, to `ws`.
 hipError_t gen_launch(const GenKernel* k, int device, const GProg& P, const GProg* dev_prog, const IOTable& io,
-                      int num_cus, hipStream_t s);
+                      int num_cus, hipStream_t s, uint32_t* ws);
 
 // Tile of a generated kernel (0 x 0 for the point form).
 void gen_tile(const GenKernel* k, int* tw, int* th);

@@ -24,6 +24,7 @@
 #include "dev_phase.hpp"
 #include "dev_reduce.hpp"
 
+#include "gen_abi.h"
 #include "hvx_desc.h"
 
 namespace hvx {
@@ -489,7 +490,9 @@ struct RedSlot {
 // indexed by the run-time slot number would be placed in scratch memory.
 struct RedState {
   RedSlot a, b;
-  uint32_t* hist;  // kHistWords words of LDS
+  uint32_t* hist;   // this wave's copy of the histogram in LDS (kHistWords words)
+  uint32_t* hist0;  // the first copy
+  int copies;       // copies of the histogram, one per wave (or one in all)
   template <class F>
   __device__ __forceinline__ void with(int k, F&& f) {
     if (k == 0) f(a);
@@ -498,14 +501,19 @@ struct RedState {
 };
 static_assert(kMaxRed == 2, "RedState holds two slots");
 
-template <int NT>
+// HC copies of the histogram (1, or one per wave: waves then do not contend
+// for the same LDS words); `hist` holds HC * kHistWords words.
+template <int NT, int HC = 1>
 __device__ __forceinline__ void red_begin(RedState& r, uint32_t* hist) {
+  static_assert(HC == 1 || HC == NT / 64, "one histogram, or one per wave");
   r.a.mn = r.b.mn = 2147483647;
   r.a.mx = r.b.mx = -2147483647 - 1;
   r.a.cmn = r.a.cmx = r.b.cmn = r.b.cmx = 0;
   r.a.s1 = r.a.s2 = r.b.s1 = r.b.s2 = 0;
-  r.hist = hist;
-  for (int b = threadIdx.x; b < kHistWords; b += NT) hist[b] = 0;
+  r.hist0 = hist;
+  r.copies = HC;
+  r.hist = hist + (HC > 1 ? (int)(threadIdx.x >> 6) * kHistWords : 0);
+  for (int b = threadIdx.x; b < HC * kHistWords; b += NT) hist[b] = 0;
   __syncthreads();
 }
 
@@ -554,8 +562,11 @@ __device__ __forceinline__ void red_end(const GProg& P, const IOTable& io, RedSt
     if (!is_reduce_op(o.kind)) continue;
     void* out = io.ptr[P.vals[o.out].io];
     if (o.kind == OP_HISTOGRAM || o.kind == OP_EQHIST) {
-      for (int b = t; b < o.p0; b += NT)
-        if (r.hist[b]) atomicAdd((uint32_t*)out + b, r.hist[b]);
+      for (int b = t; b < o.p0; b += NT) {
+        uint32_t c = 0;
+        for (int h = 0; h < r.copies; ++h) c += r.hist0[h * kHistWords + b];
+        if (c) atomicAdd((uint32_t*)out + b, c);
+      }
     } else {
       RedSlot q;
       r.with(k, [&](RedSlot& x) { q = x; });
@@ -619,6 +630,89 @@ __device__ __forceinline__ void red_end(const GProg& P, const IOTable& io, RedSt
       }
       __syncthreads();
     }
+    ++k;
+  }
+}
+
+// As red_end, but the group writes its partial results to its own slot of
+// a workspace (red_slot_words(P) words) instead of merging them into the
+// results: a second kernel merges the slots (launch_merge_partials).
+template <int NT>
+__device__ __forceinline__ void red_end_partial(const GProg& P, RedState& r, uint32_t* slot) {
+  __shared__ unsigned long long part[2][NT / 64];
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  __syncthreads();  // the LDS histogram is complete
+  int k = 0, off = 0;
+  for (int oi = 0; oi < P.nops; ++oi) {
+    const GOp& o = P.ops[oi];
+    if (!is_reduce_op(o.kind)) continue;
+    if (o.kind == OP_HISTOGRAM || o.kind == OP_EQHIST) {
+      for (int b = t; b < o.p0; b += NT) {
+        uint32_t c = 0;
+        for (int h = 0; h < r.copies; ++h) c += r.hist0[h * kHistWords + b];
+        slot[off + b] = c;
+      }
+    } else {
+      RedSlot q;
+      r.with(k, [&](RedSlot& x) { q = x; });
+      int mn = q.mn, mx = q.mx;
+      uint32_t cmn = q.cmn, cmx = q.cmx;
+      unsigned long long s1 = q.s1, s2 = q.s2;
+      if (o.kind == OP_SUMS) {
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) {
+          s1 += __shfl_xor(s1, sh);
+          s2 += __shfl_xor(s2, sh);
+        }
+      } else if (o.kind == OP_MINMAX) {
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) {
+          mn = min(mn, __shfl_xor(mn, sh));
+          mx = max(mx, __shfl_xor(mx, sh));
+        }
+      } else {
+        wave_merge_extremes(mn, cmn, mx, cmx);
+      }
+      if (lane == 0) {
+        if (o.kind == OP_SUMS) {
+          part[0][wv] = s1;
+          part[1][wv] = s2;
+        } else if (o.kind == OP_MINMAX) {
+          part[0][wv] = (unsigned long long)(unsigned)mn;
+          part[1][wv] = (unsigned long long)(unsigned)mx;
+        } else {
+          part[0][wv] = cmn ? mm_key(mn, cmn) : kMinKeyInit;
+          part[1][wv] = cmx ? mm_key(mx, cmx) : kMaxKeyInit;
+        }
+      }
+      __syncthreads();
+      if (t == 0) {
+        unsigned long long a = part[0][0], b = part[1][0];
+        for (int w = 1; w < NT / 64; ++w) {
+          if (o.kind == OP_SUMS) {
+            a += part[0][w];
+            b += part[1][w];
+          } else if (o.kind == OP_MINMAX) {
+            a = (unsigned long long)(unsigned)min((int)(unsigned)a, (int)(unsigned)part[0][w]);
+            b = (unsigned long long)(unsigned)max((int)(unsigned)b, (int)(unsigned)part[1][w]);
+          } else {
+            a = mm_merge(a, part[0][w], true);
+            b = mm_merge(b, part[1][w], false);
+          }
+        }
+        if (o.kind == OP_MINMAX) {
+          slot[off] = (uint32_t)a;
+          slot[off + 1] = (uint32_t)b;
+        } else {
+          slot[off] = (uint32_t)a;
+          slot[off + 1] = (uint32_t)(a >> 32);
+          slot[off + 2] = (uint32_t)b;
+          slot[off + 3] = (uint32_t)(b >> 32);
+        }
+      }
+      __syncthreads();
+    }
+    off += red_block_words(o.kind, o.p0);
     ++k;
   }
 }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hvx_desc.h"
+
 namespace hvx {
 
 // One image as the global kernels read it: rows of `pitch` bytes (a multiple
@@ -36,6 +38,11 @@ hipError_t launch_equalize_mapping(const GlobalImg& im, void* workspace, hipStre
 // kernels reduce into `result`
 hipError_t launch_reduce_init(int kind, void* result, int num_bins, hipStream_t s);
 hipError_t launch_reduce_finish(int kind, void* result, long long npix, hipStream_t s);
+// The partial results a generated reducing kernel left in `ws` (nslots
+// slots of slot_words words, red_slot_words) merged into the results of the
+// program's reduce operators (between launch_reduce_init and _finish).
+hipError_t launch_merge_partials(const GProg* dev_prog, const IOTable& io, const uint32_t* ws, int nslots,
+                                 int slot_words, hipStream_t s);
 // n uint32 words of device memory set to zero
 hipError_t launch_zero_words(void* p, int n, hipStream_t s);
 

@@ -14,6 +14,7 @@
 #include <mutex>
 
 #include "dev_reduce.hpp"
+#include "gen_abi.h"
 #include "global.h"
 #include "hvx_desc.h"
 
@@ -580,6 +581,130 @@ hipError_t launch_mean_std_dev(const GlobalImg& im, void* result, hipStream_t s)
 // The fused kernels merge their partial results into the operator's result
 // buffer; these kernels set its starting value before and form the final
 // values after, in the same stream.
+
+// ---- partial results of the generated reducing kernels ----------------------
+// Every work-group of such a kernel wrote the partial results of its tile to
+// its own slot (red_end_partial); here each of up to kMergeGroups groups
+// combines a contiguous range of slots and merges that into the results with
+// one atomic (per bin, per word) or compare-and-swap, as the kernel's groups
+// did directly before: the results start from launch_reduce_init's values
+// and end with launch_reduce_finish.  Few groups, so same-address atomics
+// stay few.
+constexpr int kMergeGroups = 256;
+constexpr int kMergeThreads = 256;
+
+__global__ __launch_bounds__(kMergeThreads) void k_merge_partials(const GProg* __restrict__ P, const IOTable io,
+                                                                  const uint32_t* __restrict__ ws, int nslots,
+                                                                  int slot_words) {
+  __shared__ unsigned long long part[2][kMergeThreads / 64];
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const int s0 = (int)((long long)blockIdx.x * nslots / gridDim.x);
+  const int s1 = (int)((long long)(blockIdx.x + 1) * nslots / gridDim.x);
+  int off = 0;
+  for (int oi = 0; oi < P->nops; ++oi) {
+    const GOp& o = P->ops[oi];
+    if (!is_reduce_op(o.kind)) continue;
+    void* out = io.ptr[P->vals[o.out].io];
+    if (o.kind == OP_HISTOGRAM || o.kind == OP_EQHIST) {
+      for (int b = t; b < o.p0; b += kMergeThreads) {
+        // eight slots' loads in flight at a time
+        uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int sl = s0;
+        for (; sl + 8 <= s1; sl += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) c[u] += ws[(size_t)(sl + u) * slot_words + off + b];
+        }
+        for (; sl < s1; ++sl) c[0] += ws[(size_t)sl * slot_words + off + b];
+        const uint32_t sum = c[0] + c[1] + c[2] + c[3] + c[4] + c[5] + c[6] + c[7];
+        if (sum) atomicAdd((uint32_t*)out + b, sum);
+      }
+    } else {
+      // this thread's slots, then the wave, then the group
+      unsigned long long a, b;
+      if (o.kind == OP_SUMS) {
+        a = b = 0;
+      } else if (o.kind == OP_MINMAX) {
+        a = (unsigned)INT_MAX;
+        b = (unsigned)INT_MIN;
+      } else {
+        a = kMinKeyInit;
+        b = kMaxKeyInit;
+      }
+      for (int sl = s0 + t; sl < s1; sl += kMergeThreads) {
+        const uint32_t* w = ws + (size_t)sl * slot_words + off;
+        if (o.kind == OP_MINMAX) {
+          a = (unsigned)min((int)(unsigned)a, (int)w[0]);
+          b = (unsigned)max((int)(unsigned)b, (int)w[1]);
+        } else {
+          const unsigned long long x = w[0] | (unsigned long long)w[1] << 32;
+          const unsigned long long y = w[2] | (unsigned long long)w[3] << 32;
+          if (o.kind == OP_SUMS) {
+            a += x;
+            b += y;
+          } else {
+            a = mm_merge(a, x, true);
+            b = mm_merge(b, y, false);
+          }
+        }
+      }
+#pragma unroll
+      for (int sh = 32; sh > 0; sh >>= 1) {
+        const unsigned long long x = __shfl_xor(a, sh), y = __shfl_xor(b, sh);
+        if (o.kind == OP_SUMS) {
+          a += x;
+          b += y;
+        } else if (o.kind == OP_MINMAX) {
+          a = (unsigned)min((int)(unsigned)a, (int)(unsigned)x);
+          b = (unsigned)max((int)(unsigned)b, (int)(unsigned)y);
+        } else {
+          a = mm_merge(a, x, true);
+          b = mm_merge(b, y, false);
+        }
+      }
+      if (lane == 0) {
+        part[0][wv] = a;
+        part[1][wv] = b;
+      }
+      __syncthreads();
+      if (t == 0 && s1 > s0) {
+        for (int w = 1; w < kMergeThreads / 64; ++w) {
+          if (o.kind == OP_SUMS) {
+            a += part[0][w];
+            b += part[1][w];
+          } else if (o.kind == OP_MINMAX) {
+            a = (unsigned)min((int)(unsigned)a, (int)(unsigned)part[0][w]);
+            b = (unsigned)max((int)(unsigned)b, (int)(unsigned)part[1][w]);
+          } else {
+            a = mm_merge(a, part[0][w], true);
+            b = mm_merge(b, part[1][w], false);
+          }
+        }
+        if (o.kind == OP_SUMS) {
+          atomicAdd((unsigned long long*)out, a);
+          atomicAdd((unsigned long long*)out + 1, b);
+        } else if (o.kind == OP_MINMAX) {
+          atomicMin((int32_t*)out, (int)(unsigned)a);
+          atomicMax((int32_t*)out + 1, (int)(unsigned)b);
+        } else {
+          unsigned long long* keys = (unsigned long long*)((uint8_t*)out + kMMKeyOffset);
+          const int sub = blockIdx.x % kMMSubKeys;
+          merge_key(&keys[sub], a, true);
+          merge_key(&keys[kMMSubKeys + sub], b, false);
+        }
+      }
+      __syncthreads();
+    }
+    off += red_block_words(o.kind, o.p0);
+  }
+}
+
+hipError_t launch_merge_partials(const GProg* dev_prog, const IOTable& io, const uint32_t* ws, int nslots,
+                                 int slot_words, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  const int groups = nslots < kMergeGroups ? nslots : kMergeGroups;
+  hipLaunchKernelGGL(k_merge_partials, dim3(groups), dim3(kMergeThreads), 0, s, dev_prog, io, ws, nslots, slot_words);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce_init(int kind, void* result, int num_bins, hipStream_t s) {
   switch (kind) {

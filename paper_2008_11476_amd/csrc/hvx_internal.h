@@ -173,6 +173,7 @@ struct Graph : Object {
   bool prepared = false;
   std::vector<size_t> scratch_off;
   std::vector<size_t> scratch_pitch;
+  std::vector<size_t> ws_off;  // per group: workspace of a generated reducing kernel in the scratch block
   GProg* dev_progs = nullptr;  // device copies of the groups' generic programs (index = group)
   void* last_stream = nullptr;
   bool scheduled = false;

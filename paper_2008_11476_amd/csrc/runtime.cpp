@@ -51,6 +51,7 @@ void free_graph_device(Graph* g) {
   g->scratch_total = 0;
   g->scratch_off.clear();
   g->scratch_pitch.clear();
+  g->ws_off.clear();
   g->prepared = false;
   g->scheduled = false;
 }
@@ -83,6 +84,16 @@ static hvx_status ensure_scratch(Graph* g) {
     g->scratch_off[v] = total;
     g->scratch_pitch[v] = pitch;
     total += (pitch * p.vals[v].h + 255) & ~(size_t)255;
+  }
+  // workspace of the generated kernels that reduce: one slot of partial
+  // results per work-group (tile)
+  g->ws_off.assign(p.groups.size(), 0);
+  for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+    const Group& gr = p.groups[gi];
+    if (!gr.gen || gen_batchable(gr.gen)) continue;
+    g->ws_off[gi] = total;
+    const size_t bytes = (size_t)gen_blocks(gr.gen, gr.prog.w, gr.prog.h) * red_slot_words(gr.prog) * 4;
+    total += (bytes + 255) & ~(size_t)255;
   }
   if (total && hipMalloc((void**)&g->scratch_base, total) != hipSuccess) {
     g->scratch_base = nullptr;
@@ -296,9 +307,18 @@ static hvx_status launch_group(Graph* g, const Group& gr, hipStream_t s, const B
     for (int i = 0; i < P.nops && e == hipSuccess; ++i)
       if (is_reduce_op(P.ops[i].kind))
         e = launch_reduce_init(P.ops[i].kind, io.ptr[P.vals[P.ops[i].out].io], P.ops[i].p0, s);
-    if (e == hipSuccess)
-      e = gr.gen ? gen_launch(gr.gen, g->ctx->device, P, g->dev_progs + gi, io, g->ctx->num_cus, s)
+    if (e == hipSuccess && gr.gen && !gen_batchable(gr.gen)) {
+      // a generated kernel that reduces leaves one slot of partial results
+      // per work-group; a second kernel merges them into the results
+      char* base = b && b->scratch ? b->scratch : g->scratch_base;
+      uint32_t* ws = (uint32_t*)(base + g->ws_off[gi]);
+      e = gen_launch(gr.gen, g->ctx->device, P, g->dev_progs + gi, io, g->ctx->num_cus, s, ws);
+      if (e == hipSuccess)
+        e = launch_merge_partials(g->dev_progs + gi, io, ws, (int)gen_blocks(gr.gen, P.w, P.h), red_slot_words(P), s);
+    } else if (e == hipSuccess) {
+      e = gr.gen ? gen_launch(gr.gen, g->ctx->device, P, g->dev_progs + gi, io, g->ctx->num_cus, s, nullptr)
                  : launch_generic(P, g->dev_progs + gi, io, g->ctx->num_cus, s);
+    }
     for (int i = 0; i < P.nops && e == hipSuccess; ++i)
       if (is_reduce_op(P.ops[i].kind)) {
         void* out = io.ptr[P.vals[P.ops[i].out].io];
