@@ -83,6 +83,14 @@ __device__ __forceinline__ u32 add2(u32 a, u32 b) {
 __device__ __forceinline__ u32 sub2(u32 a, u32 b) {
   return __builtin_bit_cast(u32, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
 }
+// sums and differences of integers below 1024 held as half-precision bit
+// patterns (subnormals, exact; a difference of equal values is +0)
+__device__ __forceinline__ u32 hadd2(u32 a, u32 b) {
+  return __builtin_bit_cast(u32, __builtin_bit_cast(h16x2, a) + __builtin_bit_cast(h16x2, b));
+}
+__device__ __forceinline__ u32 hsub2(u32 a, u32 b) {
+  return __builtin_bit_cast(u32, __builtin_bit_cast(h16x2, a) - __builtin_bit_cast(h16x2, b));
+}
 __device__ __forceinline__ u32 shl2(u32 a, int s) {
   return __builtin_bit_cast(u32, __builtin_bit_cast(u16x2, a) << (unsigned short)s);
 }
@@ -387,19 +395,28 @@ struct EdgeStream {
     extend<1, HEDGE>(sv, es, L, repl1, cs1);
     extend<1, HEDGE>(dv, ed, L, repl1, 0u);
     u32 gx[8], gy[8], eu[9];
+    // With the phase, the gradients are formed in half precision (dv is
+    // already): sums of integers below 1024 as subnormals are exact, and the
+    // sign-magnitude results give |gx| and |gy| by clearing one bit each,
+    // for the phase and the magnitude alike.
 #pragma unroll
-    for (int i = 0; i < 9; ++i) eu[i] = add2(ed.v[i + 1], ed.v[i + 2]);
+    for (int i = 0; i < 9; ++i) eu[i] = PHASE ? hadd2(ed.v[i + 1], ed.v[i + 2]) : add2(ed.v[i + 1], ed.v[i + 2]);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      gx[k] = sub2(es.v[k + 3], es.v[k + 1]);
-      gy[k] = add2(eu[k], eu[k + 1]);
+      gx[k] = PHASE ? hsub2(es.v[k + 3], es.v[k + 1]) : sub2(es.v[k + 3], es.v[k + 1]);
+      gy[k] = PHASE ? hadd2(eu[k], eu[k + 1]) : add2(eu[k], eu[k + 1]);
     }
     if (PHASE) {
       // levels of pixels k and k+8 in the low bytes of lv[k]'s halves; output
       // word j holds pixels 4j .. 4j+3
       u32 lv[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) lv[k] = phase_pair(gx[k], gy[k]);
+      for (int k = 0; k < 8; ++k) {
+        const u32 ax = gx[k] & 0x7FFF7FFFu, ay = gy[k] & 0x7FFF7FFFu;
+        lv[k] = phase_pair_sm(gx[k], gy[k], ax, ay);
+        gx[k] = ax;
+        gy[k] = ay;
+      }
       u32x4 po;
       const u32 a01 = perm(lv[1], lv[0], 0x06020400u), a23 = perm(lv[3], lv[2], 0x06020400u);
       const u32 a45 = perm(lv[5], lv[4], 0x06020400u), a67 = perm(lv[7], lv[6], 0x06020400u);
@@ -489,7 +506,7 @@ struct EdgeStream {
     for (int k = 0; k < 8; ++k) {
       s1[k] = add2(g0[k], g1[k]);
       sv[k] = add2(s0[k], s1[k]);
-      dv[k] = sub2(g1[k], gm1[k]);
+      dv[k] = PHASE ? hsub2(g1[k], gm1[k]) : sub2(g1[k], gm1[k]);
     }
     emit(y, sv, dv);
   }

@@ -53,6 +53,27 @@ constexpr uint32_t kPhaseAddLo = 0x81404100u, kPhaseAddHi = 0x01C0C180u;  // 64 
 // reciprocal estimate 2^6 / F ~ bits^-1(kRcpMagic - bits(F)), in 16-bit wrap-around
 constexpr unsigned short kRcpMagic = 0x8F9C;
 
+// The octant angle's two factors for two pixels, from mn = min(|gx|, |gy|)
+// and mx = max(|gx|, |gy|) (integers below 1024 in 16-bit halves): zz = z / 8
+// and p = 8 c0 - 64 c1 zz, so that zz p is 8 alpha (before rounding).
+struct PhaseZP {
+  h16x2 zz, p;
+};
+__device__ __forceinline__ PhaseZP phase_zp(i16x2 mn, i16x2 mx) {
+  const h16x2 k32768 = {(_Float16)32768.0f, (_Float16)32768.0f};
+  // mx = 0 needs no guard: the estimate for F = 0 is finite, so zz = 0
+  const h16x2 F = __builtin_bit_cast(h16x2, mx) * k32768;  // mx 2^-9
+  const w16x2 magic = {kRcpMagic, kRcpMagic};
+  const h16x2 R = __builtin_bit_cast(h16x2, magic - __builtin_bit_cast(w16x2, F));
+  const h16x2 k128 = {(_Float16)128.0f, (_Float16)128.0f};
+  const h16x2 E = __builtin_elementwise_fma(-F, R, k128);
+  PhaseZP r;
+  r.zz = (__builtin_bit_cast(h16x2, mn) * R) * E;
+  const h16x2 c0 = {(_Float16)345.0f, (_Float16)345.0f}, c1 = {(_Float16)712.0f, (_Float16)712.0f};
+  r.p = __builtin_elementwise_fma(-c1, r.zz, c0);
+  return r;
+}
+
 // gx, gy: two signed 16-bit gradients each (|g| <= 1023).  Returns the two
 // phase levels in the low bytes of the two halves.
 __device__ __forceinline__ uint32_t phase_pair(uint32_t gx, uint32_t gy) {
@@ -60,20 +81,9 @@ __device__ __forceinline__ uint32_t phase_pair(uint32_t gx, uint32_t gy) {
   const i16x2 z0 = {0, 0};
   const i16x2 ax = __builtin_elementwise_max(x, z0 - x);
   const i16x2 ay = __builtin_elementwise_max(y, z0 - y);
-  const i16x2 mn = __builtin_elementwise_min(ax, ay);
-  // mx = 0 needs no guard: the estimate for F = 0 is finite, so zz = 0
-  const i16x2 mx = __builtin_elementwise_max(ax, ay);
-  const h16x2 k32768 = {(_Float16)32768.0f, (_Float16)32768.0f};
-  const h16x2 F = __builtin_bit_cast(h16x2, mx) * k32768;  // mx 2^-9
-  const w16x2 magic = {kRcpMagic, kRcpMagic};
-  const h16x2 R = __builtin_bit_cast(h16x2, magic - __builtin_bit_cast(w16x2, F));
-  const h16x2 k128 = {(_Float16)128.0f, (_Float16)128.0f};
-  const h16x2 E = __builtin_elementwise_fma(-F, R, k128);
-  const h16x2 zz = (__builtin_bit_cast(h16x2, mn) * R) * E;
-  const h16x2 c0 = {(_Float16)345.0f, (_Float16)345.0f}, c1 = {(_Float16)712.0f, (_Float16)712.0f};
-  const h16x2 p = __builtin_elementwise_fma(-c1, zz, c0);
+  const PhaseZP f = phase_zp(__builtin_elementwise_min(ax, ay), __builtin_elementwise_max(ax, ay));
   const h16x2 k1024 = {(_Float16)1024.0f, (_Float16)1024.0f};
-  const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(zz, p, k1024));
+  const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(f.zz, f.p, k1024));
   const uint32_t d = __builtin_bit_cast(uint32_t, ax - ay);  // sign where |gy| > |gx|
   // t = gy ^ (gx & bits 13,14) ^ (d & bit 13), as two three-input bit operations
   // (truth table 0x78 is s0 ^ (s1 & s2))
@@ -83,6 +93,39 @@ __device__ __forceinline__ uint32_t phase_pair(uint32_t gx, uint32_t gy) {
   const uint32_t neg = __builtin_amdgcn_perm(kPhaseNegHi, kPhaseNegLo, o);
   const uint32_t add = __builtin_amdgcn_perm(kPhaseAddHi, kPhaseAddLo, o);
   return (a ^ neg) + add;
+}
+
+// 64 q by the code o = 4 f + 3 s1 of phase_pair_sm (entries 1, 2, 5, 6 unused)
+constexpr uint32_t kPhaseSmAddLo = 0xC0000000u, kPhaseSmAddHi = 0x40000080u;
+
+// phase_pair for gradients in sign-magnitude form: gx and gy are the
+// half-precision bit patterns of integers with |g| <= 1023 (the sign in bit
+// 15, the magnitude as a subnormal below it), as sums and differences of
+// such integers in half precision produce them exactly; ax and ay are gx and
+// gy with the sign bits cleared, i.e. |gx| and |gy| as integers.  Returns
+// the same levels as phase_pair, each in the low byte of its half.
+//  - d = gx - gy as 16-bit integers is |gx| - |gy| plus 2^15 (s2 ^ s3):
+//    bits 10..14 hold s1 and bit 15 holds s1 ^ s2 ^ s3, which is whether
+//    alpha is negated;
+//  - the negation goes into the sign of the polynomial factor, and the last
+//    fused multiply-add rounds 1280 +- alpha to the grid of spacing 1
+//    (rounding to nearest even treats +x and -x alike around an even base,
+//    so the low byte is the negated level exactly);
+//  - the multiple q of 64 levels is a function of s1 and one bit of
+//    (s2, s3, s1 ^ s2 ^ s3); one three-input bit operation on gx, gy and d
+//    puts that bit in bit 15 (truth table 0x72) and s1 in bits 13 and 14,
+//    and one shift and one byte permute look q up.
+__device__ __forceinline__ uint32_t phase_pair_sm(uint32_t gx, uint32_t gy, uint32_t ax, uint32_t ay) {
+  const i16x2 x = __builtin_bit_cast(i16x2, ax), y = __builtin_bit_cast(i16x2, ay);
+  const PhaseZP f = phase_zp(__builtin_elementwise_min(x, y), __builtin_elementwise_max(x, y));
+  const uint32_t d = __builtin_bit_cast(uint32_t, __builtin_bit_cast(w16x2, gx) - __builtin_bit_cast(w16x2, gy));
+  const h16x2 ps = __builtin_bit_cast(
+      h16x2, __builtin_amdgcn_bitop3_b32(__builtin_bit_cast(uint32_t, f.p), d, 0x80008000u, 0x78));
+  const h16x2 k1280 = {(_Float16)1280.0f, (_Float16)1280.0f};
+  const uint32_t a = __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(f.zz, ps, k1280));
+  const uint32_t t = __builtin_amdgcn_bitop3_b32(gx, gy, d, 0x72);
+  const uint32_t o = __builtin_bit_cast(uint32_t, __builtin_bit_cast(w16x2, t) >> (unsigned short)13);
+  return a + __builtin_amdgcn_perm(kPhaseSmAddHi, kPhaseSmAddLo, o);
 }
 
 }  // namespace hvx

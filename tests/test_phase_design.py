@@ -89,3 +89,62 @@ def test_octant_code_matches_the_quadrant_rules():
     assert list(ref[8:13]) == [0, 64, 128, 192, 0]
     d = np.abs(lev - ref) % 256
     assert np.all(np.minimum(d, 256 - d) <= 1)
+
+
+# the variant for gradients held as half-precision bit patterns (sign and
+# subnormal magnitude), which the fused edge + phase kernels form directly
+ADD_SM = [0x00, 0x00, 0x00, 0xC0, 0x80, 0x00, 0x00, 0x40]
+
+
+def _sign_magnitude(g):
+    return ((g < 0).astype(np.int64) << 15) | np.abs(g)
+
+
+def _bitop3(s0, s1, s2, tt):
+    """v_bitop3_b32 on 16-bit values: bit i of tt is the result for
+    (s0, s1, s2) = (i >> 2 & 1, i >> 1 & 1, i & 1)."""
+    r = np.zeros_like(s0)
+    for i in range(8):
+        if (tt >> i) & 1:
+            r |= (s0 if i & 4 else ~s0) & (s1 if i & 2 else ~s1) & (s2 if i & 1 else ~s2)
+    return r & 0xFFFF
+
+
+def _levels_sm(gx, gy):
+    hx, hy = _sign_magnitude(gx), _sign_magnitude(gy)
+    ax, ay = hx & 0x7FFF, hy & 0x7FFF
+    mn, mx = np.minimum(ax, ay), np.maximum(ax, ay)
+    F = _rnd(_half(mx) * 32768.0)
+    R = _half(MAGIC - _bits(F))
+    E = _rnd(128.0 - F * R)
+    zz = _rnd(_rnd(_half(mn) * R) * E)
+    p = _rnd(C0 - C1 * zz)
+    d = (hx - hy) & 0xFFFF                 # |gx| - |gy| + 2^15 (s2 ^ s3)
+    ps = np.where(d >> 15, -p, p)          # the sign of the factor: alpha negated
+    a = _bits(_rnd(zz * ps + 1280.0)) & 0xFF
+    o = _bitop3(hx, hy, d, 0x72) >> 13
+    return (a + np.array(ADD_SM)[o]) & 0xFF
+
+
+def test_sign_magnitude_variant_gives_the_same_levels():
+    r = np.arange(-1023, 1024, dtype=np.int64)
+    for i0 in range(0, r.size, 256):
+        gx, gy = np.meshgrid(r, r[i0:i0 + 256])
+        lev, _ = _levels(gx, gy)
+        assert np.array_equal(_levels_sm(gx, gy), lev)
+
+
+def test_half_precision_gradients_are_sign_magnitude_integers():
+    # sums and differences of integers below 1024 in half precision, as the
+    # kernels form Sobel gradients, are exact and give sign | magnitude,
+    # with +0 for a zero difference
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 1021, 200000)
+    b = rng.integers(0, 1021, 200000)
+    a[:1000] = b[:1000]
+    diff = _bits(_half(a) - _half(b))
+    assert np.array_equal(diff, _sign_magnitude(a - b))
+    u = rng.integers(-510, 511, 200000)
+    v = rng.integers(-510, 511, 200000)
+    s = _bits(_half(_sign_magnitude(u)) + _half(_sign_magnitude(v)))
+    assert np.array_equal(s, _sign_magnitude(u + v))
