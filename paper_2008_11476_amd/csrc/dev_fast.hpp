@@ -873,14 +873,27 @@ struct RowQueue {
 };
 
 // The lane's four pixels x0..x3 of an input row as two registers of 16-bit
-// pairs: even (x0, x2) and odd (x1, x3).
-__device__ __forceinline__ u32 even_pair(u32 r) { return perm(0u, r, 0x0C020C00u); }
-__device__ __forceinline__ u32 odd_pair(u32 r) { return perm(0u, r, 0x0C030C01u); }
+// pairs: even (x0, x2) and odd (x1, x3).  The selector is an operand in a
+// scalar register (the compiler otherwise rebuilds it in a vector register
+// on every row).
+__device__ __forceinline__ u32 perm_zero_s(u32 r, u32 sel) {
+  u32 o;
+  asm("v_perm_b32 %0, 0, %1, %2" : "=v"(o) : "v"(r), "s"(sel));
+  return o;
+}
+__device__ __forceinline__ u32 even_pair(u32 r) { return perm_zero_s(r, 0x0C020C00u); }
+__device__ __forceinline__ u32 odd_pair(u32 r) { return perm_zero_s(r, 0x0C030C01u); }
 // a + 2 b + c on 16-bit pairs (one packed multiply-add; the inline constant 2
 // sits in the low half, which op_sel_hi feeds to both halves)
 __device__ __forceinline__ u32 sum121(u32 a, u32 b, u32 c) {
   u32 r;
   asm("v_pk_mad_u16 %0, %1, 2, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(b), "v"(add2(a, c)));
+  return r;
+}
+// a + b + c in one instruction
+__device__ __forceinline__ int add3(int a, int b, int c) {
+  int r;
+  asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
   return r;
 }
 // signed 16-bit half h0 of a times half h1 of b (0 low, 1 high), into 32 bits
@@ -950,11 +963,14 @@ __device__ __forceinline__ void hsums(const St& s, u32 a, u32 b, u32 c, int h[3]
   for (int q = 0; q < 3; ++q) {
     int e[8];
     extend4<2, HEDGE>(p[q], e, s.L, s.repl1, s.c1);
-    const int t01 = e[0] + e[1], t23 = e[2] + e[3], t45 = e[4] + e[5], t67 = e[6] + e[7];
-    h[q][0] = t01 + t23 + e[4];
-    h[q][1] = e[1] + t23 + t45;
-    h[q][2] = t23 + t45 + e[6];
-    h[q][3] = e[3] + t45 + t67;
+    // six three-input adds: m and n are the sums of the middle and right
+    // triples, each output adds the rest of its window (written out, as the
+    // compiler re-associates the sums into eight two- and three-input adds)
+    const int m = add3(e[2], e[3], e[4]), n = add3(e[5], e[6], e[7]);
+    h[q][0] = add3(e[0], e[1], m);
+    h[q][1] = add3(e[1], m, e[5]);
+    h[q][2] = add3(m, e[5], e[6]);
+    h[q][3] = add3(e[3], e[4], n);
   }
 }
 
