@@ -159,8 +159,13 @@ def batch_run(hvx, torch, ctx, graphs, steps, warmup, modes=("persistent", "dire
     else:
         hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_ROWS, rows, ctx=ctx)
     alg = hvx.hvx_batch_query(b, hvx.HVX_QUERY_ALG_BYTES)
-    per_mode = {"rows_per_item": hvx.hvx_batch_query(b, hvx.HVX_QUERY_ROWS_PER_ITEM),
-                "work_items": hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_OPS)}
+    rows_item = hvx.hvx_batch_query(b, hvx.HVX_QUERY_ROWS_PER_ITEM)
+    if rows_item == 0:
+        # 0: each graph runs its own rows per item; report them when all agree
+        own = {hvx.hvx_graph_query(g, hvx.HVX_QUERY_ROWS_PER_ITEM) for g in graphs}
+        if len(own) == 1:
+            rows_item = own.pop()
+    per_mode = {"rows_per_item": rows_item, "work_items": hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_OPS)}
     best = None
     for mode in modes:
         hvx.hvx_batch_set_option(b, hvx.HVX_BATCH_PERSISTENT, int(mode == "persistent"))
