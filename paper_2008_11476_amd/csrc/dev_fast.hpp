@@ -256,10 +256,13 @@ struct LdsRows {
   int64_t pitch;
   u32 lin;  // lane byte offset
   int H, lane, qbase, y0, y1;
+  // the image row of stream row r is ab + ad r (ad = -1: a band streamed
+  // bottom-up, its rows reflected within the band)
+  int ab = 0, ad = 1;
 
   // direct-to-LDS load of input row r (clamped to the image) into its slot
   __device__ __forceinline__ void issue(int r) const {
-    const int rc = min(max(r, 0), H - 1);
+    const int rc = min(max(ab + ad * r, 0), H - 1);
     const uintptr_t row = uniform_addr((uintptr_t)base + (uintptr_t)((int64_t)rc * pitch));
     u32x4* slot = q + ((r - qbase) & (Q - 1)) * (64 * NB);
 #pragma unroll
@@ -317,6 +320,12 @@ constexpr int kEdgeQ = 4, kGauss5Q = 4, kUyvyQ = 4;
 // queue.
 // WIDE selects the 32-bit magnitude test; otherwise the bound fits the
 // saturating 16-bit test (thr_not >= -32768).
+// A band can stream bottom-up: stream row u is image row ab + ad u with
+// ad = -1, i.e. the band reflected within itself.  The vertical filters are
+// then applied upwards, which flips the sign of gy and nothing else, so only
+// the magnitude (gy squared) may use it.  Neighbouring bands that stream in
+// opposite directions read the rows they share at about the same time (both
+// at their start or both at their end), so the second read hits L2.
 template <bool PHASE, bool HEDGE, bool WIDE>
 struct EdgeStream {
   const EdgeDesc& d;
@@ -340,6 +349,8 @@ struct EdgeStream {
   u32 gr[3][8];   // Gaussian rows y-1, y, y+1
   u32 sr[2][8];   // G(y-1) + G(y)
   LdsRows<1, PHASE ? 2 : 1, kEdgeQ> rows;  // input rows (one 16-byte load per row; 1 or 2 stores)
+  int ab = 0, ad = 1;                      // image row of stream row u: ab + ad u
+  __device__ __forceinline__ int act(int u) const { return ab + ad * u; }
 
   __device__ __forceinline__ EdgeStream(const EdgeDesc& d_, int strip, u32x4* lds) : d(d_) {
     L = make_lanes(d.g, strip);
@@ -372,7 +383,8 @@ struct EdgeStream {
   }
   __device__ __forceinline__ void unpk(u32x4 r, int y, u32 p[8]) const {
     unpack16(r, p);
-    if (!repl0 && (y < 0 || y >= H)) {
+    const int ya = act(y);
+    if (!repl0 && (ya < 0 || ya >= H)) {
       // a rare, wave-uniform case: the empty asm keeps it a branch (the
       // compiler would otherwise select all eight registers on every row)
       asm volatile("");
@@ -424,7 +436,7 @@ struct EdgeStream {
       po.y = perm(a67, a45, 0x05040100u);
       po.z = perm(a23, a01, 0x07060302u);
       po.w = perm(a67, a45, 0x07060302u);
-      if (L.store) store_row16_uniform(ph0, pp, y, lout, po);
+      if (L.store) store_row16_uniform(ph0, pp, act(y), lout, po);
     }
     // magnitude + threshold as one integer test: gx^2 + gy^2 > T, i.e. the
     // sign of gx^2 + gy^2 + thr_not (thr_not = -T - 1); mask bytes are 0xFF
@@ -471,7 +483,7 @@ struct EdgeStream {
       o.z = tv4 ^ ((perm(r[9], r[8], 0x0c0c0b09u) | perm(r[11], r[10], 0x0b090c0cu)) & x4);
       o.w = tv4 ^ ((perm(r[13], r[12], 0x0c0c0b09u) | perm(r[15], r[14], 0x0b090c0cu)) & x4);
     }
-    if (L.store) store_row16_uniform(out0, op, y, lout, o);
+    if (L.store) store_row16_uniform(out0, op, act(y), lout, o);
   }
   // Output row y; J is the phase of y in the six-row unrolled sequence.
   template <int J>
@@ -488,7 +500,8 @@ struct EdgeStream {
     u32x4 cur;
     rows.take(y, &cur);
     keep_vgpr(lout);
-    if (y + 1 < H) {
+    const int ga = act(y + 1);  // image row of Gaussian row y+1 (past the band's end)
+    if (ad > 0 ? ga < H : ga >= 0) {
       unpk(cur, y + 2, in2);
       u32 v[8];
 #pragma unroll
@@ -510,8 +523,13 @@ struct EdgeStream {
     }
     emit(y, sv, dv);
   }
-  // Output rows [y0, y1), top to bottom.
-  __device__ __forceinline__ void run(int y0, int y1) {
+  // Output rows [y0, y1), top to bottom, or bottom to top when `up` (which
+  // only the magnitude may use: gy changes sign).
+  __device__ __forceinline__ void run(int y0, int y1, bool up = false) {
+    ab = up ? y0 + y1 - 1 : 0;
+    ad = up ? -1 : 1;
+    rows.ab = ab;
+    rows.ad = ad;
     // prologue: G(y0-1), G(y0) and the pairwise state for row y0
     rows.start(y0, y1);
     u32 a[8], b[8], c[8], e[8];
@@ -529,7 +547,8 @@ struct EdgeStream {
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = add2(add2(b[k], c[k]), add2(c[k], e[k]));
     gauss_h(v, gr[1]);  // G(y0)
-    if (y0 >= 1) {
+    const int pa = act(y0 - 1);  // image row of Gaussian row y0-1 (before the band's start)
+    if (ad > 0 ? pa >= 0 : pa < H) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) v[k] = add2(add2(a[k], b[k]), add2(b[k], c[k]));
       gauss_h(v, gr[0]);  // G(y0-1)
@@ -570,17 +589,19 @@ template <bool PHASE>
 __device__ __forceinline__ void edge_item(const EdgeDesc& d, int strip, int band, u32x4* lds) {
   const int y0 = band * d.g.rows;
   const int y1 = min(y0 + d.g.rows, d.g.h);
+  // without the phase, odd bands stream bottom-up
+  const bool up = !PHASE && (band & 1);
   if (d.thr_not < -32768) {
     // bounds above 32767 (thresholds of 181 and more): the 32-bit test, with
     // the border-aware stream on every strip
     EdgeStream<PHASE, true, true> s(d, strip, lds);
-    s.run(y0, y1);
+    s.run(y0, y1, up);
   } else if (strip == 0 || d.g.w <= (strip + 1) * kStripPx + kLanePx) {
     EdgeStream<PHASE, true, false> s(d, strip, lds);
-    s.run(y0, y1);
+    s.run(y0, y1, up);
   } else {
     EdgeStream<PHASE, false, false> s(d, strip, lds);
-    s.run(y0, y1);
+    s.run(y0, y1, up);
   }
   // no load into the queue may still be in flight when the wave moves on
   wait_vmem<0>();
