@@ -148,16 +148,22 @@ def test_batch_rows_option(ctx):
     hvx.hvx_release_batch(b)
 
 
-@pytest.mark.parametrize("kind", ["edge", "edge_phase_constant", "gauss5", "uyvy_gauss5", "corner"])
+@pytest.mark.parametrize("kind", ["edge", "edge_constant", "edge_wide", "edge_phase_constant", "gauss5", "uyvy_gauss5",
+                                  "corner"])
 def test_batch_short_bands_every_stream(ctx, kind):
     """Bands of 1 to 9 rows (shorter than the row queue and its prologue),
     on a frame whose height leaves a ragged last band, through each fused
     stream in both launch modes: the explicit memory waits of the row queues
-    have their start and end cases here."""
+    have their start and end cases here.  The edge stream without Phase runs
+    odd bands bottom-up; its ragged last band is odd for 4, 5 and 7 rows."""
     import torch
     w, h = 1100, 37
     if kind == "edge":
         spec = gs.edge_spec(synth.edge_image(w, h, seed=21))
+    elif kind == "edge_constant":
+        spec = gs.edge_spec(synth.edge_image(w, h, seed=26), b0=("constant", 9), b1=("constant", 0))
+    elif kind == "edge_wide":  # threshold 200: the 32-bit magnitude test
+        spec = gs.edge_spec(synth.edge_image(w, h, seed=27), b0=("constant", 250), thresh=200)
     elif kind == "edge_phase_constant":
         spec = gs.edge_spec(synth.edge_image(w, h, seed=22), phase=True, b0=("constant", 9), b1=("constant", 0))
     elif kind == "gauss5":
