@@ -482,8 +482,10 @@ int place_lds(const GProg& P, Layout& L, int tw, int th) {
 // Load group input v into LDS.  Interior tiles read whole 16-byte chunks
 // (every chunk holds a byte of the extent, so it lies inside the row's
 // pitch, a multiple of 64 bytes): one vector load per chunk, all of a
-// thread's loads issued before the first LDS write.  Edge tiles read
-// element by element inside the image (or the periodic copies under REPEAT).
+// thread's loads issued before the first LDS write.  (Loading four elements
+// per lane instead, so that the 16-byte LDS writes of consecutive lanes are
+// consecutive, measured slower overall.)  Edge tiles read element by element
+// inside the image (or the periodic copies under REPEAT).
 void emit_load(Text& t, const GProg& P, const Layout& L, int v, int TW, int TH) {
   const GVal& gv = P.vals[v];
   const int e = gv.ext, eh = L.eh[v], bpp = df_bytes(gv.df);
@@ -511,12 +513,12 @@ void emit_load(Text& t, const GProg& P, const Layout& L, int v, int TW, int TH) 
   t("        const int c = (int)threadIdx.x + k * %d;", kGenThreads);
   t("        if (c < %d) {", nch);
   t("          const int row = c / %d, q = c - row * %d;", cpr, cpr);
-  t("          int4* dst = (int4*)(L + %d + row * %d + q * %d);", off, rw, epc);
+  t("          gx_i4* dst = (gx_i4*)(L + %d + row * %d + q * %d);", off, rw, epc);
   t("#pragma unroll");
   t("          for (int j = 0; j < %d; j += 4)", epc);
-  t("            dst[j / 4] = make_int4(gx_elem<%d>(d[k], j), gx_elem<%d>(d[k], j + 1), gx_elem<%d>(d[k], j + 2),", gv.df,
+  t("            dst[j / 4] = gx_i4{gx_elem<%d>(d[k], j), gx_elem<%d>(d[k], j + 1), gx_elem<%d>(d[k], j + 2),", gv.df,
     gv.df, gv.df);
-  t("                                   gx_elem<%d>(d[k], j + 3));", gv.df);
+  t("                                   gx_elem<%d>(d[k], j + 3)};", gv.df);
   t("        }");
   t("      }");
   t("    } else {");
@@ -687,7 +689,7 @@ struct StageEmitter {
             return n;
           default: {
             t("        int %s[4];", n.c_str());
-            t("        { const int4 q = *(const int4*)(L + %s); %s[0] = q.x; %s[1] = q.y; %s[2] = q.z; %s[3] = q.w; }",
+            t("        { const gx_i4 q = gx_ld4(L + %s); %s[0] = q.x; %s[1] = q.y; %s[2] = q.z; %s[3] = q.w; }",
               lds_index(v, ESV, ESH, "0", "0").c_str(), n.c_str(), n.c_str(), n.c_str(), n.c_str());
             return n;
           }
@@ -717,10 +719,10 @@ struct StageEmitter {
         t("#pragma unroll");
         t("        for (int j = 0; j < %d; ++j) {", 2 * R + 1);
         const std::string dy = fmt("(j - %d)", R);
-        t("          const int4* r = (const int4*)(L + %s);", lds_index(v, ESV, ESH, "-4", dy.c_str()).c_str());
+        t("          const int32_t* r = L + %s;", lds_index(v, ESV, ESH, "-4", dy.c_str()).c_str());
         t("#pragma unroll");
         t("          for (int c = 0; c < 3; ++c) {");
-        t("            const int4 q = r[c];");
+        t("            const gx_i4 q = gx_ld4(r + 4 * c);");
         t("            w[j][4 * c] = q.x; w[j][4 * c + 1] = q.y; w[j][4 * c + 2] = q.z; w[j][4 * c + 3] = q.w;");
         t("          }");
         t("        }");
@@ -753,7 +755,7 @@ struct StageEmitter {
             ov.df, P.vals[o.in[0]].df == DF_F32 ? "true" : "false", a.c_str(), b.c_str(), c.c_str());
       }
       if (L.needs_lds[o.out])
-        t("        *(int4*)(L + %s) = make_int4(v%d[0], v%d[1], v%d[2], v%d[3]);",
+        t("        *(gx_i4*)(L + %s) = gx_i4{v%d[0], v%d[1], v%d[2], v%d[3]};",
           lds_index(o.out, ESV, ESH, "0", "0").c_str(), o.out, o.out, o.out, o.out);
       if (ov.store)
         t("        if (own%s) store4(%d, (uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);",
@@ -804,6 +806,16 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   emit_prelude(t, P, why, &ok);
   if (!ok) return false;
   t("__device__ constexpr int gx_zero4[4] = {0, 0, 0, 0};");
+  // LDS is read and written in whole 16-byte units: consecutive lanes then
+  // touch consecutive banks.  A read whose components are not all used would
+  // be narrowed to single dwords at a 16-byte lane stride, which hit a
+  // quarter of the banks; the empty asm keeps the whole vector.
+  t("typedef int gx_i4 __attribute__((ext_vector_type(4)));");
+  t("__device__ __forceinline__ gx_i4 gx_ld4(const int32_t* p) {");
+  t("  const gx_i4 q = *(const gx_i4*)p;");
+  t("  asm volatile(\"\" :: \"v\"(q));");
+  t("  return q;");
+  t("}");
   // one tile: IN = its halo lies inside the image
   t("template <bool IN>");
   t("__device__ __forceinline__ void gen_tile(const IOTable& io, int W, int H, int tx0, int ty0, int32_t* L%s) {",
