@@ -384,7 +384,7 @@ struct Batch : Object {
   int64_t alg_bytes = 0;
   int rows_override = 0;  // rows per work item for every image (0: each graph's own)
   int kinds = 0;          // bit set of the kinds in the single batch launch
-  // graphs whose plan is one generated kernel, by kernel: one launch each
+  // chains of generated kernels shared by several graphs: one launch per kernel
   struct GenSet {
     const GenKernel* k = nullptr;
     std::vector<GenBatchImage> imgs;
@@ -453,39 +453,49 @@ static hvx_status batch_build(Batch* b) {
       b->separate.push_back(g);
     }
   }
-  // graphs whose plan is one generated kernel: those sharing a kernel run
-  // in one launch over all their tiles (a work list of image and tile)
+  // graphs whose plan is a chain of generated kernels: the graphs with the
+  // same chain run it as one launch per kernel over all their tiles (a work
+  // list of image and tile), the chain's kernels in plan order, so every
+  // group still runs after the groups it reads
   {
-    std::map<const GenKernel*, std::vector<Graph*>> by_kernel;
+    auto chain_of = [](const Graph* g) {
+      std::vector<const GenKernel*> ks;
+      for (const Group& gr : g->plan->groups) {
+        if (gr.kind != FK_GENERIC || !gr.gen || !gen_batchable(gr.gen)) return std::vector<const GenKernel*>();
+        ks.push_back(gr.gen);
+      }
+      return ks;
+    };
+    std::map<std::vector<const GenKernel*>, std::vector<Graph*>> by_chain;
     for (Graph* g : b->separate) {
-      const auto& gs = g->plan->groups;
-      if (gs.size() == 1 && gs[0].kind == FK_GENERIC && gs[0].gen && gen_batchable(gs[0].gen))
-        by_kernel[gs[0].gen].push_back(g);
+      const auto ks = chain_of(g);
+      if (!ks.empty()) by_chain[ks].push_back(g);
     }
     std::vector<Graph*> rest;
     for (Graph* g : b->separate) {
-      const auto& gs = g->plan->groups;
-      const bool gen1 = gs.size() == 1 && gs[0].kind == FK_GENERIC && gs[0].gen && gen_batchable(gs[0].gen);
-      if (!gen1 || by_kernel[gs[0].gen].size() < 2) rest.push_back(g);
+      const auto ks = chain_of(g);
+      if (ks.empty() || by_chain[ks].size() < 2) rest.push_back(g);
     }
-    for (auto& kv : by_kernel) {
+    for (auto& kv : by_chain) {
       if (kv.second.size() < 2) continue;
-      Batch::GenSet set;
-      set.k = kv.first;
-      for (Graph* g : kv.second) {
-        const Group& gr = g->plan->groups[0];
-        GenBatchImage im;
-        memset(&im, 0, sizeof im);
-        hvx_status st = fill_io(g, gr, &im.io, nullptr);
-        if (st) return st;
-        im.w = gr.prog.w;
-        im.h = gr.prog.h;
-        im.block0 = (int32_t)set.blocks;
-        set.blocks += gen_blocks(set.k, gr.prog.w, gr.prog.h);
-        if (set.blocks > 0x7FFFFFFF) return set_error(c, HVX_ERROR_NOT_SUPPORTED, "batch launch too large");
-        set.imgs.push_back(im);
+      for (size_t stage = 0; stage < kv.first.size(); ++stage) {
+        Batch::GenSet set;
+        set.k = kv.first[stage];
+        for (Graph* g : kv.second) {
+          const Group& gr = g->plan->groups[stage];
+          GenBatchImage im;
+          memset(&im, 0, sizeof im);
+          hvx_status st = fill_io(g, gr, &im.io, nullptr);
+          if (st) return st;
+          im.w = gr.prog.w;
+          im.h = gr.prog.h;
+          im.block0 = (int32_t)set.blocks;
+          set.blocks += gen_blocks(set.k, gr.prog.w, gr.prog.h);
+          if (set.blocks > 0x7FFFFFFF) return set_error(c, HVX_ERROR_NOT_SUPPORTED, "batch launch too large");
+          set.imgs.push_back(im);
+        }
+        b->gensets.push_back(std::move(set));
       }
-      b->gensets.push_back(std::move(set));
     }
     b->separate.swap(rest);
     for (auto& set : b->gensets) {

@@ -558,3 +558,64 @@ def test_batch_runs_generated_kernels_once_per_kernel(ctx, use_graph):
     hvx.hvx_release_batch(b)
     for x in built:
         hvx.hvx_release_graph(x[2])
+
+
+def test_batch_runs_generated_chains_once_per_kernel(ctx, tmp_path):
+    """Graphs whose plan is a chain of generated kernels (FChain cut at every
+    value by a plan in the tune cache: three kernels) share one launch per
+    kernel of the chain, in plan order, so each kernel still runs after the
+    one it reads; outputs equal each graph run alone and the oracle."""
+    import json
+    import torch
+    from tests.test_gpu_codegen import _fchain
+    w, h = 300, 77
+    # the plan key of this graph shape, from a tuned copy in its own context
+    c1 = hvx.hvx_context_create(0)
+    try:
+        g0, outs0, keep0, imgs0 = _build(c1, _fchain(synth.edge_image(w, h, seed=1), ("replicate", 0)))
+        hvx.hvx_graph_autotune(g0, torch.cuda.current_stream().cuda_stream, 1, ctx=c1)
+        path = tmp_path / "tune.json"
+        hvx.hvx_context_save_tune_cache(c1, str(path))
+        hvx.hvx_release_graph(g0)
+    finally:
+        hvx.hvx_context_release(c1)
+    keys = [k for k in json.loads(path.read_text()) if k.startswith("plan|")]
+    assert len(keys) == 1, keys
+    forced = tmp_path / "forced.json"
+    forced.write_text(json.dumps({keys[0]: [0, 1, 1.0, list(range(64)), []]}))
+    c2 = hvx.hvx_context_create(0)
+    try:
+        hvx.hvx_context_load_tune_cache(c2, str(forced))
+        built = []
+        for seed in (2, 3, 4):
+            spec = _fchain(synth.edge_image(w, h, seed=seed), ("replicate", 0))
+            g, outs, keep, imgs = _build(c2, spec)
+            assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_KERNELS) == 3
+            assert hvx.hvx_graph_query(g, hvx.HVX_QUERY_NUM_GENERATED) == 3
+            built.append((spec, g, outs, keep))
+        alone = []
+        for spec, g, outs, keep in built:
+            hvx.hvx_graph_process(g, ctx=c2)
+            alone.append(_read(outs))
+            for t, _ in outs.values():
+                t.fill_(0x5A)
+        torch.cuda.synchronize()
+        b = hvx.hvx_batch_create(c2, [x[1] for x in built])
+        assert hvx.hvx_batch_query(b, hvx.HVX_QUERY_NUM_KERNELS) == 3
+        for rep in range(2):
+            log("generated chain batch rep %d" % rep)
+            hvx.hvx_batch_schedule(b, torch.cuda.current_stream().cuda_stream, ctx=c2)
+            torch.cuda.synchronize()
+            for (spec, g, outs, keep), ref in zip(built, alone):
+                got = _read(outs)
+                for name in got:
+                    assert np.array_equal(got[name], ref[name]), (name, rep)
+                compare(spec, got, spec.run_oracle())
+                for t, _ in outs.values():
+                    t.fill_(rep + 1)
+            torch.cuda.synchronize()
+        hvx.hvx_release_batch(b)
+        for x in built:
+            hvx.hvx_release_graph(x[1])
+    finally:
+        hvx.hvx_context_release(c2)
