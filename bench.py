@@ -595,13 +595,16 @@ def user_kernels(hvx, torch, ctx, rec, fused_only=False):
     del ib, iv, ob, ov
 
 
-def user_kernels_batch(hvx, torch, ctx, rec, nframes=32):
+def user_kernels_batch(hvx, torch, _shared_ctx, rec, nframes=32):
     """The user-kernel applications over 32 distinct 3840x2160 frames in one
     batch: the graphs share their generated kernel, so each application is
     one launch over every frame's tiles (throughput rather than one frame's
-    latency)."""
+    latency).  The graphs live in a context of their own, so they run the
+    default plan rather than the plan tuned for one frame (a smaller tile
+    that lowers one frame's latency and costs throughput over many)."""
     stream = torch.cuda.current_stream().cuda_stream
     w, h = 3840, 2160
+    ctx = hvx.hvx_context_create(0)
     inp, out = make_frames(hvx, torch, w, h, nframes)
     builders, convs = user_kernel_builders(hvx, ctx)
     handles = [(hvx.image_from_tensor(ctx, inp[i][1], hvx.HVX_DF_U8),
@@ -629,6 +632,7 @@ def user_kernels_batch(hvx, torch, ctx, rec, nframes=32):
     for a, o in handles:
         hvx.hvx_release_image(a)
         hvx.hvx_release_image(o)
+    hvx.hvx_context_release(ctx)
     del inp, out
     torch.cuda.empty_cache()
 
