@@ -96,3 +96,41 @@ def test_same_structure_other_size_and_reduction(ctx):
     hvx.hvx_graph_verify(g)
     assert _q(g, hvx.HVX_QUERY_NUM_KERNELS) == 1
     assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 1
+
+
+def test_generated_window_reads_are_whole_16_byte_lds_reads(ctx, tmp_path, monkeypatch):
+    """The LDS window reads of a generated kernel compile to 16-byte reads
+    (ds_read_b128), which consecutive lanes spread over consecutive banks.
+    Reads narrowed to single dwords at a 16-byte lane stride (ds_read2_b32,
+    ds_read_b32) would hit a quarter of the banks.  The source written at
+    verification is compiled here with hipcc for gfx950 and its assembly
+    inspected."""
+    import glob
+    import os
+    import subprocess
+    from paper_2008_11476_amd import build
+    monkeypatch.setenv("HVX_GEN_DUMP", str(tmp_path))
+    g = hvx.hvx_graph_create(ctx)
+    a, o = _img(ctx, 640, 480, k=0), _img(ctx, 640, 480, k=1)
+    v = [hvx.hvx_image_create_virtual(g) for _ in range(2)]
+    hvx.hvx_gaussian3x3_node(g, a, v[0])
+    hvx.hvx_custom_point_node(g, "a - b * 5 / 7", [a, v[0]], hvx.HVX_DF_S16, v[1])  # a source no other test builds
+    hvx.hvx_custom_point_node(g, "a + b", [a, v[1]], hvx.HVX_DF_U8, o)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 1
+    srcs = glob.glob(str(tmp_path / "hvx_gen_*.hip"))
+    assert len(srcs) == 1, srcs
+    text = open(srcs[0]).read()
+    # the hipRTC prelude declares a namespace that the full HIP headers define themselves
+    text = text.replace("namespace __hip_internal {}\nusing namespace __hip_internal;\n", "")
+    src = tmp_path / "k.hip"
+    src.write_text(text)
+    csrc = os.path.join(os.path.dirname(build.__file__), "csrc")
+    inc = os.path.join(os.path.dirname(os.path.dirname(build.__file__)), "include")
+    asm = tmp_path / "k.s"
+    r = subprocess.run([build._hipcc(), "-x", "hip", "-O3", "-std=c++17", "--offload-arch=gfx950", "--cuda-device-only",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-S", "-I", csrc, "-I", inc,
+                        str(src), "-o", str(asm)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    ops = [ln.split()[0] for ln in asm.read_text().splitlines() if ln.strip().startswith("ds_read")]
+    assert ops and all(op == "ds_read_b128" for op in ops), sorted(set(ops))
