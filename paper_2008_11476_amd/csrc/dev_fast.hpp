@@ -307,8 +307,10 @@ struct LdsRows {
   }
 };
 
-// queue depths (rows): 16 waves of a CU hold at most 160 KB of LDS
-constexpr int kEdgeQ = 4, kGauss5Q = 4, kUyvyQ = 4;
+// queue depths (rows).  The Gaussian5x5 streams run few rows per band, so
+// their queues are deeper; eight UYVY rows (16 KB per wave) leave room for
+// 10 waves per CU, which measured faster than 16 waves with four rows.
+constexpr int kEdgeQ = 4, kGauss5Q = 8, kUyvyQ = 8;
 
 // ---- Gaussian 3x3 -> Sobel 3x3 -> Magnitude -> Threshold (+ Phase) ----------
 
