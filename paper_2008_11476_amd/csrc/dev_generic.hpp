@@ -395,14 +395,16 @@ __device__ __forceinline__ int local_eval(const GOp& o, int out_df, const RD& rd
       return before < p && after <= p ? p : (out_df == DF_U8 ? 0 : -32768);
     }
     case OP_BOX5F: {
-      // fixed order: each row left to right, rows top to bottom
+      // fixed order: each column top to bottom, columns left to right (a
+      // thread that evaluates neighbouring outputs from one window forms the
+      // column sums they share once)
       float s = 0.f;
 #pragma unroll
-      for (int j = -2; j <= 2; ++j) {
-        float r = 0.f;
+      for (int i = -2; i <= 2; ++i) {
+        float c = 0.f;
 #pragma unroll
-        for (int i = -2; i <= 2; ++i) r += __int_as_float(rd(i, j));
-        s += r;
+        for (int j = -2; j <= 2; ++j) c += __int_as_float(rd(i, j));
+        s += c;
       }
       return __float_as_int(s);
     }
