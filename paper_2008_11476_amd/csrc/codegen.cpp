@@ -27,6 +27,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -84,6 +85,63 @@ std::string float_lit(float f) {
   uint32_t u;
   memcpy(&u, &f, 4);
   return fmt("__builtin_bit_cast(float, 0x%08xu)", u);
+}
+
+// A Convolve mask that is the outer product of a column and a row of
+// integers, m[j][i] = a[j] b[i], as those two factors (b divided by the gcd
+// of its entries; every integer factorisation is a multiple of that one).
+// Summing each window column with the weights a and then the column sums
+// with the weights b gives the same 32-bit wrapped sum as the mask itself,
+// since the two double sums are equal as integers.
+bool conv_rank_one(const GOp& o, int a[5], int b[5]) {
+  const int cols = o.p0, rows = o.p1;
+  int j0 = -1;
+  for (int j = 0; j < rows && j0 < 0; ++j)
+    for (int i = 0; i < cols; ++i)
+      if (o.mask[j * cols + i]) j0 = j;
+  if (j0 < 0) return false;
+  int g = 0;
+  for (int i = 0; i < cols; ++i) g = std::gcd(g, std::abs(o.mask[j0 * cols + i]));
+  int i0 = -1;
+  for (int i = 0; i < cols; ++i) {
+    b[i] = o.mask[j0 * cols + i] / g;
+    if (b[i] && i0 < 0) i0 = i;
+  }
+  for (int j = 0; j < rows; ++j) {
+    const int m0 = o.mask[j * cols + i0];
+    if (m0 % b[i0]) return false;
+    a[j] = m0 / b[i0];
+    for (int i = 0; i < cols; ++i)
+      if (o.mask[j * cols + i] != a[j] * b[i]) return false;
+  }
+  return true;
+}
+
+// column-first costs (4 + 2 rx) column sums of the non-zero weights of a
+// plus four sums of those of b, against four sums over the mask's non-zeros
+bool separable_pays(const GOp& o, const int a[5], const int b[5]) {
+  int na = 0, nb = 0, nm = 0;
+  for (int j = 0; j < o.p1; ++j) na += a[j] != 0;
+  for (int i = 0; i < o.p0; ++i) nb += b[i] != 0;
+  for (int k = 0; k < o.p0 * o.p1; ++k) nm += o.mask[k] != 0;
+  return na * (4 + 2 * o.rx) + 4 * nb < 4 * nm;
+}
+
+// "0u + c * (unsigned)(e) ..." over the non-zero weights: 32-bit wrapping.
+// With `i24` every e lies in [-2^23, 2^23): a weight that is not a power of
+// two then multiplies through the 24-bit multiplier (exact, full rate) in
+// place of the 32-bit one.
+std::string weighted_sum(const int* c, const std::vector<std::string>& e, bool i24) {
+  std::string s = "0u";
+  for (size_t k = 0; k < e.size(); ++k) {
+    if (!c[k]) continue;
+    const unsigned m = (unsigned)std::abs(c[k]);
+    s += c[k] > 0 ? " + " : " - ";
+    if (m == 1) s += "(unsigned)(" + e[k] + ")";
+    else if (i24 && (m & (m - 1))) s += "(unsigned)__mul24((int)(" + e[k] + fmt("), %u)", m);
+    else s += fmt("%uu * (unsigned)(", m) + e[k] + ")";
+  }
+  return s;
 }
 
 // The operator as a constant the device helpers fold over.
@@ -726,6 +784,33 @@ struct StageEmitter {
         t("            w[j][4 * c] = q.x; w[j][4 * c + 1] = q.y; w[j][4 * c + 2] = q.z; w[j][4 * c + 3] = q.w;");
         t("          }");
         t("        }");
+        int ca[5], cb[5];
+        const int vdf = P.vals[v].df;
+        if (o.kind == OP_CONVOLVE && (vdf == DF_U8 || vdf == DF_S16) && conv_rank_one(o, ca, cb) &&
+            separable_pays(o, ca, cb)) {
+          // column sums first (columns x - rx .. x + 3 + rx), shared by the
+          // four outputs; the mask is flipped as in the operator's definition
+          // (inputs are U8 or S16; a column sum stays within 24 bits when
+          // the sum of |a| times the input's largest magnitude does)
+          const int rx = o.rx, ry = o.ry;
+          long long bound = 0;
+          for (int j = 0; j < o.p1; ++j) bound += std::abs(ca[j]);
+          bound *= vdf == DF_U8 ? 255 : 32768;
+          for (int c = 4 - rx; c <= 7 + rx; ++c) {
+            std::vector<std::string> e;
+            for (int j = -ry; j <= ry; ++j) e.push_back(fmt("w[%d][%d]", R - j, c));
+            t("        const unsigned cs%d = %s;", c, weighted_sum(ca, e, true).c_str());
+          }
+          for (int q = 0; q < 4; ++q) {
+            std::vector<std::string> e;
+            for (int i = -rx; i <= rx; ++i) e.push_back(fmt("cs%d", 4 + q - i));
+            t("        {");
+            t("          const int s = (int)(%s);", weighted_sum(cb, e, bound < (1 << 23)).c_str());
+            t("          const int d = s >= 0 ? (s >> %d) : -((-s) >> %d);", o.p2, o.p2);
+            t("          v%d[%d] = %s(d);", o.out, q, ov.df == DF_U8 ? "sat_u8" : "sat_s16");
+            t("        }");
+          }
+        } else {
         t("        const int (*wp)[12] = w;");
         t("#pragma unroll");
         t("        for (int q = 0; q < 4; ++q) {");
@@ -739,6 +824,7 @@ struct StageEmitter {
           t("          }");
         }
         t("        }");
+        }
       } else if (o.kind == OP_LUT) {
         const std::string a = at4(0);
         t("#pragma unroll");

@@ -33,6 +33,21 @@ def _fchain(img, border):
     return gs.Spec(nodes, {"in": img}, {"c1": np.uint8, "c2": np.uint8, "out": np.uint8})
 
 
+# Convolve masks that are outer products of a column and a row (the
+# generated kernel sums window columns first): 5x3 with a zero weight, 5x5
+# with a signed row, and 5x3 whose column sums exceed 24 bits
+SEPARABLE = [(np.outer([1, -2, 0, 3, 1], [2, -1, 1]), 4, "u8"),
+             (np.outer([1, 4, 6, 4, 1], [-1, -2, 0, 2, 1]), 16, "u8"),
+             (np.outer([7000, -7000, 7000, -7000, 7000], [3, -1, 3]), 32768, "s16")]
+
+
+def _separable(img, border):
+    names = ["in", "c1", "c2", "out"]
+    nodes = [gs.N("convolve", [names[k]], [names[k + 1]], *border, params={"coeffs": m, "scale": s, "out_dtype": d})
+             for k, (m, s, d) in enumerate(SEPARABLE)]
+    return gs.Spec(nodes, {"in": img}, {"c1": np.uint8, "c2": np.uint8, "out": np.int16})
+
+
 def _tomasi(img):
     return gs.Spec([gs.N("sobel3x3", ["in"], ["gx", "gy"]),
                     gs.N("multiply_f32", ["gx", "gx"], ["pxx"]),
@@ -124,6 +139,7 @@ def _cases():
                                                                         synth.uniform_u8(w, h, seed=4))))
         for b in BORDERS:
             out.append(("fchain", (w, h, b), lambda img=img, b=b: _fchain(img, b)))
+            out.append(("separable", (w, h, b), lambda img=img, b=b: _separable(img, b)))
             out.append(("morph", (w, h, b), lambda img=img, b=b: _morph(img, b)))
             out.append(("nonlinear", (w, h, b), lambda img=img, b=b: _nonlinear(img, b)))
             out.append(("laplace_float", (w, h, b), lambda img=img, b=b: _laplace_float(img, b)))

@@ -2,6 +2,7 @@
 writes and compiles them (hipRTC needs no device), HVX_OPT_CODEGEN switches
 them off, and the groups that the one-operator kernels run with constant
 operators are not generated.  No compute call is made."""
+import numpy as np
 import pytest
 
 import paper_2008_11476_amd as hvx
@@ -134,3 +135,43 @@ def test_generated_window_reads_are_whole_16_byte_lds_reads(ctx, tmp_path, monke
     assert r.returncode == 0, r.stderr[-3000:]
     ops = [ln.split()[0] for ln in asm.read_text().splitlines() if ln.strip().startswith("ds_read")]
     assert ops and all(op == "ds_read_b128" for op in ops), sorted(set(ops))
+
+
+def test_rank_one_convolve_masks_sum_columns_first(ctx, tmp_path, monkeypatch):
+    """A Convolve mask that is the outer product of a column and a row is
+    evaluated in interior tiles as column sums shared by a thread's four
+    outputs (bit-identical in 32-bit wrapping arithmetic, since the double
+    sums agree as integers); other masks, and rank-one masks where it saves
+    nothing, keep the direct sum.  Checked on the source written at
+    verification."""
+    import glob
+    import re
+    monkeypatch.setenv("HVX_GEN_DUMP", str(tmp_path))
+    masks = [(np.outer([1, -2, 0, 3, 1], [2, -1, 5]), 1),       # rank one: 5 rows x 3 columns
+             (np.array([[1, 2, 3], [4, 5, 6], [7, 8, 11]]), 1),  # rank three
+             (np.outer([3, 0, -3], [6, -12, 6]), 1)]            # rank one, nothing saved
+    convs = [hvx.hvx_convolution_create(ctx, m, s) for m, s in masks]
+    g = hvx.hvx_graph_create(ctx)
+    a, o = _img(ctx, 640, 480, k=0), _img(ctx, 640, 480, k=1)
+    v = [hvx.hvx_image_create_virtual(g, 0, 0, hvx.HVX_DF_U8) for _ in range(2)]
+    hvx.hvx_convolve_node(g, a, convs[0], v[0])
+    hvx.hvx_convolve_node(g, v[0], convs[1], v[1])
+    hvx.hvx_convolve_node(g, v[1], convs[2], o)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 1
+    srcs = glob.glob(str(tmp_path / "hvx_gen_*.hip"))
+    assert len(srcs) == 1, srcs
+    text = open(srcs[0]).read()
+    cols = re.findall(r"const unsigned cs(\d+) = ", text)
+    # column sums for the first mask only (in each interior sweep of its
+    # stage), window columns x - 1 .. x + 4 of the 3-wide mask
+    assert cols and sorted(set(int(c) for c in cols)) == list(range(3, 9)), cols
+    assert len(cols) % 6 == 0 and all(cols.count(c) == len(cols) // 6 for c in cols)
+    # the column weights (1, -2, 3, 1; the zero dropped) and the row weights
+    # (2, -1, 5: 5 through the 24-bit multiplier)
+    assert re.search(r"cs3 = 0u \+ \(unsigned\)\(w\[4\]\[3\]\) - 2u \* \(unsigned\)\(w\[3\]\[3\]\) "
+                     r"\+ \(unsigned\)__mul24\(\(int\)\(w\[1\]\[3\]\), 3\) \+ \(unsigned\)\(w\[0\]\[3\]\);", text)
+    assert "(unsigned)__mul24((int)(cs3), 5)" in text
+    for c in convs:
+        hvx.hvx_release_convolution(c)
+    hvx.hvx_release_graph(g)
