@@ -65,34 +65,57 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int n, uint32_t a, uint32_t
 
 // ---- histogram of a U8 image ------------------------------------------------
 // Bin of value v: (v - offset) * num_bins / range for offset <= v < offset +
-// range, none otherwise.  The division is a multiply-high by m = ceil(2^32 /
-// range) (0 for range 1), exact because (v - offset) * num_bins < 2^16 and
-// range <= 2^8.  Pixels outside the interval, and the bytes past the row's
-// end in its last chunk, go to a spare counter (index 256), so that every
-// lane adds for every byte without a branch.  Each wave counts into its own
-// LDS sub-histogram (fewer collisions between waves).
-__global__ __launch_bounds__(kGThreads) void k_histogram(GlobalImg im, int num_bins, int offset, int range,
-                                                         uint32_t m, uint32_t* __restrict__ counts) {
-  constexpr int kSlots = 257;
-  __shared__ uint32_t sub[kGThreads / 64][kSlots];
+// range, none otherwise.  With y = (v - offset) * num_bins * 256 (mod 2^32),
+// formed as one 24-bit multiply-add v * B + D, the bin is the high word of
+// y * m for m = ceil(2^24 / range) (0 for range 1): y and m fit 24 bits, so
+// both products run on the full-rate 24-bit multiplier, and the quotient is
+// exact because (v - offset) * num_bins * (m * range - 2^24) < 2^16 * 2^8.
+// v lies in the interval exactly when y < R = range * num_bins * 256 (below
+// the offset y wraps past 2^32 - 2^24).  The 256-bin histogram over [0, 256)
+// takes the byte itself.  Pixels outside the interval, and the bytes past
+// the row's end in its last chunk, go to a spare counter (index 256), so that
+// every lane adds for every byte without a branch.  Each wave counts into its
+// own LDS sub-histogram, held as kCopies interleaved copies (copy c of bin b
+// at word b * kCopies + c, lane l adding to copy l mod kCopies): lanes that
+// draw the same bin, or bins in the same bank, collide less (measured on
+// uniform random bytes: 78 / 71 / 66 / 66 us for 1 / 2 / 4 / 8 copies).
+struct HistBins {
+  uint32_t B, D, R, m;
+};
+
+template <bool kIdentity>
+__global__ __launch_bounds__(kGThreads) void k_histogram(GlobalImg im, int num_bins, HistBins hb,
+                                                         uint32_t* __restrict__ counts) {
+  constexpr int kSlots = 257, kCopies = 4;
+  __shared__ uint32_t sub[kGThreads / 64][kSlots * kCopies];
   const int t = threadIdx.x, wv = t >> 6;
-  for (int k = t; k < (kGThreads / 64) * kSlots; k += kGThreads) (&sub[0][0])[k] = 0;
+  for (int k = t; k < (kGThreads / 64) * kSlots * kCopies; k += kGThreads) (&sub[0][0])[k] = 0;
   __syncthreads();
-  uint32_t* mine = sub[wv];
+  uint32_t* mine = sub[wv] + (t & (kCopies - 1));
+  const uint32_t B = hb.B & 0xFFFFFFu, m = hb.m & 0xFFFFFFu;
   stream_image<16, kGThreads, 2>(im, [&](const uint4& q, int n) {
     const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const uint32_t x = ((wd[k >> 2] >> (8 * (k & 3))) & 0xFFu) - (uint32_t)offset;
-      const uint32_t b = __umulhi(x * (uint32_t)num_bins, m);
-      atomicAdd(&mine[(k < n && x < (uint32_t)range) ? b : 256u], 1u);
+      const uint32_t v = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+      uint32_t b;
+      if constexpr (kIdentity) {
+        b = k < n ? v : 256u;
+      } else {
+        const uint32_t y = v * B + hb.D;
+        const uint32_t h = (uint32_t)(((uint64_t)(y & 0xFFFFFFu) * m) >> 32);
+        b = (k < n && y < hb.R) ? h : 256u;
+      }
+      atomicAdd(&mine[b * kCopies], 1u);
     }
   });
   __syncthreads();
   for (int b = t; b < num_bins; b += kGThreads) {
     uint32_t s = 0;
 #pragma unroll
-    for (int w = 0; w < kGThreads / 64; ++w) s += sub[w][b];
+    for (int w = 0; w < kGThreads / 64; ++w)
+#pragma unroll
+      for (int c = 0; c < kCopies; ++c) s += sub[w][b * kCopies + c];
     if (s) atomicAdd(&counts[b], s);
   }
 }
@@ -102,9 +125,16 @@ hipError_t launch_histogram(const GlobalImg& im, int num_bins, int offset, int r
   hipLaunchKernelGGL(k_fill_u32, dim3((num_bins + 255) / 256), dim3(256), 0, s, counts, num_bins, 0u, 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || im.w <= 0 || im.h <= 0) return e;
-  const uint32_t m = range == 1 ? 0u : (uint32_t)((((uint64_t)1 << 32) + (uint64_t)range - 1) / (uint64_t)range);
-  hipLaunchKernelGGL(k_histogram, dim3(global_grid(im, 2, 2048)), dim3(kGThreads), 0, s, im, num_bins, offset, range, m,
-                     counts);
+  HistBins hb;
+  hb.B = (uint32_t)num_bins << 8;
+  hb.D = 0u - (uint32_t)offset * hb.B;
+  hb.R = (uint32_t)range * hb.B;
+  hb.m = range == 1 ? 0u : (uint32_t)(((1u << 24) + (uint32_t)range - 1) / (uint32_t)range);
+  const dim3 grid(global_grid(im, 2, 2048));
+  if (offset == 0 && range == 256 && num_bins == 256)
+    hipLaunchKernelGGL(k_histogram<true>, grid, dim3(kGThreads), 0, s, im, num_bins, hb, counts);
+  else
+    hipLaunchKernelGGL(k_histogram<false>, grid, dim3(kGThreads), 0, s, im, num_bins, hb, counts);
   return hipGetLastError();
 }
 
