@@ -188,7 +188,9 @@ __global__ __launch_bounds__(kGThreads) void k_apply_lut(GlobalImg im, const uin
         o[j] = (uint32_t)tab[wd[j] & 0xFF] | (uint32_t)tab[(wd[j] >> 8) & 0xFF] << 8 |
                (uint32_t)tab[(wd[j] >> 16) & 0xFF] << 16 | (uint32_t)tab[wd[j] >> 24] << 24;
       }
-      *(uint4*)(orow + 16 * c) = make_uint4(o[0], o[1], o[2], o[3]);
+      // streamed past the caches: nothing here reads the output again
+      typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(u4v{o[0], o[1], o[2], o[3]}, (u4v*)(orow + 16 * c));
     }
   }
 }
