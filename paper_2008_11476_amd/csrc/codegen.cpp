@@ -319,7 +319,7 @@ void emit_prelude(Text& t, const GProg& P, std::string* why, bool* ok) {
 
 // ---- the point form ----------------------------------------------------------
 
-bool emit_points(const GProg& P, GenSource* out, std::string* why) {
+bool emit_points(const GProg& P, uint32_t stream, GenSource* out, std::string* why) {
   Text t;
   bool ok = true;
   emit_prelude(t, P, why, &ok);
@@ -371,7 +371,9 @@ bool emit_points(const GProg& P, GenSource* out, std::string* why) {
       t("    v%d[q] = point_eval(gop%d, %d, %s, %s, %s, %s);", o.out, k, ov.df,
         P.vals[o.in[0]].df == DF_F32 ? "true" : "false", in(0).c_str(), in(1).c_str(), in(2).c_str());
     t("  }");
-    if (ov.store) t("  store4(%d, (uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);", ov.df, ov.io, ov.io, o.out);
+    if (ov.store)
+      t("  store4<%s>(%d, (uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);",
+        (stream >> o.out) & 1 ? "true" : "false", ov.df, ov.io, ov.io, o.out);
   }
   t("}");
   out->text = t.s;
@@ -647,6 +649,7 @@ struct StageEmitter {
   const Layout& L;
   int TW, TH;
   int* slot;
+  uint32_t stream;  // values no later kernel reads: non-temporal stores
 
   void geometry(int v, int* rw, int* co) const { value_geometry(P, L, v, TW, rw, co); }
 
@@ -844,15 +847,15 @@ struct StageEmitter {
         t("        *(gx_i4*)(L + %s) = gx_i4{v%d[0], v%d[1], v%d[2], v%d[3]};",
           lds_index(o.out, ESV, ESH, "0", "0").c_str(), o.out, o.out, o.out, o.out);
       if (ov.store)
-        t("        if (own%s) store4(%d, (uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);",
-          edge ? " && y < H" : "", ov.df, ov.io, ov.io, o.out);
+        t("        if (own%s) store4<%s>(%d, (uint8_t*)io.ptr[%d] + (size_t)y * io.pitch[%d], x, W, v%d);",
+          edge ? " && y < H" : "", (stream >> o.out) & 1 ? "true" : "false", ov.df, ov.io, ov.io, o.out);
       t("      }");
     }
     t("    }");
   }
 };
 
-bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::string* why) {
+bool emit_tiles(const GProg& P, int tw_req, int th_req, uint32_t stream, GenSource* out, std::string* why) {
   Layout L;
   plan_stages(P, L);
   int nred = 0;
@@ -917,10 +920,10 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
   for (int s = 0; s < L.nstages; ++s) {
     t("  // stage %d: extent %d rows, %d columns", s, L.stage_ev[s], L.stage_eh[s]);
     t("  if constexpr (IN) {");
-    StageEmitter{t, P, L, TW, TH, &slot_in}.four_pixels(s, false);
+    StageEmitter{t, P, L, TW, TH, &slot_in, stream}.four_pixels(s, false);
     t("  } else {");
     if (L.resolved) {
-      StageEmitter{t, P, L, TW, TH, &slot_edge}.four_pixels(s, true);
+      StageEmitter{t, P, L, TW, TH, &slot_edge, stream}.four_pixels(s, true);
       // values of this stage that later windows read: their border
       bool fills = false;
       for (int k = 0; k < P.nops; ++k) {
@@ -931,7 +934,7 @@ bool emit_tiles(const GProg& P, int tw_req, int th_req, GenSource* out, std::str
         emit_fill(t, P, L, v, TW, TH);
       }
     } else {
-      StageEmitter{t, P, L, TW, TH, &slot_edge}.one_pixel(s);
+      StageEmitter{t, P, L, TW, TH, &slot_edge, stream}.one_pixel(s);
     }
     t("  }");
     if (s + 1 < L.nstages) t("  __syncthreads();");
@@ -1022,7 +1025,7 @@ bool gen_wanted(const GProg& P) {
          (in_df != DF_U8 && in_df != DF_F32);
 }
 
-bool gen_source(const GProg& P, int tw, int th, GenSource* out, std::string* why) {
+bool gen_source(const GProg& P, int tw, int th, uint32_t stream, GenSource* out, std::string* why) {
   bool any_local = false, any_red = false;
   for (int k = 0; k < P.nops; ++k) {
     const int kind = P.ops[k].kind;
@@ -1033,8 +1036,8 @@ bool gen_source(const GProg& P, int tw, int th, GenSource* out, std::string* why
     any_local |= is_local(kind);
     any_red |= is_reduce_op(kind);
   }
-  if (!any_local && !any_red) return emit_points(P, out, why);
-  return emit_tiles(P, tw, th, out, why);
+  if (!any_local && !any_red) return emit_points(P, stream, out, why);
+  return emit_tiles(P, tw, th, stream, out, why);
 }
 
 const GenKernel* gen_compile(const GenSource& src, std::string* why) {

@@ -43,9 +43,10 @@ struct GenSource {
 bool gen_wanted(const GProg& P);
 
 // Emit the kernel of program P with an output tile of tw x th (0: the
-// largest that fits the LDS budget).  False, with the reason, if P cannot be
-// generated at that tile.
-bool gen_source(const GProg& P, int tw, int th, GenSource* out, std::string* why);
+// largest that fits the LDS budget).  Bit i of `stream` marks value i as an
+// output that no later kernel reads (written with non-temporal stores).
+// False, with the reason, if P cannot be generated at that tile.
+bool gen_source(const GProg& P, int tw, int th, uint32_t stream, GenSource* out, std::string* why);
 
 // Compile (or find in the process cache) the kernel for `src`.  Null, with
 // the compiler's log, on failure.  Compiling needs no device.

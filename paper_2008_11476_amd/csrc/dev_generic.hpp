@@ -840,19 +840,31 @@ __device__ __forceinline__ void load4(int df, const uint8_t* row, int x, int W, 
   for (int k = 0; k < 4; ++k) v[k] = x + k < W ? gload(df, row, 0, x + k, 0) : 0;
 }
 
+// NT: a non-temporal store, for outputs that no later kernel of the graph
+// reads (they stream past the caches instead of waiting there to be
+// written back while the next kernels read)
+template <bool NT, class T>
+__device__ __forceinline__ void put(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <bool NT = false>
 __device__ __forceinline__ void store4(int df, uint8_t* row, int x, int W, const int v[4]) {
+  typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+  typedef uint32_t u4v __attribute__((ext_vector_type(4)));
   if (x + 3 < W) {
     switch (df) {
       case DF_U8:
-        *(uint32_t*)(row + x) = (uint32_t)(v[0] & 0xFF) | (uint32_t)(v[1] & 0xFF) << 8 |
-                                (uint32_t)(v[2] & 0xFF) << 16 | (uint32_t)(v[3] & 0xFF) << 24;
+        put<NT>((uint32_t*)(row + x), (uint32_t)(v[0] & 0xFF) | (uint32_t)(v[1] & 0xFF) << 8 |
+                                          (uint32_t)(v[2] & 0xFF) << 16 | (uint32_t)(v[3] & 0xFF) << 24);
         return;
       case DF_S16:
-        *(uint2*)(row + 2 * x) = make_uint2((uint32_t)(v[0] & 0xFFFF) | (uint32_t)v[1] << 16,
-                                            (uint32_t)(v[2] & 0xFFFF) | (uint32_t)v[3] << 16);
+        put<NT>((u2v*)(row + 2 * x), u2v{(uint32_t)(v[0] & 0xFFFF) | (uint32_t)v[1] << 16,
+                                          (uint32_t)(v[2] & 0xFFFF) | (uint32_t)v[3] << 16});
         return;
       default:
-        *(uint4*)(row + 4 * x) = make_uint4((uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]);
+        put<NT>((u4v*)(row + 4 * x), u4v{(uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]});
         return;
     }
   }

@@ -1035,8 +1035,18 @@ hvx_status verify_graph(Graph* g) {
             tw = t[1];
             th = t[2];
           }
+      // outputs that no other group reads stream past the caches
+      uint32_t stream = 0;
+      const std::set<int> own(gr.ops.begin(), gr.ops.end());
+      for (size_t i = 0; i < gr.gvals.size(); ++i) {
+        if (!gr.prog.vals[i].store) continue;
+        bool later = false;
+        for (int c : p.vals[gr.gvals[i]].consumers) later |= !own.count(c);
+        if (!later) stream |= 1u << i;
+      }
       // a chosen tile that does not fit falls back to the default one
-      if (!(tw && gen_source(gr.prog, tw, th, &src, &why)) && !gen_source(gr.prog, 0, 0, &src, &why)) src.text.clear();
+      if (!(tw && gen_source(gr.prog, tw, th, stream, &src, &why)) && !gen_source(gr.prog, 0, 0, stream, &src, &why))
+        src.text.clear();
       if (!src.text.empty()) gr.gen = gen_compile(src, &why);
       if (gr.gen && src.form == GEN_TILES) p.tiles.push_back({gr.ops[0], src.tw, src.th});
       if (gr.gen) {

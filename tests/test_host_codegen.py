@@ -175,3 +175,29 @@ def test_rank_one_convolve_masks_sum_columns_first(ctx, tmp_path, monkeypatch):
     for c in convs:
         hvx.hvx_release_convolution(c)
     hvx.hvx_release_graph(g)
+
+
+def test_outputs_no_later_kernel_reads_use_non_temporal_stores(ctx, tmp_path, monkeypatch):
+    """A generated kernel writes a value with non-temporal stores when no
+    later kernel of the graph reads it (it would only wait in the caches to
+    be written back), and with ordinary stores when a later kernel does.
+    Node by node, the three user point kernels of a graph that no other
+    test builds each get their own kernel: the two that feed the next one
+    store ordinarily, the last one streams."""
+    import glob
+    import re
+    monkeypatch.setenv("HVX_GEN_DUMP", str(tmp_path))
+    g = hvx.hvx_graph_create(ctx)
+    a, o = _img(ctx, 640, 480, k=0), _img(ctx, 640, 480, k=1)
+    v = [hvx.hvx_image_create_virtual(g) for _ in range(2)]
+    hvx.hvx_custom_point_node(g, "a * 7 - 3", [a], hvx.HVX_DF_S16, v[0])
+    hvx.hvx_custom_point_node(g, "a / 5 + b", [v[0], a], hvx.HVX_DF_S16, v[1])
+    hvx.hvx_custom_point_node(g, "a - b * 2", [v[1], a], hvx.HVX_DF_U8, o)
+    hvx.hvx_graph_set_option(g, hvx.HVX_OPT_FUSION, 0)
+    hvx.hvx_graph_verify(g)
+    assert _q(g, hvx.HVX_QUERY_NUM_KERNELS) == 3 and _q(g, hvx.HVX_QUERY_NUM_GENERATED) == 3
+    kinds = []
+    for src in glob.glob(str(tmp_path / "hvx_gen_*.hip")):
+        kinds += re.findall(r"store4<(true|false)>", open(src).read())
+    assert sorted(kinds) == ["false", "false", "true"], kinds
+    hvx.hvx_release_graph(g)
