@@ -870,7 +870,7 @@ def main():
                     help="headline launch mode (default: time both, keep the faster)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path: images and requests shard with "
+        print("bench.py runs on one GPU only (the library has no multi-GPU path: images and requests shard with "
               "no exchange); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
