@@ -30,7 +30,8 @@ def _img(w, h, seed, kind="edge"):
 
 
 @pytest.mark.parametrize("w,h", SIZES)
-@pytest.mark.parametrize("bins,offset,rng", [(256, 0, 256), (16, 0, 256), (10, 20, 200), (1, 0, 256), (7, 100, 21)])
+@pytest.mark.parametrize("bins,offset,rng", [(256, 0, 256), (16, 0, 256), (10, 20, 200), (1, 0, 256), (7, 100, 21),
+                                             (1, 77, 1), (5, 250, 6), (255, 1, 255)])
 def test_histogram(ctx, w, h, bins, offset, rng):
     import torch
     log("histogram %dx%d bins %d offset %d range %d" % (w, h, bins, offset, rng))
