@@ -41,11 +41,18 @@ SEPARABLE = [(np.outer([1, -2, 0, 3, 1], [2, -1, 1]), 4, "u8"),
              (np.outer([7000, -7000, 7000, -7000, 7000], [3, -1, 3]), 32768, "s16")]
 
 
-def _separable(img, border):
-    names = ["in", "c1", "c2", "out"]
+# 3x3 and 3-row by 5-column rank-one masks (column sums over three rows)
+SEPARABLE3 = [(np.outer([1, -2, 1], [3, 1, 3]), 2, "u8"),
+              (np.outer([2, 5, 2], [1, 3, -6, 3, 1]), 8, "s16")]
+
+
+def _separable(img, border, masks=SEPARABLE):
+    names = ["in", "c1", "c2", "out"][:len(masks)] + ["out"]
     nodes = [gs.N("convolve", [names[k]], [names[k + 1]], *border, params={"coeffs": m, "scale": s, "out_dtype": d})
-             for k, (m, s, d) in enumerate(SEPARABLE)]
-    return gs.Spec(nodes, {"in": img}, {"c1": np.uint8, "c2": np.uint8, "out": np.int16})
+             for k, (m, s, d) in enumerate(masks)]
+    outs = {n: np.uint8 for n in names[1:-1]}
+    outs["out"] = np.int16
+    return gs.Spec(nodes, {"in": img}, outs)
 
 
 def _tomasi(img):
@@ -140,6 +147,7 @@ def _cases():
         for b in BORDERS:
             out.append(("fchain", (w, h, b), lambda img=img, b=b: _fchain(img, b)))
             out.append(("separable", (w, h, b), lambda img=img, b=b: _separable(img, b)))
+            out.append(("separable3", (w, h, b), lambda img=img, b=b: _separable(img, b, SEPARABLE3)))
             out.append(("morph", (w, h, b), lambda img=img, b=b: _morph(img, b)))
             out.append(("nonlinear", (w, h, b), lambda img=img, b=b: _nonlinear(img, b)))
             out.append(("laplace_float", (w, h, b), lambda img=img, b=b: _laplace_float(img, b)))
